@@ -1,0 +1,35 @@
+"""Reference derivatives of the oracle (test infrastructure only).
+
+The paper has no adjoint; the gradient of a loss of the final state with
+respect to the initial velocity field is checked against the complex-step
+derivative of the oracle itself:
+
+    d L / d eps (u0 + eps d) = Im L(u0 + i h d) / h,   h = 1e-30,
+
+which is exact to rounding because every operation of the step (interpolation
+with geometry-only weights, moments, division by rho, the polynomial
+equilibrium, the relaxation) is analytic in the populations and the cell
+search depends only on the geometry.
+
+``kinetic_misfit_loss`` is the loss used for the adjoint workload:
+L = 1/2 sum_v M_v rho |u|^2 + sum_v M_v |u - u_target|^2 at the final step,
+with M_v the exact integral of node v's shape function.
+"""
+import numpy as np
+
+
+def kinetic_misfit_loss(sim, F, u_target, v_target):
+    rho, ux, uy, _ = sim.moments(F)
+    M = sim.grid.node_mass()
+    ke = 0.5 * np.sum(M * rho * (ux * ux + uy * uy))
+    mis = np.sum(M * ((ux - u_target) ** 2 + (uy - v_target) ** 2))
+    return ke + mis
+
+
+def complex_step_directional(sim, rho0, ux0, uy0, T0, dux, duy, nsteps, loss, h=1e-30):
+    """Directional derivative of loss(run(init(rho0, ux0 + eps dux, uy0 + eps duy, T0)))."""
+    ux = ux0 + 1j * h * dux
+    uy = uy0 + 1j * h * duy
+    F = sim.init(rho0.astype(complex), ux, uy, T0.astype(complex))
+    F = sim.run(F, nsteps)
+    return float(np.imag(loss(sim, F)) / h)

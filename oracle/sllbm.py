@@ -1,0 +1,161 @@
+"""One SLLBM time step, literally (oracle; test infrastructure only).
+
+Order of operations per step (Sec. II.D eq. (16) and Sec. II.E eq. (17)), with
+the reading that the collision is applied at the nodes and the post-collision
+field is what gets interpolated (so f, f_eq and f* "at x - dt xi_i" in eq. (16)
+are values of the interpolant of the nodal post-collision populations):
+
+1. stream: for every node x and velocity xi_i, the departure point
+   x - dt xi_i is moved back into the domain (periodic wrap, or zero-gradient
+   clamp to the boundary), its cell is found by brute force, and the cell's
+   Lagrange interpolant of the post-collision populations f+_i of the previous
+   step is evaluated there, eq. (17);
+2. moments of the streamed populations, eqs. (3)-(5): rho = sum f,
+   rho u = sum xi f, 2 rho E = sum (|xi|^2 f + g);
+3. temperature: theta = (2 rho E - rho |u|^2) / (2 C_v rho); for a single
+   population (monatomic gas, C_v = D/2) the g sum is absent; isothermal
+   models fix theta = 1 (Sec. III.A);
+4. BGK relaxation toward the 4th-order equilibrium with
+   tau = nu / (c_s^2 dt) + 1/2 (Sec. II.D), Prandtl number 1 so the
+   quasi-equilibrium term of eq. (16) vanishes:
+   f+ = f - (f - f_eq)/tau, g+ = g - (g - g_eq)/tau.
+
+Populations are stored as an array of shape (S, Q, nnodes) with S = 1 (f) or
+S = 2 (f, g) and node index v = iy * nx + ix.
+"""
+import numpy as np
+
+from .equilibrium import cv_of_gamma, f_eq, g_eq
+from .grid import lagrange_basis
+from .velocity import D, d1q5, tensor_product
+
+MODELS = ("isothermal", "monatomic", "polyatomic")
+
+
+class Sim:
+    def __init__(self, grid, dt, nu, model, gamma=1.4, xi1=None, w1=None):
+        if model not in MODELS:
+            raise ValueError(model)
+        self.grid = grid
+        self.dt = float(dt)
+        self.nu = float(nu)
+        self.model = model
+        if xi1 is None:
+            xi1, w1 = d1q5()
+        self.xi, self.w = tensor_product(np.asarray(xi1, float), np.asarray(w1, float))
+        self.Q = len(self.w)
+        # relaxation time tau = nu/(c_s^2 dt) + 1/2 with c_s = 1 (Sec. II.D);
+        # nu = inf means pure streaming (1/tau = 0)
+        self.tau = np.inf if np.isinf(self.nu) else self.nu / self.dt + 0.5
+        self.omega = 0.0 if np.isinf(self.tau) else 1.0 / self.tau
+        if model == "polyatomic":
+            self.gamma = float(gamma)
+            self.cv = cv_of_gamma(self.gamma)
+            self.S = 2
+        elif model == "monatomic":
+            self.cv = D / 2.0
+            self.gamma = 1.0 + 1.0 / self.cv
+            self.S = 1
+        else:
+            self.cv = None
+            self.gamma = None
+            self.S = 1
+        self.X, self.Y = grid.coords()
+
+    # ---- equilibrium and initialisation -------------------------------------------
+    def equilibrium(self, rho, ux, uy, theta):
+        feq = f_eq(self.xi, self.w, rho, ux, uy, theta)
+        if self.S == 1:
+            return feq[None]
+        return np.stack([feq, g_eq(feq, theta, self.gamma)])
+
+    def init(self, rho, ux, uy, T):
+        """Populations at equilibrium with the given node fields (the paper is
+        silent on initialisation; f = f_eq and g = g_eq is the reading used)."""
+        theta = np.ones_like(rho) if self.model == "isothermal" else T
+        return self.equilibrium(rho, ux, uy, theta)
+
+    # ---- streaming ------------------------------------------------------------
+    def departure_stencil(self, i, nodes):
+        """For velocity i and the selected nodes: source node indices (p+1, p+1, n)
+        and interpolation weights (p+1, p+1, n) of the departure point."""
+        g = self.grid
+        xd = g.ax.apply_boundary(self.X[nodes] - self.dt * self.xi[i, 0])
+        yd = g.ay.apply_boundary(self.Y[nodes] - self.dt * self.xi[i, 1])
+        cx, rx = g.ax.locate(xd)
+        cy, ry = g.ay.locate(yd)
+        lx = lagrange_basis(g.ax.r, rx)
+        ly = lagrange_basis(g.ay.r, ry)
+        P1 = g.p + 1
+        src = np.zeros((P1, P1, len(nodes)), dtype=np.int64)
+        wgt = np.zeros((P1, P1, len(nodes)))
+        for a in range(P1):
+            for b in range(P1):
+                src[a, b] = g.ay.node_of(cy, b) * g.nx + g.ax.node_of(cx, a)
+                wgt[a, b] = lx[a] * ly[b]
+        return src, wgt
+
+    def stream(self, F, nodes=None):
+        """Values of the interpolant of F at the departure points, eq. (17)."""
+        if nodes is None:
+            nodes = np.arange(self.grid.nnodes)
+        nodes = np.asarray(nodes)
+        out = np.zeros((F.shape[0], self.Q, len(nodes)), dtype=F.dtype)
+        for i in range(self.Q):
+            src, wgt = self.departure_stencil(i, nodes)
+            acc = np.zeros((F.shape[0], len(nodes)), dtype=F.dtype)
+            for a in range(self.grid.p + 1):
+                for b in range(self.grid.p + 1):
+                    acc = acc + wgt[a, b] * F[:, i, src[a, b]]
+            out[:, i] = acc
+        return out
+
+    # ---- moments and collision --------------------------------------------------
+    def moments(self, F):
+        """rho, u_x, u_y, theta of a population array (S, Q, n), eqs. (3)-(5)."""
+        f = F[0]
+        rho = f.sum(axis=0)
+        jx = (self.xi[:, 0, None] * f).sum(axis=0)
+        jy = (self.xi[:, 1, None] * f).sum(axis=0)
+        ux = jx / rho
+        uy = jy / rho
+        if self.model == "isothermal":
+            theta = np.ones_like(rho)
+        else:
+            two_rho_e = ((self.xi[:, 0] ** 2 + self.xi[:, 1] ** 2)[:, None] * f).sum(axis=0)
+            if self.S == 2:
+                two_rho_e = two_rho_e + F[1].sum(axis=0)
+            theta = (two_rho_e - rho * (ux * ux + uy * uy)) / (2.0 * self.cv * rho)
+        return rho, ux, uy, theta
+
+    def collide(self, F):
+        """BGK relaxation at the nodes (eq. (16) with Pr = 1)."""
+        rho, ux, uy, theta = self.moments(F)
+        feq = self.equilibrium(rho, ux, uy, theta)
+        return F - self.omega * (F - feq)
+
+    def step(self, F, nodes=None):
+        """One full time step; with ``nodes`` only those nodes' new values are returned."""
+        return self.collide(self.stream(F, nodes))
+
+    def run(self, F, nsteps):
+        for _ in range(nsteps):
+            F = self.step(F)
+        return F
+
+    # ---- outputs ---------------------------------------------------------------
+    def macro(self, F):
+        """rho, u_x, u_y, T per node (T = theta with T0 = R = 1)."""
+        return self.moments(F)
+
+    def mass(self, F):
+        """Integral of the interpolated density: sum_v M_v rho_v."""
+        rho = F[0].sum(axis=0)
+        return float(np.sum(self.grid.node_mass() * rho))
+
+    def unstable(self, F):
+        """The paper's stability criterion: all macroscopic values bounded."""
+        rho, ux, uy, theta = self.moments(F)
+        ok = np.all(np.isfinite(rho)) and np.all(np.isfinite(ux)) and np.all(np.isfinite(uy))
+        ok = ok and np.all(np.isfinite(theta)) and np.all(rho > 0) and np.all(theta > 0)
+        return not ok

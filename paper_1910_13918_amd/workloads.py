@@ -1,0 +1,296 @@
+"""Seeded, synthetic workloads shaped like the paper's test cases.
+
+This module only describes problems: domains, cell edges, orders, boundary
+kinds, physical parameters and initial macroscopic fields evaluated at given
+node coordinates.  It holds none of the lattice Boltzmann arithmetic (no
+velocity set, no equilibrium, no interpolation), so both the HIP path and the
+CPU oracle can draw their inputs from it.
+
+Units are code units with c_s = R = T0 = 1, so the pressure is P = rho T.
+Time steps follow a CFL number of 0.5 on the smallest node spacing,
+CFL = dt * XI_MAX / dx_min, with XI_MAX the largest D1Q5 speed; when an end
+time is given the step count is rounded up and dt shrunk to hit it exactly.
+
+Shapes (Sec. III of arXiv:1910.13918):
+* ``tgv``      -- Taylor-Green vortex, periodic [0, 2 pi]^2 (Sec. III.A);
+* ``sod``      -- Sod shock tube as a quasi-1-D strip (Sec. III.C, with the
+                  standard 1 / 0.125 density and 1 / 0.1 pressure ratios);
+* ``riemann``  -- four-quadrant Riemann problem on [0, 1]^2 with zero-gradient
+                  boundaries (Sec. III.D) and seeded quadrant states;
+* ``svi``      -- stationary normal shock plus an isentropic vortex on a grid
+                  stretched in x by the sinusoidal map of Sec. III.E;
+* ``smooth_density`` -- density wave advected at constant velocity and
+                  pressure (Sec. III.B).
+"""
+import math
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+
+XI_MAX = 2.8569700138728056  # sqrt(5 + sqrt(10)), largest D1Q5 speed (CFL definition)
+# smallest gap between neighbouring Gauss-Lobatto-Chebyshev points of a unit cell, per order
+GLC_MIN_GAP = {1: 1.0, 2: 0.5, 3: 0.25, 4: 0.14644660940672627}
+
+
+def cfl_time_step(dx_min, cfl=0.5, t_end=None, steps=None):
+    dt = cfl * dx_min / XI_MAX
+    if t_end is not None:
+        n = int(math.ceil(t_end / dt - 1e-9))
+        return t_end / n, n
+    return dt, steps
+
+
+def uniform_edges(ncells, lo, hi):
+    return lo + (hi - lo) * np.arange(ncells + 1, dtype=float) / ncells
+
+
+@dataclass
+class Workload:
+    name: str
+    edges_x: np.ndarray
+    edges_y: np.ndarray
+    p: int
+    periodic_x: bool
+    periodic_y: bool
+    model: str            # "isothermal" | "monatomic" | "polyatomic"
+    gamma: float
+    nu: float
+    dt: float
+    steps: int
+    fields: Callable      # (x, y) -> rho, ux, uy, T
+    uniform: bool = True
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ncx(self):
+        return len(self.edges_x) - 1
+
+    @property
+    def ncy(self):
+        return len(self.edges_y) - 1
+
+    @property
+    def nx(self):
+        return self.ncx * self.p + (0 if self.periodic_x else 1)
+
+    @property
+    def ny(self):
+        return self.ncy * self.p + (0 if self.periodic_y else 1)
+
+    @property
+    def nnodes(self):
+        return self.nx * self.ny
+
+    @property
+    def nsets(self):
+        return 2 if self.model == "polyatomic" else 1
+
+
+# ---------------------------------------------------------------------------- TGV
+def tgv(ncells=8, p=2, U0=0.1, Re=100.0, steps=200, cfl=0.5, model="isothermal", name=None):
+    """Taylor-Green vortex on [0, 2 pi]^2: u = U0 sin x cos y, v = -U0 cos x sin y,
+    rho = 1 + (U0^2 / 4)(cos 2x + cos 2y) (pressure of the closed form with
+    P = rho for the isothermal model), nu = U0 * 2 pi / Re."""
+    L = 2.0 * np.pi
+    h = L / ncells
+    dt, n = cfl_time_step(h * GLC_MIN_GAP[p], cfl, steps=steps)
+    nu = U0 * L / Re
+
+    def fields(x, y):
+        ux = U0 * np.sin(x) * np.cos(y)
+        uy = -U0 * np.cos(x) * np.sin(y)
+        rho = 1.0 + 0.25 * U0 * U0 * (np.cos(2 * x) + np.cos(2 * y))
+        return rho, ux, uy, np.ones_like(x)
+
+    e = uniform_edges(ncells, 0.0, L)
+    return Workload(name or f"tgv_{ncells}x{ncells}_p{p}", e, e.copy(), p, True, True, model,
+                    1.4, nu, dt, n, fields, True, {"U0": U0, "Re": Re})
+
+
+# ---------------------------------------------------------------------------- Sod
+def sod(ncx=1024, ncy=4, p=3, t_end=0.2, nu=1.2e-4, gamma=1.4, cfl=0.5, name=None):
+    """Sod tube on x in [0, 1] (zero-gradient), y periodic with ncy square cells.
+    Left (x < 1/2): rho = 1, P = 1; right: rho = 0.125, P = 0.1; u = 0."""
+    h = 1.0 / ncx
+    dt, n = cfl_time_step(h * GLC_MIN_GAP[p], cfl, t_end=t_end)
+
+    def fields(x, y):
+        left = x < 0.5
+        rho = np.where(left, 1.0, 0.125)
+        P = np.where(left, 1.0, 0.1)
+        return rho, np.zeros_like(x), np.zeros_like(x), P / rho
+
+    return Workload(name or f"sod_{ncx}x{ncy}_p{p}", uniform_edges(ncx, 0.0, 1.0),
+                    uniform_edges(ncy, 0.0, ncy * h), p, False, True, "polyatomic", gamma,
+                    nu, dt, n, fields, True, {"t_end": t_end})
+
+
+# ------------------------------------------------------------------------- Riemann
+RIEMANN_DEFAULT_SEED = 0
+
+
+def riemann_states(seed):
+    """Quadrant states (NE, NW, SW, SE) drawn with numpy's default_rng(seed):
+    rho ~ U[0.1, 1.5], P ~ U[0.03, 1.5], |u| ~ U[0, 1.2], angle ~ U[0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    states = []
+    for _ in range(4):
+        rho = rng.uniform(0.1, 1.5)
+        P = rng.uniform(0.03, 1.5)
+        speed = rng.uniform(0.0, 1.2)
+        ang = rng.uniform(0.0, 2.0 * np.pi)
+        states.append((rho, speed * np.cos(ang), speed * np.sin(ang), P))
+    return states
+
+
+def riemann(ncells=512, p=2, seed=None, t_end=0.25, nu=1.73e-4, gamma=1.4, cfl=0.5,
+            states=None, name=None):
+    """Four-quadrant Riemann problem on [0, 1]^2 with zero-gradient boundaries;
+    quadrant boundaries at x = 1/2 and y = 1/2 (a node on x = 1/2 or y = 1/2
+    takes the state of the upper / right side)."""
+    if states is None:
+        states = riemann_states(RIEMANN_DEFAULT_SEED if seed is None else seed)
+    h = 1.0 / ncells
+    dt, n = cfl_time_step(h * GLC_MIN_GAP[p], cfl, t_end=t_end)
+
+    def fields(x, y):
+        east = x >= 0.5
+        north = y >= 0.5
+        quad = np.where(north, np.where(east, 0, 1), np.where(east, 3, 2))
+        tab = np.array(states)
+        rho, ux, uy, P = (tab[quad, k] for k in range(4))
+        return rho, ux, uy, P / rho
+
+    e = uniform_edges(ncells, 0.0, 1.0)
+    return Workload(name or f"riemann_{ncells}x{ncells}_p{p}", e, e.copy(), p, False, False,
+                    "polyatomic", gamma, nu, dt, n, fields, True,
+                    {"seed": seed, "states": [tuple(map(float, s)) for s in states]})
+
+
+# ------------------------------------------------------------------ adjoint TGV
+def adjoint_tgv(ncells=128, p=4, U0=0.3, Re=100.0, steps=500, cfl=0.5, name=None):
+    return tgv(ncells, p, U0, Re, steps, cfl, "isothermal",
+               name or f"adjoint_tgv_{ncells}x{ncells}_p{p}")
+
+
+def fourier_target(x, y, U0, seed=1234, modes=8, kmax=4):
+    """Seeded target velocity field: a sum of ``modes`` random Fourier modes with
+    integer wave vectors |k| <= kmax and amplitudes below U0."""
+    rng = np.random.default_rng(seed)
+    ut = np.zeros_like(x)
+    vt = np.zeros_like(x)
+    for _ in range(modes):
+        while True:
+            k = rng.integers(-kmax, kmax + 1, size=2)
+            if 0 < k[0] ** 2 + k[1] ** 2 <= kmax * kmax:
+                break
+        amp = rng.uniform(0.0, U0, size=2) / modes
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=2)
+        arg = k[0] * x + k[1] * y
+        ut += amp[0] * np.sin(arg + ph[0])
+        vt += amp[1] * np.sin(arg + ph[1])
+    return ut, vt
+
+
+def random_directions(n, count, seed=4321):
+    """``count`` seeded unit directions in R^(2n) (for u and v of n nodes)."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((count, 2, n))
+    d /= np.sqrt((d * d).sum(axis=(1, 2)))[:, None, None]
+    return d
+
+
+# --------------------------------------------------------------------------- SVI
+def rankine_hugoniot(mach, gamma=1.4):
+    """Downstream/upstream ratios across a normal shock: (rho_B/rho_A, P_B/P_A, Ma_B)."""
+    m2 = mach * mach
+    rr = (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    pr = 1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0)
+    mb = math.sqrt(((gamma - 1.0) * m2 + 2.0) / (2.0 * gamma * m2 - (gamma - 1.0)))
+    return rr, pr, mb
+
+
+def stretched_edges(ncells, length, lam=0.95):
+    """Cell edges of the sinusoidal map of Sec. III.E scaled to [0, length]:
+    x_t = (L / 2 pi)(lam sin(2 pi x / L) + 2 pi x / L); cells are finest
+    (by the factor 1 - lam) at x = L / 2."""
+    x = uniform_edges(ncells, 0.0, length)
+    k = 2.0 * np.pi / length
+    return (lam * np.sin(k * x) + k * x) / k
+
+
+def isentropic_vortex(x, y, xc, yc, radius, mach_v, rho_inf, P_inf, u_inf, gamma=1.4):
+    """Isentropic vortex of Sec. III.E on a uniform stream (rho_inf, P_inf, u_inf, 0):
+    u_theta = c Ma_v r' exp((1 - r'^2)/2), r' = r / radius, c = sqrt(gamma P_inf / rho_inf),
+    rho = rho_inf phi^(1/(gamma-1)), P = P_inf phi^(gamma/(gamma-1)),
+    phi = 1 - (gamma - 1)/2 Ma_v^2 exp(1 - r'^2)
+    (with Ma_v squared, which makes dP/dr = rho u_theta^2 / r hold exactly)."""
+    dx = x - xc
+    dy = y - yc
+    rp = np.sqrt(dx * dx + dy * dy) / radius
+    c = math.sqrt(gamma * P_inf / rho_inf)
+    ut = c * mach_v * rp * np.exp(0.5 * (1.0 - rp * rp))
+    phi = 1.0 - 0.5 * (gamma - 1.0) * mach_v * mach_v * np.exp(1.0 - rp * rp)
+    rho = rho_inf * phi ** (1.0 / (gamma - 1.0))
+    P = P_inf * phi ** (gamma / (gamma - 1.0))
+    r = np.maximum(np.sqrt(dx * dx + dy * dy), 1e-300)
+    ux = u_inf - ut * dy / r
+    uy = ut * dx / r
+    return rho, ux, uy, P
+
+
+def svi(ncx=1024, ncy=512, p=3, steps=2000, mach_s=1.2, mach_v=0.25, radius=0.075, Re=800.0,
+        gamma=1.4, lam=0.95, cfl=0.5, name=None):
+    """Stationary normal shock at x = 1 on [0, 2] x [0, 1] (x zero-gradient and
+    stretched, y periodic), upstream state A (x > 1): rho = 1, T = 1,
+    u = -Ma_s sqrt(gamma); downstream state B from Rankine-Hugoniot; an
+    isentropic vortex of radius 0.075 centred at (1.15, 0.5) on the upstream
+    flow; nu = c_A * radius / Re."""
+    Lx, Ly = 2.0, 1.0
+    hx = Lx / ncx
+    dt, n = cfl_time_step(hx * GLC_MIN_GAP[p], cfl, steps=steps)
+    cA = math.sqrt(gamma)
+    uA = -mach_s * cA
+    rr, pr, _ = rankine_hugoniot(mach_s, gamma)
+    rhoB, PB, uB = rr, pr, uA / rr
+    nu = cA * radius / Re
+
+    def fields(x, y):
+        rv, uxv, uyv, Pv = isentropic_vortex(x, y, 1.15, 0.5, radius, mach_v, 1.0, 1.0, uA, gamma)
+        up = x > 1.0
+        rho = np.where(up, rv, rhoB)
+        ux = np.where(up, uxv, uB)
+        uy = np.where(up, uyv, 0.0)
+        P = np.where(up, Pv, PB)
+        return rho, ux, uy, P / rho
+
+    return Workload(name or f"svi_{ncx}x{ncy}_p{p}", stretched_edges(ncx, Lx, lam),
+                    uniform_edges(ncy, 0.0, Ly), p, False, True, "polyatomic", gamma, nu, dt,
+                    n, fields, False, {"mach_s": mach_s, "mach_v": mach_v, "Re": Re})
+
+
+# --------------------------------------------------------------- smooth density
+def smooth_density(ncells=4, p=4, t_end=2.0, ux0=1.0, nu=1e-10, gamma=1.4, cfl=0.5,
+                   steps: Optional[int] = None, name=None):
+    """rho = 1 + 0.2 sin(pi (x - ux0 t)) sin(pi y), u = (ux0, 0), P = 1 on
+    [-1, 1]^2 periodic (Sec. III.B); the exact solution is pure advection."""
+    h = 2.0 / ncells
+    if steps is None:
+        dt, n = cfl_time_step(h * GLC_MIN_GAP[p], cfl, t_end=t_end)
+    else:
+        dt, n = t_end / steps, steps
+
+    def fields(x, y):
+        rho = 1.0 + 0.2 * np.sin(np.pi * x) * np.sin(np.pi * y)
+        return rho, np.full_like(x, ux0), np.zeros_like(x), 1.0 / rho
+
+    e = uniform_edges(ncells, -1.0, 1.0)
+    return Workload(name or f"smooth_density_{ncells}x{ncells}_p{p}", e, e.copy(), p, True, True,
+                    "polyatomic", gamma, nu, dt, n, fields, True, {"ux0": ux0, "t_end": t_end})
+
+
+def population_noise(shape, seed, rel=0.05):
+    """Seeded multiplicative perturbation factors 1 + rel * U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    return 1.0 + rel * rng.uniform(-1.0, 1.0, size=shape)

@@ -1,0 +1,248 @@
+"""Pins of the oracle's full step: collision invariants, steady states,
+closed-form flows, the exact Riemann solution, and the set-up physics.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import riemann
+from oracle.adjoint import complex_step_directional, kinetic_misfit_loss
+from oracle.grid import Grid, uniform_edges
+from oracle.sllbm import Sim
+from paper_1910_13918_amd import workloads as W
+from tests.conftest import GOLDEN
+
+
+def _sim(model, p=2, nc=3, periodic=True, nu=0.01, dt=0.05):
+    g = Grid(uniform_edges(nc, 0, 1.0), uniform_edges(nc, 0, 1.0), p, periodic, periodic)
+    return g, Sim(g, dt, nu, model)
+
+
+def _random_macro(n, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.uniform(0.5, 1.5, n), rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n),
+            rng.uniform(0.7, 1.3, n))
+
+
+@pytest.mark.parametrize("model", ["isothermal", "monatomic", "polyatomic"])
+def test_collision_fixed_point(model):
+    """f = f_eq(rho, u, theta) is left unchanged by the BGK collision."""
+    g, sim = _sim(model)
+    F = sim.init(*_random_macro(g.nnodes, 1))
+    np.testing.assert_allclose(sim.collide(F), F, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("model", ["isothermal", "monatomic", "polyatomic"])
+def test_moments_recover_macro_fields(model):
+    g, sim = _sim(model)
+    rho, ux, uy, T = _random_macro(g.nnodes, 2)
+    r, u, v, t = sim.moments(sim.init(rho, ux, uy, T))
+    np.testing.assert_allclose(r, rho, rtol=1e-14)
+    np.testing.assert_allclose(u, ux, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(v, uy, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(t, 1.0 if model == "isothermal" else T, rtol=1e-13)
+
+
+@pytest.mark.parametrize("model", ["isothermal", "monatomic", "polyatomic"])
+def test_collision_conserves_invariants(model):
+    """Per node: sum f, sum xi f and (thermal) sum |xi|^2 f + sum g are unchanged."""
+    g, sim = _sim(model)
+    F = sim.init(*_random_macro(g.nnodes, 3)) * W.population_noise((sim.S, 25, g.nnodes), 4, 0.1)
+    Fp = sim.collide(F)
+    xi = sim.xi
+    np.testing.assert_allclose(Fp[0].sum(0), F[0].sum(0), rtol=1e-14)
+    np.testing.assert_allclose((xi[:, 0, None] * Fp[0]).sum(0), (xi[:, 0, None] * F[0]).sum(0),
+                               rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose((xi[:, 1, None] * Fp[0]).sum(0), (xi[:, 1, None] * F[0]).sum(0),
+                               rtol=1e-12, atol=1e-14)
+    if model != "isothermal":
+        e2 = (xi ** 2).sum(1)[:, None]
+        en = lambda F_: (e2 * F_[0]).sum(0) + (F_[1].sum(0) if sim.S == 2 else 0.0)
+        np.testing.assert_allclose(en(Fp), en(F), rtol=1e-13)
+
+
+@pytest.mark.parametrize("p", [1, 3])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_uniform_state_stays_uniform(p, periodic):
+    g, sim = _sim("polyatomic", p=p, periodic=periodic)
+    n = g.nnodes
+    F = sim.init(np.full(n, 1.1), np.full(n, 0.3), np.full(n, -0.2), np.full(n, 0.9))
+    F1 = sim.run(F, 5)
+    np.testing.assert_allclose(F1, F, rtol=1e-13, atol=1e-16)
+
+
+def test_tgv_decay_convergence():
+    """Taylor-Green vortex against the closed form u ~ exp(-2 nu t) (Sec. III.A):
+    at p = 2 the error falls by more than 2^1.5 per refinement, at p = 4 it is
+    already small on coarse grids (spatial order p, Sec. II.E error estimate)."""
+    t_end = 2.0
+    errs = {}
+    for p, ncs in ((2, (4, 8, 16)), (4, (4,))):
+        for nc in ncs:
+            wl = W.tgv(nc, p)
+            steps = int(np.ceil(t_end / wl.dt))
+            g = Grid(wl.edges_x, wl.edges_y, p, True, True)
+            sim = Sim(g, t_end / steps, wl.nu, wl.model)
+            X, Y = g.coords()
+            F = sim.run(sim.init(*wl.fields(X, Y)), steps)
+            _, u, v, _ = sim.macro(F)
+            dec = np.exp(-2 * wl.nu * t_end)
+            errs[(p, nc)] = max(np.abs(u - 0.1 * np.sin(X) * np.cos(Y) * dec).max(),
+                                np.abs(v + 0.1 * np.cos(X) * np.sin(Y) * dec).max()) / 0.1
+    o1 = np.log2(errs[(2, 4)] / errs[(2, 8)])
+    o2 = np.log2(errs[(2, 8)] / errs[(2, 16)])
+    assert o1 > 1.5 and o2 > 1.5, errs
+    assert errs[(4, 4)] < 3e-3, errs
+
+
+def test_tgv_config_decay_and_momentum():
+    """The 8x8-cell, p = 2 Taylor-Green workload: total momentum stays zero by
+    symmetry, the vortex decays monotonically, and the decay is within 20 % of
+    exp(-2 nu t) after 200 steps (coarse-grid numerical viscosity adds to nu)."""
+    wl = W.tgv()
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, True, True)
+    sim = Sim(g, wl.dt, wl.nu, wl.model)
+    X, Y = g.coords()
+    F = sim.init(*wl.fields(X, Y))
+    M = g.node_mass()
+    amp = []
+    for k in range(wl.steps):
+        F = sim.step(F)
+        if k % 50 == 49:
+            rho, u, v, _ = sim.macro(F)
+            assert abs(np.sum(M * rho * u)) < 1e-13 and abs(np.sum(M * rho * v)) < 1e-13
+            amp.append(np.abs(u).max())
+    assert all(a > b for a, b in zip(amp[:-1], amp[1:]))
+    ratio = amp[-1] / 0.1 / np.exp(-2 * wl.nu * wl.dt * wl.steps)
+    assert 0.8 < ratio < 1.0
+
+
+@pytest.mark.slow
+def test_sod_against_exact_solution():
+    """Sod tube (Sec. III.C) against the exact Riemann solution: the L1 density
+    error shrinks under refinement and the shock lands within 3 nodes."""
+    gamma = 1.4
+    errs = []
+    for ncx in (32, 64):
+        wl = W.sod(ncx, 1, 3, t_end=0.15)
+        g = Grid(wl.edges_x, wl.edges_y, wl.p, False, True)
+        sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=gamma)
+        X, Y = g.coords()
+        F = sim.run(sim.init(*wl.fields(X, Y)), wl.steps)
+        rho, u, v, T = sim.macro(F)
+        x = X[: g.nx]
+        r_ex, u_ex, p_ex = riemann.solution((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), gamma, x, 0.5,
+                                            wl.dt * wl.steps)
+        errs.append(np.mean(np.abs(rho[: g.nx] - r_ex)))
+        # shock: last node where the density exceeds the mean of the post-shock and right states
+        thr = 0.5 * (0.125 + 0.26557)
+        xs_num = x[np.nonzero(rho[: g.nx] > thr)[0].max()]
+        xs_ex = x[np.nonzero(r_ex > thr)[0].max()]
+        assert abs(xs_num - xs_ex) <= 3 * (1.0 / ncx / 3) + 1e-12
+        assert not sim.unstable(F)
+    assert errs[1] < errs[0], errs
+
+
+# ------------------------------------------------------------ exact Riemann solver
+def _flux(rho, u, p, gamma):
+    E = p / (gamma - 1) + 0.5 * rho * u * u
+    return np.array([rho * u, rho * u * u + p, u * (E + p)]), np.array([rho, rho * u, E])
+
+
+def test_exact_riemann_jump_conditions():
+    """Across the right shock the Rankine-Hugoniot conditions F_R - F_* = s (U_R - U_*)
+    hold; across the left rarefaction entropy and the Riemann invariant
+    u + 2c/(gamma - 1) are constant; pressure and velocity are continuous at the contact."""
+    gamma = 1.4
+    L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    ps, us = riemann.star_state(L, R, gamma)
+    # right shock: the post-shock state is sampled from the solver, the shock
+    # speed follows from mass conservation, momentum and energy must then balance
+    rs, u2, p2 = riemann.sample(L, R, gamma, us + 1e-6)
+    assert u2 == pytest.approx(us) and p2 == pytest.approx(ps)
+    s = (R[0] * R[1] - rs * us) / (R[0] - rs)
+    FR, UR = _flux(*R, gamma)
+    Fs, Us = _flux(rs, us, ps, gamma)
+    np.testing.assert_allclose(FR - Fs, s * (UR - Us), atol=1e-12)
+    # the solver puts the jump at that speed
+    assert riemann.sample(L, R, gamma, s - 1e-9)[0] == pytest.approx(rs)
+    assert riemann.sample(L, R, gamma, s + 1e-9)[0] == pytest.approx(R[0])
+    # left fan, sampled at several points
+    cL = np.sqrt(gamma)
+    for x in np.linspace(-cL + 1e-3, us - np.sqrt(gamma * ps / (L[0] * (ps / L[2]) ** (1 / gamma))) - 1e-3, 7):
+        rho, u, p = riemann.sample(L, R, gamma, x)
+        assert p / rho ** gamma == pytest.approx(L[2] / L[0] ** gamma, rel=1e-12)
+        assert u + 2 * np.sqrt(gamma * p / rho) / (gamma - 1) == pytest.approx(2 * cL / (gamma - 1), rel=1e-12)
+    a = riemann.sample(L, R, gamma, us - 1e-9)
+    b = riemann.sample(L, R, gamma, us + 1e-9)
+    assert a[2] == pytest.approx(b[2], rel=1e-12) and a[1] == pytest.approx(b[1], rel=1e-12)
+    # equal states: nothing happens
+    rho, u, p = riemann.solution(L, L, gamma, np.linspace(0, 1, 9), 0.5, 0.1)
+    np.testing.assert_allclose(rho, 1.0)
+    np.testing.assert_allclose(u, 0.0, atol=1e-12)
+
+
+# ------------------------------------------------------------------- set-up physics
+def test_rankine_hugoniot_matches_paper():
+    gold = json.load(open(os.path.join(GOLDEN, "paper_numbers.json")))["shock_vortex_mach_downstream"]
+    rr, pr, mb = W.rankine_hugoniot(gold["mach_upstream"], gold["gamma"])
+    assert round(mb, gold["digits"]) == gold["value"]
+    # mass and momentum flux continuity across the shock (A: rho=1, P=1)
+    gamma = gold["gamma"]
+    uA = gold["mach_upstream"] * np.sqrt(gamma)
+    uB = uA / rr
+    assert 1.0 * uA == pytest.approx(rr * uB, rel=1e-14)
+    assert uA * uA + 1.0 == pytest.approx(rr * uB * uB + pr, rel=1e-14)
+    assert mb == pytest.approx(uB / np.sqrt(gamma * pr / rr), rel=1e-14)
+
+
+def test_riemann_tau_relation_matches_paper():
+    gold = json.load(open(os.path.join(GOLDEN, "paper_numbers.json")))["riemann_relaxation_time"]
+    dt = gold["t_end"] / gold["steps"]
+    tau = gold["nu"] / dt + 0.5
+    # the printed viscosity is rounded to 3 digits
+    assert tau == pytest.approx(gold["tau"], abs=2e-3)
+
+
+def test_isentropic_vortex_radial_equilibrium():
+    gamma, R, Ma = 1.4, 0.075, 0.25
+    r = np.linspace(0.2 * R, 4 * R, 50)
+    h = 1e-6
+    _, _, _, Pp = W.isentropic_vortex(r + h, 0 * r, 0.0, 0.0, R, Ma, 1.0, 1.0, 0.0, gamma)
+    _, _, _, Pm = W.isentropic_vortex(r - h, 0 * r, 0.0, 0.0, R, Ma, 1.0, 1.0, 0.0, gamma)
+    rho, ux, uy, _ = W.isentropic_vortex(r, 0 * r, 0.0, 0.0, R, Ma, 1.0, 1.0, 0.0, gamma)
+    np.testing.assert_allclose((Pp - Pm) / (2 * h), rho * uy * uy / r, rtol=1e-6, atol=1e-8)
+
+
+# ------------------------------------------------------------------- complex step
+def test_complex_step_matches_finite_differences():
+    wl = W.tgv(2, 2, U0=0.3)
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, True, True)
+    sim = Sim(g, wl.dt, wl.nu, wl.model)
+    X, Y = g.coords()
+    rho, ux, uy, T = wl.fields(X, Y)
+    ut, vt = W.fourier_target(X, Y, 0.3)
+    loss = lambda s, F: kinetic_misfit_loss(s, F, ut, vt)
+    d = W.random_directions(g.nnodes, 1)[0]
+    cs = complex_step_directional(sim, rho, ux, uy, T, d[0], d[1], 4, loss)
+    eps = 1e-5
+
+    def L(e):
+        return loss(sim, sim.run(sim.init(rho, ux + e * d[0], uy + e * d[1], T), 4))
+
+    fd = (L(eps) - L(-eps)) / (2 * eps)
+    assert cs == pytest.approx(fd, rel=1e-7)
+
+
+def test_stability_criterion():
+    g, sim = _sim("polyatomic")
+    F = sim.init(*_random_macro(g.nnodes, 9))
+    assert not sim.unstable(F)
+    F2 = F.copy()
+    F2[0, 3, 5] = np.nan
+    assert sim.unstable(F2)
+    F3 = F.copy()
+    F3[1] *= -1.0  # negative internal energy -> theta <= 0
+    assert sim.unstable(F3)
