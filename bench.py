@@ -1,0 +1,151 @@
+"""Benchmark of the SLLBM stream + collide step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload riemann|svi|sod|tgv|adjoint_tgv]
+                    [--precision fp32|fp64] [--path auto|direct|tiled|records] [--no-cpu-baseline]
+
+One "step" is one time step of the whole hot path over the grid: departure
+gather with Lagrange interpolation, moments, temperature, 4th-order
+equilibrium, BGK relaxation and store (one fused kernel launch), with inputs
+resident in HBM.  Default workload: the four-quadrant Riemann problem on
+512 x 512 cells of order 2 (1025^2 nodes, f and g populations, float32
+populations with float64 moments).  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D2Q25 node-updates/s FP32 vs FP64 at stated error; adjoint/forward cost ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    from paper_1910_13918_amd import workloads as W
+    if name == "riemann":
+        return W.riemann(512, 2), "riemann2d_512x512cells_p2"
+    if name == "svi":
+        return W.svi(1024, 512, 3), "shock_vortex_1024x512cells_p3_stretched"
+    if name == "sod":
+        return W.sod(1024, 4, 3), "sod_1024x4cells_p3"
+    if name == "tgv":
+        return W.tgv(), "tgv_8x8cells_p2"
+    if name == "adjoint_tgv":
+        return W.adjoint_tgv(), "tgv_128x128cells_p4"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def bytes_per_node_update(wl, precision, path):
+    """Algorithmic HBM bytes per node update: every population read once and
+    written once (tables excluded); per-(node, velocity) departure records add
+    a 4-byte cell index and two reference coordinates per velocity."""
+    size = 4 if precision == "fp32" else 8
+    b = 2 * wl.nsets * 25 * size
+    if path == "records":
+        b += 25 * (4 + 2 * size)
+    return b
+
+
+def cpu_baseline(wl, solver_state, sample_nodes=250000, seed=0):
+    """Time the FP64 oracle on a bounded sample of the same workload: one step
+    at `sample_nodes` seeded nodes, from the same initial state.  Also returns
+    the GPU's error against it at those nodes."""
+    import numpy as np
+
+    from oracle.grid import Grid
+    from oracle.sllbm import Sim
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+    X, Y = g.coords()
+    F0 = sim.init(*wl.fields(X, Y))
+    rng = np.random.default_rng(seed)
+    nodes = np.sort(rng.choice(g.nnodes, size=min(sample_nodes, g.nnodes), replace=False))
+    t0 = time.perf_counter()
+    F1 = sim.step(F0, nodes)
+    dt = time.perf_counter() - t0
+    G1 = solver_state[:, :, nodes]
+    err = float(np.abs(G1 - F1).max() / np.abs(F1).max())
+    return {"value": len(nodes) / dt, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 oracle step at {len(nodes)} seeded nodes of the same workload "
+                      f"({dt:.1f} s, numpy, single thread)"}, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="riemann")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--path", default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-compare", action="store_true", help="also time the FP64 path")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the stream + collide step is a single-GPU kernel "
+              "(the multi-GPU domain decomposition is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1910_13918_amd.solver import Solver
+    wl, wname = workload(args.workload)
+
+    def timed(precision, path):
+        s = Solver.from_workload(wl, precision=precision, path=path)
+        s.init_from_workload()
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(s.stream)
+        s.step(args.steps)
+        ev1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        unstable, _ = s.flags()
+        return s, ms, unstable
+
+    s, ms, unstable = timed(args.precision, args.path)
+    nu_s = s.n * args.steps / (ms * 1e-3)
+    bpn = bytes_per_node_update(wl, args.precision, args.path)
+    achieved = nu_s * bpn / 1e9
+    out = {
+        "metric": METRIC, "value": nu_s, "unit": "node-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": wname, "nodes": s.n, "populations": wl.nsets * 25,
+                   "order": wl.p, "precision": args.precision + ("-pop/f64-moments" if args.precision == "fp32" else ""),
+                   "path": args.path, "dt": wl.dt, "nu": wl.nu, "unstable_flag": unstable},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_node_update": bpn,
+                     "kernel": "stream+collide (one launch per step)",
+                     "avg_kernel_ms": ms / args.steps},
+    }
+    if args.fp64_compare and args.precision != "fp64":
+        s64, ms64, _ = timed("fp64", args.path)
+        out["fp64"] = {"value": s64.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps}
+        s64.close()
+    if not args.no_cpu_baseline:
+        # same initial state, one GPU step, compared with the oracle at the sample
+        s1 = Solver.from_workload(wl, precision=args.precision, path=args.path)
+        s1.init_from_workload()
+        s1.step(1)
+        G1 = s1.populations().astype(np.float64)
+        s1.close()
+        cb, err = cpu_baseline(wl, G1)
+        out["cpu_baseline"] = cb
+        out["accuracy"] = {"one_step_max_rel_err_vs_fp64_oracle": err,
+                           "sample_nodes": 250000}
+    s.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

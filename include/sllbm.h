@@ -1,0 +1,223 @@
+/*
+ * sllbm.h -- C ABI of libsllbm, the MI355X (gfx950) semi-Lagrangian lattice
+ * Boltzmann step of Wilde, Kraemer, Reith, Foysi, "Semi-Lagrangian lattice
+ * Boltzmann method for compressible flows" (arXiv:1910.13918).
+ *
+ * One time step (sllbm_step) does, for every grid node x and each of the Q
+ * discrete velocities xi_i:
+ *   1. trace the characteristic back to x - dt xi_i, find the departure cell
+ *      and evaluate the cell-local Lagrange interpolant of order p on
+ *      Gauss-Lobatto-Chebyshev support points of the previous post-collision
+ *      populations (Sec. II.E, eq. (17));
+ *   2. moments rho, rho u, 2 rho E of the streamed populations (Sec. II,
+ *      eqs. (3)-(5)) and the temperature theta;
+ *   3. BGK relaxation toward the 4th-order Hermite equilibrium (Sec. II.A,
+ *      eqs. (9)-(10)) with tau = nu/(c_s^2 dt) + 1/2 (Sec. II.D, eq. (16));
+ *      the second population g relaxes toward g_eq = (2 C_v - D) theta f_eq
+ *      (Sec. II.D, eq. (15)).
+ * The collision acts on node values and the interpolant of the post-collision
+ * field is what is streamed.  The Prandtl number is 1 (the quasi-equilibrium
+ * term of eq. (16) vanishes).  Code units: c_s = R = T0 = 1, D = 2.
+ *
+ * Conventions
+ *   - Every function returns an sllbm_status; nothing throws or aborts across
+ *     the ABI.  sllbm_last_error() returns the message of the last failure on
+ *     that context (valid until the next call on it).
+ *   - Set-up calls (velocity set, order, grid, physics, precision, path) only
+ *     touch host memory and validate their arguments before anything else;
+ *     they work without a GPU.  Device memory is allocated on first need
+ *     (bind / init / set_populations / step).
+ *   - Call order: create -> [set_velocity_set] -> set_order -> init_grid_* ->
+ *     set_physics -> [bind_populations] -> init_macro | set_populations ->
+ *     step / moments / mass / get_populations.  Changing the order, grid or
+ *     physics after initialisation returns SLLBM_E_STATE.
+ *   - Node arrays are node-major: element (iy, ix) at iy * nx + ix, float64.
+ *   - Populations are structure-of-arrays [S][Q][ny][nx] of the population
+ *     type (float64 for SLLBM_FP64, float32 for SLLBM_FP32), with S = 2 for
+ *     the polyatomic model (f then g) and 1 otherwise, and i = a + q1 * b
+ *     for the velocity (xi_a, xi_b).
+ *   - Device pointers are HIP device addresses on the context's device.
+ *     Kernels run asynchronously on the bound stream (default: the null
+ *     stream); calls that return host data synchronise that stream.
+ *   - One context per thread; contexts are independent.
+ *   - The library never takes ownership of caller memory.
+ */
+#ifndef SLLBM_H
+#define SLLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sllbm_ctx sllbm_ctx;
+
+typedef enum {
+  SLLBM_OK = 0,
+  SLLBM_E_ARG = -1,         /* invalid argument (range, NaN, null pointer, size) */
+  SLLBM_E_STATE = -2,       /* call out of order */
+  SLLBM_E_DEVICE = -3,      /* HIP runtime error (no device, launch failure, ...) */
+  SLLBM_E_OOM = -4,         /* device allocation failed */
+  SLLBM_E_UNSTABLE = -5,    /* stability flag raised: rho <= 0, theta <= 0 or non-finite */
+  SLLBM_E_UNSUPPORTED = -6  /* valid but not implemented combination */
+} sllbm_status;
+
+typedef enum {
+  SLLBM_FP64 = 0, /* float64 populations, interpolation, moments, equilibrium */
+  SLLBM_FP32 = 1  /* float32 populations and interpolation; float64 moments,
+                     temperature, equilibrium and relaxation */
+} sllbm_precision;
+
+typedef enum { SLLBM_PERIODIC = 0, SLLBM_ZERO_GRADIENT = 1 } sllbm_bc;
+
+typedef enum { SLLBM_NODES_GLC = 0, SLLBM_NODES_EQUIDISTANT = 1 } sllbm_nodes;
+
+typedef enum {
+  SLLBM_ISOTHERMAL = 0, /* f only, theta = 1 (Sec. III.A) */
+  SLLBM_MONATOMIC = 1,  /* f only, theta from the energy moment, gamma = (D+2)/D */
+  SLLBM_POLYATOMIC = 2  /* f and g, gamma given (Sec. II.D) */
+} sllbm_model;
+
+typedef enum {
+  SLLBM_PATH_AUTO = 0,    /* library choice: TILED */
+  SLLBM_PATH_DIRECT = 1,  /* one thread per node, (p+1)^2 gathers per velocity
+                             through per-axis departure tables */
+  SLLBM_PATH_TILED = 2,   /* separable x-then-y interpolation staged through LDS */
+  SLLBM_PATH_RECORDS = 3  /* per-(node, velocity) departure records (cell, r, s)
+                             with weights evaluated in the kernel: the general
+                             gather for grids that are not axis products */
+} sllbm_path;
+
+/* ---- lifetime ------------------------------------------------------------ */
+
+/* Create a context for HIP device `hip_device` (checked lazily, at the first
+ * device call).  *out receives the context; on failure *out is NULL. */
+int sllbm_create(sllbm_ctx **out, int hip_device, int precision);
+
+/* Free the context's device tables and any buffers the library allocated.
+ * Bound (caller-owned) buffers are not freed.  NULL is accepted. */
+void sllbm_destroy(sllbm_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Never NULL. */
+const char *sllbm_last_error(const sllbm_ctx *ctx);
+
+/* Run all later kernels on `hip_stream` (a hipStream_t; NULL = null stream). */
+int sllbm_set_stream(sllbm_ctx *ctx, void *hip_stream);
+
+/* ---- set-up (host only) -------------------------------------------------- */
+
+/* 1-D velocity set of the tensor-product 2-D set (Sec. II.B).  xi1d/w1d hold
+ * q1d abscissae and weights in code units (c_s = 1).  NULL/NULL selects the
+ * D1Q5 Gauss-Hermite set of Table I: 0, +sqrt(5-sqrt(10)), +sqrt(5+sqrt(10)),
+ * -sqrt(5-sqrt(10)), -sqrt(5+sqrt(10)).  Only q1d = 5 is supported
+ * (SLLBM_E_UNSUPPORTED otherwise).  Weights must be positive and finite. */
+int sllbm_set_velocity_set(sllbm_ctx *ctx, int q1d, const double *xi1d, const double *w1d);
+
+/* Interpolation order p in 1..4 and support-point family (Sec. II.E:
+ * Gauss-Lobatto-Chebyshev points; equidistant points as the unstable
+ * comparison of Sec. III.D). */
+int sllbm_set_order(sllbm_ctx *ctx, int p, int nodes);
+
+/* Uniform grid of ncx x ncy cells on [x0, x1] x [y0, y1].  Periodic axes
+ * carry nc * p unique nodes, zero-gradient axes nc * p + 1 (outer support
+ * points are shared between neighbouring cells).  Zero-gradient boundaries
+ * clamp departure points to the boundary (the paper's "d f = 0"). */
+int sllbm_init_grid_uniform(sllbm_ctx *ctx, int ncx, int ncy, double x0, double x1, double y0,
+                            double y1, int bcx, int bcy);
+
+/* Tensor-product grid from strictly increasing cell edges (ncx + 1 and
+ * ncy + 1 values, copied), cells affine per axis -- e.g. the transformed grid
+ * of Sec. III.E.  Same node numbering and boundaries as the uniform grid. */
+int sllbm_init_grid_mapped(sllbm_ctx *ctx, int ncx, int ncy, const double *edges_x,
+                           const double *edges_y, int bcx, int bcy);
+
+/* Time step dt > 0, kinematic viscosity nu >= 0 (nu = +inf: no collision,
+ * pure streaming), heat-capacity ratio gamma > 1 (used by SLLBM_POLYATOMIC
+ * only), Prandtl number (only 1 is supported), model (sllbm_model). */
+int sllbm_set_physics(sllbm_ctx *ctx, double dt, double nu, double gamma, double Pr, int model);
+
+/* Streaming kernel family (sllbm_path).  SLLBM_PATH_TILED needs departures
+ * that stay within a bounded row window (checked; SLLBM_E_UNSUPPORTED
+ * otherwise). */
+int sllbm_set_path(sllbm_ctx *ctx, int path);
+
+/* ---- queries (host only, after init_grid; tables after set_physics) -------- */
+
+int sllbm_num_nodes(const sllbm_ctx *ctx, int64_t *nx, int64_t *ny);
+
+/* Number of population sets S (1 or 2) and bytes per population value. */
+int sllbm_population_layout(const sllbm_ctx *ctx, int *nsets, int *q, int *bytes_per_value);
+
+/* Node coordinates per axis: x[nx], y[ny] (host arrays). */
+int sllbm_node_coords(const sllbm_ctx *ctx, double *x, double *y);
+
+/* Departure table of one axis (0 = x, 1 = y) and 1-D velocity index comp:
+ * for each node j of that axis, src[j * (p+1) + m] is the source node along
+ * the axis and w[j * (p+1) + m] the Lagrange weight, so that the 1-D value
+ * at the departure point is sum_m w * value[src].  Host arrays. */
+int sllbm_departure_table(const sllbm_ctx *ctx, int axis, int comp, int32_t *src, double *w);
+
+/* Integral of each node's shape function per axis (mass weights): the 2-D
+ * weight of node (iy, ix) is my[iy] * mx[ix]. */
+int sllbm_mass_weights(const sllbm_ctx *ctx, double *mx, double *my);
+
+/* Relaxation time tau = nu/(c_s^2 dt) + 1/2 (Sec. II.D); +inf for nu = +inf. */
+int sllbm_relaxation_time(const sllbm_ctx *ctx, double *tau);
+
+/* ---- state ----------------------------------------------------------------- */
+
+/* Use two caller-owned device buffers of S*Q*nx*ny population values each
+ * as the ping-pong pair.  The caller keeps ownership and must keep them
+ * alive while the context uses them.  Without this call the library
+ * allocates the pair itself. */
+int sllbm_bind_populations(sllbm_ctx *ctx, void *dev_a, void *dev_b);
+
+/* Initialise populations at equilibrium: f = f_eq(rho, u, theta) and, for
+ * the polyatomic model, g = g_eq (the paper does not state its
+ * initialisation; this is the reading used).  rho, ux, uy, T are node arrays
+ * (host if on_device = 0, device otherwise).  rho and T must be positive
+ * and every value finite (checked for host arrays; SLLBM_E_ARG).  The
+ * isothermal model ignores T.  Resets the step counter and stability flag. */
+int sllbm_init_macro(sllbm_ctx *ctx, const double *rho, const double *ux, const double *uy,
+                     const double *T, int on_device);
+
+/* ---- time stepping ----------------------------------------------------------- */
+
+/* Advance n >= 0 steps, asynchronously on the bound stream.  The stability
+ * flag (set when any node has rho <= 0, theta <= 0 or a non-finite moment,
+ * the paper's "bounded" criterion of Sec. III.C) is read back every
+ * check_interval steps if that interval is > 0 (sllbm_set_check_interval),
+ * in which case SLLBM_E_UNSTABLE is returned at the first raised flag. */
+int sllbm_step(sllbm_ctx *ctx, int64_t n);
+
+/* Interval for the flag read-back inside sllbm_step (0 = never; default 0). */
+int sllbm_set_check_interval(sllbm_ctx *ctx, int64_t k);
+
+/* Synchronise and report the stability flag (1 = raised) and step count. */
+int sllbm_status_flags(sllbm_ctx *ctx, int *unstable, int64_t *steps_done);
+
+/* ---- outputs ----------------------------------------------------------------- */
+
+/* rho, ux, uy, T per node (T = theta; T0 = 1) from the current populations.
+ * rho, ux, uy, T and the collision invariants they derive from are equal
+ * before and after the collision, so these are the post-streaming moments.
+ * Arrays of nx*ny float64, host (synchronises) or device (async). */
+int sllbm_moments(sllbm_ctx *ctx, double *rho, double *ux, double *uy, double *T, int on_device);
+
+/* Total mass sum_v M_v rho_v with M_v the integral of node v's shape function
+ * (relative mass m/m0 is the monitor of Sec. III.E).  Deterministic FP64
+ * reduction; synchronises. */
+int sllbm_mass(sllbm_ctx *ctx, double *mass);
+
+/* Copy the current populations out / in ([S][Q][ny][nx], population type).
+ * set_populations makes the given state current (step counter unchanged,
+ * stability flag cleared). */
+int sllbm_get_populations(sllbm_ctx *ctx, void *dst, int on_device);
+int sllbm_set_populations(sllbm_ctx *ctx, const void *src, int on_device);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLLBM_H */

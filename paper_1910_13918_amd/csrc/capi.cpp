@@ -1,0 +1,738 @@
+// C ABI of libsllbm (declarations and contracts in include/sllbm.h).
+//
+// Host side: argument validation, the set-up state machine, host tables
+// (tables.cpp), device memory for tables and (unless bound) populations, and
+// kernel launches (kernels.hip).  Set-up calls never touch the HIP runtime.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/sllbm.h"
+#include "launch.hpp"
+#include "tables.hpp"
+
+using namespace sllbm;
+
+namespace {
+
+constexpr int kTileRows = 8;          // rows per workgroup of the tiled kernel
+constexpr size_t kMaxTileLds = 65536; // LDS budget of one tiled workgroup (bytes)
+
+struct DeviceBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sllbm_ctx {
+  int device = 0;
+  int fp32 = 0;
+  std::string err;
+  hipStream_t stream = nullptr;
+
+  VelocitySet vs = default_velocity_set();
+  int p = 0;
+  bool glc = true;
+  bool have_grid = false;
+  Axis ax, ay;
+  bool have_phys = false;
+  double dt = 0, nu = 0, gamma = 1.4, Pr = 1.0, tau = 0, omega = 0;
+  int model = 0;
+  int path = SLLBM_PATH_AUTO;
+  int64_t check_interval = 0;
+
+  // host tables (rebuilt when set-up changes)
+  bool host_dirty = true;
+  AxisTable xt[kQ1], yt[kQ1];
+  std::vector<double> mx, my;
+  int win_rows = 0;
+  std::vector<int32_t> ywin, yrel;
+
+  // device
+  bool dev_checked = false;
+  bool dev_dirty = true;
+  bool rec_dirty = true;
+  DeviceBuf xsrc, xw, ysrc, yw, yrel_d, ywin_d, mxd, myd, flag, partial, scalar, macro;
+  DeviceBuf rec_cell, rec_r, rec_s;
+  void *pop[2] = {nullptr, nullptr};
+  bool own_pop = false;
+  size_t pop_bytes = 0;
+  int cur = 0;
+  bool initialised = false;
+  int64_t steps_done = 0;
+};
+
+namespace {
+
+int fail(sllbm_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                        \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? SLLBM_E_OOM : SLLBM_E_DEVICE,  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+int nsets(const sllbm_ctx *c) { return c->model == SLLBM_POLYATOMIC ? 2 : 1; }
+size_t pop_size(const sllbm_ctx *c) { return c->fp32 ? 4 : 8; }
+long long nnodes(const sllbm_ctx *c) { return (long long)c->ax.n * c->ay.n; }
+
+int ready_for_tables(sllbm_ctx *c) {
+  if (c->p == 0) return fail(c, SLLBM_E_STATE, "interpolation order not set (sllbm_set_order)");
+  if (!c->have_grid) return fail(c, SLLBM_E_STATE, "grid not set (sllbm_init_grid_*)");
+  if (!c->have_phys) return fail(c, SLLBM_E_STATE, "physics not set (sllbm_set_physics)");
+  return SLLBM_OK;
+}
+
+void build_host_tables(sllbm_ctx *c) {
+  if (!c->host_dirty) return;
+  for (int a = 0; a < kQ1; ++a) {
+    c->xt[a] = build_axis_table(c->ax, -c->dt * c->vs.xi[a]);
+    c->yt[a] = build_axis_table(c->ay, -c->dt * c->vs.xi[a]);
+  }
+  c->mx = c->ax.node_mass();
+  c->my = c->ay.node_mass();
+  // row windows of the tiled kernel: tile t covers rows [t*TY, min((t+1)*TY, ny))
+  const int ny = c->ay.n, P1 = c->p + 1;
+  const int ntiles = (ny + kTileRows - 1) / kTileRows;
+  c->ywin.assign(size_t(kQ1) * ntiles, 0);
+  c->yrel.assign(size_t(kQ1) * P1 * ny, 0);
+  int W = 0;
+  for (int b = 0; b < kQ1; ++b) {
+    for (int t = 0; t < ntiles; ++t) {
+      const int r0 = t * kTileRows, r1 = std::min(r0 + kTileRows, ny);
+      long lo = std::numeric_limits<long>::max(), hi = std::numeric_limits<long>::min();
+      for (int iy = r0; iy < r1; ++iy) {
+        const long base = c->yt[b].ucell[iy] * c->p;
+        lo = std::min(lo, base);
+        hi = std::max(hi, base + c->p);
+      }
+      c->ywin[size_t(b) * ntiles + t] = int32_t(lo);
+      W = std::max<int>(W, int(hi - lo + 1));
+      for (int iy = r0; iy < r1; ++iy) {
+        const long base = c->yt[b].ucell[iy] * c->p;
+        for (int n = 0; n < P1; ++n)
+          c->yrel[(size_t(b) * P1 + n) * ny + iy] = int32_t(base + n - lo);
+      }
+    }
+  }
+  c->win_rows = W;
+  c->host_dirty = false;
+  c->dev_dirty = true;
+  c->rec_dirty = true;
+}
+
+// The tiled kernel double-buffers S window rows of 64 values in LDS.
+bool tiled_fits(const sllbm_ctx *c) {
+  const size_t lds = size_t(2) * nsets(c) * size_t(c->win_rows) * 64 * pop_size(c);
+  return lds <= kMaxTileLds;
+}
+
+int effective_path(const sllbm_ctx *c) {
+  if (c->path == SLLBM_PATH_AUTO) return tiled_fits(c) ? kPathTiled : kPathDirect;
+  return c->path;
+}
+
+void free_buf(DeviceBuf &b) {
+  if (b.ptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+int alloc_buf(sllbm_ctx *c, DeviceBuf &b, size_t bytes) {
+  if (b.ptr && b.bytes >= bytes) return SLLBM_OK;
+  free_buf(b);
+  HIP_TRY(c, hipMalloc(&b.ptr, bytes > 0 ? bytes : 8));
+  b.bytes = bytes;
+  return SLLBM_OK;
+}
+
+template <typename V>
+int upload(sllbm_ctx *c, DeviceBuf &b, const std::vector<V> &v) {
+  int rc = alloc_buf(c, b, v.size() * sizeof(V));
+  if (rc) return rc;
+  HIP_TRY(c, hipMemcpy(b.ptr, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice));
+  return SLLBM_OK;
+}
+
+// Weights in the population type.
+int upload_weights(sllbm_ctx *c, DeviceBuf &b, const std::vector<double> &w) {
+  if (!c->fp32) return upload(c, b, w);
+  std::vector<float> f(w.begin(), w.end());
+  return upload(c, b, f);
+}
+
+int check_device(sllbm_ctx *c) {
+  if (!c->dev_checked) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0)
+      return fail(c, SLLBM_E_DEVICE, "no HIP device available");
+    if (c->device < 0 || c->device >= n)
+      return fail(c, SLLBM_E_ARG, "HIP device index out of range");
+    c->dev_checked = true;
+  }
+  HIP_TRY(c, hipSetDevice(c->device));
+  return SLLBM_OK;
+}
+
+// Per-axis tables in [comp][m][node] order.
+template <typename V>
+std::vector<V> comp_major(const AxisTable *t, int n, int P1, bool weights) {
+  std::vector<V> out(size_t(kQ1) * P1 * n);
+  for (int a = 0; a < kQ1; ++a)
+    for (int m = 0; m < P1; ++m)
+      for (int j = 0; j < n; ++j)
+        out[(size_t(a) * P1 + m) * n + j] =
+            weights ? V(t[a].w[size_t(j) * P1 + m]) : V(t[a].src[size_t(j) * P1 + m]);
+  return out;
+}
+
+int prepare_device(sllbm_ctx *c) {
+  int rc = ready_for_tables(c);
+  if (rc) return rc;
+  rc = check_device(c);
+  if (rc) return rc;
+  build_host_tables(c);
+  if (c->dev_dirty) {
+    const int P1 = c->p + 1;
+    rc = upload(c, c->xsrc, comp_major<int32_t>(c->xt, c->ax.n, P1, false));
+    if (!rc) rc = upload_weights(c, c->xw, comp_major<double>(c->xt, c->ax.n, P1, true));
+    if (!rc) rc = upload(c, c->ysrc, comp_major<int32_t>(c->yt, c->ay.n, P1, false));
+    if (!rc) rc = upload_weights(c, c->yw, comp_major<double>(c->yt, c->ay.n, P1, true));
+    if (!rc) rc = upload(c, c->yrel_d, c->yrel);
+    if (!rc) rc = upload(c, c->ywin_d, c->ywin);
+    if (!rc) rc = upload(c, c->mxd, c->mx);
+    if (!rc) rc = upload(c, c->myd, c->my);
+    if (!rc) rc = alloc_buf(c, c->flag, sizeof(int));
+    if (!rc) rc = alloc_buf(c, c->scalar, 2 * sizeof(double));
+    if (!rc) rc = alloc_buf(c, c->partial, sizeof(double) * (size_t(nnodes(c)) / 256 + 2));
+    if (rc) return rc;
+    c->dev_dirty = false;
+  }
+  if (effective_path(c) == kPathRecords && c->rec_dirty) {
+    const long long N = nnodes(c);
+    std::vector<int32_t> cell(size_t(kQ) * N);
+    std::vector<double> r(size_t(kQ) * N), s(size_t(kQ) * N);
+    for (int b = 0; b < kQ1; ++b)
+      for (int a = 0; a < kQ1; ++a) {
+        const int i = a + kQ1 * b;
+        for (int iy = 0; iy < c->ay.n; ++iy)
+          for (int ix = 0; ix < c->ax.n; ++ix) {
+            const size_t k = size_t(i) * N + size_t(iy) * c->ax.n + ix;
+            cell[k] = c->xt[a].cell[ix] | (c->yt[b].cell[iy] << 16);
+            r[k] = c->xt[a].rref[ix];
+            s[k] = c->yt[b].rref[iy];
+          }
+      }
+    rc = upload(c, c->rec_cell, cell);
+    if (!rc) rc = upload_weights(c, c->rec_r, r);
+    if (!rc) rc = upload_weights(c, c->rec_s, s);
+    if (rc) return rc;
+    c->rec_dirty = false;
+  }
+  return SLLBM_OK;
+}
+
+StepConsts make_consts(const sllbm_ctx *c) {
+  StepConsts k{};
+  k.nx = c->ax.n;
+  k.ny = c->ay.n;
+  k.n = nnodes(c);
+  k.ncx = c->ax.ncells;
+  k.ncy = c->ay.ncells;
+  k.p = c->p;
+  k.omega = c->omega;
+  const double D = kDim;
+  double cv = D / 2.0;  // monatomic: C_v = D/2 (R = 1)
+  if (c->model == SLLBM_POLYATOMIC) cv = 1.0 / (c->gamma - 1.0);
+  k.gfac = 2.0 * cv - D;
+  k.inv_2cv = 1.0 / (2.0 * cv);
+  for (int a = 0; a < kQ1; ++a) {
+    k.xi[a] = c->vs.xi[a];
+    k.w[a] = c->vs.w[a];
+    for (int j = 0; j < 5; ++j) k.hk[a][j] = c->vs.hk[a][j];
+  }
+  for (int m = 0; m <= c->p; ++m) {
+    k.rn[m] = c->ax.r[m];
+    double d = 1.0;
+    for (int n = 0; n <= c->p; ++n)
+      if (n != m) d *= (c->ax.r[m] - c->ax.r[n]);
+    k.lden[m] = 1.0 / d;
+  }
+  k.perx = c->ax.periodic;
+  k.pery = c->ay.periodic;
+  return k;
+}
+
+DevTables make_tables(const sllbm_ctx *c) {
+  DevTables t{};
+  t.xsrc = static_cast<const int32_t *>(c->xsrc.ptr);
+  t.xw = c->xw.ptr;
+  t.ysrc = static_cast<const int32_t *>(c->ysrc.ptr);
+  t.yw = c->yw.ptr;
+  t.rec_cell = static_cast<const int32_t *>(c->rec_cell.ptr);
+  t.rec_r = c->rec_r.ptr;
+  t.rec_s = c->rec_s.ptr;
+  t.mx = static_cast<const double *>(c->mxd.ptr);
+  t.my = static_cast<const double *>(c->myd.ptr);
+  t.yrel = static_cast<const int32_t *>(c->yrel_d.ptr);
+  t.ywin = static_cast<const int32_t *>(c->ywin_d.ptr);
+  t.tile_rows = kTileRows;
+  t.win_rows = c->win_rows;
+  return t;
+}
+
+int ensure_populations(sllbm_ctx *c) {
+  const size_t bytes = size_t(nsets(c)) * kQ * size_t(nnodes(c)) * pop_size(c);
+  if (c->pop[0] && c->pop_bytes == bytes) return SLLBM_OK;
+  if (c->pop[0] && !c->own_pop)
+    return fail(c, SLLBM_E_STATE, "bound population buffers do not match the current set-up");
+  if (c->own_pop) {
+    (void)hipFree(c->pop[0]);
+    (void)hipFree(c->pop[1]);
+    c->pop[0] = c->pop[1] = nullptr;
+  }
+  HIP_TRY(c, hipMalloc(&c->pop[0], bytes));
+  HIP_TRY(c, hipMalloc(&c->pop[1], bytes));
+  c->own_pop = true;
+  c->pop_bytes = bytes;
+  return SLLBM_OK;
+}
+
+int clear_flag(sllbm_ctx *c) {
+  HIP_TRY(c, launch_clear_flag(static_cast<int *>(c->flag.ptr), c->stream));
+  return SLLBM_OK;
+}
+
+int setup_allowed(sllbm_ctx *c) {
+  if (!c) return SLLBM_E_ARG;
+  if (c->initialised)
+    return fail(c, SLLBM_E_STATE, "set-up cannot change after the populations are initialised");
+  return SLLBM_OK;
+}
+
+void invalidate(sllbm_ctx *c) {
+  c->host_dirty = true;
+  c->dev_dirty = true;
+  c->rec_dirty = true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sllbm_create(sllbm_ctx **out, int hip_device, int precision) {
+  if (!out) return SLLBM_E_ARG;
+  *out = nullptr;
+  if (hip_device < 0) return SLLBM_E_ARG;
+  if (precision != SLLBM_FP64 && precision != SLLBM_FP32) return SLLBM_E_ARG;
+  sllbm_ctx *c = new (std::nothrow) sllbm_ctx();
+  if (!c) return SLLBM_E_OOM;
+  c->device = hip_device;
+  c->fp32 = precision == SLLBM_FP32;
+  *out = c;
+  return SLLBM_OK;
+}
+
+void sllbm_destroy(sllbm_ctx *c) {
+  if (!c) return;
+  if (c->dev_checked) {
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    DeviceBuf *bufs[] = {&c->xsrc, &c->xw, &c->ysrc, &c->yw, &c->yrel_d, &c->ywin_d, &c->mxd,
+                         &c->myd, &c->flag, &c->partial, &c->scalar, &c->macro, &c->rec_cell,
+                         &c->rec_r, &c->rec_s};
+    for (DeviceBuf *b : bufs) free_buf(*b);
+    if (c->own_pop) {
+      (void)hipFree(c->pop[0]);
+      (void)hipFree(c->pop[1]);
+    }
+  }
+  delete c;
+}
+
+const char *sllbm_last_error(const sllbm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int sllbm_set_stream(sllbm_ctx *c, void *stream) {
+  if (!c) return SLLBM_E_ARG;
+  c->stream = static_cast<hipStream_t>(stream);
+  return SLLBM_OK;
+}
+
+int sllbm_set_velocity_set(sllbm_ctx *c, int q1d, const double *xi1d, const double *w1d) {
+  int rc = setup_allowed(c);
+  if (rc) return rc;
+  if (!xi1d && !w1d) {
+    c->vs = default_velocity_set();
+    invalidate(c);
+    return SLLBM_OK;
+  }
+  if (!xi1d || !w1d) return fail(c, SLLBM_E_ARG, "xi1d and w1d must both be given or both NULL");
+  if (q1d != kQ1) return fail(c, SLLBM_E_UNSUPPORTED, "only 5 velocities per axis are supported");
+  VelocitySet vs{};
+  for (int a = 0; a < kQ1; ++a) {
+    if (!is_finite(xi1d[a]) || !is_finite(w1d[a]) || !(w1d[a] > 0))
+      return fail(c, SLLBM_E_ARG, "velocities must be finite and weights positive");
+    vs.xi[a] = xi1d[a];
+    vs.w[a] = w1d[a];
+  }
+  fill_hermite_constants(vs);
+  c->vs = vs;
+  invalidate(c);
+  return SLLBM_OK;
+}
+
+int sllbm_set_order(sllbm_ctx *c, int p, int nodes) {
+  int rc = setup_allowed(c);
+  if (rc) return rc;
+  if (p < 1 || p > kMaxOrder) return fail(c, SLLBM_E_ARG, "order p must be in 1..4");
+  if (nodes != SLLBM_NODES_GLC && nodes != SLLBM_NODES_EQUIDISTANT)
+    return fail(c, SLLBM_E_ARG, "unknown support-point family");
+  c->p = p;
+  c->glc = nodes == SLLBM_NODES_GLC;
+  c->have_grid = false;  // the grid depends on the order
+  invalidate(c);
+  return SLLBM_OK;
+}
+
+static int init_grid(sllbm_ctx *c, int ncx, int ncy, const std::vector<double> &ex,
+                     const std::vector<double> &ey, int bcx, int bcy, bool uniform) {
+  const std::vector<double> r = support_points(c->p, c->glc);
+  c->ax.setup(ex, c->p, bcx == SLLBM_PERIODIC, uniform, r);
+  c->ay.setup(ey, c->p, bcy == SLLBM_PERIODIC, uniform, r);
+  if ((long long)c->ax.n * c->ay.n > (1LL << 31) / 64)
+    return fail(c, SLLBM_E_ARG, "grid too large (nx * ny * 50 must fit in 32 bits)");
+  (void)ncx;
+  (void)ncy;
+  c->have_grid = true;
+  invalidate(c);
+  return SLLBM_OK;
+}
+
+static int check_grid_args(sllbm_ctx *c, int ncx, int ncy, int bcx, int bcy) {
+  if (c->p == 0) return fail(c, SLLBM_E_STATE, "set the order before the grid");
+  if (ncx < 1 || ncy < 1 || ncx > 65535 || ncy > 65535)
+    return fail(c, SLLBM_E_ARG, "cell counts must be in 1..65535");
+  for (int bc : {bcx, bcy})
+    if (bc != SLLBM_PERIODIC && bc != SLLBM_ZERO_GRADIENT)
+      return fail(c, SLLBM_E_ARG, "unknown boundary kind");
+  return SLLBM_OK;
+}
+
+int sllbm_init_grid_uniform(sllbm_ctx *c, int ncx, int ncy, double x0, double x1, double y0,
+                            double y1, int bcx, int bcy) {
+  int rc = setup_allowed(c);
+  if (rc) return rc;
+  rc = check_grid_args(c, ncx, ncy, bcx, bcy);
+  if (rc) return rc;
+  if (!is_finite(x0) || !is_finite(x1) || !is_finite(y0) || !is_finite(y1) || !(x1 > x0) || !(y1 > y0))
+    return fail(c, SLLBM_E_ARG, "domain bounds must be finite with x1 > x0 and y1 > y0");
+  std::vector<double> ex(ncx + 1), ey(ncy + 1);
+  for (int k = 0; k <= ncx; ++k) ex[k] = x0 + (x1 - x0) * double(k) / ncx;
+  for (int k = 0; k <= ncy; ++k) ey[k] = y0 + (y1 - y0) * double(k) / ncy;
+  ex[ncx] = x1;
+  ey[ncy] = y1;
+  return init_grid(c, ncx, ncy, ex, ey, bcx, bcy, true);
+}
+
+int sllbm_init_grid_mapped(sllbm_ctx *c, int ncx, int ncy, const double *edges_x,
+                           const double *edges_y, int bcx, int bcy) {
+  int rc = setup_allowed(c);
+  if (rc) return rc;
+  rc = check_grid_args(c, ncx, ncy, bcx, bcy);
+  if (rc) return rc;
+  if (!edges_x || !edges_y) return fail(c, SLLBM_E_ARG, "null edge array");
+  std::vector<double> ex(edges_x, edges_x + ncx + 1), ey(edges_y, edges_y + ncy + 1);
+  for (const auto *e : {&ex, &ey})
+    for (size_t k = 0; k < e->size(); ++k) {
+      if (!is_finite((*e)[k])) return fail(c, SLLBM_E_ARG, "cell edges must be finite");
+      if (k > 0 && !((*e)[k] > (*e)[k - 1]))
+        return fail(c, SLLBM_E_ARG, "cell edges must be strictly increasing");
+    }
+  return init_grid(c, ncx, ncy, ex, ey, bcx, bcy, false);
+}
+
+int sllbm_set_physics(sllbm_ctx *c, double dt, double nu, double gamma, double Pr, int model) {
+  int rc = setup_allowed(c);
+  if (rc) return rc;
+  if (!is_finite(dt) || !(dt > 0)) return fail(c, SLLBM_E_ARG, "dt must be positive and finite");
+  if (std::isnan(nu) || !(nu > 0))
+    return fail(c, SLLBM_E_ARG, "nu must be positive (tau = nu/dt + 1/2 > 1/2) or +inf");
+  if (model < SLLBM_ISOTHERMAL || model > SLLBM_POLYATOMIC)
+    return fail(c, SLLBM_E_ARG, "unknown model");
+  if (model == SLLBM_POLYATOMIC && (!is_finite(gamma) || !(gamma > 1.0)))
+    return fail(c, SLLBM_E_ARG, "gamma must be finite and > 1");
+  if (!is_finite(Pr) || !(Pr > 0)) return fail(c, SLLBM_E_ARG, "Pr must be positive and finite");
+  if (Pr != 1.0) return fail(c, SLLBM_E_UNSUPPORTED, "only Pr = 1 is implemented");
+  c->dt = dt;
+  c->nu = nu;
+  c->gamma = gamma;
+  c->Pr = Pr;
+  c->model = model;
+  c->tau = std::isinf(nu) ? std::numeric_limits<double>::infinity() : nu / dt + 0.5;
+  c->omega = std::isinf(nu) ? 0.0 : 1.0 / c->tau;
+  c->have_phys = true;
+  invalidate(c);
+  return SLLBM_OK;
+}
+
+int sllbm_set_path(sllbm_ctx *c, int path) {
+  if (!c) return SLLBM_E_ARG;
+  if (path < SLLBM_PATH_AUTO || path > SLLBM_PATH_RECORDS)
+    return fail(c, SLLBM_E_ARG, "unknown path");
+  c->path = path;
+  return SLLBM_OK;
+}
+
+int sllbm_num_nodes(const sllbm_ctx *c, int64_t *nx, int64_t *ny) {
+  if (!c || !nx || !ny) return SLLBM_E_ARG;
+  if (!c->have_grid) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "grid not set");
+  *nx = c->ax.n;
+  *ny = c->ay.n;
+  return SLLBM_OK;
+}
+
+int sllbm_population_layout(const sllbm_ctx *c, int *ns, int *q, int *bytes) {
+  if (!c || !ns || !q || !bytes) return SLLBM_E_ARG;
+  if (!c->have_phys) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "physics not set");
+  *ns = nsets(c);
+  *q = kQ;
+  *bytes = int(pop_size(c));
+  return SLLBM_OK;
+}
+
+int sllbm_node_coords(const sllbm_ctx *c, double *x, double *y) {
+  if (!c || !x || !y) return SLLBM_E_ARG;
+  if (!c->have_grid) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "grid not set");
+  for (int j = 0; j < c->ax.n; ++j) x[j] = c->ax.coord(j);
+  for (int j = 0; j < c->ay.n; ++j) y[j] = c->ay.coord(j);
+  return SLLBM_OK;
+}
+
+int sllbm_departure_table(const sllbm_ctx *cc, int axis, int comp, int32_t *src, double *w) {
+  sllbm_ctx *c = const_cast<sllbm_ctx *>(cc);
+  if (!c || !src || !w) return SLLBM_E_ARG;
+  if (axis != 0 && axis != 1) return fail(c, SLLBM_E_ARG, "axis must be 0 or 1");
+  if (comp < 0 || comp >= kQ1) return fail(c, SLLBM_E_ARG, "velocity component out of range");
+  int rc = ready_for_tables(c);
+  if (rc) return rc;
+  build_host_tables(c);
+  const AxisTable &t = axis == 0 ? c->xt[comp] : c->yt[comp];
+  std::memcpy(src, t.src.data(), t.src.size() * sizeof(int32_t));
+  std::memcpy(w, t.w.data(), t.w.size() * sizeof(double));
+  return SLLBM_OK;
+}
+
+int sllbm_mass_weights(const sllbm_ctx *c, double *mx, double *my) {
+  if (!c || !mx || !my) return SLLBM_E_ARG;
+  if (!c->have_grid) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "grid not set");
+  const std::vector<double> a = c->ax.node_mass(), b = c->ay.node_mass();
+  std::memcpy(mx, a.data(), a.size() * sizeof(double));
+  std::memcpy(my, b.data(), b.size() * sizeof(double));
+  return SLLBM_OK;
+}
+
+int sllbm_relaxation_time(const sllbm_ctx *c, double *tau) {
+  if (!c || !tau) return SLLBM_E_ARG;
+  if (!c->have_phys) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "physics not set");
+  *tau = c->tau;
+  return SLLBM_OK;
+}
+
+int sllbm_bind_populations(sllbm_ctx *c, void *a, void *b) {
+  if (!c) return SLLBM_E_ARG;
+  if (!a || !b || a == b) return fail(c, SLLBM_E_ARG, "need two distinct device buffers");
+  int rc = ready_for_tables(c);
+  if (rc) return rc;
+  if (c->own_pop) {
+    (void)hipFree(c->pop[0]);
+    (void)hipFree(c->pop[1]);
+  }
+  c->pop[0] = a;
+  c->pop[1] = b;
+  c->own_pop = false;
+  c->pop_bytes = size_t(nsets(c)) * kQ * size_t(nnodes(c)) * pop_size(c);
+  c->cur = 0;
+  c->initialised = false;
+  return SLLBM_OK;
+}
+
+int sllbm_init_macro(sllbm_ctx *c, const double *rho, const double *ux, const double *uy,
+                     const double *T, int on_device) {
+  if (!c) return SLLBM_E_ARG;
+  if (!rho || !ux || !uy || (!T && c->model != SLLBM_ISOTHERMAL))
+    return fail(c, SLLBM_E_ARG, "null macroscopic field");
+  int rc = ready_for_tables(c);
+  if (rc) return rc;
+  const long long N = nnodes(c);
+  if (!on_device) {
+    for (long long v = 0; v < N; ++v) {
+      if (!is_finite(rho[v]) || !is_finite(ux[v]) || !is_finite(uy[v]) || !(rho[v] > 0))
+        return fail(c, SLLBM_E_ARG, "rho must be positive and all fields finite");
+      if (c->model != SLLBM_ISOTHERMAL && (!is_finite(T[v]) || !(T[v] > 0)))
+        return fail(c, SLLBM_E_ARG, "T must be positive and finite");
+    }
+  }
+  rc = prepare_device(c);
+  if (!rc) rc = ensure_populations(c);
+  if (rc) return rc;
+  const double *d[4] = {rho, ux, uy, T};
+  if (!on_device) {
+    rc = alloc_buf(c, c->macro, sizeof(double) * 4 * size_t(N));
+    if (rc) return rc;
+    double *m = static_cast<double *>(c->macro.ptr);
+    for (int k = 0; k < 4; ++k) {
+      if (!d[k]) {
+        d[k] = nullptr;
+        continue;
+      }
+      HIP_TRY(c, hipMemcpyAsync(m + k * N, d[k], sizeof(double) * N, hipMemcpyHostToDevice,
+                                c->stream));
+      d[k] = m + k * N;
+    }
+  }
+  c->cur = 0;
+  HIP_TRY(c, launch_init_eq(c->fp32, c->model, make_consts(c), d[0], d[1], d[2], d[3],
+                            c->pop[0], c->stream));
+  rc = clear_flag(c);
+  if (rc) return rc;
+  if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->steps_done = 0;
+  c->initialised = true;
+  return SLLBM_OK;
+}
+
+int sllbm_set_check_interval(sllbm_ctx *c, int64_t k) {
+  if (!c) return SLLBM_E_ARG;
+  if (k < 0) return fail(c, SLLBM_E_ARG, "interval must be >= 0");
+  c->check_interval = k;
+  return SLLBM_OK;
+}
+
+static int read_flag(sllbm_ctx *c, int *flag) {
+  HIP_TRY(c, hipMemcpyAsync(flag, c->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SLLBM_OK;
+}
+
+int sllbm_step(sllbm_ctx *c, int64_t n) {
+  if (!c) return SLLBM_E_ARG;
+  if (n < 0) return fail(c, SLLBM_E_ARG, "n must be >= 0");
+  if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
+  int rc = prepare_device(c);
+  if (rc) return rc;
+  const int path = effective_path(c);
+  if (path == kPathTiled && !tiled_fits(c))
+    return fail(c, SLLBM_E_UNSUPPORTED, "departures span too many rows for the tiled kernel");
+  const StepConsts k = make_consts(c);
+  const DevTables t = make_tables(c);
+  int *flag = static_cast<int *>(c->flag.ptr);
+  for (int64_t s = 0; s < n; ++s) {
+    HIP_TRY(c, launch_step(c->fp32, c->model, path, k, t, c->pop[c->cur], c->pop[1 - c->cur],
+                           flag, c->stream));
+    c->cur ^= 1;
+    ++c->steps_done;
+    if (c->check_interval > 0 && c->steps_done % c->check_interval == 0) {
+      int f = 0;
+      rc = read_flag(c, &f);
+      if (rc) return rc;
+      if (f) return fail(c, SLLBM_E_UNSTABLE, "stability flag raised (rho, theta or moments)");
+    }
+  }
+  return SLLBM_OK;
+}
+
+int sllbm_status_flags(sllbm_ctx *c, int *unstable, int64_t *steps_done) {
+  if (!c || !unstable || !steps_done) return SLLBM_E_ARG;
+  if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
+  int rc = read_flag(c, unstable);
+  if (rc) return rc;
+  *steps_done = c->steps_done;
+  return SLLBM_OK;
+}
+
+int sllbm_moments(sllbm_ctx *c, double *rho, double *ux, double *uy, double *T, int on_device) {
+  if (!c) return SLLBM_E_ARG;
+  if (!rho || !ux || !uy || !T) return fail(c, SLLBM_E_ARG, "null output array");
+  if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
+  int rc = prepare_device(c);
+  if (rc) return rc;
+  const long long N = nnodes(c);
+  double *d[4] = {rho, ux, uy, T};
+  if (!on_device) {
+    rc = alloc_buf(c, c->macro, sizeof(double) * 4 * size_t(N));
+    if (rc) return rc;
+    for (int k = 0; k < 4; ++k) d[k] = static_cast<double *>(c->macro.ptr) + k * N;
+  }
+  HIP_TRY(c, launch_moments(c->fp32, c->model, make_consts(c), make_tables(c), c->pop[c->cur],
+                            d[0], d[1], d[2], d[3], static_cast<double *>(c->partial.ptr),
+                            c->stream));
+  if (!on_device) {
+    double *h[4] = {rho, ux, uy, T};
+    for (int k = 0; k < 4; ++k)
+      HIP_TRY(c, hipMemcpyAsync(h[k], d[k], sizeof(double) * N, hipMemcpyDeviceToHost,
+                                c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return SLLBM_OK;
+}
+
+int sllbm_mass(sllbm_ctx *c, double *mass) {
+  if (!c || !mass) return SLLBM_E_ARG;
+  if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
+  int rc = prepare_device(c);
+  if (rc) return rc;
+  const StepConsts k = make_consts(c);
+  double *part = static_cast<double *>(c->partial.ptr);
+  HIP_TRY(c, launch_moments(c->fp32, c->model, k, make_tables(c), c->pop[c->cur], nullptr,
+                            nullptr, nullptr, nullptr, part, c->stream));
+  double *out = static_cast<double *>(c->scalar.ptr);
+  HIP_TRY(c, launch_sum(part, mass_blocks(k), out, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(mass, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SLLBM_OK;
+}
+
+int sllbm_get_populations(sllbm_ctx *c, void *dst, int on_device) {
+  if (!c || !dst) return SLLBM_E_ARG;
+  if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(dst, c->pop[c->cur], c->pop_bytes,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            c->stream));
+  if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SLLBM_OK;
+}
+
+int sllbm_set_populations(sllbm_ctx *c, const void *src, int on_device) {
+  if (!c || !src) return SLLBM_E_ARG;
+  int rc = ready_for_tables(c);
+  if (rc) return rc;
+  rc = prepare_device(c);
+  if (!rc) rc = ensure_populations(c);
+  if (rc) return rc;
+  c->cur = 0;
+  HIP_TRY(c, hipMemcpyAsync(c->pop[0], src, c->pop_bytes,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            c->stream));
+  rc = clear_flag(c);
+  if (rc) return rc;
+  if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->initialised = true;
+  return SLLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Interface between the C-ABI host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sllbm {
+
+// Per-step scalar constants, passed by value as kernel arguments.
+struct StepConsts {
+  int nx, ny;
+  long long n;        // nx * ny
+  int ncx, ncy, p;
+  double omega;       // 1 / tau
+  double gfac;        // 2 C_v - D  (g_eq = gfac * theta * f_eq)
+  double inv_2cv;     // 1 / (2 C_v)  (theta from the energy moment)
+  double xi[5];       // 1-D abscissae
+  double w[5];        // 1-D weights
+  double hk[5][5];    // He_k(xi_a) / k!
+  double rn[5];       // reference support points r_0..r_p
+  double lden[5];     // 1 / prod_{n != m} (r_m - r_n)
+  int perx, pery;     // periodic axes
+};
+
+// Device-side departure data.  Per-axis tables are laid out [comp][m][node]
+// so that neighbouring threads read neighbouring words.
+struct DevTables {
+  const int32_t *xsrc;  // [5][p+1][nx]
+  const void *xw;       // [5][p+1][nx], population type
+  const int32_t *ysrc;  // [5][p+1][ny]
+  const void *yw;       // [5][p+1][ny]
+  const int32_t *rec_cell;  // [25][n]: cx | cy << 16
+  const void *rec_r;        // [25][n] reference x coordinate, population type
+  const void *rec_s;        // [25][n] reference y coordinate
+  const double *rnodes;     // p + 1 reference support points (records path)
+  const double *mx;     // [nx] mass weights
+  const double *my;     // [ny]
+  // tiled path: per-tile row windows
+  const int32_t *yrel;  // [5][p+1][ny]: source row relative to the tile's window
+  const int32_t *ywin;  // [5][ntiles_y]: first (unwrapped) source row of the window
+  int tile_rows;        // target rows per tile
+  int win_rows;         // source rows staged per tile (max over tiles)
+};
+
+enum Path { kPathDirect = 1, kPathTiled = 2, kPathRecords = 3 };
+
+hipError_t launch_init_eq(int fp32, int model, const StepConsts &c, const double *rho,
+                          const double *ux, const double *uy, const double *T, void *f,
+                          hipStream_t s);
+
+hipError_t launch_step(int fp32, int model, int path, const StepConsts &c, const DevTables &t,
+                       const void *fin, void *fout, int *flag, hipStream_t s);
+
+// Moments per node (any output pointer may be null) and per-block partial
+// sums of M_v rho_v into `partial` (mass_blocks(c) entries).
+int mass_blocks(const StepConsts &c);
+hipError_t launch_moments(int fp32, int model, const StepConsts &c, const DevTables &t,
+                          const void *f, double *rho, double *ux, double *uy, double *T,
+                          double *partial, hipStream_t s);
+hipError_t launch_sum(const double *partial, int n, double *out, hipStream_t s);
+
+// flag = 0 (a kernel, not a memset, so the call can live inside a captured graph)
+hipError_t launch_clear_flag(int *flag, hipStream_t s);
+
+}  // namespace sllbm

@@ -1,0 +1,78 @@
+// Host-side precomputation for the SLLBM step: velocity set constants,
+// support points, Lagrange weights, departure tables, mass weights.
+//
+// All tables are built once per (grid, dt, velocity set) in float64 on the
+// host; the kernels only read them.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sllbm {
+
+constexpr int kMaxOrder = 4;
+constexpr int kQ1 = 5;           // 1-D velocities of the tensor-product set
+constexpr int kQ = kQ1 * kQ1;    // 2-D velocities
+constexpr int kDim = 2;
+
+// 1-D velocity set (Sec. II.B, Table I) and per-velocity Hermite constants.
+struct VelocitySet {
+  double xi[kQ1];
+  double w[kQ1];
+  // hk[a][k] = He_k(xi_a) / k!  (probabilists' Hermite polynomials, k <= 4)
+  double hk[kQ1][5];
+};
+
+VelocitySet default_velocity_set();
+void fill_hermite_constants(VelocitySet &vs);
+
+// Reference support points on [0, 1] for order p (Sec. II.E).
+std::vector<double> support_points(int p, bool glc);
+
+// Lagrange weights l_m(r), m = 0..p, product formula on the given points.
+void lagrange_weights(const std::vector<double> &pts, double r, double *out);
+
+// Integrals over [0, 1] of each Lagrange polynomial, by exact integration of
+// the monomial expansion.
+std::vector<double> lagrange_integrals(const std::vector<double> &pts);
+
+// One grid direction.
+struct Axis {
+  std::vector<double> edges;  // ncells + 1, strictly increasing
+  int ncells = 0;
+  int p = 0;
+  bool periodic = true;
+  bool uniform = true;
+  int n = 0;                  // unique nodes
+  std::vector<double> r;      // reference support points (p + 1)
+
+  void setup(const std::vector<double> &e, int order, bool per, bool unif,
+             const std::vector<double> &pts);
+  double coord(int j) const;
+  // Cell and local support-point index of node j (the last node of a
+  // non-periodic axis is the right vertex of the last cell).
+  void cell_of(int j, int &cell, int &local) const;
+  int node(int cell, int m) const { int j = cell * p + m; return periodic ? j % n : j; }
+  // Departure point of node j displaced by `disp`: cell and reference
+  // coordinate after the boundary treatment (periodic wrap / clamp).
+  // `unwrapped` (optional) receives the cell index before the periodic wrap
+  // (it may be negative or >= ncells), which keeps neighbouring departures
+  // contiguous across the seam.
+  void departure(int j, double disp, int &cell, double &r, long *unwrapped = nullptr) const;
+  std::vector<double> node_mass() const;
+};
+
+// Per-axis departure table for one 1-D velocity: src[j * (p+1) + m],
+// w[j * (p+1) + m].
+struct AxisTable {
+  std::vector<int32_t> src;
+  std::vector<double> w;
+  std::vector<int32_t> cell;   // departure cell per node
+  std::vector<double> rref;    // reference coordinate per node
+  std::vector<long> ucell;     // departure cell before the periodic wrap
+};
+
+AxisTable build_axis_table(const Axis &ax, double disp);
+
+}  // namespace sllbm

@@ -1,0 +1,158 @@
+"""Thin convenience layer over the C ABI: torch owns the device buffers and the
+stream, libsllbm does every step of the method.
+
+    s = Solver.from_workload(workloads.riemann(512, 2), precision="fp32")
+    s.init_from_workload()
+    s.step(100)
+    rho, ux, uy, T = s.moments()
+"""
+import numpy as np
+import torch
+
+from . import sllbm as C
+
+_PREC = {"fp64": C.FP64, "fp32": C.FP32}
+_MODEL = {"isothermal": C.ISOTHERMAL, "monatomic": C.MONATOMIC, "polyatomic": C.POLYATOMIC}
+_PATH = {"auto": C.PATH_AUTO, "direct": C.PATH_DIRECT, "tiled": C.PATH_TILED,
+         "records": C.PATH_RECORDS}
+
+
+def _ptr(a):
+    """Address of a contiguous float64/int32 numpy array or a torch tensor."""
+    if isinstance(a, torch.Tensor):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+class Solver:
+    def __init__(self, *, p, edges_x, edges_y, periodic_x, periodic_y, dt, nu, model,
+                 gamma=1.4, precision="fp32", uniform=True, path="auto", device=0,
+                 nodes="glc", xi1d=None, w1d=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a HIP device (torch.cuda is not available)")
+        self.device = torch.device("cuda", device)
+        self.precision = precision
+        self.model = model
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        self.ctx = C.sllbm_create(device, _PREC[precision])
+        try:
+            if xi1d is not None:
+                self._xi = np.ascontiguousarray(xi1d, dtype=np.float64)
+                self._w = np.ascontiguousarray(w1d, dtype=np.float64)
+                C.sllbm_set_velocity_set(self.ctx, 5, _ptr(self._xi), _ptr(self._w))
+            C.sllbm_set_order(self.ctx, p, C.NODES_GLC if nodes == "glc" else C.NODES_EQUIDISTANT)
+            bcx = C.PERIODIC if periodic_x else C.ZERO_GRADIENT
+            bcy = C.PERIODIC if periodic_y else C.ZERO_GRADIENT
+            ex = np.ascontiguousarray(edges_x, dtype=np.float64)
+            ey = np.ascontiguousarray(edges_y, dtype=np.float64)
+            if uniform:
+                C.sllbm_init_grid_uniform(self.ctx, len(ex) - 1, len(ey) - 1, ex[0], ex[-1], ey[0],
+                                          ey[-1], bcx, bcy)
+            else:
+                C.sllbm_init_grid_mapped(self.ctx, len(ex) - 1, len(ey) - 1, _ptr(ex), _ptr(ey),
+                                         bcx, bcy)
+            C.sllbm_set_physics(self.ctx, dt, nu, gamma, 1.0, _MODEL[model])
+            C.sllbm_set_path(self.ctx, _PATH[path])
+            self.nx, self.ny = C.sllbm_num_nodes(self.ctx)
+            self.nsets, self.q, _ = C.sllbm_population_layout(self.ctx)
+            self.n = self.nx * self.ny
+            with torch.cuda.device(self.device):
+                self.stream = torch.cuda.current_stream(self.device)
+                C.sllbm_set_stream(self.ctx, self.stream.cuda_stream)
+                size = self.nsets * self.q * self.n
+                self.buf_a = torch.empty(size, dtype=self.dtype, device=self.device)
+                self.buf_b = torch.empty(size, dtype=self.dtype, device=self.device)
+            C.sllbm_bind_populations(self.ctx, self.buf_a.data_ptr(), self.buf_b.data_ptr())
+        except Exception:
+            C.sllbm_destroy(self.ctx)
+            self.ctx = None
+            raise
+        self.workload = None
+
+    @classmethod
+    def from_workload(cls, wl, precision="fp32", path="auto", device=0):
+        s = cls(p=wl.p, edges_x=wl.edges_x, edges_y=wl.edges_y, periodic_x=wl.periodic_x,
+                periodic_y=wl.periodic_y, dt=wl.dt, nu=wl.nu, model=wl.model, gamma=wl.gamma,
+                precision=precision, uniform=wl.uniform, path=path, device=device)
+        s.workload = wl
+        return s
+
+    # ---- geometry -------------------------------------------------------------
+    def axis_coords(self):
+        x = np.zeros(self.nx)
+        y = np.zeros(self.ny)
+        C.sllbm_node_coords(self.ctx, _ptr(x), _ptr(y))
+        return x, y
+
+    def coords(self):
+        x, y = self.axis_coords()
+        return np.tile(x, self.ny), np.repeat(y, self.nx)
+
+    def relaxation_time(self):
+        return C.sllbm_relaxation_time(self.ctx)
+
+    # ---- state -----------------------------------------------------------------
+    def init_macro(self, rho, ux, uy, T):
+        if isinstance(rho, torch.Tensor):
+            arrs = [t.to(device=self.device, dtype=torch.float64).contiguous()
+                    for t in (rho, ux, uy, T)]
+            C.sllbm_init_macro(self.ctx, *[a.data_ptr() for a in arrs], 1)
+            torch.cuda.synchronize(self.device)
+            return
+        arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, ux, uy, T)]
+        for a in arrs:
+            if a.size != self.n:
+                raise ValueError("field size does not match the grid")
+        C.sllbm_init_macro(self.ctx, *[_ptr(a) for a in arrs], 0)
+
+    def init_from_workload(self):
+        X, Y = self.coords()
+        self.init_macro(*self.workload.fields(X, Y))
+
+    def set_populations(self, F):
+        if isinstance(F, torch.Tensor):
+            t = F.to(device=self.device, dtype=self.dtype).contiguous().reshape(-1)
+            C.sllbm_set_populations(self.ctx, t.data_ptr(), 1)
+            torch.cuda.synchronize(self.device)
+            return
+        a = np.ascontiguousarray(F, dtype=np.float32 if self.precision == "fp32" else np.float64)
+        if a.size != self.nsets * self.q * self.n:
+            raise ValueError("population array size does not match the grid")
+        C.sllbm_set_populations(self.ctx, _ptr(a), 0)
+
+    def populations(self):
+        a = np.empty(self.nsets * self.q * self.n,
+                     dtype=np.float32 if self.precision == "fp32" else np.float64)
+        C.sllbm_get_populations(self.ctx, _ptr(a), 0)
+        return a.reshape(self.nsets, self.q, self.n)
+
+    # ---- stepping and outputs ----------------------------------------------------
+    def step(self, n=1):
+        C.sllbm_step(self.ctx, n)
+
+    def flags(self):
+        return C.sllbm_status_flags(self.ctx)
+
+    def moments(self):
+        out = [np.empty(self.n) for _ in range(4)]
+        C.sllbm_moments(self.ctx, *[_ptr(a) for a in out], 0)
+        return tuple(out)
+
+    def moments_device(self):
+        out = [torch.empty(self.n, dtype=torch.float64, device=self.device) for _ in range(4)]
+        C.sllbm_moments(self.ctx, *[t.data_ptr() for t in out], 1)
+        return tuple(out)
+
+    def mass(self):
+        return C.sllbm_mass(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            C.sllbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,236 @@
+"""CPU tests of libsllbm's host path: exported symbols, argument validation and
+call-order errors, and the host-side tables (node coordinates, departure
+tables, mass weights) against the oracle's brute-force geometry.
+
+No kernel is launched here; set-up calls never touch the HIP runtime.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.grid import Grid
+from oracle.sllbm import Sim
+from paper_1910_13918_amd import sllbm as C
+from paper_1910_13918_amd import workloads as W
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "sllbm.h")
+
+
+def test_every_declared_symbol_is_exported():
+    src = open(HEADER).read()
+    names = set(re.findall(r"\b(sllbm_[a-z_]+)\s*\(", src))
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(C.lib, n), n
+        assert n in C.EXPORTED, n
+
+
+def _ctx(precision=C.FP64):
+    return C.sllbm_create(0, precision)
+
+
+def _code(fn, *args):
+    try:
+        fn(*args)
+        return C.OK
+    except C.SllbmError as e:
+        return e.code
+
+
+def _setup(ctx, p=2, nc=4, bc=C.PERIODIC, model=C.POLYATOMIC, dt=0.01, nu=0.01):
+    C.sllbm_set_order(ctx, p, C.NODES_GLC)
+    C.sllbm_init_grid_uniform(ctx, nc, nc, 0.0, 1.0, 0.0, 1.0, bc, bc)
+    C.sllbm_set_physics(ctx, dt, nu, 1.4, 1.0, model)
+
+
+def test_create_validation():
+    h = ctypes.c_void_p()
+    assert C.lib.sllbm_create(ctypes.byref(h), 0, 7) == C.E_ARG
+    assert C.lib.sllbm_create(ctypes.byref(h), -1, 0) == C.E_ARG
+    assert C.lib.sllbm_create(None, 0, 0) == C.E_ARG
+    C.sllbm_destroy(None)  # accepted
+
+
+def test_setup_validation_and_call_order():
+    ctx = _ctx()
+    try:
+        # grid before order
+        assert _code(C.sllbm_init_grid_uniform, ctx, 4, 4, 0, 1, 0, 1, 0, 0) == C.E_STATE
+        assert "order" in C.sllbm_last_error(ctx)
+        assert _code(C.sllbm_set_order, ctx, 0, 0) == C.E_ARG
+        assert _code(C.sllbm_set_order, ctx, 5, 0) == C.E_ARG
+        assert _code(C.sllbm_set_order, ctx, 2, 9) == C.E_ARG
+        C.sllbm_set_order(ctx, 3, C.NODES_GLC)
+        assert _code(C.sllbm_init_grid_uniform, ctx, 0, 4, 0, 1, 0, 1, 0, 0) == C.E_ARG
+        assert _code(C.sllbm_init_grid_uniform, ctx, 4, 4, 1, 0, 0, 1, 0, 0) == C.E_ARG
+        assert _code(C.sllbm_init_grid_uniform, ctx, 4, 4, 0, float("nan"), 0, 1, 0, 0) == C.E_ARG
+        assert _code(C.sllbm_init_grid_uniform, ctx, 4, 4, 0, 1, 0, 1, 2, 0) == C.E_ARG
+        bad = np.array([0.0, 0.5, 0.4, 1.0])
+        good = np.array([0.0, 0.3, 0.6, 1.0])
+        assert _code(C.sllbm_init_grid_mapped, ctx, 3, 3, bad.ctypes.data, good.ctypes.data, 0, 0) == C.E_ARG
+        assert _code(C.sllbm_init_grid_mapped, ctx, 3, 3, None, good.ctypes.data, 0, 0) == C.E_ARG
+        C.sllbm_init_grid_uniform(ctx, 4, 4, 0, 1, 0, 1, 0, 1)
+        assert C.sllbm_num_nodes(ctx) == (12, 13)
+        # physics
+        assert _code(C.sllbm_set_physics, ctx, 0.0, 0.1, 1.4, 1.0, 2) == C.E_ARG
+        assert _code(C.sllbm_set_physics, ctx, 0.1, 0.0, 1.4, 1.0, 2) == C.E_ARG   # tau = 1/2
+        assert _code(C.sllbm_set_physics, ctx, 0.1, -1.0, 1.4, 1.0, 2) == C.E_ARG
+        assert _code(C.sllbm_set_physics, ctx, 0.1, float("nan"), 1.4, 1.0, 2) == C.E_ARG
+        assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.0, 1.0, 2) == C.E_ARG
+        assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.4, 0.75, 2) == C.E_UNSUPPORTED
+        assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.4, 1.0, 3) == C.E_ARG
+        # queries before physics
+        assert _code(C.sllbm_relaxation_time, ctx) == C.E_STATE
+        C.sllbm_set_physics(ctx, 0.1, 0.2, 1.4, 1.0, C.POLYATOMIC)
+        assert C.sllbm_relaxation_time(ctx) == pytest.approx(0.2 / 0.1 + 0.5)
+        assert C.sllbm_population_layout(ctx) == (2, 25, 8)
+        # stepping before initialisation
+        assert _code(C.sllbm_step, ctx, 1) == C.E_STATE
+        assert _code(C.sllbm_step, ctx, -1) == C.E_ARG
+        assert _code(C.sllbm_mass, ctx) == C.E_STATE
+        assert _code(C.sllbm_set_path, ctx, 9) == C.E_ARG
+        assert _code(C.sllbm_set_check_interval, ctx, -2) == C.E_ARG
+    finally:
+        C.sllbm_destroy(ctx)
+
+
+def test_velocity_set_validation():
+    ctx = _ctx()
+    try:
+        xi = np.zeros(5)
+        w = np.ones(5)
+        assert _code(C.sllbm_set_velocity_set, ctx, 3, xi.ctypes.data, w.ctypes.data) == C.E_UNSUPPORTED
+        w[2] = -1.0
+        assert _code(C.sllbm_set_velocity_set, ctx, 5, xi.ctypes.data, w.ctypes.data) == C.E_ARG
+        assert _code(C.sllbm_set_velocity_set, ctx, 5, xi.ctypes.data, None) == C.E_ARG
+        C.sllbm_set_velocity_set(ctx, 5, None, None)
+    finally:
+        C.sllbm_destroy(ctx)
+
+
+def test_init_macro_validates_host_fields_before_device():
+    ctx = _ctx()
+    try:
+        _setup(ctx, nc=2)
+        nx, ny = C.sllbm_num_nodes(ctx)
+        n = nx * ny
+        rho = np.ones(n)
+        u = np.zeros(n)
+        T = np.ones(n)
+        rho[3] = -1.0
+        args = [a.ctypes.data for a in (rho, u, u, T)]
+        assert _code(C.sllbm_init_macro, ctx, *args, 0) == C.E_ARG
+        rho[3] = 1.0
+        T[1] = float("nan")
+        args = [a.ctypes.data for a in (rho, u, u, T)]
+        assert _code(C.sllbm_init_macro, ctx, *args, 0) == C.E_ARG
+        T[1] = 0.0
+        args = [a.ctypes.data for a in (rho, u, u, T)]
+        assert _code(C.sllbm_init_macro, ctx, *args, 0) == C.E_ARG
+        assert _code(C.sllbm_init_macro, ctx, None, args[1], args[2], args[3], 0) == C.E_ARG
+    finally:
+        C.sllbm_destroy(ctx)
+
+
+def _oracle_and_lib(wl, kind=C.NODES_GLC):
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y,
+             "glc" if kind == C.NODES_GLC else "equidistant")
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+    ctx = _ctx()
+    C.sllbm_set_order(ctx, wl.p, kind)
+    bcx = C.PERIODIC if wl.periodic_x else C.ZERO_GRADIENT
+    bcy = C.PERIODIC if wl.periodic_y else C.ZERO_GRADIENT
+    ex = np.ascontiguousarray(wl.edges_x)
+    ey = np.ascontiguousarray(wl.edges_y)
+    if wl.uniform:
+        C.sllbm_init_grid_uniform(ctx, len(ex) - 1, len(ey) - 1, ex[0], ex[-1], ey[0], ey[-1], bcx, bcy)
+    else:
+        C.sllbm_init_grid_mapped(ctx, len(ex) - 1, len(ey) - 1, ex.ctypes.data, ey.ctypes.data, bcx, bcy)
+    C.sllbm_set_physics(ctx, wl.dt, wl.nu, wl.gamma, 1.0,
+                        {"isothermal": 0, "monatomic": 1, "polyatomic": 2}[wl.model])
+    return g, sim, ctx
+
+
+CASES = [
+    W.tgv(3, 2, name="tgv"),
+    W.tgv(2, 4, name="tgv_p4"),
+    W.sod(6, 1, 3, name="sod"),
+    W.riemann(3, 1, seed=1, name="riemann_p1"),
+    W.svi(7, 2, 3, name="svi"),
+    W.riemann(2, 4, seed=1, cfl=3.0, name="riemann_bigcfl"),
+]
+
+
+@pytest.mark.parametrize("wl", CASES, ids=lambda w: w.name)
+def test_node_coords_and_mass_weights(wl):
+    g, sim, ctx = _oracle_and_lib(wl)
+    try:
+        nx, ny = C.sllbm_num_nodes(ctx)
+        assert (nx, ny) == (g.nx, g.ny)
+        x = np.zeros(nx)
+        y = np.zeros(ny)
+        C.sllbm_node_coords(ctx, x.ctypes.data, y.ctypes.data)
+        np.testing.assert_allclose(x, g.ax.node_coords(), rtol=0, atol=1e-14)
+        np.testing.assert_allclose(y, g.ay.node_coords(), rtol=0, atol=1e-14)
+        mx = np.zeros(nx)
+        my = np.zeros(ny)
+        C.sllbm_mass_weights(ctx, mx.ctypes.data, my.ctypes.data)
+        np.testing.assert_allclose(mx, g.ax.node_mass(), rtol=1e-13, atol=1e-16)
+        np.testing.assert_allclose(my, g.ay.node_mass(), rtol=1e-13, atol=1e-16)
+        assert C.sllbm_relaxation_time(ctx) == pytest.approx(sim.tau, rel=1e-15)
+    finally:
+        C.sllbm_destroy(ctx)
+
+
+@pytest.mark.parametrize("wl", CASES, ids=lambda w: w.name)
+def test_departure_tables_match_bruteforce(wl):
+    """The library's separable (x-table times y-table) departure weights, as a
+    dense streaming matrix per velocity, equal the oracle's brute-force
+    stencil (absolute coordinates, linear cell scan)."""
+    g, sim, ctx = _oracle_and_lib(wl)
+    try:
+        P1 = wl.p + 1
+        N = g.nnodes
+        tabs = {}
+        for axis, n in ((0, g.nx), (1, g.ny)):
+            for comp in range(5):
+                src = np.zeros(n * P1, dtype=np.int32)
+                w = np.zeros(n * P1)
+                C.sllbm_departure_table(ctx, axis, comp, src.ctypes.data, w.ctypes.data)
+                tabs[axis, comp] = (src.reshape(n, P1), w.reshape(n, P1))
+        nodes = np.arange(N)
+        for b in range(5):
+            for a in range(5):
+                i = a + 5 * b
+                osrc, owgt = sim.departure_stencil(i, nodes)
+                M_o = np.zeros((N, N))
+                for aa in range(P1):
+                    for bb in range(P1):
+                        np.add.at(M_o, (nodes, osrc[aa, bb]), owgt[aa, bb])
+                sx, wx = tabs[0, a]
+                sy, wy = tabs[1, b]
+                ix = nodes % g.nx
+                iy = nodes // g.nx
+                M_l = np.zeros((N, N))
+                for m in range(P1):
+                    for k in range(P1):
+                        np.add.at(M_l, (nodes, sy[iy, k] * g.nx + sx[ix, m]), wx[ix, m] * wy[iy, k])
+                np.testing.assert_allclose(M_l, M_o, rtol=0, atol=2e-13, err_msg=f"velocity {i}")
+    finally:
+        C.sllbm_destroy(ctx)
+
+
+def test_equidistant_nodes_tables():
+    wl = W.tgv(3, 4, name="equi")
+    g, sim, ctx = _oracle_and_lib(wl, C.NODES_EQUIDISTANT)
+    try:
+        x = np.zeros(g.nx)
+        y = np.zeros(g.ny)
+        C.sllbm_node_coords(ctx, x.ctypes.data, y.ctypes.data)
+        np.testing.assert_allclose(x, g.ax.node_coords(), atol=1e-14)
+    finally:
+        C.sllbm_destroy(ctx)

@@ -1,0 +1,257 @@
+"""GPU parity of the stream + collide step against the FP64 CPU oracle.
+
+Every case feeds the same seeded input to both sides (the oracle's own
+equilibrium initialisation, optionally perturbed by seeded noise) and compares
+element by element.  Tolerances:
+  * FP64 path, one step: max |dF| / max |F| <= 1e-12;
+  * FP64 path, 200-step Taylor-Green trajectory: <= 1e-11;
+  * FP32 populations (FP64 moments): one step <= 2e-6 relative to max |F|
+    (a few float32 roundings of O(1) values through at most 25 weights).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.grid import Grid
+from oracle.sllbm import Sim
+from paper_1910_13918_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a HIP device")]
+
+
+def _solver(wl, precision, path):
+    from paper_1910_13918_amd.solver import Solver
+    return Solver.from_workload(wl, precision=precision, path=path)
+
+
+def _oracle(wl):
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+    return g, sim
+
+
+def _state(wl, sim, g, seed, rel):
+    X, Y = g.coords()
+    F = sim.init(*wl.fields(X, Y))
+    if rel:
+        F = F * W.population_noise(F.shape, seed, rel)
+    return F
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+# several tiles in x (64 nodes) and y (8 rows) plus ragged tails
+def _cases():
+    out = []
+    for model in ("isothermal", "monatomic", "polyatomic"):
+        for p in (1, 2, 3, 4):
+            ncx = {1: 70, 2: 35, 3: 23, 4: 17}[p]
+            ncy = {1: 19, 2: 9, 3: 6, 4: 5}[p]
+            for periodic in (True, False):
+                out.append((model, p, periodic, ncx, ncy))
+    return out
+
+
+def _wl(model, p, periodic, ncx, ncy):
+    wl = W.riemann(ncx, p, seed=5) if model == "polyatomic" else W.tgv(ncx, p, U0=0.2, model=model)
+    # ncy rows of cells of the same size as in x
+    wl.edges_y = wl.edges_y[0] + (wl.edges_x[1] - wl.edges_x[0]) * np.arange(ncy + 1)
+    wl.periodic_x = wl.periodic_y = periodic
+    if model == "monatomic":
+        base = wl.fields
+
+        def fields(x, y):
+            rho, ux, uy, _ = base(x, y)
+            return rho, ux, uy, 0.8 + 0.3 * np.cos(x) * np.sin(y)
+
+        wl.fields = fields
+    return wl
+
+
+@pytest.mark.parametrize("path", ["direct", "tiled", "records"])
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: f"{c[0]}-p{c[1]}-{'per' if c[2] else 'zg'}")
+def test_one_step_fp64(case, path):
+    wl = _wl(*case)
+    g, sim = _oracle(wl)
+    F0 = _state(wl, sim, g, seed=11, rel=0.05)
+    F1 = sim.step(F0)
+    s = _solver(wl, "fp64", path)
+    try:
+        print(f"[gpu] one step fp64 {case} path={path} nodes={g.nnodes}", flush=True)
+        s.set_populations(F0)
+        s.step(1)
+        G1 = s.populations()
+        assert _rel(G1, F1) <= 1e-12
+        assert s.flags() == (0, 1)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("path", ["direct", "tiled", "records"])
+@pytest.mark.parametrize("case", [("polyatomic", 2, False, 35, 9), ("polyatomic", 3, True, 23, 6),
+                                  ("isothermal", 4, True, 17, 5)],
+                         ids=lambda c: f"{c[0]}-p{c[1]}")
+def test_one_step_fp32(case, path):
+    wl = _wl(*case)
+    g, sim = _oracle(wl)
+    F0 = _state(wl, sim, g, seed=12, rel=0.05)
+    F0 = F0.astype(np.float32).astype(np.float64)  # same rounded input on both sides
+    F1 = sim.step(F0)
+    s = _solver(wl, "fp32", path)
+    try:
+        s.set_populations(F0)
+        s.step(1)
+        assert _rel(s.populations(), F1) <= 2e-6
+    finally:
+        s.close()
+
+
+def test_mapped_grid_one_step_all_paths():
+    """Stretched grid of the shock-vortex case (departures cross several cells
+    in the refined zone)."""
+    wl = W.svi(48, 10, 3)
+    g, sim = _oracle(wl)
+    F0 = _state(wl, sim, g, seed=13, rel=0.02)
+    F1 = sim.step(F0)
+    for path in ("direct", "tiled", "records"):
+        s = _solver(wl, "fp64", path)
+        try:
+            s.set_populations(F0)
+            s.step(1)
+            assert _rel(s.populations(), F1) <= 1e-12, path
+        finally:
+            s.close()
+
+
+def test_tgv_trajectory_fp64_and_outputs():
+    """The 8 x 8-cell, p = 2 Taylor-Green workload, 200 steps from f = f_eq:
+    populations, moments and mass against the oracle."""
+    wl = W.tgv()
+    g, sim = _oracle(wl)
+    X, Y = g.coords()
+    F = sim.init(*wl.fields(X, Y))
+    m0 = sim.mass(F)
+    FN = sim.run(F, wl.steps)
+    s = _solver(wl, "fp64", "auto")
+    try:
+        s.init_macro(*wl.fields(*s.coords()))
+        np.testing.assert_allclose(s.populations(), F, rtol=0, atol=1e-15)
+        assert s.mass() == pytest.approx(m0, rel=1e-14)
+        s.step(wl.steps)
+        assert _rel(s.populations(), FN) <= 1e-11
+        rho, ux, uy, T = s.moments()
+        r, u, v, t = sim.macro(FN)
+        np.testing.assert_allclose(rho, r, rtol=1e-11)
+        np.testing.assert_allclose(ux, u, rtol=0, atol=1e-11)
+        np.testing.assert_allclose(uy, v, rtol=0, atol=1e-11)
+        np.testing.assert_allclose(T, 1.0)
+        assert s.mass() == pytest.approx(sim.mass(FN), rel=1e-12)
+        assert s.flags() == (0, wl.steps)
+    finally:
+        s.close()
+
+
+def test_sod_trajectory_fp64_vs_fp32():
+    """Reduced Sod tube (64 x 1 cells, p = 3), 100 steps: the FP64 path tracks
+    the oracle to 1e-11; FP32 populations stay within 1e-5 on rho, u, T."""
+    wl = W.sod(64, 1, 3)
+    g, sim = _oracle(wl)
+    X, Y = g.coords()
+    F = sim.run(sim.init(*wl.fields(X, Y)), 100)
+    r, u, v, t = sim.macro(F)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-5)):
+        s = _solver(wl, prec, "auto")
+        try:
+            s.init_macro(*wl.fields(*s.coords()))
+            s.step(100)
+            rho, ux, uy, T = s.moments()
+            assert np.abs(rho - r).max() <= tol, prec
+            assert np.abs(ux - u).max() <= tol, prec
+            assert np.abs(T - t).max() <= tol, prec
+        finally:
+            s.close()
+
+
+def test_stability_flag_and_check_interval():
+    from paper_1910_13918_amd import sllbm as C
+    wl = W.riemann(9, 2, seed=2)
+    g, sim = _oracle(wl)
+    F0 = _state(wl, sim, g, seed=3, rel=0.0)
+    F0[0, 7, 100] = np.nan
+    s = _solver(wl, "fp64", "auto")
+    try:
+        s.set_populations(F0)
+        s.step(1)
+        assert s.flags()[0] == 1
+        s.set_populations(F0)
+        C.sllbm_set_check_interval(s.ctx, 1)
+        with pytest.raises(C.SllbmError) as e:
+            s.step(3)
+        assert e.value.code == C.E_UNSTABLE
+    finally:
+        s.close()
+
+
+def test_bitwise_reproducible_and_uniform_state():
+    wl = W.riemann(20, 3, seed=4)
+    runs = []
+    for _ in range(2):
+        s = _solver(wl, "fp32", "auto")
+        try:
+            s.init_from_workload()
+            s.step(7)
+            runs.append(s.populations().copy())
+        finally:
+            s.close()
+    assert np.array_equal(runs[0], runs[1])
+    s = _solver(wl, "fp64", "auto")
+    try:
+        n = s.n
+        s.init_macro(np.full(n, 1.2), np.full(n, 0.3), np.full(n, -0.4), np.full(n, 0.9))
+        F0 = s.populations().copy()
+        s.step(5)
+        np.testing.assert_allclose(s.populations(), F0, rtol=1e-13, atol=1e-16)
+    finally:
+        s.close()
+
+
+def test_pure_streaming_reproduces_polynomials():
+    """nu = inf (no collision): the GPU interpolation reproduces the oracle's
+    exactly-interpolated polynomial on a zero-gradient grid."""
+    wl = W.riemann(11, 4, seed=1)
+    wl.nu = np.inf
+    wl.model = "isothermal"
+    g, sim = _oracle(wl)
+    X, Y = g.coords()
+    P = 1.0 + 0.3 * X ** 4 - 0.2 * X * Y ** 3 + 0.1 * Y ** 2
+    F0 = np.tile(P, (1, 25, 1))
+    F1 = sim.stream(F0)
+    for path in ("direct", "tiled", "records"):
+        s = _solver(wl, "fp64", path)
+        try:
+            s.set_populations(F0)
+            s.step(1)
+            assert _rel(s.populations(), F1) <= 1e-13, path
+        finally:
+            s.close()
+
+
+def test_tiny_grids():
+    """Edge cases: one cell per axis (periodic: a single node per axis)."""
+    for per in (True, False):
+        wl = W.tgv(1, 1, model="isothermal")
+        wl.periodic_x = wl.periodic_y = per
+        g, sim = _oracle(wl)
+        F0 = _state(wl, sim, g, seed=9, rel=0.05)
+        F1 = sim.step(F0)
+        for path in ("direct", "tiled", "records"):
+            s = _solver(wl, "fp64", path)
+            try:
+                s.set_populations(F0)
+                s.step(1)
+                assert _rel(s.populations(), F1) <= 1e-12, (per, path)
+            finally:
+                s.close()
