@@ -129,6 +129,11 @@ def sod(ncx=1024, ncy=4, p=3, t_end=0.2, nu=1.2e-4, gamma=1.4, cfl=0.5, name=Non
 # ------------------------------------------------------------------------- Riemann
 RIEMANN_DEFAULT_SEED = 0
 
+# Quadrant states (NE, NW, SW, SE) of the Lax-Liu configuration printed in
+# Table III (Sec. III.D): (rho, u_x, u_y, P).
+RIEMANN_TABLE3_STATES = [(0.5313, 0.0, 0.0, 0.4), (1.0, 0.7276, 0.0, 1.0),
+                         (0.8, 0.0, 0.0, 1.0), (1.0, 0.0, 0.7276, 1.0)]
+
 
 def riemann_states(seed):
     """Quadrant states (NE, NW, SW, SE) drawn with numpy's default_rng(seed):
