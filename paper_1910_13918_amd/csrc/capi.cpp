@@ -20,8 +20,9 @@ using namespace sllbm;
 
 namespace {
 
-constexpr int kTileRows = 8;          // rows per workgroup of the tiled kernel
-constexpr size_t kMaxTileLds = 65536; // LDS budget of one tiled workgroup (bytes)
+constexpr int kTileRows = 4;          // rows per workgroup of the tiled kernel
+constexpr int kTileCols = 64;         // columns per workgroup (one per lane)
+constexpr int kMaxWindowCols = 128;   // widest staged source window
 
 struct DeviceBuf {
   void *ptr = nullptr;
@@ -51,14 +52,15 @@ struct sllbm_ctx {
   bool host_dirty = true;
   AxisTable xt[kQ1], yt[kQ1];
   std::vector<double> mx, my;
-  int win_rows = 0;
-  std::vector<int32_t> ywin, yrel;
+  int win_rows = 0, win_cols = 0;
+  std::vector<int32_t> ywin, yrel, xwin, xrel;
 
   // device
   bool dev_checked = false;
   bool dev_dirty = true;
   bool rec_dirty = true;
-  DeviceBuf xsrc, xw, ysrc, yw, yrel_d, ywin_d, mxd, myd, flag, partial, scalar, macro;
+  DeviceBuf xsrc, xw, ysrc, yw, yrel_d, ywin_d, xrel_d, xwin_d, mxd, myd, flag, partial, scalar,
+      macro;
   DeviceBuf rec_cell, rec_r, rec_s;
   void *pop[2] = {nullptr, nullptr};
   bool own_pop = false;
@@ -96,6 +98,39 @@ int ready_for_tables(sllbm_ctx *c) {
   return SLLBM_OK;
 }
 
+// Source windows of the tiled kernel along one axis.  For tile t (nodes
+// [t*tile, min((t+1)*tile, n))) and 1-D velocity comp, the window starts at
+// the smallest unwrapped source node of the tile's departure stencils; rel
+// holds each node's stencil relative to its tile's window ([comp][m][node]).
+// Unwrapped indices keep the window contiguous across a periodic seam.
+// Returns the widest window.
+int build_windows(const AxisTable *t, int n, int p, int tile, std::vector<int32_t> &win,
+                  std::vector<int32_t> &rel) {
+  const int P1 = p + 1;
+  const int ntiles = (n + tile - 1) / tile;
+  win.assign(size_t(kQ1) * ntiles, 0);
+  rel.assign(size_t(kQ1) * P1 * n, 0);
+  int width = 0;
+  for (int a = 0; a < kQ1; ++a) {
+    for (int k = 0; k < ntiles; ++k) {
+      const int j0 = k * tile, j1 = std::min(j0 + tile, n);
+      long lo = std::numeric_limits<long>::max(), hi = std::numeric_limits<long>::min();
+      for (int j = j0; j < j1; ++j) {
+        const long base = t[a].ucell[j] * p;
+        lo = std::min(lo, base);
+        hi = std::max(hi, base + p);
+      }
+      win[size_t(a) * ntiles + k] = int32_t(lo);
+      width = std::max<int>(width, int(hi - lo + 1));
+      for (int j = j0; j < j1; ++j) {
+        const long base = t[a].ucell[j] * p;
+        for (int m = 0; m < P1; ++m) rel[(size_t(a) * P1 + m) * n + j] = int32_t(base + m - lo);
+      }
+    }
+  }
+  return width;
+}
+
 void build_host_tables(sllbm_ctx *c) {
   if (!c->host_dirty) return;
   for (int a = 0; a < kQ1; ++a) {
@@ -104,40 +139,18 @@ void build_host_tables(sllbm_ctx *c) {
   }
   c->mx = c->ax.node_mass();
   c->my = c->ay.node_mass();
-  // row windows of the tiled kernel: tile t covers rows [t*TY, min((t+1)*TY, ny))
-  const int ny = c->ay.n, P1 = c->p + 1;
-  const int ntiles = (ny + kTileRows - 1) / kTileRows;
-  c->ywin.assign(size_t(kQ1) * ntiles, 0);
-  c->yrel.assign(size_t(kQ1) * P1 * ny, 0);
-  int W = 0;
-  for (int b = 0; b < kQ1; ++b) {
-    for (int t = 0; t < ntiles; ++t) {
-      const int r0 = t * kTileRows, r1 = std::min(r0 + kTileRows, ny);
-      long lo = std::numeric_limits<long>::max(), hi = std::numeric_limits<long>::min();
-      for (int iy = r0; iy < r1; ++iy) {
-        const long base = c->yt[b].ucell[iy] * c->p;
-        lo = std::min(lo, base);
-        hi = std::max(hi, base + c->p);
-      }
-      c->ywin[size_t(b) * ntiles + t] = int32_t(lo);
-      W = std::max<int>(W, int(hi - lo + 1));
-      for (int iy = r0; iy < r1; ++iy) {
-        const long base = c->yt[b].ucell[iy] * c->p;
-        for (int n = 0; n < P1; ++n)
-          c->yrel[(size_t(b) * P1 + n) * ny + iy] = int32_t(base + n - lo);
-      }
-    }
-  }
-  c->win_rows = W;
+  // windows of the tiled kernel: tiles of kTileCols columns by kTileRows rows
+  c->win_rows = build_windows(c->yt, c->ay.n, c->p, kTileRows, c->ywin, c->yrel);
+  c->win_cols = build_windows(c->xt, c->ax.n, c->p, kTileCols, c->xwin, c->xrel);
   c->host_dirty = false;
   c->dev_dirty = true;
   c->rec_dirty = true;
 }
 
-// The tiled kernel double-buffers S window rows of 64 values in LDS.
+// The tiled kernel stages window rows (up to 3 per wavefront) of
+// up to 128 columns; LDS always fits (one x-component per phase if need be).
 bool tiled_fits(const sllbm_ctx *c) {
-  const size_t lds = size_t(2) * nsets(c) * size_t(c->win_rows) * 64 * pop_size(c);
-  return lds <= kMaxTileLds;
+  return c->win_rows <= 3 * kTileRows && c->win_cols <= kMaxWindowCols;
 }
 
 int effective_path(const sllbm_ctx *c) {
@@ -214,6 +227,8 @@ int prepare_device(sllbm_ctx *c) {
     if (!rc) rc = upload_weights(c, c->yw, comp_major<double>(c->yt, c->ay.n, P1, true));
     if (!rc) rc = upload(c, c->yrel_d, c->yrel);
     if (!rc) rc = upload(c, c->ywin_d, c->ywin);
+    if (!rc) rc = upload(c, c->xrel_d, c->xrel);
+    if (!rc) rc = upload(c, c->xwin_d, c->xwin);
     if (!rc) rc = upload(c, c->mxd, c->mx);
     if (!rc) rc = upload(c, c->myd, c->my);
     if (!rc) rc = alloc_buf(c, c->flag, sizeof(int));
@@ -290,8 +305,11 @@ DevTables make_tables(const sllbm_ctx *c) {
   t.my = static_cast<const double *>(c->myd.ptr);
   t.yrel = static_cast<const int32_t *>(c->yrel_d.ptr);
   t.ywin = static_cast<const int32_t *>(c->ywin_d.ptr);
+  t.xrel = static_cast<const int32_t *>(c->xrel_d.ptr);
+  t.xwin = static_cast<const int32_t *>(c->xwin_d.ptr);
   t.tile_rows = kTileRows;
   t.win_rows = c->win_rows;
+  t.win_cols = c->win_cols;
   return t;
 }
 
@@ -352,7 +370,8 @@ void sllbm_destroy(sllbm_ctx *c) {
   if (c->dev_checked) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    DeviceBuf *bufs[] = {&c->xsrc, &c->xw, &c->ysrc, &c->yw, &c->yrel_d, &c->ywin_d, &c->mxd,
+    DeviceBuf *bufs[] = {&c->xsrc, &c->xw, &c->ysrc, &c->yw, &c->yrel_d, &c->ywin_d,
+                         &c->xrel_d, &c->xwin_d, &c->mxd,
                          &c->myd, &c->flag, &c->partial, &c->scalar, &c->macro, &c->rec_cell,
                          &c->rec_r, &c->rec_s};
     for (DeviceBuf *b : bufs) free_buf(*b);

@@ -1,5 +1,5 @@
-// HIP kernels (gfx950) of the SLLBM step: initialisation, stream + collide,
-// moments and the mass reduction.
+// HIP kernels (gfx950) around the SLLBM step: initialisation, moments, the
+// mass reduction, and the dispatch to the stream + collide kernels.
 //
 // Memory layout: populations are structure-of-arrays [S][25][ny][nx] (S = 2:
 // f then g), so a wavefront of 64 consecutive x-nodes touches 64
@@ -9,7 +9,6 @@
 
 #include "launch.hpp"
 #include "step_common.hpp"
-#include "tiled.hpp"
 
 namespace sllbm {
 
@@ -31,119 +30,6 @@ __global__ __launch_bounds__(256) void k_init_eq(const double *__restrict__ rho,
     f[i * N + v] = T(feq);
     if (Sets<MODEL>::S == 2) f[(25 + i) * N + v] = T(c.gfac * th * feq);
   });
-}
-
-// ---------------------------------------------------------------------------
-// stream + collide, direct gather through per-axis departure tables
-// ---------------------------------------------------------------------------
-template <typename T, int P, int MODEL>
-__global__ __launch_bounds__(256) void k_step_direct(const T *__restrict__ fin,
-                                                     T *__restrict__ fout,
-                                                     const int32_t *__restrict__ xsrc,
-                                                     const T *__restrict__ xw,
-                                                     const int32_t *__restrict__ ysrc,
-                                                     const T *__restrict__ yw, StepConsts c,
-                                                     int *__restrict__ flag) {
-  constexpr int S = Sets<MODEL>::S;
-  constexpr int P1 = P + 1;
-  const int ix = blockIdx.x * 64 + threadIdx.x;
-  const int iy = blockIdx.y * 4 + threadIdx.y;
-  if (ix >= c.nx || iy >= c.ny) return;
-  const long long N = c.n;
-  T fs[S][25];
-#pragma unroll
-  for (int b = 0; b < 5; ++b) {
-    int yo[P1];
-    T wy[P1];
-#pragma unroll
-    for (int n = 0; n < P1; ++n) {
-      yo[n] = ysrc[(b * P1 + n) * c.ny + iy] * c.nx;
-      wy[n] = yw[(b * P1 + n) * c.ny + iy];
-    }
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      int xo[P1];
-      T wx[P1];
-#pragma unroll
-      for (int m = 0; m < P1; ++m) {
-        xo[m] = xsrc[(a * P1 + m) * c.nx + ix];
-        wx[m] = xw[(a * P1 + m) * c.nx + ix];
-      }
-      const int i = a + 5 * b;
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const T *src = fin + (long long)(s * 25 + i) * N;
-        T acc = T(0);
-#pragma unroll
-        for (int n = 0; n < P1; ++n) {
-          T row = T(0);
-#pragma unroll
-          for (int m = 0; m < P1; ++m) row = fma(wx[m], src[yo[n] + xo[m]], row);
-          acc = fma(wy[n], row, acc);
-        }
-        fs[s][i] = acc;
-      }
-    }
-  }
-  collide_store<T, MODEL>(fs, c, fout, (long long)iy * c.nx + ix, flag);
-}
-
-// ---------------------------------------------------------------------------
-// stream + collide, general gather through per-(node, velocity) records
-// (departure cell and reference coordinates; weights evaluated here)
-// ---------------------------------------------------------------------------
-template <typename T, int P, int MODEL>
-__global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
-                                                      T *__restrict__ fout,
-                                                      const int32_t *__restrict__ cell,
-                                                      const T *__restrict__ rr,
-                                                      const T *__restrict__ ss, StepConsts c,
-                                                      int *__restrict__ flag) {
-  constexpr int S = Sets<MODEL>::S;
-  constexpr int P1 = P + 1;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= c.n) return;
-  const long long N = c.n;
-  T rn[P1], den[P1];
-#pragma unroll
-  for (int m = 0; m < P1; ++m) {
-    rn[m] = T(c.rn[m]);
-    den[m] = T(c.lden[m]);
-  }
-  T fs[S][25];
-#pragma unroll
-  for (int i = 0; i < 25; ++i) {
-    const int rec = cell[i * N + v];
-    const int cx = rec & 0xffff, cy = rec >> 16;
-    T wx[P1], wy[P1];
-    lagrange_eval<T, P1>(rr[i * N + v], rn, den, wx);
-    lagrange_eval<T, P1>(ss[i * N + v], rn, den, wy);
-    int xo[P1];
-    long long yo[P1];
-#pragma unroll
-    for (int m = 0; m < P1; ++m) {
-      int jx = cx * P + m;
-      if (jx >= c.nx) jx -= c.nx;  // periodic seam: last vertex is node 0
-      xo[m] = jx;
-      int jy = cy * P + m;
-      if (jy >= c.ny) jy -= c.ny;
-      yo[m] = (long long)jy * c.nx;
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const T *src = fin + (long long)(s * 25 + i) * N;
-      T acc = T(0);
-#pragma unroll
-      for (int n = 0; n < P1; ++n) {
-        T row = T(0);
-#pragma unroll
-        for (int m = 0; m < P1; ++m) row = fma(wx[m], src[yo[n] + xo[m]], row);
-        acc = fma(wy[n], row, acc);
-      }
-      fs[s][i] = acc;
-    }
-  }
-  collide_store<T, MODEL>(fs, c, fout, v, flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -203,41 +89,6 @@ hipError_t init_t(const StepConsts &c, const double *rho, const double *ux, cons
   return hipGetLastError();
 }
 
-template <typename T, int P, int MODEL>
-hipError_t step_tp(int path, const StepConsts &c, const DevTables &t, const void *fin, void *fout,
-                   int *flag, hipStream_t s) {
-  const T *in = static_cast<const T *>(fin);
-  T *out = static_cast<T *>(fout);
-  if (path == kPathDirect) {
-    dim3 grid((c.nx + 63) / 64, (c.ny + 3) / 4);
-    k_step_direct<T, P, MODEL><<<grid, dim3(64, 4), 0, s>>>(
-        in, out, t.xsrc, static_cast<const T *>(t.xw), t.ysrc, static_cast<const T *>(t.yw), c,
-        flag);
-    return hipGetLastError();
-  }
-  if (path == kPathRecords) {
-    const unsigned blocks = unsigned((c.n + 255) / 256);
-    k_step_records<T, P, MODEL><<<blocks, 256, 0, s>>>(
-        in, out, t.rec_cell, static_cast<const T *>(t.rec_r), static_cast<const T *>(t.rec_s), c,
-        flag);
-    return hipGetLastError();
-  }
-  if (path == kPathTiled) return launch_step_tiled<T, P, MODEL>(c, t, in, out, flag, s);
-  return hipErrorInvalidValue;
-}
-
-template <typename T, int MODEL>
-hipError_t step_t(int path, const StepConsts &c, const DevTables &t, const void *fin, void *fout,
-                  int *flag, hipStream_t s) {
-  switch (c.p) {
-    case 1: return step_tp<T, 1, MODEL>(path, c, t, fin, fout, flag, s);
-    case 2: return step_tp<T, 2, MODEL>(path, c, t, fin, fout, flag, s);
-    case 3: return step_tp<T, 3, MODEL>(path, c, t, fin, fout, flag, s);
-    case 4: return step_tp<T, 4, MODEL>(path, c, t, fin, fout, flag, s);
-  }
-  return hipErrorInvalidValue;
-}
-
 template <typename T, int MODEL>
 hipError_t moments_t(const StepConsts &c, const DevTables &t, const void *f, double *rho,
                      double *ux, double *uy, double *temp, double *partial, hipStream_t s) {
@@ -263,14 +114,12 @@ hipError_t launch_init_eq(int fp32, int model, const StepConsts &c, const double
 
 hipError_t launch_step(int fp32, int model, int path, const StepConsts &c, const DevTables &t,
                        const void *fin, void *fout, int *flag, hipStream_t s) {
-  if (fp32) {
-    if (model == kIsothermal) return step_t<float, kIsothermal>(path, c, t, fin, fout, flag, s);
-    if (model == kMonatomic) return step_t<float, kMonatomic>(path, c, t, fin, fout, flag, s);
-    return step_t<float, kPolyatomic>(path, c, t, fin, fout, flag, s);
+  switch (path) {
+    case kPathDirect: return launch_step_direct(fp32, model, c, t, fin, fout, flag, s);
+    case kPathTiled: return launch_step_tiled(fp32, model, c, t, fin, fout, flag, s);
+    case kPathRecords: return launch_step_records(fp32, model, c, t, fin, fout, flag, s);
   }
-  if (model == kIsothermal) return step_t<double, kIsothermal>(path, c, t, fin, fout, flag, s);
-  if (model == kMonatomic) return step_t<double, kMonatomic>(path, c, t, fin, fout, flag, s);
-  return step_t<double, kPolyatomic>(path, c, t, fin, fout, flag, s);
+  return hipErrorInvalidValue;
 }
 
 int mass_blocks(const StepConsts &c) { return int((c.n + 255) / 256); }

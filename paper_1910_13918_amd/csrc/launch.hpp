@@ -36,11 +36,14 @@ struct DevTables {
   const double *rnodes;     // p + 1 reference support points (records path)
   const double *mx;     // [nx] mass weights
   const double *my;     // [ny]
-  // tiled path: per-tile row windows
+  // tiled path: per-tile source windows (tiles of 64 columns by tile_rows rows)
   const int32_t *yrel;  // [5][p+1][ny]: source row relative to the tile's window
   const int32_t *ywin;  // [5][ntiles_y]: first (unwrapped) source row of the window
+  const int32_t *xrel;  // [5][p+1][nx]: source column relative to the tile's window
+  const int32_t *xwin;  // [5][ntiles_x]: first (unwrapped) source column of the window
   int tile_rows;        // target rows per tile
   int win_rows;         // source rows staged per tile (max over tiles)
+  int win_cols;         // source columns staged per tile (max over tiles)
 };
 
 enum Path { kPathDirect = 1, kPathTiled = 2, kPathRecords = 3 };
@@ -51,6 +54,12 @@ hipError_t launch_init_eq(int fp32, int model, const StepConsts &c, const double
 
 hipError_t launch_step(int fp32, int model, int path, const StepConsts &c, const DevTables &t,
                        const void *fin, void *fout, int *flag, hipStream_t s);
+hipError_t launch_step_direct(int fp32, int model, const StepConsts &c, const DevTables &t,
+                              const void *fin, void *fout, int *flag, hipStream_t s);
+hipError_t launch_step_tiled(int fp32, int model, const StepConsts &c, const DevTables &t,
+                             const void *fin, void *fout, int *flag, hipStream_t s);
+hipError_t launch_step_records(int fp32, int model, const StepConsts &c, const DevTables &t,
+                               const void *fin, void *fout, int *flag, hipStream_t s);
 
 // Moments per node (any output pointer may be null) and per-block partial
 // sums of M_v rho_v into `partial` (mass_blocks(c) entries).

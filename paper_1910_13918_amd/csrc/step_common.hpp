@@ -16,6 +16,84 @@ struct Sets {
   static constexpr int S = (MODEL == kPolyatomic) ? 2 : 1;
 };
 
+// Raw buffer loads: a 128-bit resource (base, size in bytes) in scalar
+// registers plus a 32-bit per-lane byte offset and a uniform byte offset.
+// Offsets past the size read 0 instead of faulting.
+constexpr int kBufferRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           kBufferRsrcWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                    unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                      unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buffer_store(T v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                             unsigned soff);
+
+template <>
+__device__ __forceinline__ void buffer_store<float>(float v, __amdgpu_buffer_rsrc_t r,
+                                                    unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+template <>
+__device__ __forceinline__ void buffer_store<double>(double v, __amdgpu_buffer_rsrc_t r,
+                                                     unsigned voff, unsigned soff) {
+  using u2 = __attribute__((ext_vector_type(2))) unsigned;
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+}
+
+// P1 consecutive values starting at byte offset voff + soff, with the widest
+// buffer loads (up to 16 bytes per lane per instruction).
+template <typename T, int P1>
+__device__ __forceinline__ void buffer_load_run(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                unsigned soff, T (&v)[P1]) {
+  using u4 = __attribute__((ext_vector_type(4))) unsigned;
+  using u3 = __attribute__((ext_vector_type(3))) unsigned;
+  using u2 = __attribute__((ext_vector_type(2))) unsigned;
+  constexpr int W32 = P1 * int(sizeof(T)) / 4;  // 32-bit words to read
+  unsigned w[W32];
+  int k = 0;
+#pragma unroll
+  for (; k + 4 <= W32; k += 4) {
+    const u4 q = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 4 * k, soff, 0);
+    w[k] = q[0]; w[k + 1] = q[1]; w[k + 2] = q[2]; w[k + 3] = q[3];
+  }
+  if constexpr (W32 % 4 == 3) {
+    const u3 q = __builtin_amdgcn_raw_buffer_load_b96(r, voff + 4 * k, soff, 0);
+    w[k] = q[0]; w[k + 1] = q[1]; w[k + 2] = q[2];
+  } else if constexpr (W32 % 4 == 2) {
+    const u2 q = __builtin_amdgcn_raw_buffer_load_b64(r, voff + 4 * k, soff, 0);
+    w[k] = q[0]; w[k + 1] = q[1];
+  } else if constexpr (W32 % 4 == 1) {
+    w[k] = __builtin_amdgcn_raw_buffer_load_b32(r, voff + 4 * k, soff, 0);
+  }
+#pragma unroll
+  for (int m = 0; m < P1; ++m) {
+    if constexpr (sizeof(T) == 4) {
+      v[m] = __builtin_bit_cast(T, w[m]);
+    } else {
+      const unsigned long long lo = w[2 * m], hi = w[2 * m + 1];
+      v[m] = __builtin_bit_cast(T, lo | (hi << 32));
+    }
+  }
+}
+
 // Lagrange weights l_m(r) = den_m * prod_{n != m} (r - r_n).
 template <typename T, int P1>
 __device__ __forceinline__ void lagrange_eval(T r, const T (&rn)[P1], const T (&den)[P1],
@@ -83,31 +161,25 @@ __device__ __forceinline__ void for_each_equilibrium(double rho, double ux, doub
                         ux2 * ux2 + 6.0 * ux2 * t + 3.0 * t * t};
   const double Ay[5] = {1.0, uy, uy2 + t, uy * (uy2 + 3.0 * t),
                         uy2 * uy2 + 6.0 * uy2 * t + 3.0 * t * t};
-  // partial sums over the y-order: Yc[b][j] = sum_{m <= j} A_m(u_y) He_m(xi_b)/m!
-  double Yc[5][5];
 #pragma unroll
   for (int b = 0; b < 5; ++b) {
+    // partial sums over the y-order: Yc[j] = sum_{m <= j} A_m(u_y) He_m(xi_b)/m!
+    double Yc[5];
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
       acc = fma(Ay[j], c.hk[b][j], acc);
-      Yc[b][j] = acc;
+      Yc[j] = acc;
     }
-  }
+    const double rw = rho * c.w[b];
 #pragma unroll
-  for (int a = 0; a < 5; ++a) {
-    double X[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) X[k] = Ax[k] * c.hk[a][k];
-    const double rw = rho * c.w[a];
-#pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      double s = X[0] * Yc[b][4];
-      s = fma(X[1], Yc[b][3], s);
-      s = fma(X[2], Yc[b][2], s);
-      s = fma(X[3], Yc[b][1], s);
-      s = fma(X[4], Yc[b][0], s);
-      fn(a + 5 * b, rw * c.w[b] * s);
+    for (int a = 0; a < 5; ++a) {
+      double s = (Ax[0] * c.hk[a][0]) * Yc[4];
+      s = fma(Ax[1] * c.hk[a][1], Yc[3], s);
+      s = fma(Ax[2] * c.hk[a][2], Yc[2], s);
+      s = fma(Ax[3] * c.hk[a][3], Yc[1], s);
+      s = fma(Ax[4] * c.hk[a][4], Yc[0], s);
+      fn(a + 5 * b, rw * c.w[a] * s);
     }
   }
 }
@@ -128,14 +200,27 @@ __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][25],
   const long long N = c.n;
   const double om = c.omega;
   const double gf = c.gfac * m[3];
+  // one 32-bit lane offset for every plane; the plane base lives in the
+  // (scalar) buffer resource
+  const unsigned voff = unsigned(v) * unsigned(sizeof(T));
+  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   for_each_equilibrium(m[0], m[1], m[2], m[3], c, [&](int i, double feq) {
     const double f = double(fs[0][i]);
-    fout[i * N + v] = T(fma(om, feq - f, f));
+    buffer_store<T>(T(fma(om, feq - f, f)), make_rsrc(fout + i * N, plane_bytes), voff, 0);
     if (Sets<MODEL>::S == 2) {
       const double g = double(fs[1][i]);
-      fout[(25 + i) * N + v] = T(fma(om, gf * feq - g, g));
+      buffer_store<T>(T(fma(om, gf * feq - g, g)), make_rsrc(fout + (25 + i) * N, plane_bytes),
+                      voff, 0);
     }
   });
+}
+
+// Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
+// wait for outstanding global loads, so prefetches stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Sum over a block of 256 threads (4 wavefronts of 64) in a fixed order;
@@ -152,8 +237,28 @@ __device__ __forceinline__ double block_sum_256(double v) {
   return t;
 }
 
-template <typename T, int P, int MODEL>
-hipError_t launch_step_tiled(const StepConsts &c, const DevTables &t, const T *in, T *out,
-                             int *flag, hipStream_t s);
+// Calls f.template operator()<T, P, MODEL>() for the runtime population type
+// (float / double), order p and model.
+template <class F>
+hipError_t dispatch_step(int fp32, int p, int model, F &&f) {
+  auto by_p = [&]<typename T, int MODEL>() -> hipError_t {
+    switch (p) {
+      case 1: return f.template operator()<T, 1, MODEL>();
+      case 2: return f.template operator()<T, 2, MODEL>();
+      case 3: return f.template operator()<T, 3, MODEL>();
+      case 4: return f.template operator()<T, 4, MODEL>();
+    }
+    return hipErrorInvalidValue;
+  };
+  auto by_model = [&]<typename T>() -> hipError_t {
+    switch (model) {
+      case kIsothermal: return by_p.template operator()<T, kIsothermal>();
+      case kMonatomic: return by_p.template operator()<T, kMonatomic>();
+      case kPolyatomic: return by_p.template operator()<T, kPolyatomic>();
+    }
+    return hipErrorInvalidValue;
+  };
+  return fp32 ? by_model.template operator()<float>() : by_model.template operator()<double>();
+}
 
 }  // namespace sllbm

@@ -9,7 +9,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsllbm.so")
+# SLLBM_LIBRARY may name another build of the same library (e.g. a tuning build)
+LIB_PATH = os.environ.get("SLLBM_LIBRARY") or os.path.join(_HERE, "libsllbm.so")
 
 OK = 0
 E_ARG = -1
