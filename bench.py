@@ -83,7 +83,19 @@ def main():
     ap.add_argument("--path", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-compare", action="store_true", help="also time the FP64 path")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB device-to-device three times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(256 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the stream + collide step is a single-GPU kernel "
               "(the multi-GPU domain decomposition is a design, not built)", file=sys.stderr)

@@ -8,6 +8,15 @@ module raises at import time -- there is no fallback.
 import ctypes
 import os
 
+# torch ships its own HIP runtime (same soname as ROCm's).  Loading torch
+# first makes libsllbm bind to that already-loaded runtime; loading libsllbm
+# first would pull a second HIP/HSA runtime into the process, and whichever
+# initialises second cannot open the device.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the C ABI itself does not need torch
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # SLLBM_LIBRARY may name another build of the same library (e.g. a tuning build)
 LIB_PATH = os.environ.get("SLLBM_LIBRARY") or os.path.join(_HERE, "libsllbm.so")
