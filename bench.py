@@ -49,6 +49,26 @@ def bytes_per_node_update(wl, precision, path):
     return b
 
 
+def profiled_traffic(wname, precision, path, launches):
+    """HBM bytes per launch from the committed counter profile of this workload
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when no
+    profile exists or the kernel source has changed since it was taken."""
+    import hashlib
+    tag = {"riemann2d_512x512cells_p2": "riemann512_p2"}.get(wname)
+    if tag is None or path not in ("auto", "tiled"):
+        return None
+    f = os.path.join(ROOT, "profiles", f"stream_collide_{tag}_{precision}.json")
+    if not os.path.exists(f):
+        return None
+    prof = json.load(open(f))
+    m = hashlib.sha256()
+    for src in prof["source_files"]:
+        m.update(open(os.path.join(ROOT, src), "rb").read())
+    if m.hexdigest()[:16] != prof["source_sha256_16"]:
+        return None
+    return prof["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(wl, solver_state, sample_nodes=250000, seed=0):
     """Time the FP64 oracle on a bounded sample of the same workload: one step
     at `sample_nodes` seeded nodes, from the same initial state.  Also returns
@@ -135,7 +155,8 @@ def main():
                    "order": wl.p, "precision": args.precision + ("-pop/f64-moments" if args.precision == "fp32" else ""),
                    "path": args.path, "dt": wl.dt, "nu": wl.nu, "unstable_flag": unstable},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(wname, args.precision, args.path, args.steps),
                      "bytes_per_node_update": bpn,
                      "kernel": "stream+collide (one launch per step)",
                      "avg_kernel_ms": ms / args.steps},
