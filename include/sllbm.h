@@ -194,6 +194,13 @@ int sllbm_step(sllbm_ctx *ctx, int64_t n);
 /* Interval for the flag read-back inside sllbm_step (0 = never; default 0). */
 int sllbm_set_check_interval(sllbm_ctx *ctx, int64_t k);
 
+/* sllbm_step that also records, for each of the n steps, the moments of the
+ * streamed (pre-collision) state: moments[s][0..2][ny][nx] = rho, u_x, u_y
+ * (float64, device pointer, 3 * nx * ny values per step).  These are the
+ * moments the collision Jacobian of step s depends on; the adjoint sweep
+ * replays a checkpointed segment with this call. */
+int sllbm_step_record(sllbm_ctx *ctx, int64_t n, double *moments);
+
 /* Synchronise and report the stability flag (1 = raised) and step count. */
 int sllbm_status_flags(sllbm_ctx *ctx, int *unstable, int64_t *steps_done);
 
@@ -215,6 +222,34 @@ int sllbm_mass(sllbm_ctx *ctx, double *mass);
  * stability flag cleared). */
 int sllbm_get_populations(sllbm_ctx *ctx, void *dst, int on_device);
 int sllbm_set_populations(sllbm_ctx *ctx, const void *src, int on_device);
+
+/* ---- adjoint of the step (isothermal model; SLLBM_E_UNSUPPORTED otherwise) ----
+ * The paper has no adjoint; these calls differentiate exactly the step above.
+ * One step is F' = C(S F) with S the interpolation of every population plane
+ * (Sec. II.E, eq. (17)) and C the BGK collision (Sec. II.D, eq. (16)).
+ * Reverse sweep:  mu^n = J_C(M^n)^T lambda^{n+1},  lambda^n = S^T mu^n,
+ * where M^n are the moments recorded by sllbm_step_record for step n.
+ * All arrays are device pointers on the context's device; lambda / mu arrays
+ * are [25][ny][nx] in the population type; node fields are float64 [ny][nx].
+ * Calls are asynchronous on the bound stream. */
+
+/* lambda = dL/dF of the current populations F for a loss with gradients
+ * g_rho, g_ux, g_uy with respect to the node moments rho, u_x, u_y of F. */
+int sllbm_adjoint_seed(sllbm_ctx *ctx, const double *g_rho, const double *g_ux, const double *g_uy,
+                       void *lambda);
+
+/* mu = J_C(M)^T lambda node by node; moments = [3][ny][nx] rho, u_x, u_y. */
+int sllbm_adjoint_collide(sllbm_ctx *ctx, const void *lambda, const double *moments, void *mu);
+
+/* out = S^T mu (the transposed interpolation, a gather through transposed
+ * departure tables), followed by J_C(M_prev)^T when moments_prev (the moments
+ * of the previous step, [3][ny][nx]) is not NULL.  mu and out must differ. */
+int sllbm_adjoint_step(sllbm_ctx *ctx, const void *mu, const double *moments_prev, void *out);
+
+/* Gradient through the initialisation f = f_eq(rho0, u0) (theta = 1):
+ * g_rho0 = sum_i lambda_i df_eq_i/drho0, g_u0 = sum_i lambda_i df_eq_i/du0. */
+int sllbm_eq_init_vjp(sllbm_ctx *ctx, const void *lambda0, const double *rho0, const double *ux0,
+                      const double *uy0, double *g_rho0, double *g_ux0, double *g_uy0);
 
 #ifdef __cplusplus
 }

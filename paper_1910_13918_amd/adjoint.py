@@ -1,0 +1,80 @@
+"""Gradients through an SLLBM rollout (isothermal model) for torch autograd.
+
+``rollout(rho0, ux0, uy0, solver, nsteps, every)`` initialises the solver at
+equilibrium with the given node fields, advances ``nsteps`` steps and returns
+the final node moments (rho, u_x, u_y).  Its backward pass runs the adjoint
+of every step in the library:
+
+* forward: a copy of the populations is kept every ``every`` steps;
+* backward: for each segment, newest first, the checkpoint is restored and the
+  segment replayed with ``sllbm_step_record`` (which keeps only the three
+  moments per node and step that the collision Jacobian needs), then
+  ``mu = J_C^T lambda`` and ``lambda = S^T mu`` are applied step by step, and
+  finally the gradient is carried through the initialisation f = f_eq.
+
+Memory: one population copy per checkpoint plus 3 float64 per node and step of
+one segment.  Every arithmetic step runs in the HIP kernels; this module only
+sequences the calls and owns the torch buffers.
+"""
+import torch
+
+from . import sllbm as C
+
+
+class SLLBMRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rho0, ux0, uy0, solver, nsteps, every):
+        if solver.model != "isothermal":
+            raise ValueError("the adjoint is implemented for the isothermal model")
+        dev = solver.device
+        rho0 = rho0.detach().to(device=dev, dtype=torch.float64).contiguous()
+        ux0 = ux0.detach().to(device=dev, dtype=torch.float64).contiguous()
+        uy0 = uy0.detach().to(device=dev, dtype=torch.float64).contiguous()
+        solver.init_macro(rho0, ux0, uy0, torch.ones_like(rho0))
+        checkpoints, lengths = [], []
+        done = 0
+        while done < nsteps:
+            k = min(every, nsteps - done)
+            checkpoints.append(solver.populations_device())
+            lengths.append(k)
+            solver.step(k)
+            done += k
+        final = solver.populations_device()
+        rho, ux, uy, _ = solver.moments_device()
+        ctx.save_for_backward(rho0, ux0, uy0)
+        ctx.solver = solver
+        ctx.checkpoints = checkpoints
+        ctx.lengths = lengths
+        ctx.final = final
+        return rho, ux, uy
+
+    @staticmethod
+    def backward(ctx, g_rho, g_ux, g_uy):
+        rho0, ux0, uy0 = ctx.saved_tensors
+        s = ctx.solver
+        dev = s.device
+        zeros = torch.zeros(s.n, dtype=torch.float64, device=dev)
+        g = [t.to(dtype=torch.float64).contiguous() if t is not None else zeros
+             for t in (g_rho, g_ux, g_uy)]
+        lam = torch.empty((s.q, s.n), dtype=s.dtype, device=dev)
+        mu = torch.empty_like(lam)
+        mu2 = torch.empty_like(lam)
+        s.set_populations(ctx.final)
+        C.sllbm_adjoint_seed(s.ctx, g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(),
+                             lam.data_ptr())
+        for ck, L in zip(reversed(ctx.checkpoints), reversed(ctx.lengths)):
+            s.set_populations(ck)
+            mom = s.step_record(L)
+            C.sllbm_adjoint_collide(s.ctx, lam.data_ptr(), mom[L - 1].data_ptr(), mu.data_ptr())
+            for t in range(L - 1, 0, -1):
+                C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), mom[t - 1].data_ptr(), mu2.data_ptr())
+                mu, mu2 = mu2, mu
+            C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, lam.data_ptr())
+        out = [torch.empty(s.n, dtype=torch.float64, device=dev) for _ in range(3)]
+        C.sllbm_eq_init_vjp(s.ctx, lam.data_ptr(), rho0.data_ptr(), ux0.data_ptr(),
+                            uy0.data_ptr(), *[o.data_ptr() for o in out])
+        return out[0], out[1], out[2], None, None, None
+
+
+def rollout(rho0, ux0, uy0, solver, nsteps, every=50):
+    return SLLBMRollout.apply(rho0, ux0, uy0, solver, nsteps, every)

@@ -55,6 +55,13 @@ struct sllbm_ctx {
   int win_rows = 0, win_cols = 0;
   std::vector<int32_t> ywin, yrel, xwin, xrel;
 
+  // adjoint: transposed tables, windows (built on first use)
+  bool adj_dirty = true;
+  AxisTable xtT[kQ1], ytT[kQ1];
+  int taps_T = 0, win_rowsT = 0, win_colsT = 0;
+  std::vector<int32_t> ywinT, yrelT, xwinT, xrelT;
+  DeviceBuf xsrcT, xwT, ysrcT, ywT, yrelT_d, ywinT_d, xrelT_d, xwinT_d;
+
   // device
   bool dev_checked = false;
   bool dev_dirty = true;
@@ -104,28 +111,26 @@ int ready_for_tables(sllbm_ctx *c) {
 // holds each node's stencil relative to its tile's window ([comp][m][node]).
 // Unwrapped indices keep the window contiguous across a periodic seam.
 // Returns the widest window.
-int build_windows(const AxisTable *t, int n, int p, int tile, std::vector<int32_t> &win,
+int build_windows(const AxisTable *t, int n, int tile, std::vector<int32_t> &win,
                   std::vector<int32_t> &rel) {
-  const int P1 = p + 1;
+  const int taps = t[0].taps;
   const int ntiles = (n + tile - 1) / tile;
   win.assign(size_t(kQ1) * ntiles, 0);
-  rel.assign(size_t(kQ1) * P1 * n, 0);
+  rel.assign(size_t(kQ1) * taps * n, 0);
   int width = 0;
   for (int a = 0; a < kQ1; ++a) {
     for (int k = 0; k < ntiles; ++k) {
       const int j0 = k * tile, j1 = std::min(j0 + tile, n);
       long lo = std::numeric_limits<long>::max(), hi = std::numeric_limits<long>::min();
       for (int j = j0; j < j1; ++j) {
-        const long base = t[a].ucell[j] * p;
-        lo = std::min(lo, base);
-        hi = std::max(hi, base + p);
+        lo = std::min(lo, t[a].start[j]);
+        hi = std::max(hi, t[a].start[j] + taps - 1);
       }
       win[size_t(a) * ntiles + k] = int32_t(lo);
       width = std::max<int>(width, int(hi - lo + 1));
-      for (int j = j0; j < j1; ++j) {
-        const long base = t[a].ucell[j] * p;
-        for (int m = 0; m < P1; ++m) rel[(size_t(a) * P1 + m) * n + j] = int32_t(base + m - lo);
-      }
+      for (int j = j0; j < j1; ++j)
+        for (int m = 0; m < taps; ++m)
+          rel[(size_t(a) * taps + m) * n + j] = int32_t(t[a].start[j] + m - lo);
     }
   }
   return width;
@@ -140,8 +145,8 @@ void build_host_tables(sllbm_ctx *c) {
   c->mx = c->ax.node_mass();
   c->my = c->ay.node_mass();
   // windows of the tiled kernel: tiles of kTileCols columns by kTileRows rows
-  c->win_rows = build_windows(c->yt, c->ay.n, c->p, kTileRows, c->ywin, c->yrel);
-  c->win_cols = build_windows(c->xt, c->ax.n, c->p, kTileCols, c->xwin, c->xrel);
+  c->win_rows = build_windows(c->yt, c->ay.n, kTileRows, c->ywin, c->yrel);
+  c->win_cols = build_windows(c->xt, c->ax.n, kTileCols, c->xwin, c->xrel);
   c->host_dirty = false;
   c->dev_dirty = true;
   c->rec_dirty = true;
@@ -310,6 +315,7 @@ DevTables make_tables(const sllbm_ctx *c) {
   t.tile_rows = kTileRows;
   t.win_rows = c->win_rows;
   t.win_cols = c->win_cols;
+  t.taps = c->p + 1;
   return t;
 }
 
@@ -346,6 +352,80 @@ void invalidate(sllbm_ctx *c) {
   c->host_dirty = true;
   c->dev_dirty = true;
   c->rec_dirty = true;
+  c->adj_dirty = true;
+}
+
+// Extends every node of a table to `taps` entries (zero weights).
+void pad_taps(AxisTable &t, const Axis &ax, int taps) {
+  if (t.taps == taps) return;
+  const int old = t.taps;
+  std::vector<int32_t> src(size_t(ax.n) * taps);
+  std::vector<double> w(size_t(ax.n) * taps, 0.0);
+  for (int j = 0; j < ax.n; ++j)
+    for (int q = 0; q < taps; ++q) {
+      long v = t.start[j] + q;
+      if (ax.periodic) {
+        v %= ax.n;
+        if (v < 0) v += ax.n;
+      } else {
+        v = std::min<long>(std::max<long>(v, 0), ax.n - 1);
+      }
+      src[size_t(j) * taps + q] = int32_t(v);
+      if (q < old) w[size_t(j) * taps + q] = t.w[size_t(j) * old + q];
+    }
+  t.src.swap(src);
+  t.w.swap(w);
+  t.taps = taps;
+}
+
+int prepare_adjoint(sllbm_ctx *c) {
+  int rc = prepare_device(c);
+  if (rc) return rc;
+  if (c->model != SLLBM_ISOTHERMAL)
+    return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint step is implemented for the isothermal model");
+  if (!c->adj_dirty) return SLLBM_OK;
+  int taps = 0;
+  for (int a = 0; a < kQ1; ++a) {
+    c->xtT[a] = transpose_axis_table(c->ax, c->xt[a]);
+    c->ytT[a] = transpose_axis_table(c->ay, c->yt[a]);
+    taps = std::max({taps, c->xtT[a].taps, c->ytT[a].taps});
+  }
+  if (taps > 12) return fail(c, SLLBM_E_UNSUPPORTED, "transposed stencil wider than 12 nodes");
+  for (int a = 0; a < kQ1; ++a) {
+    pad_taps(c->xtT[a], c->ax, taps);
+    pad_taps(c->ytT[a], c->ay, taps);
+  }
+  c->taps_T = taps;
+  c->win_rowsT = build_windows(c->ytT, c->ay.n, kTileRows, c->ywinT, c->yrelT);
+  c->win_colsT = build_windows(c->xtT, c->ax.n, kTileCols, c->xwinT, c->xrelT);
+  rc = upload(c, c->xsrcT, comp_major<int32_t>(c->xtT, c->ax.n, taps, false));
+  if (!rc) rc = upload_weights(c, c->xwT, comp_major<double>(c->xtT, c->ax.n, taps, true));
+  if (!rc) rc = upload(c, c->ysrcT, comp_major<int32_t>(c->ytT, c->ay.n, taps, false));
+  if (!rc) rc = upload_weights(c, c->ywT, comp_major<double>(c->ytT, c->ay.n, taps, true));
+  if (!rc) rc = upload(c, c->yrelT_d, c->yrelT);
+  if (!rc) rc = upload(c, c->ywinT_d, c->ywinT);
+  if (!rc) rc = upload(c, c->xrelT_d, c->xrelT);
+  if (!rc) rc = upload(c, c->xwinT_d, c->xwinT);
+  if (rc) return rc;
+  c->adj_dirty = false;
+  return SLLBM_OK;
+}
+
+DevTables make_adjoint_tables(const sllbm_ctx *c) {
+  DevTables t{};
+  t.xsrc = static_cast<const int32_t *>(c->xsrcT.ptr);
+  t.xw = c->xwT.ptr;
+  t.ysrc = static_cast<const int32_t *>(c->ysrcT.ptr);
+  t.yw = c->ywT.ptr;
+  t.yrel = static_cast<const int32_t *>(c->yrelT_d.ptr);
+  t.ywin = static_cast<const int32_t *>(c->ywinT_d.ptr);
+  t.xrel = static_cast<const int32_t *>(c->xrelT_d.ptr);
+  t.xwin = static_cast<const int32_t *>(c->xwinT_d.ptr);
+  t.tile_rows = kTileRows;
+  t.win_rows = c->win_rowsT;
+  t.win_cols = c->win_colsT;
+  t.taps = c->taps_T;
+  return t;
 }
 
 }  // namespace
@@ -371,7 +451,8 @@ void sllbm_destroy(sllbm_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     DeviceBuf *bufs[] = {&c->xsrc, &c->xw, &c->ysrc, &c->yw, &c->yrel_d, &c->ywin_d,
-                         &c->xrel_d, &c->xwin_d, &c->mxd,
+                         &c->xrel_d, &c->xwin_d, &c->xsrcT, &c->xwT, &c->ysrcT, &c->ywT,
+                         &c->yrelT_d, &c->ywinT_d, &c->xrelT_d, &c->xwinT_d, &c->mxd,
                          &c->myd, &c->flag, &c->partial, &c->scalar, &c->macro, &c->rec_cell,
                          &c->rec_r, &c->rec_s};
     for (DeviceBuf *b : bufs) free_buf(*b);
@@ -647,7 +728,7 @@ static int read_flag(sllbm_ctx *c, int *flag) {
   return SLLBM_OK;
 }
 
-int sllbm_step(sllbm_ctx *c, int64_t n) {
+static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   if (!c) return SLLBM_E_ARG;
   if (n < 0) return fail(c, SLLBM_E_ARG, "n must be >= 0");
   if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
@@ -656,10 +737,11 @@ int sllbm_step(sllbm_ctx *c, int64_t n) {
   const int path = effective_path(c);
   if (path == kPathTiled && !tiled_fits(c))
     return fail(c, SLLBM_E_UNSUPPORTED, "departures span too many rows for the tiled kernel");
-  const StepConsts k = make_consts(c);
+  StepConsts k = make_consts(c);
   const DevTables t = make_tables(c);
   int *flag = static_cast<int *>(c->flag.ptr);
   for (int64_t s = 0; s < n; ++s) {
+    k.mom_out = moments ? moments + s * 3 * k.n : nullptr;
     HIP_TRY(c, launch_step(c->fp32, c->model, path, k, t, c->pop[c->cur], c->pop[1 - c->cur],
                            flag, c->stream));
     c->cur ^= 1;
@@ -671,6 +753,60 @@ int sllbm_step(sllbm_ctx *c, int64_t n) {
       if (f) return fail(c, SLLBM_E_UNSTABLE, "stability flag raised (rho, theta or moments)");
     }
   }
+  return SLLBM_OK;
+}
+
+int sllbm_step(sllbm_ctx *c, int64_t n) { return run_steps(c, n, nullptr); }
+
+int sllbm_step_record(sllbm_ctx *c, int64_t n, double *moments) {
+  if (!c) return SLLBM_E_ARG;
+  if (!moments) return fail(c, SLLBM_E_ARG, "null moments buffer");
+  return run_steps(c, n, moments);
+}
+
+int sllbm_adjoint_seed(sllbm_ctx *c, const double *g_rho, const double *g_ux, const double *g_uy,
+                       void *lam) {
+  if (!c) return SLLBM_E_ARG;
+  if (!g_rho || !g_ux || !g_uy || !lam) return fail(c, SLLBM_E_ARG, "null device pointer");
+  if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
+  int rc = prepare_adjoint(c);
+  if (rc) return rc;
+  HIP_TRY(c, launch_adjoint_seed(c->fp32, make_consts(c), c->pop[c->cur], g_rho, g_ux, g_uy, lam,
+                                 c->stream));
+  return SLLBM_OK;
+}
+
+int sllbm_adjoint_collide(sllbm_ctx *c, const void *lam, const double *moments, void *mu) {
+  if (!c) return SLLBM_E_ARG;
+  if (!lam || !moments || !mu) return fail(c, SLLBM_E_ARG, "null device pointer");
+  int rc = prepare_adjoint(c);
+  if (rc) return rc;
+  HIP_TRY(c, launch_adjoint_collide(c->fp32, make_consts(c), lam, moments, mu, c->stream));
+  return SLLBM_OK;
+}
+
+int sllbm_adjoint_step(sllbm_ctx *c, const void *mu, const double *moments_prev, void *out) {
+  if (!c) return SLLBM_E_ARG;
+  if (!mu || !out) return fail(c, SLLBM_E_ARG, "null device pointer");
+  if (mu == out) return fail(c, SLLBM_E_ARG, "input and output must differ");
+  int rc = prepare_adjoint(c);
+  if (rc) return rc;
+  const bool tiled = c->path != SLLBM_PATH_DIRECT && c->win_rowsT <= 3 * kTileRows &&
+                     c->win_colsT <= kMaxWindowCols;
+  HIP_TRY(c, launch_adjoint_step(c->fp32, tiled, make_consts(c), make_adjoint_tables(c), mu,
+                                 moments_prev, out, c->stream));
+  return SLLBM_OK;
+}
+
+int sllbm_eq_init_vjp(sllbm_ctx *c, const void *lam0, const double *rho0, const double *ux0,
+                      const double *uy0, double *g_rho0, double *g_ux0, double *g_uy0) {
+  if (!c) return SLLBM_E_ARG;
+  if (!lam0 || !rho0 || !ux0 || !uy0 || !g_rho0 || !g_ux0 || !g_uy0)
+    return fail(c, SLLBM_E_ARG, "null device pointer");
+  int rc = prepare_adjoint(c);
+  if (rc) return rc;
+  HIP_TRY(c, launch_eq_init_vjp(c->fp32, make_consts(c), lam0, rho0, ux0, uy0, g_rho0, g_ux0,
+                                g_uy0, c->stream));
   return SLLBM_OK;
 }
 

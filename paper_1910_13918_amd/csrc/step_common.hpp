@@ -194,6 +194,11 @@ __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][25],
                                               long long v, int *__restrict__ flag) {
   double m[4];
   node_moments<T, MODEL>(fs, c, m);
+  if (c.mom_out) {  // recorded for the adjoint (uniform branch)
+    c.mom_out[v] = m[0];
+    c.mom_out[c.n + v] = m[1];
+    c.mom_out[2 * c.n + v] = m[2];
+  }
   const bool ok = (m[0] > 0.0) && (m[3] > 0.0) && isfinite(m[0]) && isfinite(m[1]) &&
                   isfinite(m[2]) && isfinite(m[3]);
   if (!ok) atomicOr(flag, 1);

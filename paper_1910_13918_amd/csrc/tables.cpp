@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
+#include <utility>
 
 namespace sllbm {
 
@@ -174,11 +176,12 @@ std::vector<double> Axis::node_mass() const {
 AxisTable build_axis_table(const Axis &ax, double disp) {
   AxisTable t;
   const int P1 = ax.p + 1;
+  t.taps = P1;
   t.src.resize(size_t(ax.n) * P1);
   t.w.resize(size_t(ax.n) * P1);
   t.cell.resize(ax.n);
   t.rref.resize(ax.n);
-  t.ucell.resize(ax.n);
+  t.start.resize(ax.n);
   double lw[kMaxOrder + 1];
   for (int j = 0; j < ax.n; ++j) {
     int c;
@@ -187,12 +190,57 @@ AxisTable build_axis_table(const Axis &ax, double disp) {
     ax.departure(j, disp, c, rr, &uc);
     lagrange_weights(ax.r, rr, lw);
     t.cell[j] = c;
-    t.ucell[j] = uc;
+    t.start[j] = uc * ax.p;
     t.rref[j] = rr;
     for (int m = 0; m < P1; ++m) {
       t.src[size_t(j) * P1 + m] = ax.node(c, m);
       t.w[size_t(j) * P1 + m] = lw[m];
     }
+  }
+  return t;
+}
+
+AxisTable transpose_axis_table(const Axis &ax, const AxisTable &fwd) {
+  const int n = ax.n, P1 = fwd.taps;
+  // (virtual target, weight) pairs per source node
+  std::vector<std::vector<std::pair<long, double>>> in(n);
+  for (int v = 0; v < n; ++v)
+    for (int m = 0; m < P1; ++m) {
+      const long su = fwd.start[v] + m;  // unwrapped source index
+      long j = su % n;
+      if (j < 0) j += n;
+      const long k = (su - j) / n;       // periodic image of the source
+      in[j].push_back({long(v) - k * n, fwd.w[size_t(v) * P1 + m]});
+    }
+  AxisTable t;
+  int taps = 1;
+  std::vector<long> lo(n, 0);
+  for (int j = 0; j < n; ++j) {
+    long a = std::numeric_limits<long>::max(), b = std::numeric_limits<long>::min();
+    for (const auto &e : in[j]) {
+      a = std::min(a, e.first);
+      b = std::max(b, e.first);
+    }
+    if (in[j].empty()) a = b = j;
+    lo[j] = a;
+    taps = std::max<int>(taps, int(b - a + 1));
+  }
+  t.taps = taps;
+  t.start = lo;
+  t.src.assign(size_t(n) * taps, 0);
+  t.w.assign(size_t(n) * taps, 0.0);
+  for (int j = 0; j < n; ++j) {
+    for (int q = 0; q < taps; ++q) {
+      long v = lo[j] + q;
+      if (ax.periodic) {
+        v %= n;
+        if (v < 0) v += n;
+      } else {
+        v = std::min<long>(std::max<long>(v, 0), n - 1);
+      }
+      t.src[size_t(j) * taps + q] = int32_t(v);
+    }
+    for (const auto &e : in[j]) t.w[size_t(j) * taps + (e.first - lo[j])] += e.second;
   }
   return t;
 }

@@ -63,16 +63,26 @@ struct Axis {
   std::vector<double> node_mass() const;
 };
 
-// Per-axis departure table for one 1-D velocity: src[j * (p+1) + m],
-// w[j * (p+1) + m].
+// Per-axis gather table for one 1-D velocity: node j combines `taps`
+// consecutive nodes starting at the unwrapped index start[j]:
+// value(j) = sum_t w[j * taps + t] * f[src[j * taps + t]], with src the
+// start + t wrapped onto the axis.  For the forward step the taps are the
+// p+1 nodes of the departure cell; for the transposed step (adjoint) they are
+// the targets whose departure stencil contains j.
 struct AxisTable {
+  int taps = 0;
   std::vector<int32_t> src;
   std::vector<double> w;
-  std::vector<int32_t> cell;   // departure cell per node
-  std::vector<double> rref;    // reference coordinate per node
-  std::vector<long> ucell;     // departure cell before the periodic wrap
+  std::vector<long> start;     // unwrapped first tap (contiguous across a periodic seam)
+  std::vector<int32_t> cell;   // forward only: departure cell per node
+  std::vector<double> rref;    // forward only: reference coordinate per node
 };
 
 AxisTable build_axis_table(const Axis &ax, double disp);
+
+// Transpose of a forward table: entry (j, t) holds the weight with which
+// node j's value enters target start[j] + t.  Targets of one source node are
+// consecutive because departures are monotone along the axis.
+AxisTable transpose_axis_table(const Axis &ax, const AxisTable &fwd);
 
 }  // namespace sllbm

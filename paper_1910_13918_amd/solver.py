@@ -120,6 +120,12 @@ class Solver:
             raise ValueError("population array size does not match the grid")
         C.sllbm_set_populations(self.ctx, _ptr(a), 0)
 
+    def populations_device(self):
+        """Copy of the current populations as a device tensor [S, Q, n]."""
+        t = torch.empty(self.nsets * self.q * self.n, dtype=self.dtype, device=self.device)
+        C.sllbm_get_populations(self.ctx, t.data_ptr(), 1)
+        return t.view(self.nsets, self.q, self.n)
+
     def populations(self):
         a = np.empty(self.nsets * self.q * self.n,
                      dtype=np.float32 if self.precision == "fp32" else np.float64)
@@ -129,6 +135,13 @@ class Solver:
     # ---- stepping and outputs ----------------------------------------------------
     def step(self, n=1):
         C.sllbm_step(self.ctx, n)
+
+    def step_record(self, n):
+        """Advance n steps and return the moments (rho, u_x, u_y) of each step's
+        streamed state as a device tensor [n, 3, nodes] (float64)."""
+        m = torch.empty((n, 3, self.n), dtype=torch.float64, device=self.device)
+        C.sllbm_step_record(self.ctx, n, m.data_ptr())
+        return m
 
     def flags(self):
         return C.sllbm_status_flags(self.ctx)

@@ -1,0 +1,190 @@
+"""GPU tests of the adjoint step and the checkpointed rollout gradient.
+
+* transposed streaming: <mu, S v> = <S^T mu, v> (dot-product test, FP64);
+* one full step: <S^T J_C^T lam, v> against central differences of
+  <lam, step(F + eps v)> (FP64);
+* rollout gradient (checkpointed) against the oracle's complex-step
+  derivative (exact to rounding) on a reduced Taylor-Green instance;
+* FP32 rollout gradient against the FP64 one;
+* the 128 x 128-cell, p = 4 adjoint workload against central differences on
+  the FP64 path.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.adjoint import complex_step_directional, kinetic_misfit_loss
+from oracle.grid import Grid
+from oracle.sllbm import Sim
+from paper_1910_13918_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a HIP device")]
+
+
+def _solver(wl, precision="fp64", path="auto"):
+    from paper_1910_13918_amd.solver import Solver
+    return Solver.from_workload(wl, precision=precision, path=path)
+
+
+def _rand(shape, seed, dtype=torch.float64):
+    g = torch.Generator().manual_seed(seed)
+    return torch.randn(shape, generator=g, dtype=torch.float64).to(dtype=dtype, device="cuda")
+
+
+GRIDS = [
+    ("tgv_per", lambda: W.tgv(9, 4, U0=0.3)),
+    ("tgv_p2", lambda: W.tgv(37, 2, U0=0.3)),
+    ("zero_gradient", lambda: _iso(W.riemann(23, 3, states=W.RIEMANN_TABLE3_STATES))),
+    ("stretched", lambda: _iso(W.svi(40, 6, 3))),
+]
+
+
+def _iso(wl):
+    wl.model = "isothermal"
+    return wl
+
+
+@pytest.mark.parametrize("path", ["tiled", "direct"])
+@pytest.mark.parametrize("name,make", GRIDS, ids=[g[0] for g in GRIDS])
+def test_transposed_streaming_dot_product(name, make, path):
+    from paper_1910_13918_amd import sllbm as C
+    wl = make()
+    wl.nu = np.inf  # 1/tau = 0: the step is the interpolation alone
+    s = _solver(wl, "fp64", path)
+    try:
+        print(f"[gpu] adjoint dot product {name} {path} nodes={s.n}", flush=True)
+        v = _rand((25, s.n), 1)
+        mu = _rand((25, s.n), 2)
+        s.set_populations(v)
+        s.step(1)
+        Sv = s.populations_device()[0]
+        StMu = torch.empty_like(mu)
+        C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, StMu.data_ptr())
+        torch.cuda.synchronize()
+        lhs = float((mu * Sv).sum())
+        rhs = float((StMu * v).sum())
+        assert lhs == pytest.approx(rhs, rel=1e-12)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("name,make", GRIDS[:3], ids=[g[0] for g in GRIDS[:3]])
+def test_one_step_adjoint_against_central_differences(name, make):
+    from paper_1910_13918_amd import sllbm as C
+    wl = make()
+    s = _solver(wl, "fp64")
+    try:
+        s.init_from_workload()
+        s.step(3)
+        F = s.populations_device()[0].clone()
+        lam = _rand((25, s.n), 3)
+        v = _rand((25, s.n), 4) * F.abs().mean()
+        # adjoint: S^T J_C(M)^T lam with M of this step
+        s.set_populations(F)
+        mom = s.step_record(1)
+        mu = torch.empty_like(lam)
+        out = torch.empty_like(lam)
+        C.sllbm_adjoint_collide(s.ctx, lam.data_ptr(), mom[0].data_ptr(), mu.data_ptr())
+        C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, out.data_ptr())
+        torch.cuda.synchronize()
+        adj = float((out * v).sum())
+        eps = 1e-6
+
+        def g(e):
+            s.set_populations(F + e * v)
+            s.step(1)
+            return float((lam * s.populations_device()[0]).sum())
+
+        fd = (g(eps) - g(-eps)) / (2 * eps)
+        assert adj == pytest.approx(fd, rel=1e-6)
+    finally:
+        s.close()
+
+
+def _loss_torch(rho, ux, uy, M, ut, vt):
+    return 0.5 * (M * rho * (ux * ux + uy * uy)).sum() + (M * ((ux - ut) ** 2 + (uy - vt) ** 2)).sum()
+
+
+def _mass_weights(s):
+    from paper_1910_13918_amd import sllbm as C
+    mx = np.zeros(s.nx)
+    my = np.zeros(s.ny)
+    C.sllbm_mass_weights(s.ctx, mx.ctypes.data, my.ctypes.data)
+    return torch.tensor(np.outer(my, mx).reshape(-1), device="cuda")
+
+
+def _rollout_grad(wl, precision, nsteps, every, seed_target=1234):
+    from paper_1910_13918_amd.adjoint import rollout
+    s = _solver(wl, precision)
+    X, Y = s.coords()
+    rho0, ux0, uy0, _ = wl.fields(X, Y)
+    ut, vt = W.fourier_target(X, Y, wl.meta["U0"], seed=seed_target)
+    t = lambda a: torch.tensor(a, device="cuda")
+    u0 = t(ux0).requires_grad_(True)
+    v0 = t(uy0).requires_grad_(True)
+    r0 = t(rho0).requires_grad_(True)
+    rho, ux, uy = rollout(r0, u0, v0, s, nsteps, every)
+    L = _loss_torch(rho, ux, uy, _mass_weights(s), t(ut), t(vt))
+    L.backward()
+    out = (float(L), u0.grad.detach().cpu().numpy(), v0.grad.detach().cpu().numpy(),
+           r0.grad.detach().cpu().numpy(), s)
+    return out
+
+
+def test_rollout_gradient_matches_complex_step():
+    """8 x 8 cells p = 4, 20 steps, checkpoints every 7 steps (uneven last
+    segment): directional derivatives of the GPU gradient against the oracle's
+    complex-step derivative."""
+    wl = W.tgv(8, 4, U0=0.3, steps=20)
+    L, gu, gv, gr, s = _rollout_grad(wl, "fp64", 20, 7)
+    s.close()
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, True, True)
+    sim = Sim(g, wl.dt, wl.nu, wl.model)
+    X, Y = g.coords()
+    rho0, ux0, uy0, T0 = wl.fields(X, Y)
+    ut, vt = W.fourier_target(X, Y, 0.3)
+    loss = lambda sm, F: kinetic_misfit_loss(sm, F, ut, vt)
+    for d in W.random_directions(g.nnodes, 3, seed=4321):
+        ref = complex_step_directional(sim, rho0, ux0, uy0, T0, d[0], d[1], 20, loss)
+        got = float(np.dot(gu, d[0]) + np.dot(gv, d[1]))
+        assert got == pytest.approx(ref, rel=1e-9, abs=1e-14)
+
+
+def test_fp32_rollout_gradient_close_to_fp64():
+    wl = W.tgv(16, 4, U0=0.3, steps=60)
+    _, gu64, gv64, _, s = _rollout_grad(wl, "fp64", 60, 25)
+    s.close()
+    _, gu32, gv32, _, s = _rollout_grad(wl, "fp32", 60, 25)
+    s.close()
+    g64 = np.concatenate([gu64, gv64])
+    g32 = np.concatenate([gu32, gv32])
+    assert np.linalg.norm(g32 - g64) <= 1e-3 * np.linalg.norm(g64)
+
+
+def test_adjoint_workload_against_central_differences():
+    """The 128 x 128-cell, p = 4 Taylor-Green adjoint workload (500 steps,
+    checkpoints every 50), FP64 path: the gradient's directional derivatives
+    against central differences with eps = 1e-4 along 4 seeded directions."""
+    from paper_1910_13918_amd.solver import Solver
+    wl = W.adjoint_tgv()
+    L, gu, gv, _, s = _rollout_grad(wl, "fp64", wl.steps, 50)
+    M = _mass_weights(s)
+    X, Y = s.coords()
+    rho0, ux0, uy0, _ = wl.fields(X, Y)
+    ut, vt = (torch.tensor(a, device="cuda") for a in W.fourier_target(X, Y, 0.3))
+
+    def loss(dx, dy, e):
+        s.init_macro(rho0, ux0 + e * dx, uy0 + e * dy, np.ones_like(rho0))
+        s.step(wl.steps)
+        rho, ux, uy, _ = s.moments_device()
+        return float(_loss_torch(rho, ux, uy, M, ut, vt))
+
+    try:
+        for d in W.random_directions(s.n, 4, seed=4321):
+            fd = (loss(d[0], d[1], 1e-4) - loss(d[0], d[1], -1e-4)) / 2e-4
+            got = float(np.dot(gu, d[0]) + np.dot(gv, d[1]))
+            assert got == pytest.approx(fd, rel=1e-5)
+    finally:
+        s.close()
+    assert isinstance(Solver, type)
