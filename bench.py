@@ -69,6 +69,47 @@ def profiled_traffic(wname, precision, path, launches):
     return prof["traffic_bytes_per_launch"]
 
 
+def adjoint_cost(precision="fp32", every=50, reps=3):
+    """Forward and backward time of the checkpointed rollout on the adjoint
+    workload (Taylor-Green, 128 x 128 cells, p = 4, 500 steps, loss = kinetic
+    energy + misfit to a seeded target): backward includes the recomputation."""
+    import numpy as np
+    import torch
+
+    from paper_1910_13918_amd import sllbm as C
+    from paper_1910_13918_amd import workloads as W
+    from paper_1910_13918_amd.adjoint import rollout
+    from paper_1910_13918_amd.solver import Solver
+    wl = W.adjoint_tgv()
+    s = Solver.from_workload(wl, precision=precision)
+    X, Y = s.coords()
+    rho0, ux0, uy0, _ = wl.fields(X, Y)
+    ut, vt = W.fourier_target(X, Y, wl.meta["U0"])
+    mx, my = np.zeros(s.nx), np.zeros(s.ny)
+    C.sllbm_mass_weights(s.ctx, mx.ctypes.data, my.ctypes.data)
+    t = lambda a: torch.tensor(a, device="cuda")
+    M, ut, vt = t(np.outer(my, mx).reshape(-1)), t(ut), t(vt)
+    fwd, bwd = [], []
+    for _ in range(reps + 1):
+        u0 = t(ux0).requires_grad_(True)
+        v0 = t(uy0).requires_grad_(True)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        rho, ux, uy = rollout(t(rho0), u0, v0, s, wl.steps, every)
+        e1.record()
+        L = 0.5 * (M * rho * (ux * ux + uy * uy)).sum() + (M * ((ux - ut) ** 2 + (uy - vt) ** 2)).sum()
+        L.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        fwd.append(e0.elapsed_time(e1))
+        bwd.append(e1.elapsed_time(e2))
+    s.close()
+    f, b = min(fwd[1:]), min(bwd[1:])
+    return {"workload": "tgv_128x128cells_p4_500steps", "precision": precision,
+            "checkpoint_every": every, "forward_ms": f, "backward_ms": b, "ratio": b / f}
+
+
 def cpu_baseline(wl, solver_state, sample_nodes=250000, seed=0):
     """Time the FP64 oracle on a bounded sample of the same workload: one step
     at `sample_nodes` seeded nodes, from the same initial state.  Also returns
@@ -102,6 +143,7 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--path", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost ratio")
     ap.add_argument("--fp64-compare", action="store_true", help="also time the FP64 path")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device-to-device three times (calibrates the "
@@ -165,6 +207,8 @@ def main():
         s64, ms64, _ = timed("fp64", args.path)
         out["fp64"] = {"value": s64.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps}
         s64.close()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_cost()
     if not args.no_cpu_baseline:
         # same initial state, one GPU step, compared with the oracle at the sample
         s1 = Solver.from_workload(wl, precision=args.precision, path=args.path)

@@ -127,7 +127,9 @@ def sod(ncx=1024, ncy=4, p=3, t_end=0.2, nu=1.2e-4, gamma=1.4, cfl=0.5, name=Non
 
 
 # ------------------------------------------------------------------------- Riemann
-RIEMANN_DEFAULT_SEED = 0
+# First seed >= 0 whose states survive to t = 0.25 on 64 x 64 cells of order 2
+# with the FP64 oracle (search and log: tests/golden/make_riemann_seed.py).
+RIEMANN_DEFAULT_SEED = 14
 
 # Quadrant states (NE, NW, SW, SE) of the Lax-Liu configuration printed in
 # Table III (Sec. III.D): (rho, u_x, u_y, P).

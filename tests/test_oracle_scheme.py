@@ -246,3 +246,16 @@ def test_stability_criterion():
     F3 = F.copy()
     F3[1] *= -1.0  # negative internal energy -> theta <= 0
     assert sim.unstable(F3)
+
+
+def test_riemann_default_seed_is_the_accepted_one():
+    """The stored seed search (written by tests/golden/make_riemann_seed.py from
+    the oracle alone) names the default seed of the seeded Riemann workload,
+    every earlier seed is logged as unstable, and the stored states are the
+    generator's."""
+    rec = json.load(open(os.path.join(GOLDEN, "riemann_seed.json")))
+    assert rec["seed"] == W.RIEMANN_DEFAULT_SEED
+    assert [t["seed"] for t in rec["tried"]] == list(range(rec["seed"] + 1))
+    assert all(not t["stable"] for t in rec["tried"][:-1]) and rec["tried"][-1]["stable"]
+    np.testing.assert_array_equal(np.array(rec["states"]), np.array(W.riemann_states(rec["seed"])))
+    assert W.riemann(64, 2).meta["states"] == [tuple(map(float, s)) for s in rec["states"]]
