@@ -1,14 +1,19 @@
 """Benchmark of the SLLBM stream + collide step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload riemann|svi|sod|tgv|adjoint_tgv]
-                    [--precision fp32|fp64] [--path auto|direct|tiled|records] [--no-cpu-baseline]
+                    [--precision fp32|fp64] [--path auto|direct|tiled|records]
+                    [--no-fp64] [--no-svi] [--no-adjoint] [--no-cpu-baseline]
 
 One "step" is one time step of the whole hot path over the grid: departure
 gather with Lagrange interpolation, moments, temperature, 4th-order
 equilibrium, BGK relaxation and store (one fused kernel launch), with inputs
 resident in HBM.  Default workload: the four-quadrant Riemann problem on
 512 x 512 cells of order 2 (1025^2 nodes, f and g populations, float32
-populations with float64 moments).  Prints one JSON line.
+populations with float64 moments).  Prints one JSON line; besides the headline
+it carries the FP64 run of the same workload and the FP32-FP64 difference of
+the moments after the timed steps, the stretched shock-vortex grid with
+departure records and with per-axis tables, the adjoint/forward cost ratio of
+the checkpointed Taylor-Green rollout, and the FP64 oracle timed on a sample.
 """
 import argparse
 import json
@@ -67,6 +72,44 @@ def profiled_traffic(wname, precision, path, launches):
     if m.hexdigest()[:16] != prof["source_sha256_16"]:
         return None
     return prof["traffic_bytes_per_launch"]
+
+
+def timed(wl, precision, path, steps, warmup):
+    """Initialise the workload, run `warmup` steps, then time `steps` steps with
+    HIP events on the solver's stream.  Returns (solver, ms, unstable flag)."""
+    import torch
+
+    from paper_1910_13918_amd.solver import Solver
+    s = Solver.from_workload(wl, precision=precision, path=path)
+    s.init_from_workload()
+    s.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    s.step(steps)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    unstable, _ = s.flags()
+    return s, ev0.elapsed_time(ev1), unstable
+
+
+def shock_vortex_entry(precision, steps=20, warmup=3):
+    """Throughput on the stretched shock-vortex grid (1024 x 512 cells, p = 3,
+    3073 x 1536 nodes, f + g) with per-(node, velocity) departure records and
+    with the per-axis tables the separable map allows."""
+    wl, wname = workload("svi")
+    out = {"workload": wname, "steps": steps, "warmup": warmup}
+    for label, path in (("records", "records"), ("axis_tables", "auto")):
+        s, ms, unstable = timed(wl, precision, path, steps, warmup)
+        nu_s = s.n * steps / (ms * 1e-3)
+        bpn = bytes_per_node_update(wl, precision, s.resolved_path())
+        out[label] = {"path": s.resolved_path(), "value": nu_s, "unit": "node-updates/s",
+                      "ms_per_step": ms / steps, "bytes_per_node_update": bpn,
+                      "achieved_gbs": nu_s * bpn / 1e9, "frac": nu_s * bpn / 1e9 / HBM_PEAK_GBS,
+                      "unstable_flag": unstable}
+        s.close()
+    return out
 
 
 def adjoint_cost(precision="fp32", every=50, reps=3):
@@ -144,7 +187,11 @@ def main():
     ap.add_argument("--path", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost ratio")
-    ap.add_argument("--fp64-compare", action="store_true", help="also time the FP64 path")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-svi", action="store_true",
+                    help="skip the shock-vortex (stretched 1024 x 512 cells, p = 3) lines")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only time the checkpointed adjoint rollout (prints its JSON object)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device-to-device three times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -158,35 +205,21 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}))
         return
+    if args.adjoint_only:
+        print(json.dumps(adjoint_cost(args.precision)))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the stream + collide step is a single-GPU kernel "
               "(the multi-GPU domain decomposition is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     from paper_1910_13918_amd.solver import Solver
     wl, wname = workload(args.workload)
-
-    def timed(precision, path):
-        s = Solver.from_workload(wl, precision=precision, path=path)
-        s.init_from_workload()
-        s.step(args.warmup)
-        torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(s.stream)
-        s.step(args.steps)
-        ev1.record(s.stream)
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1)
-        unstable, _ = s.flags()
-        return s, ms, unstable
-
-    s, ms, unstable = timed(args.precision, args.path)
+    s, ms, unstable = timed(wl, args.precision, args.path, args.steps, args.warmup)
     nu_s = s.n * args.steps / (ms * 1e-3)
-    bpn = bytes_per_node_update(wl, args.precision, args.path)
+    bpn = bytes_per_node_update(wl, args.precision, s.resolved_path())
     achieved = nu_s * bpn / 1e9
     out = {
         "metric": METRIC, "value": nu_s, "unit": "node-updates/s", "n_gpus": 1,
@@ -195,7 +228,8 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": wname, "nodes": s.n, "populations": wl.nsets * 25,
                    "order": wl.p, "precision": args.precision + ("-pop/f64-moments" if args.precision == "fp32" else ""),
-                   "path": args.path, "dt": wl.dt, "nu": wl.nu, "unstable_flag": unstable},
+                   "path": args.path, "path_resolved": s.resolved_path(), "dt": wl.dt,
+                   "nu": wl.nu, "seed": wl.meta.get("seed"), "unstable_flag": unstable},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": profiled_traffic(wname, args.precision, args.path, args.steps),
@@ -203,10 +237,20 @@ def main():
                      "kernel": "stream+collide (one launch per step)",
                      "avg_kernel_ms": ms / args.steps},
     }
-    if args.fp64_compare and args.precision != "fp64":
-        s64, ms64, _ = timed("fp64", args.path)
-        out["fp64"] = {"value": s64.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps}
+    if not args.no_fp64 and args.precision != "fp64":
+        s64, ms64, _ = timed(wl, "fp64", args.path, args.steps, args.warmup)
+        m32, m64 = s.moments(), s64.moments()
+        out["fp64"] = {"value": s64.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps,
+                       "bytes_per_node_update": bytes_per_node_update(wl, "fp64", s64.resolved_path()),
+                       "fp32_vs_fp64_after_steps": {
+                           "steps": args.warmup + args.steps,
+                           "rho_max_rel": float(np.abs(m32[0] - m64[0]).max() / np.abs(m64[0]).max()),
+                           "u_max_abs": float(max(np.abs(m32[1] - m64[1]).max(),
+                                                  np.abs(m32[2] - m64[2]).max())),
+                           "theta_max_rel": float(np.abs(m32[3] - m64[3]).max() / np.abs(m64[3]).max())}}
         s64.close()
+    if not args.no_svi and args.workload == "riemann":
+        out["shock_vortex"] = shock_vortex_entry(args.precision)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_cost()
     if not args.no_cpu_baseline:

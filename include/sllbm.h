@@ -80,10 +80,12 @@ typedef enum {
 } sllbm_model;
 
 typedef enum {
-  SLLBM_PATH_AUTO = 0,    /* library choice: TILED */
+  SLLBM_PATH_AUTO = 0,    /* library choice: TILED when the departure windows
+                             fit it, else DIRECT (sllbm_resolved_path) */
   SLLBM_PATH_DIRECT = 1,  /* one thread per node, (p+1)^2 gathers per velocity
                              through per-axis departure tables */
-  SLLBM_PATH_TILED = 2,   /* separable x-then-y interpolation staged through LDS */
+  SLLBM_PATH_TILED = 2,   /* raw source windows of each velocity staged in LDS
+                             per tile of 64 x 4 nodes, interpolated from LDS */
   SLLBM_PATH_RECORDS = 3  /* per-(node, velocity) departure records (cell, r, s)
                              with weights evaluated in the kernel: the general
                              gather for grids that are not axis products */
@@ -132,7 +134,7 @@ int sllbm_init_grid_uniform(sllbm_ctx *ctx, int ncx, int ncy, double x0, double 
 int sllbm_init_grid_mapped(sllbm_ctx *ctx, int ncx, int ncy, const double *edges_x,
                            const double *edges_y, int bcx, int bcy);
 
-/* Time step dt > 0, kinematic viscosity nu >= 0 (nu = +inf: no collision,
+/* Time step dt > 0, kinematic viscosity nu > 0 (nu = +inf: no collision,
  * pure streaming), heat-capacity ratio gamma > 1 (used by SLLBM_POLYATOMIC
  * only), Prandtl number (only 1 is supported), model (sllbm_model). */
 int sllbm_set_physics(sllbm_ctx *ctx, double dt, double nu, double gamma, double Pr, int model);
@@ -141,6 +143,10 @@ int sllbm_set_physics(sllbm_ctx *ctx, double dt, double nu, double gamma, double
  * that stay within a bounded row window (checked; SLLBM_E_UNSUPPORTED
  * otherwise). */
 int sllbm_set_path(sllbm_ctx *ctx, int path);
+
+/* The kernel family the next step runs (sllbm_path, never AUTO), after grid,
+ * order and physics are set.  Host only. */
+int sllbm_resolved_path(const sllbm_ctx *ctx, int *path);
 
 /* ---- queries (host only, after init_grid; tables after set_physics) -------- */
 

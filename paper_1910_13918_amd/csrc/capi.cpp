@@ -597,6 +597,16 @@ int sllbm_set_path(sllbm_ctx *c, int path) {
   return SLLBM_OK;
 }
 
+int sllbm_resolved_path(const sllbm_ctx *cc, int *path) {
+  sllbm_ctx *c = const_cast<sllbm_ctx *>(cc);
+  if (!c || !path) return SLLBM_E_ARG;
+  const int rc = ready_for_tables(c);
+  if (rc) return rc;
+  build_host_tables(c);
+  *path = effective_path(c);
+  return SLLBM_OK;
+}
+
 int sllbm_num_nodes(const sllbm_ctx *c, int64_t *nx, int64_t *ny) {
   if (!c || !nx || !ny) return SLLBM_E_ARG;
   if (!c->have_grid) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "grid not set");

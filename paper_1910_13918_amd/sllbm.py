@@ -72,6 +72,7 @@ _SIGS = {
     "sllbm_init_grid_mapped": ([_vp, _c, _c, _vp, _vp, _c, _c], _c),
     "sllbm_set_physics": ([_vp, _d, _d, _d, _d, _c], _c),
     "sllbm_set_path": ([_vp, _c], _c),
+    "sllbm_resolved_path": ([_vp, _ip], _c),
     "sllbm_num_nodes": ([_vp, _i64p, _i64p], _c),
     "sllbm_population_layout": ([_vp, _ip, _ip, _ip], _c),
     "sllbm_node_coords": ([_vp, _vp, _vp], _c),
@@ -158,6 +159,12 @@ def sllbm_set_physics(ctx, dt, nu, gamma, Pr, model):
 
 def sllbm_set_path(ctx, path):
     return check(ctx, lib.sllbm_set_path(ctx, path))
+
+
+def sllbm_resolved_path(ctx):
+    p = ctypes.c_int()
+    check(ctx, lib.sllbm_resolved_path(ctx, ctypes.byref(p)))
+    return p.value
 
 
 def sllbm_num_nodes(ctx):

@@ -88,6 +88,11 @@ class Solver:
         x, y = self.axis_coords()
         return np.tile(x, self.ny), np.repeat(y, self.nx)
 
+    def resolved_path(self):
+        """Name of the kernel family the next step runs ("direct", "tiled", "records")."""
+        code = C.sllbm_resolved_path(self.ctx)
+        return next(k for k, v in _PATH.items() if v == code and k != "auto")
+
     def relaxation_time(self):
         return C.sllbm_relaxation_time(self.ctx)
 

@@ -157,7 +157,8 @@ def riemann(ncells=512, p=2, seed=None, t_end=0.25, nu=1.73e-4, gamma=1.4, cfl=0
     quadrant boundaries at x = 1/2 and y = 1/2 (a node on x = 1/2 or y = 1/2
     takes the state of the upper / right side)."""
     if states is None:
-        states = riemann_states(RIEMANN_DEFAULT_SEED if seed is None else seed)
+        seed = RIEMANN_DEFAULT_SEED if seed is None else seed
+        states = riemann_states(seed)
     h = 1.0 / ncells
     dt, n = cfl_time_step(h * GLC_MIN_GAP[p], cfl, t_end=t_end)
 

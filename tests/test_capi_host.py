@@ -85,6 +85,7 @@ def test_setup_validation_and_call_order():
         assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.4, 1.0, 3) == C.E_ARG
         # queries before physics
         assert _code(C.sllbm_relaxation_time, ctx) == C.E_STATE
+        assert _code(C.sllbm_resolved_path, ctx) == C.E_STATE
         C.sllbm_set_physics(ctx, 0.1, 0.2, 1.4, 1.0, C.POLYATOMIC)
         assert C.sllbm_relaxation_time(ctx) == pytest.approx(0.2 / 0.1 + 0.5)
         assert C.sllbm_population_layout(ctx) == (2, 25, 8)
@@ -94,6 +95,30 @@ def test_setup_validation_and_call_order():
         assert _code(C.sllbm_mass, ctx) == C.E_STATE
         assert _code(C.sllbm_set_path, ctx, 9) == C.E_ARG
         assert _code(C.sllbm_set_check_interval, ctx, -2) == C.E_ARG
+    finally:
+        C.sllbm_destroy(ctx)
+
+
+def test_resolved_path():
+    """AUTO resolves to TILED while every tile's source window fits the LDS
+    staging (at most 3 rows per wavefront, 128 columns), else to DIRECT."""
+    ctx = _ctx()
+    try:
+        _setup(ctx, nc=20, dt=1e-3)
+        assert C.sllbm_resolved_path(ctx) == C.PATH_TILED
+        for p in (C.PATH_DIRECT, C.PATH_TILED, C.PATH_RECORDS):
+            C.sllbm_set_path(ctx, p)
+            assert C.sllbm_resolved_path(ctx) == p
+        C.sllbm_set_path(ctx, C.PATH_AUTO)
+        # 200 cells of width 1e-3 next to 10 cells of width 0.1: departures of
+        # 0.05 from the wide cells cross ~100 narrow cells, a window far wider
+        # than 128 columns
+        ex = np.concatenate([np.linspace(0.0, 0.2, 201), 0.2 + 0.1 * np.arange(1, 11)])
+        ey = np.linspace(0.0, 1.0, 11)
+        C.sllbm_init_grid_mapped(ctx, len(ex) - 1, len(ey) - 1, ex.ctypes.data, ey.ctypes.data,
+                                 C.ZERO_GRADIENT, C.PERIODIC)
+        C.sllbm_set_physics(ctx, 0.05 / W.XI_MAX, 0.01, 1.4, 1.0, C.POLYATOMIC)
+        assert C.sllbm_resolved_path(ctx) == C.PATH_DIRECT
     finally:
         C.sllbm_destroy(ctx)
 
