@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step_direct(
 }
 
 // S^T with the LDS-staged gather of the forward step.
-template <typename T, int TAPS, int WX, int R>
+template <typename T, int TAPS, int HALO, int R>
 __global__ __launch_bounds__(64 * kTileRowsTY) void k_adjoint_step_tiled(
     const T *__restrict__ mu, const int32_t *__restrict__ xrel, const T *__restrict__ xw,
     const int32_t *__restrict__ xwin, const int32_t *__restrict__ yrel, const T *__restrict__ yw,
@@ -217,8 +217,8 @@ __global__ __launch_bounds__(64 * kTileRowsTY) void k_adjoint_step_tiled(
   const int ixc = ix < c.nx ? ix : c.nx - 1;
   const int iyc = iy < c.ny ? iy : c.ny - 1;
   T lam[1][25];
-  tiled_stream<T, TAPS, 1, TY, WX, 5, R>(mu, xrel, xw, xwin, yrel, yw, ywin, W, ntx, nty, tx, ty,
-                                         ixc, iyc, lane, wv, c, lds, lam);
+  tiled_stream<T, TAPS, 1, TY, HALO, 5, R, (TAPS >= kSeparableTaps)>(
+      mu, xrel, xw, xwin, yrel, yw, ywin, W, ntx, nty, tx, ty, ixc, iyc, lane, wv, c, lds, lam);
   if (ix < c.nx && iy < c.ny) {
     const long long v = (long long)iy * c.nx + ix;
     if (mom)
@@ -314,19 +314,23 @@ hipError_t launch_adjoint_step(int fp32, bool tiled, const StepConsts &c, const 
       const int ntx = (c.nx + 63) / 64, nty = (c.ny + TY - 1) / TY;
       const int grid = ((ntx * nty + 7) / 8) * 8;
       const int W = t.win_rows;
-      if (W > 3 * TY || t.win_cols > 128) return hipErrorInvalidValue;
-      auto go = [&]<int WX, int R>() {
-        k_adjoint_step_tiled<T, TAPS, WX, R>
-            <<<grid, dim3(64, TY), tiled_lds_bytes<T, 1>(5, R, WX), s>>>(
-                in, t.xrel, static_cast<const T *>(t.xw), t.xwin, t.yrel,
-                static_cast<const T *>(t.yw), t.ywin, W, ntx, nty, mom_prev, o, c);
+      const int halo = tiled_halo(t.win_cols, c.nx, c.ny);
+      if (W > 3 * TY || halo == 0) return hipErrorInvalidValue;
+      constexpr bool SEP = TAPS >= kSeparableTaps;
+      const size_t lds = tiled_lds_bytes(sizeof(T), 1, 5, W, halo, SEP);
+      if (lds > kTiledLdsBudget) return hipErrorInvalidValue;
+      auto go = [&]<int HALO, int R>() {
+        k_adjoint_step_tiled<T, TAPS, HALO, R><<<grid, dim3(64, TY), lds, s>>>(
+            in, t.xrel, static_cast<const T *>(t.xw), t.xwin, t.yrel,
+            static_cast<const T *>(t.yw), t.ywin, W, ntx, nty, mom_prev, o, c);
       };
-      const bool narrow = t.win_cols <= 72;
-      if (W <= 2 * TY) {
-        if (narrow) go.template operator()<72, 2>(); else go.template operator()<128, 2>();
-      } else {
-        if (narrow) go.template operator()<72, 3>(); else go.template operator()<128, 3>();
-      }
+      auto by_rows = [&]<int HALO>() {
+        if (W <= 2 * TY) go.template operator()<HALO, 2>();
+        else go.template operator()<HALO, 3>();
+      };
+      if (halo == 4) by_rows.template operator()<4>();
+      else if (halo == 8) by_rows.template operator()<8>();
+      else by_rows.template operator()<64>();
       return hipGetLastError();
     }
     dim3 grid((c.nx + 63) / 64, (c.ny + 3) / 4);

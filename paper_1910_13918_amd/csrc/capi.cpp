@@ -283,7 +283,10 @@ StepConsts make_consts(const sllbm_ctx *c) {
   for (int a = 0; a < kQ1; ++a) {
     k.xi[a] = c->vs.xi[a];
     k.w[a] = c->vs.w[a];
-    for (int j = 0; j < 5; ++j) k.hk[a][j] = c->vs.hk[a][j];
+    for (int j = 0; j < 5; ++j) {
+      k.hk[a][j] = c->vs.hk[a][j];
+      k.whk[a][j] = c->vs.w[a] * c->vs.hk[a][j];
+    }
   }
   for (int m = 0; m <= c->p; ++m) {
     k.rn[m] = c->ax.r[m];

@@ -18,6 +18,7 @@ struct StepConsts {
   double xi[5];       // 1-D abscissae
   double w[5];        // 1-D weights
   double hk[5][5];    // He_k(xi_a) / k!
+  double whk[5][5];   // w_a He_k(xi_a) / k!
   double rn[5];       // reference support points r_0..r_p
   double lden[5];     // 1 / prod_{n != m} (r_m - r_n)
   int perx, pery;     // periodic axes

@@ -152,6 +152,9 @@ __device__ __forceinline__ void node_moments(const T (&fs)[Sets<MODEL>::S][25],
 // (the Hermite moments of a Gaussian of mean u and variance theta),
 // f_eq_{a+5b} = rho w_a w_b sum_{k+m<=4} A_k(u_x) He_k(xi_a)/k! A_m(u_y) He_m(xi_b)/m!,
 // which equals the full tensor contraction of eqs. (9)-(10).
+// Evaluated per b as Z_k = A_k(u_x) sum_{m<=4-k} A_m(u_y) He_m(xi_b)/m! and
+// f_eq_{a+5b} = rho w_b sum_k (w_a He_k(xi_a)/k!) Z_k, the bracket a kernel
+// constant: five live values per b instead of 25 hoisted products.
 template <class Fn>
 __device__ __forceinline__ void for_each_equilibrium(double rho, double ux, double uy,
                                                      double theta, const StepConsts &c, Fn &&fn) {
@@ -163,23 +166,21 @@ __device__ __forceinline__ void for_each_equilibrium(double rho, double ux, doub
                         uy2 * uy2 + 6.0 * uy2 * t + 3.0 * t * t};
 #pragma unroll
   for (int b = 0; b < 5; ++b) {
-    // partial sums over the y-order: Yc[j] = sum_{m <= j} A_m(u_y) He_m(xi_b)/m!
-    double Yc[5];
+    // Z[k] = A_k(u_x) sum_{m <= 4-k} A_m(u_y) He_m(xi_b)/m!
+    double Z[5];
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
       acc = fma(Ay[j], c.hk[b][j], acc);
-      Yc[j] = acc;
+      Z[4 - j] = Ax[4 - j] * acc;
     }
     const double rw = rho * c.w[b];
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
-      double s = (Ax[0] * c.hk[a][0]) * Yc[4];
-      s = fma(Ax[1] * c.hk[a][1], Yc[3], s);
-      s = fma(Ax[2] * c.hk[a][2], Yc[2], s);
-      s = fma(Ax[3] * c.hk[a][3], Yc[1], s);
-      s = fma(Ax[4] * c.hk[a][4], Yc[0], s);
-      fn(a + 5 * b, rw * c.w[a] * s);
+      double s = c.whk[a][0] * Z[0];
+#pragma unroll
+      for (int k = 1; k < 5; ++k) s = fma(c.whk[a][k], Z[k], s);
+      fn(a + 5 * b, rw * s);
     }
   }
 }
@@ -210,10 +211,15 @@ __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][25],
   const unsigned voff = unsigned(v) * unsigned(sizeof(T));
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   for_each_equilibrium(m[0], m[1], m[2], m[3], c, [&](int i, double feq) {
-    const double f = double(fs[0][i]);
+    // convert again rather than keep the moments' 25 (50) doubles alive
+    T fr = fs[0][i];
+    asm volatile("" : "+v"(fr));
+    const double f = double(fr);
     buffer_store<T>(T(fma(om, feq - f, f)), make_rsrc(fout + i * N, plane_bytes), voff, 0);
     if (Sets<MODEL>::S == 2) {
-      const double g = double(fs[1][i]);
+      T gr = fs[1][i];
+      asm volatile("" : "+v"(gr));
+      const double g = double(gr);
       buffer_store<T>(T(fma(om, gf * feq - g, g)), make_rsrc(fout + (25 + i) * N, plane_bytes),
                       voff, 0);
     }

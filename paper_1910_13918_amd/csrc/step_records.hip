@@ -11,6 +11,31 @@ namespace sllbm {
 // stream + collide, general gather through per-(node, velocity) records
 // (departure cell and reference coordinates; weights evaluated here)
 // ---------------------------------------------------------------------------
+// The p+1 stencil columns of a departure cell are consecutive nodes except
+// when the cell is the last one before a periodic seam (its right vertex is
+// node 0): rows are then read one value at a time, in a wave-uniform branch.
+template <typename T, int P1, bool SEAM>
+__device__ __forceinline__ T records_interp(__amdgpu_buffer_rsrc_t rs, const unsigned (&xo)[P1],
+                                            const unsigned (&yo)[P1], const T (&wx)[P1],
+                                            const T (&wy)[P1]) {
+  T acc = T(0);
+#pragma unroll
+  for (int n = 0; n < P1; ++n) {
+    T v[P1];
+    if constexpr (SEAM) {
+#pragma unroll
+      for (int m = 0; m < P1; ++m) v[m] = buffer_load<T>(rs, yo[n] + xo[m], 0);
+    } else {
+      buffer_load_run<T, P1>(rs, yo[n] + xo[0], 0, v);
+    }
+    T row = T(0);
+#pragma unroll
+    for (int m = 0; m < P1; ++m) row = fma(wx[m], v[m], row);
+    acc = fma(wy[n], row, acc);
+  }
+  return acc;
+}
+
 template <typename T, int P, int MODEL>
 __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
                                                       T *__restrict__ fout,
@@ -23,6 +48,10 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.n) return;
   const long long N = c.n;
+  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
+  const unsigned voff = unsigned(v) * unsigned(sizeof(T));
+  const auto rcell = make_rsrc(cell, unsigned(N * 25 * (long long)sizeof(int32_t)));
+  const unsigned cell_off = unsigned(v) * unsigned(sizeof(int32_t));
   T rn[P1], den[P1];
 #pragma unroll
   for (int m = 0; m < P1; ++m) {
@@ -32,33 +61,32 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
   T fs[S][25];
 #pragma unroll
   for (int i = 0; i < 25; ++i) {
-    const int rec = cell[i * N + v];
+    const int rec = int(__builtin_amdgcn_raw_buffer_load_b32(rcell, cell_off,
+                                                             unsigned(i) * unsigned(N) * 4u, 0));
     const int cx = rec & 0xffff, cy = rec >> 16;
     T wx[P1], wy[P1];
-    lagrange_eval<T, P1>(rr[i * N + v], rn, den, wx);
-    lagrange_eval<T, P1>(ss[i * N + v], rn, den, wy);
-    int xo[P1];
-    long long yo[P1];
+    lagrange_eval<T, P1>(buffer_load<T>(make_rsrc(rr + i * N, plane_bytes), voff, 0), rn, den, wx);
+    lagrange_eval<T, P1>(buffer_load<T>(make_rsrc(ss + i * N, plane_bytes), voff, 0), rn, den, wy);
+    unsigned xo[P1], yo[P1];
+    bool seam = false;
 #pragma unroll
     for (int m = 0; m < P1; ++m) {
       int jx = cx * P + m;
+      seam |= jx >= c.nx;
       if (jx >= c.nx) jx -= c.nx;  // periodic seam: last vertex is node 0
-      xo[m] = jx;
+      xo[m] = unsigned(jx) * unsigned(sizeof(T));
       int jy = cy * P + m;
       if (jy >= c.ny) jy -= c.ny;
-      yo[m] = (long long)jy * c.nx;
+      yo[m] = unsigned(jy) * unsigned(c.nx) * unsigned(sizeof(T));
     }
+    const bool any_seam = __builtin_amdgcn_ballot_w64(seam) != 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const T *src = fin + (long long)(s * 25 + i) * N;
-      T acc = T(0);
-#pragma unroll
-      for (int n = 0; n < P1; ++n) {
-        T row = T(0);
-#pragma unroll
-        for (int m = 0; m < P1; ++m) row = fma(wx[m], src[yo[n] + xo[m]], row);
-        acc = fma(wy[n], row, acc);
-      }
+      const auto rs = make_rsrc(fin + (long long)(s * 25 + i) * N, plane_bytes);
+      T acc = any_seam ? records_interp<T, P1, true>(rs, xo, yo, wx, wy)
+                       : records_interp<T, P1, false>(rs, xo, yo, wx, wy);
+      // keep the interpolation next to its loads
+      asm volatile("" : "+v"(acc));
       fs[s][i] = acc;
     }
   }

@@ -1,24 +1,7 @@
-// Stream + collide with the departure gather served from LDS.
-//
-// A workgroup owns a tile of 64 x-nodes (one per lane) by TY rows (one
-// wavefront per row).  For the departure points of velocity i = a + 5b, the
-// tile needs a window of source rows that depends only on b and a window of
-// source columns that depends only on a (both precomputed per tile: the
-// departure geometry is static).  Per phase (one b and a group of G
-// x-components, for every population set) the workgroup
-//   1. stages the raw source windows (W rows by WX columns, WX = 72 or 128)
-//      into LDS with row-contiguous buffer loads -- one or two loads per lane
-//      per window row, instead of (p+1)^2 scattered gathers per node;
-//   2. evaluates each node's cell-local tensor Lagrange interpolant (eq. (17))
-//      from LDS: an x-pass over p+1 columns on each of the node's p+1 rows,
-//      then the y-combination, keeping all 25 (or 50) streamed values of the
-//      node in registers.
-// The collision then runs in float64 and the post-collision populations are
-// stored with coalesced writes.
-//
-// Workgroups are numbered so that each of the 8 XCDs (which receive
-// workgroups round-robin) sweeps a contiguous band of tiles; vertically
-// neighbouring tiles, which share halo rows, then meet in the same L2.
+// Stream + collide with the departure gather served from LDS: the windows
+// of source rows and columns each tile of 64 x 4 nodes needs are staged per
+// velocity group (tiled_common.hpp), interpolated from LDS, and the node's
+// streamed populations are collided and stored in the same kernel.
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -27,7 +10,7 @@
 
 namespace sllbm {
 
-template <typename T, int P, int MODEL, int TY, int WX, int G, int R>
+template <typename T, int P, int MODEL, int TY, int HALO, int G, int R>
 __global__ __launch_bounds__(64 * TY) void k_step_tiled(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
     const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ yrel,
@@ -46,26 +29,29 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(
   const int ixc = ix < c.nx ? ix : c.nx - 1;
   const int iyc = iy < c.ny ? iy : c.ny - 1;
   T fs[S][25];
-  tiled_stream<T, P + 1, S, TY, WX, G, R>(fin, xrel, xw, xwin, yrel, yw, ywin, W, ntx, nty, tx,
-                                          ty, ixc, iyc, lane, wv, c, lds, fs);
+  tiled_stream<T, P + 1, S, TY, HALO, G, R, (P + 1 >= kSeparableTaps)>(
+      fin, xrel, xw, xwin, yrel, yw, ywin, W, ntx, nty, tx, ty, ixc, iyc, lane, wv, c, lds, fs);
   if (ix < c.nx && iy < c.ny) collide_store<T, MODEL>(fs, c, fout, (long long)iy * c.nx + ix, flag);
 }
 
-template <typename T, int P, int MODEL, int WX, int R>
+template <typename T, int P, int MODEL, int HALO, int R>
 hipError_t launch_tiled(const StepConsts &c, const DevTables &t, const T *in, T *out, int *flag,
                         hipStream_t s) {
   constexpr int TY = kTileRowsTY;
   constexpr int S = Sets<MODEL>::S;
+  constexpr bool SEP = P + 1 >= kSeparableTaps;
   const int ntx = (c.nx + 63) / 64, nty = (c.ny + TY - 1) / TY;
   const int grid = ((ntx * nty + 7) / 8) * 8;
   const dim3 block(64, TY);
-  // all five x-components per phase when both LDS buffers fit, else one
-  if (tiled_lds_bytes<T, S>(5, R, WX) <= kTiledLdsBudget) {
-    k_step_tiled<T, P, MODEL, TY, WX, 5, R><<<grid, block, tiled_lds_bytes<T, S>(5, R, WX), s>>>(
+  // all five x-components per phase when the LDS buffers fit, else one
+  const size_t lds5 = tiled_lds_bytes(sizeof(T), S, 5, t.win_rows, HALO, SEP);
+  if (lds5 <= kTiledLdsBudget) {
+    k_step_tiled<T, P, MODEL, TY, HALO, 5, R><<<grid, block, lds5, s>>>(
         in, out, t.xrel, static_cast<const T *>(t.xw), t.xwin, t.yrel,
         static_cast<const T *>(t.yw), t.ywin, t.win_rows, ntx, nty, c, flag);
   } else {
-    k_step_tiled<T, P, MODEL, TY, WX, 1, R><<<grid, block, tiled_lds_bytes<T, S>(1, R, WX), s>>>(
+    const size_t lds1 = tiled_lds_bytes(sizeof(T), S, 1, t.win_rows, HALO, SEP);
+    k_step_tiled<T, P, MODEL, TY, HALO, 1, R><<<grid, block, lds1, s>>>(
         in, out, t.xrel, static_cast<const T *>(t.xw), t.xwin, t.yrel,
         static_cast<const T *>(t.yw), t.ywin, t.win_rows, ntx, nty, c, flag);
   }
@@ -86,12 +72,14 @@ hipError_t launch_step_tiled(int fp32, int model, const StepConsts &c, const Dev
   return dispatch_step(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
     const T *in = static_cast<const T *>(fin);
     T *out = static_cast<T *>(fout);
-    const bool narrow = t.win_cols <= 72;
-    if (t.win_rows <= 2 * kTileRowsTY)
-      return narrow ? launch_tiled<T, P, MODEL, 72, 2>(c, t, in, out, flag, s)
-                    : launch_tiled<T, P, MODEL, 128, 2>(c, t, in, out, flag, s);
-    return narrow ? launch_tiled<T, P, MODEL, 72, 3>(c, t, in, out, flag, s)
-                  : launch_tiled<T, P, MODEL, 128, 3>(c, t, in, out, flag, s);
+    const int halo = tiled_halo(t.win_cols, c.nx, c.ny);
+    auto go = [&]<int R>() {
+      if (halo == 4) return launch_tiled<T, P, MODEL, 4, R>(c, t, in, out, flag, s);
+      if (halo == 8) return launch_tiled<T, P, MODEL, 8, R>(c, t, in, out, flag, s);
+      return launch_tiled<T, P, MODEL, 64, R>(c, t, in, out, flag, s);
+    };
+    return t.win_rows <= 2 * kTileRowsTY ? go.template operator()<2>()
+                                          : go.template operator()<3>();
   });
 }
 

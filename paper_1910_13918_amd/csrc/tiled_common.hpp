@@ -7,13 +7,19 @@
 // source columns that depends only on a (both precomputed per tile: the
 // departure geometry is static).  Per phase (one b and a group of G
 // x-components, for every population set) the workgroup
-//   1. stages the raw source windows (W rows by WX columns, WX = 72 or 128)
-//      into LDS with row-contiguous buffer loads -- one or two loads per lane
-//      per window row, instead of (p+1)^2 scattered gathers per node;
+//   1. stages the raw source windows (W rows by WX = 64 + HALO columns) into
+//      LDS with row-contiguous buffer loads: one load per lane per window
+//      row for the 64 main columns; the HALO (4 or 8) extra columns of up to
+//      64 / HALO rows travel together in one load, so a narrow halo costs a
+//      fraction of a load per row rather than a whole one;
 //   2. evaluates each node's cell-local tensor Lagrange interpolant (eq. (17))
 //      from LDS: an x-pass over p+1 columns on each of the node's p+1 rows,
 //      then the y-combination, keeping all 25 (or 50) streamed values of the
-//      node in registers.
+//      node in registers.  From 6 taps per axis on, the x-pass runs once per
+//      staged row and column (shared by the tile's rows) into a second LDS
+//      buffer before the y-combination.
+// Loads for the next phase are issued before this phase's interpolation and
+// written to the other LDS buffer after it, so they stay in flight meanwhile.
 // The collision then runs in float64 and the post-collision populations are
 // stored with coalesced writes.
 //
@@ -29,9 +35,39 @@
 
 namespace sllbm {
 
+constexpr size_t kTiledLdsBudget = 163840;  // gfx950: 160 KiB of LDS per workgroup
+constexpr int kTileRowsTY = 4;
+
+// Separable evaluation from this many taps per axis on (the transposed
+// tables of the adjoint); below it the direct 2-D form measured faster.
+constexpr int kSeparableTaps = 6;
+
+// Index j wrapped into a periodic axis of n nodes or clamped into [0, n-1]
+// (staged nodes past the window are never weighted).
+__device__ __forceinline__ int wrap_or_clamp(int j, int n, int periodic) {
+  int w = j % n;
+  w += w < 0 ? n : 0;
+  const int cl = j < 0 ? 0 : (j < n - 1 ? j : n - 1);
+  return periodic ? w : cl;
+}
+
+// The same for j within one period of [0, n) (the packed halo loads, which
+// the host enables only on axes much longer than a window).
+__device__ __forceinline__ int wrap_or_clamp_near(int j, int n, int periodic) {
+  const int w = j < 0 ? j + n : (j >= n ? j - n : j);
+  const int cl = j < 0 ? 0 : (j < n - 1 ? j : n - 1);
+  return periodic ? w : cl;
+}
+
+#ifndef SLLBM_TILED_PACK
+#define SLLBM_TILED_PACK 0
+#endif
+
 // P1 = taps per axis: p+1 for the forward step, the transposed table width
-// for the adjoint.
-template <typename T, int P1, int S, int TY, int WX, int G, int R>
+// for the adjoint.  R = staged rows per wavefront (W <= R * TY).  SEP selects
+// the separable evaluation: (R + 1) P1 FMAs per value instead of P1 (P1 + 1),
+// paid for with a second barrier per phase.
+template <typename T, int P1, int S, int TY, int HALO, int G, int R, bool SEP>
 __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
                                              const int32_t *__restrict__ xrel,
                                              const T *__restrict__ xw,
@@ -42,21 +78,28 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
                                              int nty, int tx, int ty, int ixc, int iyc, int lane,
                                              int wv, const StepConsts &c, T *lds,
                                              T (&fs)[S][25]) {
-  constexpr int ROWS = R * TY;            // staged rows per plane (>= window rows)
-  constexpr int PLANE = ROWS * WX;
-  constexpr int BUF = S * G * PLANE;      // one of two LDS buffers
-  constexpr int NPH = 5 * (5 / G);        // phases: (b, group of G x-components)
-  T *const dummy = lds + 2 * BUF;         // 64 slots for the unused half-row lanes
+  static_assert(HALO == 4 || HALO == 8 || HALO == 64, "halo of 4, 8 or 64 columns");
+  constexpr int WX = 64 + HALO;
+  constexpr int NQ = S * G;                              // planes staged per phase
+  constexpr bool PACKED = HALO < 64 && SLLBM_TILED_PACK;
+  constexpr int HROWS = PACKED ? 64 / HALO : 1;          // rows per packed halo load
+  constexpr int HPARTS = PACKED ? (R * TY + HROWS - 1) / HROWS : 0;  // loads per plane
+  constexpr int NH = PACKED ? (NQ * HPARTS + TY - 1) / TY : 0;       // per wavefront
+  constexpr int MAINH = PACKED ? 1 : 2;                  // loads per staged row
+  constexpr int NPH = 5 * (5 / G);                       // phases: (b, group of G a's)
+  const int PLANE = W * WX;                              // exact window rows per plane
+  const int BUF = NQ * PLANE;                            // one of two raw buffers
+  T *const dummy = lds + 2 * BUF;                        // 64 slots for unused lanes
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
-  // this lane's x-stencils for the 5 x-components: p+1 consecutive
-  // window-relative columns starting at xr0[a], with weights wx[a][m]
+  const unsigned row_bytes = unsigned(c.nx) * unsigned(sizeof(T));
+  // this lane's x-stencils for the 5 x-components: P1 consecutive
+  // window-relative columns starting at xr0[a], with weights wx[a][m];
+  // col_off = byte offset of the staged main column x0 + lane (and, for a
+  // 64-column halo, of x0 + 64 + lane)
   int xr0[5];
   T wx[5][P1];
-  // staged columns in bytes: x0 + lane, and the halo x0 + 64 + lane for
-  // WX = 128 or x0 + 64 + (lane % 8) for WX = 72 (lanes 8..63 then repeat
-  // lanes 0..7, so the halo load moves only the 8 columns it needs)
-  unsigned col_off[5][2];
+  unsigned col_off[5][MAINH];
 #pragma unroll
   for (int a = 0; a < 5; ++a) {
     xr0[a] = xrel[(a * P1) * c.nx + ixc];
@@ -64,50 +107,80 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
     for (int m = 0; m < P1; ++m) wx[a][m] = xw[(a * P1 + m) * c.nx + ixc];
     const int x0 = xwin[a * ntx + tx];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int col = x0 + 64 * h + (h == 0 || WX == 128 ? lane : (lane & (WX - 65)));
-      int wrapped = col % c.nx;
-      wrapped += wrapped < 0 ? c.nx : 0;
-      const int clamped = col < c.nx - 1 ? col : c.nx - 1;
-      col_off[a][h] = unsigned(c.perx ? wrapped : clamped) * unsigned(sizeof(T));
+    for (int h = 0; h < MAINH; ++h) {
+      // unpacked narrow halo: lanes 8.. repeat the first HALO columns
+      const int off = h == 0 || HALO == 64 ? lane : lane % HALO;
+      col_off[a][h] =
+          unsigned(wrap_or_clamp(x0 + 64 * h + off, c.nx, c.perx)) * unsigned(sizeof(T));
     }
   }
-  // prefetch registers: R rows x G planes x S sets x 2 half-rows
-  T pre[R][G][S][2];
+  // packed halo: this lane's row within a halo load and its halo column
+  const int hrow = lane / HALO, hcol = lane % HALO;
+  auto row_off = [&](int r) { return unsigned(wrap_or_clamp(r, c.ny, c.pery)) * row_bytes; };
+  // prefetch registers: main rows (R x G x S) and this wavefront's share of
+  // the packed halo loads
+  T pre[R][G][S][MAINH];
+  T preh[NH > 0 ? NH : 1];
   auto load = [&](int ph) {
     const int b = ph / (5 / G), a0 = (ph % (5 / G)) * G;
     const int w0 = ywin[b * nty + ty];
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
-      if (rr > 0 && wv + rr * TY >= W) break;  // wave-uniform: rows past the window
-      int r = w0 + wv + rr * TY;
-      int rw = r % c.ny;
-      rw += rw < 0 ? c.ny : 0;
-      r = c.pery ? rw : (r < c.ny - 1 ? r : c.ny - 1);  // rows past the window: never weighted
-      const unsigned rowoff = unsigned(r) * unsigned(c.nx) * unsigned(sizeof(T));
+      if (wv + rr * TY >= W) break;  // wave-uniform: rows past the window
+      const unsigned ro = row_off(w0 + wv + rr * TY);
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const auto rs = make_rsrc(fin + (long long)(s * 25 + a0 + g + 5 * b) * N, plane_bytes);
-          pre[rr][g][s][0] = buffer_load<T>(rs, col_off[a0 + g][0], rowoff);
-          pre[rr][g][s][1] = buffer_load<T>(rs, col_off[a0 + g][1], rowoff);
+#pragma unroll
+          for (int h = 0; h < MAINH; ++h)
+            pre[rr][g][s][h] = buffer_load<T>(rs, col_off[a0 + g][h], ro);
         }
+    }
+    if constexpr (PACKED) {
+#pragma unroll
+      for (int t = 0; t < NH; ++t) {
+        const int j = wv + TY * t;  // halo job: plane q, part k (wave-uniform)
+        if (j >= NQ * HPARTS) break;
+        const int q = j / HPARTS, k = j % HPARTS;
+        const int g = q % G, s = q / G;
+        const int x0 = xwin[(a0 + g) * ntx + tx];
+        const int r = wrap_or_clamp_near(w0 + k * HROWS + hrow, c.ny, c.pery);
+        const unsigned off =
+            unsigned(wrap_or_clamp_near(x0 + 64 + hcol, c.nx, c.perx)) * unsigned(sizeof(T)) +
+            unsigned(r) * row_bytes;
+        const auto rs = make_rsrc(fin + (long long)(s * 25 + a0 + g + 5 * b) * N, plane_bytes);
+        preh[t] = buffer_load<T>(rs, off, 0);
+      }
     }
   };
   auto store = [&](T *buf) {
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
-      if (rr > 0 && wv + rr * TY >= W) break;
+      if (wv + rr * TY >= W) break;
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          T *dst = buf + ((s * G + g) * ROWS + wv + rr * TY) * WX;
+          T *dst = buf + (s * G + g) * PLANE + (wv + rr * TY) * WX;
           dst[lane] = pre[rr][g][s][0];
-          T *slot = (WX == 128 || lane < WX - 64) ? dst + 64 + lane : dummy + lane;
-          *slot = pre[rr][g][s][1];
+          if constexpr (MAINH == 2) {
+            T *slot = HALO == 64 || lane < HALO ? dst + 64 + lane : dummy + lane;
+            *slot = pre[rr][g][s][MAINH - 1];
+          }
         }
+    }
+    if constexpr (PACKED) {
+#pragma unroll
+      for (int t = 0; t < NH; ++t) {
+        const int j = wv + TY * t;
+        if (j >= NQ * HPARTS) break;
+        const int q = j / HPARTS, k = j % HPARTS;
+        const int row = k * HROWS + hrow;
+        T *slot = row < W ? buf + q * PLANE + row * WX + 64 + hcol : dummy + lane;
+        *slot = preh[t];
+      }
     }
   };
   load(0);
@@ -122,26 +195,75 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
     T wy[P1];
 #pragma unroll
     for (int n = 0; n < P1; ++n) wy[n] = yw[(b * P1 + n) * c.ny + iyc];
+    if constexpr (SEP) {
+      T *const xb = lds + 2 * BUF + 64;  // [S][G][W][64] x-interpolated rows
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int a = a0 + g;
-      const T *corner = cur + (yr0 * WX + xr0[a]);
+      for (int rr = 0; rr < R; ++rr) {
+        const int row = wv + rr * TY;
+        if (row >= W) break;  // wave-uniform
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const T *src = corner + (s * G + g) * PLANE;
-        T acc = T(0);
+        for (int g = 0; g < G; ++g) {
+          const int a = a0 + g;
 #pragma unroll
-        for (int n = 0; n < P1; ++n) {
-          T rv = T(0);
+          for (int s = 0; s < S; ++s) {
+            const T *src = cur + (s * G + g) * PLANE + row * WX + xr0[a];
+            T xv = T(0);
 #pragma unroll
-          for (int m = 0; m < P1; ++m) rv = fma(wx[a][m], src[n * WX + m], rv);
-          acc = fma(wy[n], rv, acc);
+            for (int m = 0; m < P1; ++m) xv = fma(wx[a][m], src[m], xv);
+            xb[((s * G + g) * W + row) * 64 + lane] = xv;
+          }
         }
-        // keep the FMAs in this phase: otherwise the compiler sinks them all
-        // to the collision and keeps every LDS value of every phase alive
-        asm volatile("" : "+v"(acc));
-        fs[s][a + 5 * b] = acc;
       }
+      lds_barrier();
+      T acc[G][S];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const T *col = xb + ((s * G + g) * W + yr0) * 64 + lane;
+          T v = T(0);
+#pragma unroll
+          for (int n = 0; n < P1; ++n) v = fma(wy[n], col[n * 64], v);
+          acc[g][s] = v;
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          asm volatile("" : "+v"(acc[g][s]));
+          fs[s][a0 + g + 5 * b] = acc[g][s];
+        }
+    } else {
+      T acc[G][S];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int a = a0 + g;
+        const T *corner = cur + (yr0 * WX + xr0[a]);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const T *src = corner + (s * G + g) * PLANE;
+          T v = T(0);
+#pragma unroll
+          for (int n = 0; n < P1; ++n) {
+            T rv = T(0);
+#pragma unroll
+            for (int m = 0; m < P1; ++m) rv = fma(wx[a][m], src[n * WX + m], rv);
+            v = fma(wy[n], rv, v);
+          }
+          acc[g][s] = v;
+        }
+      }
+      // keep the FMAs in this phase (otherwise the compiler sinks them all to
+      // the collision and keeps every LDS value of every phase alive), but
+      // pin the phase as a whole so that its LDS reads overlap
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          asm volatile("" : "+v"(acc[g][s]));
+          fs[s][a0 + g + 5 * b] = acc[g][s];
+        }
     }
     if (ph + 1 < NPH) store(lds + ((ph + 1) & 1) * BUF);
     lds_barrier();
@@ -155,12 +277,20 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
   return (bid & 7) * per + (bid >> 3);
 }
 
-constexpr size_t kTiledLdsBudget = 163840;  // gfx950: 160 KiB of LDS per workgroup
-constexpr int kTileRowsTY = 4;
+// LDS bytes of a tiled launch: two raw window buffers (S G planes of W rows
+// by 64 + halo columns), 64 spare slots, and with SEP the x-pass buffer.
+inline size_t tiled_lds_bytes(size_t tsize, int S, int G, int W, int halo, bool sep) {
+  const size_t planes = size_t(S) * G;
+  return (2 * planes * W * (64 + halo) + 64 + (sep ? planes * W * 64 : 0)) * tsize;
+}
 
-template <typename T, int S>
-size_t tiled_lds_bytes(int G, int R, int WX) {
-  return (size_t(2) * S * G * R * kTileRowsTY * WX + 64) * sizeof(T);
+// Narrowest halo (4, 8 or 64 extra columns) that covers a window of
+// win_cols columns; 0 when none does.  Narrow halos need axes of at least
+// 256 columns and 32 rows (their loads wrap indices by one period at most).
+inline int tiled_halo(int win_cols, int nx, int ny) {
+  if (win_cols > 128) return 0;
+  if (nx < 256 || ny < 32 || win_cols > 72) return 64;
+  return win_cols <= 68 ? 4 : 8;
 }
 
 }  // namespace sllbm
