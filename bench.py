@@ -242,6 +242,7 @@ def main():
         m32, m64 = s.moments(), s64.moments()
         out["fp64"] = {"value": s64.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps,
                        "bytes_per_node_update": bytes_per_node_update(wl, "fp64", s64.resolved_path()),
+                       "traffic": profiled_traffic(wname, "fp64", args.path, args.steps),
                        "fp32_vs_fp64_after_steps": {
                            "steps": args.warmup + args.steps,
                            "rho_max_rel": float(np.abs(m32[0] - m64[0]).max() / np.abs(m64[0]).max()),

@@ -9,9 +9,10 @@
 // x-components, for every population set) the workgroup
 //   1. stages the raw source windows (W rows by WX = 64 + HALO columns) into
 //      LDS with row-contiguous buffer loads: one load per lane per window
-//      row for the 64 main columns; the HALO (4 or 8) extra columns of up to
-//      64 / HALO rows travel together in one load, so a narrow halo costs a
-//      fraction of a load per row rather than a whole one;
+//      row for the 64 main columns, and for the HALO extra columns either a
+//      second load per row (float32, and any 64-column halo) or, for a
+//      narrow halo of float64 values, one load carrying the halo columns of
+//      64 / HALO rows;
 //   2. evaluates each node's cell-local tensor Lagrange interpolant (eq. (17))
 //      from LDS: an x-pass over p+1 columns on each of the node's p+1 rows,
 //      then the y-combination, keeping all 25 (or 50) streamed values of the
@@ -59,9 +60,6 @@ __device__ __forceinline__ int wrap_or_clamp_near(int j, int n, int periodic) {
   return periodic ? w : cl;
 }
 
-#ifndef SLLBM_TILED_PACK
-#define SLLBM_TILED_PACK 0
-#endif
 
 // P1 = taps per axis: p+1 for the forward step, the transposed table width
 // for the adjoint.  R = staged rows per wavefront (W <= R * TY).  SEP selects
@@ -81,7 +79,9 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
   static_assert(HALO == 4 || HALO == 8 || HALO == 64, "halo of 4, 8 or 64 columns");
   constexpr int WX = 64 + HALO;
   constexpr int NQ = S * G;                              // planes staged per phase
-  constexpr bool PACKED = HALO < 64 && SLLBM_TILED_PACK;
+  // packed halo loads measured faster for float64 values, slower for float32
+  // (their address arithmetic outweighs the loads they save)
+  constexpr bool PACKED = HALO < 64 && sizeof(T) == 8;
   constexpr int HROWS = PACKED ? 64 / HALO : 1;          // rows per packed halo load
   constexpr int HPARTS = PACKED ? (R * TY + HROWS - 1) / HROWS : 0;  // loads per plane
   constexpr int NH = PACKED ? (NQ * HPARTS + TY - 1) / TY : 0;       // per wavefront
