@@ -54,6 +54,14 @@ def bytes_per_node_update(wl, precision, path):
     return b
 
 
+def mfma_flops_per_node_update(wl):
+    """Matrix-core flops of the x-pass per node update: per tile of 64 x 4
+    nodes and x-component, 4 blocks of 16 columns x 16 (set, row) pairs x
+    4 ks columns, 2 flops each, 5 components per phase, 5 phases."""
+    ks = (16 + 2 * wl.p + 3) // 4
+    return 5 * 5 * 4 * (16 * 16 * 4 * ks * 2) / (64 * 4)
+
+
 def profiled_traffic(wname, precision, path, launches):
     """HBM bytes per launch from the committed counter profile of this workload
     (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when no
@@ -188,6 +196,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost ratio")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-mfma", action="store_true", help="skip the matrix-core x-pass line")
     ap.add_argument("--no-svi", action="store_true",
                     help="skip the shock-vortex (stretched 1024 x 512 cells, p = 3) lines")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -250,6 +259,15 @@ def main():
                                                   np.abs(m32[2] - m64[2]).max())),
                            "theta_max_rel": float(np.abs(m32[3] - m64[3]).max() / np.abs(m64[3]).max())}}
         s64.close()
+    if not args.no_mfma and args.precision == "fp32" and args.workload == "riemann":
+        # the same step with the x-pass of the interpolation on the matrix cores
+        sm, msm, _ = timed(wl, "fp32", "mfma", args.steps, args.warmup)
+        v = sm.n * args.steps / (msm * 1e-3)
+        out["mfma_x_pass"] = {"path": "mfma", "value": v, "unit": "node-updates/s",
+                              "ms_per_step": msm / args.steps,
+                              "achieved_gbs": v * bpn / 1e9, "frac": v * bpn / 1e9 / HBM_PEAK_GBS,
+                              "mfma_tflops": v * mfma_flops_per_node_update(wl) / 1e12}
+        sm.close()
     if not args.no_svi and args.workload == "riemann":
         out["shock_vortex"] = shock_vortex_entry(args.precision)
     if not args.no_adjoint:

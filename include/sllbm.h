@@ -86,9 +86,15 @@ typedef enum {
                              through per-axis departure tables */
   SLLBM_PATH_TILED = 2,   /* raw source windows of each velocity staged in LDS
                              per tile of 64 x 4 nodes, interpolated from LDS */
-  SLLBM_PATH_RECORDS = 3  /* per-(node, velocity) departure records (cell, r, s)
+  SLLBM_PATH_RECORDS = 3, /* per-(node, velocity) departure records (cell, r, s)
                              with weights evaluated in the kernel: the general
                              gather for grids that are not axis products */
+  SLLBM_PATH_MFMA = 4     /* as TILED, with the x-pass of the interpolation as
+                             16 x 16 x 4 float32 matrix-core products (float32
+                             populations, at most 16 population-set x window
+                             rows, departures within one node spacing of their
+                             cell; SLLBM_E_UNSUPPORTED otherwise); never chosen
+                             by AUTO */
 } sllbm_path;
 
 /* ---- lifetime ------------------------------------------------------------ */

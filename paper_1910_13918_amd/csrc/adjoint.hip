@@ -217,7 +217,7 @@ __global__ __launch_bounds__(64 * kTileRowsTY) void k_adjoint_step_tiled(
   const int ixc = ix < c.nx ? ix : c.nx - 1;
   const int iyc = iy < c.ny ? iy : c.ny - 1;
   T lam[1][25];
-  tiled_stream<T, TAPS, 1, TY, HALO, 5, R, (TAPS >= kSeparableTaps)>(
+  tiled_stream<T, TAPS, 1, TY, HALO, 5, R, (TAPS >= kSeparableTaps ? kInterpSep : kInterp2D)>(
       mu, xrel, xw, xwin, yrel, yw, ywin, W, ntx, nty, tx, ty, ixc, iyc, lane, wv, c, lds, lam);
   if (ix < c.nx && iy < c.ny) {
     const long long v = (long long)iy * c.nx + ix;
@@ -317,7 +317,7 @@ hipError_t launch_adjoint_step(int fp32, bool tiled, const StepConsts &c, const 
       const int halo = tiled_halo(t.win_cols, c.nx, c.ny);
       if (W > 3 * TY || halo == 0) return hipErrorInvalidValue;
       constexpr bool SEP = TAPS >= kSeparableTaps;
-      const size_t lds = tiled_lds_bytes(sizeof(T), 1, 5, W, halo, SEP);
+      const size_t lds = tiled_lds_bytes(sizeof(T), 1, 5, W, 64 + halo, SEP);
       if (lds > kTiledLdsBudget) return hipErrorInvalidValue;
       auto go = [&]<int HALO, int R>() {
         k_adjoint_step_tiled<T, TAPS, HALO, R><<<grid, dim3(64, TY), lds, s>>>(

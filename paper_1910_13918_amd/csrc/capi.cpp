@@ -53,6 +53,7 @@ struct sllbm_ctx {
   AxisTable xt[kQ1], yt[kQ1];
   std::vector<double> mx, my;
   int win_rows = 0, win_cols = 0;
+  bool mfma_blocks_ok = false;
   std::vector<int32_t> ywin, yrel, xwin, xrel;
 
   // adjoint: transposed tables, windows (built on first use)
@@ -136,6 +137,23 @@ int build_windows(const AxisTable *t, int n, int tile, std::vector<int32_t> &win
   return width;
 }
 
+// The matrix-core x-pass covers each block of 16 target columns with
+// 4 * ks staged columns starting at the stencil of the block's first column,
+// ks = (16 + 2p + 3) / 4 (as in the kernel).
+bool mfma_blocks_fit(const sllbm_ctx *c) {
+  const int P1 = c->p + 1, n = c->ax.n;
+  const int K = 4 * ((16 + 2 * c->p + 3) / 4);
+  for (int a = 0; a < kQ1; ++a)
+    for (int n0 = 0; n0 < n; n0 += 16) {
+      const int32_t base = c->xrel[(size_t(a) * P1) * n + n0];
+      for (int j = n0; j < std::min(n0 + 16, n); ++j) {
+        const int32_t st = c->xrel[(size_t(a) * P1) * n + j];
+        if (st < base || st + c->p - base > K - 1) return false;
+      }
+    }
+  return true;
+}
+
 void build_host_tables(sllbm_ctx *c) {
   if (!c->host_dirty) return;
   for (int a = 0; a < kQ1; ++a) {
@@ -147,6 +165,7 @@ void build_host_tables(sllbm_ctx *c) {
   // windows of the tiled kernel: tiles of kTileCols columns by kTileRows rows
   c->win_rows = build_windows(c->yt, c->ay.n, kTileRows, c->ywin, c->yrel);
   c->win_cols = build_windows(c->xt, c->ax.n, kTileCols, c->xwin, c->xrel);
+  c->mfma_blocks_ok = mfma_blocks_fit(c);
   c->host_dirty = false;
   c->dev_dirty = true;
   c->rec_dirty = true;
@@ -156,6 +175,12 @@ void build_host_tables(sllbm_ctx *c) {
 // up to 128 columns; LDS always fits (one x-component per phase if need be).
 bool tiled_fits(const sllbm_ctx *c) {
   return c->win_rows <= 3 * kTileRows && c->win_cols <= kMaxWindowCols;
+}
+
+// The matrix-core path: tiled windows, float32, at most 16 (set, row) pairs
+// per window, every x-stencil block within the product's columns.
+bool mfma_fits(const sllbm_ctx *c) {
+  return tiled_fits(c) && c->fp32 && nsets(c) * c->win_rows <= 16 && c->mfma_blocks_ok;
 }
 
 int effective_path(const sllbm_ctx *c) {
@@ -319,6 +344,7 @@ DevTables make_tables(const sllbm_ctx *c) {
   t.win_rows = c->win_rows;
   t.win_cols = c->win_cols;
   t.taps = c->p + 1;
+  t.mfma_ok = c->mfma_blocks_ok ? 1 : 0;
   return t;
 }
 
@@ -594,7 +620,7 @@ int sllbm_set_physics(sllbm_ctx *c, double dt, double nu, double gamma, double P
 
 int sllbm_set_path(sllbm_ctx *c, int path) {
   if (!c) return SLLBM_E_ARG;
-  if (path < SLLBM_PATH_AUTO || path > SLLBM_PATH_RECORDS)
+  if (path < SLLBM_PATH_AUTO || path > SLLBM_PATH_MFMA)
     return fail(c, SLLBM_E_ARG, "unknown path");
   c->path = path;
   return SLLBM_OK;
@@ -750,6 +776,10 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   const int path = effective_path(c);
   if (path == kPathTiled && !tiled_fits(c))
     return fail(c, SLLBM_E_UNSUPPORTED, "departures span too many rows for the tiled kernel");
+  if (path == kPathMfma && !mfma_fits(c))
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "matrix-core path needs float32, at most 16 set x window rows and departures "
+                "within one node spacing of their cell");
   StepConsts k = make_consts(c);
   const DevTables t = make_tables(c);
   int *flag = static_cast<int *>(c->flag.ptr);

@@ -118,6 +118,7 @@ hipError_t launch_step(int fp32, int model, int path, const StepConsts &c, const
     case kPathDirect: return launch_step_direct(fp32, model, c, t, fin, fout, flag, s);
     case kPathTiled: return launch_step_tiled(fp32, model, c, t, fin, fout, flag, s);
     case kPathRecords: return launch_step_records(fp32, model, c, t, fin, fout, flag, s);
+    case kPathMfma: return launch_step_mfma(fp32, model, c, t, fin, fout, flag, s);
   }
   return hipErrorInvalidValue;
 }

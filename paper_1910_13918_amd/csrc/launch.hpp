@@ -47,9 +47,10 @@ struct DevTables {
   int win_rows;         // source rows staged per tile (max over tiles)
   int win_cols;         // source columns staged per tile (max over tiles)
   int taps;             // table entries per node (p+1 forward, more when transposed)
+  int mfma_ok;          // every 16-column block's x-stencils fit the matrix-core x-pass
 };
 
-enum Path { kPathDirect = 1, kPathTiled = 2, kPathRecords = 3 };
+enum Path { kPathDirect = 1, kPathTiled = 2, kPathRecords = 3, kPathMfma = 4 };
 
 hipError_t launch_init_eq(int fp32, int model, const StepConsts &c, const double *rho,
                           const double *ux, const double *uy, const double *T, void *f,
@@ -63,6 +64,8 @@ hipError_t launch_step_tiled(int fp32, int model, const StepConsts &c, const Dev
                              const void *fin, void *fout, int *flag, hipStream_t s);
 hipError_t launch_step_records(int fp32, int model, const StepConsts &c, const DevTables &t,
                                const void *fin, void *fout, int *flag, hipStream_t s);
+hipError_t launch_step_mfma(int fp32, int model, const StepConsts &c, const DevTables &t,
+                            const void *fin, void *fout, int *flag, hipStream_t s);
 
 // Moments per node (any output pointer may be null) and per-block partial
 // sums of M_v rho_v into `partial` (mass_blocks(c) entries).

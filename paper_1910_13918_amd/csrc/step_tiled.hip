@@ -29,7 +29,8 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(
   const int ixc = ix < c.nx ? ix : c.nx - 1;
   const int iyc = iy < c.ny ? iy : c.ny - 1;
   T fs[S][25];
-  tiled_stream<T, P + 1, S, TY, HALO, G, R, (P + 1 >= kSeparableTaps)>(
+  tiled_stream<T, P + 1, S, TY, HALO, G, R,
+               (P + 1 >= kSeparableTaps ? kInterpSep : kInterp2D)>(
       fin, xrel, xw, xwin, yrel, yw, ywin, W, ntx, nty, tx, ty, ixc, iyc, lane, wv, c, lds, fs);
   if (ix < c.nx && iy < c.ny) collide_store<T, MODEL>(fs, c, fout, (long long)iy * c.nx + ix, flag);
 }
@@ -44,13 +45,13 @@ hipError_t launch_tiled(const StepConsts &c, const DevTables &t, const T *in, T 
   const int grid = ((ntx * nty + 7) / 8) * 8;
   const dim3 block(64, TY);
   // all five x-components per phase when the LDS buffers fit, else one
-  const size_t lds5 = tiled_lds_bytes(sizeof(T), S, 5, t.win_rows, HALO, SEP);
+  const size_t lds5 = tiled_lds_bytes(sizeof(T), S, 5, t.win_rows, 64 + HALO, SEP);
   if (lds5 <= kTiledLdsBudget) {
     k_step_tiled<T, P, MODEL, TY, HALO, 5, R><<<grid, block, lds5, s>>>(
         in, out, t.xrel, static_cast<const T *>(t.xw), t.xwin, t.yrel,
         static_cast<const T *>(t.yw), t.ywin, t.win_rows, ntx, nty, c, flag);
   } else {
-    const size_t lds1 = tiled_lds_bytes(sizeof(T), S, 1, t.win_rows, HALO, SEP);
+    const size_t lds1 = tiled_lds_bytes(sizeof(T), S, 1, t.win_rows, 64 + HALO, SEP);
     k_step_tiled<T, P, MODEL, TY, HALO, 1, R><<<grid, block, lds1, s>>>(
         in, out, t.xrel, static_cast<const T *>(t.xw), t.xwin, t.yrel,
         static_cast<const T *>(t.yw), t.ywin, t.win_rows, ntx, nty, c, flag);

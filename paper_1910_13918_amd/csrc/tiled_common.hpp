@@ -61,11 +61,27 @@ __device__ __forceinline__ int wrap_or_clamp_near(int j, int n, int periodic) {
 }
 
 
+// Interpolation from the staged windows: the direct 2-D form; the separable
+// form (x-pass per staged row into LDS, then y); or the separable form with
+// the x-pass on the matrix cores (float32).
+enum InterpMode { kInterp2D = 0, kInterpSep = 1, kInterpMfma = 2 };
+
+// k-steps of 4 of the matrix-core x-pass: 16 target columns need at most
+// 16 + 2 (P1 - 1) staged columns (departures within one node spacing of the
+// cell; the host checks every block).
+template <int P1>
+constexpr int mfma_ksteps() { return (16 + 2 * (P1 - 1) + 3) / 4; }
+
+// Row pitch of the staged windows: 64 + halo columns, plus (for the
+// matrix-core x-pass) zero columns that the last k-steps may read.
+template <int P1, int HALO, int IM>
+constexpr int tiled_pitch() { return 64 + HALO + (IM == kInterpMfma ? 4 * mfma_ksteps<P1>() : 0); }
+
 // P1 = taps per axis: p+1 for the forward step, the transposed table width
-// for the adjoint.  R = staged rows per wavefront (W <= R * TY).  SEP selects
-// the separable evaluation: (R + 1) P1 FMAs per value instead of P1 (P1 + 1),
+// for the adjoint.  R = staged rows per wavefront (W <= R * TY).  The
+// separable forms cost (R + 1) P1 FMAs per value instead of P1 (P1 + 1),
 // paid for with a second barrier per phase.
-template <typename T, int P1, int S, int TY, int HALO, int G, int R, bool SEP>
+template <typename T, int P1, int S, int TY, int HALO, int G, int R, int IM>
 __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
                                              const int32_t *__restrict__ xrel,
                                              const T *__restrict__ xw,
@@ -77,7 +93,9 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
                                              int wv, const StepConsts &c, T *lds,
                                              T (&fs)[S][25]) {
   static_assert(HALO == 4 || HALO == 8 || HALO == 64, "halo of 4, 8 or 64 columns");
-  constexpr int WX = 64 + HALO;
+  static_assert(IM != kInterpMfma || sizeof(T) == 4, "matrix-core x-pass in float32");
+  constexpr bool SEP = IM != kInterp2D;
+  constexpr int WX = tiled_pitch<P1, HALO, IM>();        // staged row pitch
   constexpr int NQ = S * G;                              // planes staged per phase
   // packed halo loads measured faster for float64 values, slower for float32
   // (their address arithmetic outweighs the loads they save)
@@ -183,6 +201,35 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
       }
     }
   };
+  // matrix-core x-pass: this lane's A-operand entries (banded Lagrange
+  // weights of target column 16 wv + lane % 16 against staged column
+  // base_a + 4 k + lane / 16, base_a = stencil start of the block's first
+  // column), and zeros in the pad columns of both raw buffers
+  constexpr int KS = IM == kInterpMfma ? mfma_ksteps<P1>() : 1;
+  float amat[IM == kInterpMfma ? 5 : 1][KS];
+  int xbase[5];
+  if constexpr (IM == kInterpMfma) {
+    const int n = 16 * wv + (lane & 15), kq = lane >> 4;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      xbase[a] = __shfl(xr0[a], 16 * wv);
+      const int d0 = xbase[a] + kq - __shfl(xr0[a], n);
+      float wn[P1];
+#pragma unroll
+      for (int m = 0; m < P1; ++m) wn[m] = __shfl(float(wx[a][m]), n);
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int d = d0 + 4 * k;
+        float v = 0.0f;
+#pragma unroll
+        for (int m = 0; m < P1; ++m) v = d == m ? wn[m] : v;
+        amat[a][k] = v;
+      }
+    }
+    constexpr int PADC = WX - 64 - HALO;  // pad columns of every staged row
+    for (int e = wv * 64 + lane; e < 2 * NQ * W * PADC; e += TY * 64)
+      lds[(e / PADC) * WX + 64 + HALO + e % PADC] = T(0);  // rows of both buffers in turn
+  }
   load(0);
   store(lds);
   lds_barrier();
@@ -197,21 +244,43 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
     for (int n = 0; n < P1; ++n) wy[n] = yw[(b * P1 + n) * c.ny + iyc];
     if constexpr (SEP) {
       T *const xb = lds + 2 * BUF + 64;  // [S][G][W][64] x-interpolated rows
+      if constexpr (IM == kInterpSep) {
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-        const int row = wv + rr * TY;
-        if (row >= W) break;  // wave-uniform
+        for (int rr = 0; rr < R; ++rr) {
+          const int row = wv + rr * TY;
+          if (row >= W) break;  // wave-uniform
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int a = a0 + g;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+              const T *src = cur + (s * G + g) * PLANE + row * WX + xr0[a];
+              T xv = T(0);
+#pragma unroll
+              for (int m = 0; m < P1; ++m) xv = fma(wx[a][m], src[m], xv);
+              xb[((s * G + g) * W + row) * 64 + lane] = xv;
+            }
+          }
+        }
+      } else {
+        // X[16 columns of block wv][(set, row) pairs] = A_a (16 x 4 KS) x
+        // staged columns (4 KS x pairs): lane l supplies A[l % 16][l / 16]
+        // and B[l / 16][l % 16] and receives X[4 (l / 16) + t][l % 16]
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const int j = lane & 15, kq = lane >> 4;
+        const bool jok = j < S * W;
+        const int jc = jok ? j : 0, js = jc / W, jr = jc % W;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
           const int a = a0 + g;
+          const float *src = cur + (js * G + g) * PLANE + jr * WX + xbase[a] + kq;
+          f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-          for (int s = 0; s < S; ++s) {
-            const T *src = cur + (s * G + g) * PLANE + row * WX + xr0[a];
-            T xv = T(0);
-#pragma unroll
-            for (int m = 0; m < P1; ++m) xv = fma(wx[a][m], src[m], xv);
-            xb[((s * G + g) * W + row) * 64 + lane] = xv;
-          }
+          for (int k = 0; k < KS; ++k)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(amat[a][k], jok ? src[4 * k] : 0.0f, acc,
+                                                       0, 0, 0);
+          if (jok)
+            *reinterpret_cast<f4 *>(xb + ((js * G + g) * W + jr) * 64 + 16 * wv + 4 * kq) = acc;
         }
       }
       lds_barrier();
@@ -278,10 +347,11 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
 }
 
 // LDS bytes of a tiled launch: two raw window buffers (S G planes of W rows
-// by 64 + halo columns), 64 spare slots, and with SEP the x-pass buffer.
-inline size_t tiled_lds_bytes(size_t tsize, int S, int G, int W, int halo, bool sep) {
+// of `pitch` columns), 64 spare slots, and for the separable forms the
+// x-pass buffer.
+inline size_t tiled_lds_bytes(size_t tsize, int S, int G, int W, int pitch, bool sep) {
   const size_t planes = size_t(S) * G;
-  return (2 * planes * W * (64 + halo) + 64 + (sep ? planes * W * 64 : 0)) * tsize;
+  return (2 * planes * W * pitch + 64 + (sep ? planes * W * 64 : 0)) * tsize;
 }
 
 // Narrowest halo (4, 8 or 64 extra columns) that covers a window of

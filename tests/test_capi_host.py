@@ -94,6 +94,7 @@ def test_setup_validation_and_call_order():
         assert _code(C.sllbm_step, ctx, -1) == C.E_ARG
         assert _code(C.sllbm_mass, ctx) == C.E_STATE
         assert _code(C.sllbm_set_path, ctx, 9) == C.E_ARG
+        assert _code(C.sllbm_set_path, ctx, 5) == C.E_ARG
         assert _code(C.sllbm_set_check_interval, ctx, -2) == C.E_ARG
     finally:
         C.sllbm_destroy(ctx)
@@ -106,7 +107,7 @@ def test_resolved_path():
     try:
         _setup(ctx, nc=20, dt=1e-3)
         assert C.sllbm_resolved_path(ctx) == C.PATH_TILED
-        for p in (C.PATH_DIRECT, C.PATH_TILED, C.PATH_RECORDS):
+        for p in (C.PATH_DIRECT, C.PATH_TILED, C.PATH_RECORDS, C.PATH_MFMA):
             C.sllbm_set_path(ctx, p)
             assert C.sllbm_resolved_path(ctx) == p
         C.sllbm_set_path(ctx, C.PATH_AUTO)

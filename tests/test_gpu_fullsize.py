@@ -2,7 +2,7 @@
 
 * Riemann, 512 x 512 cells of order 2 (1025^2 nodes, f + g), in the launch
   configuration the benchmark times (FP32, automatic path) and on every other
-  path: one step at 4000 seeded nodes against the FP64 oracle, and two full
+  path (the matrix-core x-pass included): one step at 4000 seeded nodes against the FP64 oracle, and two full
   steps at every node on the automatic path.
 * Shock-vortex interaction, 1024 x 512 cells of order 3 with the stretched x
   map (3073 x 1536 nodes): one step at 4000 seeded nodes on every path.
@@ -73,7 +73,8 @@ def _one_step(case, precision, path):
 
 @pytest.mark.parametrize("precision,path", [("fp32", "auto"), ("fp32", "tiled"),
                                             ("fp32", "direct"), ("fp32", "records"),
-                                            ("fp64", "auto"), ("fp64", "records")])
+                                            ("fp32", "mfma"), ("fp64", "auto"),
+                                            ("fp64", "records")])
 def test_riemann_512_one_step_sampled(riemann_case, precision, path):
     G = _one_step(riemann_case, precision, path)
     err = np.abs(G - riemann_case.F1).max() / riemann_case.scale
@@ -97,7 +98,8 @@ def test_riemann_512_two_steps_every_node(riemann_case):
 
 
 @pytest.mark.parametrize("precision,path", [("fp32", "auto"), ("fp32", "direct"),
-                                            ("fp32", "records"), ("fp64", "auto")])
+                                            ("fp32", "records"), ("fp32", "mfma"),
+                                            ("fp64", "auto")])
 def test_svi_one_step_sampled(svi_case, precision, path):
     G = _one_step(svi_case, precision, path)
     err = np.abs(G - svi_case.F1).max() / svi_case.scale

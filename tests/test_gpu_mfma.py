@@ -1,0 +1,134 @@
+"""GPU parity of the matrix-core x-pass path (SLLBM_PATH_MFMA) against the FP64
+CPU oracle.
+
+The x-pass runs as float32 16 x 16 x 4 matrix products, so the tolerance is
+the float32 one of the other paths: one step <= 2e-6 relative to max |F|
+(inputs rounded to float32 on both sides).  Cases span several 64-column
+tiles and 4-row tiles with ragged tails, every model and order, periodic and
+zero-gradient boundaries; the path must refuse float64 contexts and stencils
+that leave the product's columns.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.grid import Grid
+from oracle.sllbm import Sim
+from paper_1910_13918_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a HIP device")]
+
+
+def _solver(wl, precision, path):
+    from paper_1910_13918_amd.solver import Solver
+    return Solver.from_workload(wl, precision=precision, path=path)
+
+
+def _oracle(wl):
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
+    return g, Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+
+
+def _wl(model, p, periodic, ncx, ncy):
+    if model == "polyatomic":
+        wl = W.riemann(ncx, p, states=W.RIEMANN_TABLE3_STATES)
+    else:
+        wl = W.tgv(ncx, p, U0=0.2, model=model)
+    wl.edges_y = wl.edges_y[0] + (wl.edges_x[1] - wl.edges_x[0]) * np.arange(ncy + 1)
+    wl.periodic_x = wl.periodic_y = periodic
+    if model == "monatomic":
+        base = wl.fields
+
+        def fields(x, y):
+            rho, ux, uy, _ = base(x, y)
+            return rho, ux, uy, 0.8 + 0.3 * np.cos(x) * np.sin(y)
+
+        wl.fields = fields
+    return wl
+
+
+def _state32(wl, sim, g, seed):
+    X, Y = g.coords()
+    F = sim.init(*wl.fields(X, Y))
+    F = F * W.population_noise(F.shape, seed, 0.05)
+    return F.astype(np.float32).astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+CASES = [(model, p, periodic, {1: 70, 2: 35, 3: 23, 4: 17}[p], {1: 19, 2: 9, 3: 6, 4: 5}[p])
+         for model in ("isothermal", "monatomic", "polyatomic") for p in (1, 2, 3, 4)
+         for periodic in (True, False)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-p{c[1]}-{'per' if c[2] else 'zg'}")
+def test_one_step_fp32(case):
+    wl = _wl(*case)
+    g, sim = _oracle(wl)
+    F0 = _state32(wl, sim, g, seed=21)
+    F1 = sim.step(F0)
+    s = _solver(wl, "fp32", "mfma")
+    try:
+        print(f"[gpu] mfma one step {case} nodes={g.nnodes}", flush=True)
+        assert s.resolved_path() == "mfma"
+        s.set_populations(F0)
+        if case[0] == "polyatomic" and case[1] == 4:
+            # f and g over a 9-row window: 18 (set, row) pairs > 16 columns of B
+            from paper_1910_13918_amd import sllbm as C
+            with pytest.raises(C.SllbmError) as e:
+                s.step(1)
+            assert e.value.code == C.E_UNSUPPORTED
+            return
+        s.step(1)
+        assert _rel(s.populations(), F1) <= 2e-6
+        assert s.flags() == (0, 1)
+    finally:
+        s.close()
+
+
+def test_trajectory_matches_vector_path():
+    """40 steps of the Riemann problem (Table III states, 64 x 64 cells, p = 2):
+    the matrix-core and the vector x-pass differ only by float32 rounding."""
+    wl = W.riemann(64, 2, states=W.RIEMANN_TABLE3_STATES)
+    out = {}
+    for path in ("tiled", "mfma"):
+        s = _solver(wl, "fp32", path)
+        try:
+            s.init_from_workload()
+            s.step(40)
+            out[path] = s.moments()
+            assert s.flags()[0] == 0
+        finally:
+            s.close()
+    for k in range(4):
+        assert _rel(out["mfma"][k], out["tiled"][k]) <= 1e-5
+
+
+def test_refuses_fp64_and_wide_departures():
+    from paper_1910_13918_amd import sllbm as C
+    wl = W.riemann(16, 2, states=W.RIEMANN_TABLE3_STATES)
+    s = _solver(wl, "fp64", "mfma")
+    try:
+        s.init_from_workload()
+        with pytest.raises(C.SllbmError) as e:
+            s.step(1)
+        assert e.value.code == C.E_UNSUPPORTED
+    finally:
+        s.close()
+    # 200 cells of width 1e-3 next to 10 cells of width 0.1 and departures of
+    # 0.05: x-stencils of neighbouring columns lie ~100 columns apart
+    wl = W.riemann(16, 2, states=W.RIEMANN_TABLE3_STATES)
+    wl.edges_x = np.concatenate([np.linspace(0.0, 0.2, 201), 0.2 + 0.1 * np.arange(1, 11)])
+    wl.uniform = False
+    wl.dt = 0.05 / W.XI_MAX
+    s = _solver(wl, "fp32", "mfma")
+    try:
+        s.init_from_workload()
+        with pytest.raises(C.SllbmError) as e:
+            s.step(1)
+        assert e.value.code == C.E_UNSUPPORTED
+    finally:
+        s.close()
