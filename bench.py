@@ -272,6 +272,10 @@ def main():
         out["shock_vortex"] = shock_vortex_entry(args.precision)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_cost()
+        rec = adjoint_cost(every=0)
+        out["adjoint"]["recorded_moments"] = {
+            "note": "every step's moments kept in the forward (24 B per node and step), no replay",
+            "forward_ms": rec["forward_ms"], "backward_ms": rec["backward_ms"], "ratio": rec["ratio"]}
     if not args.no_cpu_baseline:
         # same initial state, one GPU step, compared with the oracle at the sample
         s1 = Solver.from_workload(wl, precision=args.precision, path=args.path)

@@ -151,6 +151,18 @@ def test_rollout_gradient_matches_complex_step():
         assert got == pytest.approx(ref, rel=1e-9, abs=1e-14)
 
 
+def test_recorded_rollout_equals_checkpointed():
+    """every = 0 (moments of every step recorded in the forward, no replay)
+    gives the checkpointed gradient: the replay recomputes the same moments."""
+    wl = W.tgv(16, 4, U0=0.3, steps=30)
+    _, gu_c, gv_c, gr_c, s = _rollout_grad(wl, "fp64", 30, 7)
+    s.close()
+    _, gu_r, gv_r, gr_r, s = _rollout_grad(wl, "fp64", 30, 0)
+    s.close()
+    for a, b in ((gu_c, gu_r), (gv_c, gv_r), (gr_c, gr_r)):
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-14 * np.abs(a).max())
+
+
 def test_fp32_rollout_gradient_close_to_fp64():
     wl = W.tgv(16, 4, U0=0.3, steps=60)
     _, gu64, gv64, _, s = _rollout_grad(wl, "fp64", 60, 25)
