@@ -120,6 +120,43 @@ def shock_vortex_entry(precision, steps=20, warmup=3):
     return out
 
 
+def aux_kernels(s, reps=20):
+    """Average duration of the initialisation f = f_eq (from device fields),
+    the moments output and the mass reduction on the benchmark grid, with
+    their algorithmic bytes: init reads 4 float64 fields and writes every
+    population; moments read every population and write 4 float64 fields;
+    the mass reads the f populations."""
+    import torch
+
+    from paper_1910_13918_amd import sllbm as C
+    X, Y = s.coords()
+    fields = [torch.tensor(a, device=s.device) for a in s.workload.fields(X, Y)]
+    outs = [torch.empty(s.n, dtype=torch.float64, device=s.device) for _ in range(4)]
+    size = 4 if s.precision == "fp32" else 8
+    pops = s.nsets * 25 * size
+
+    def timed_call(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    res = {}
+    for name, fn, nbytes in (
+            ("init_eq", lambda: C.sllbm_init_macro(s.ctx, *[t.data_ptr() for t in fields], 1),
+             32 + pops),
+            ("moments", lambda: C.sllbm_moments(s.ctx, *[t.data_ptr() for t in outs], 1), pops + 32),
+            ("mass", lambda: C.sllbm_mass(s.ctx), 25 * size)):
+        ms = timed_call(fn)
+        res[name] = {"ms": ms, "bytes_per_node": nbytes, "achieved_gbs": s.n * nbytes / (ms * 1e6)}
+    return res
+
+
 def adjoint_cost(precision="fp32", every=50, reps=3):
     """Forward and backward time of the checkpointed rollout on the adjoint
     workload (Taylor-Green, 128 x 128 cells, p = 4, 500 steps, loss = kinetic
@@ -259,6 +296,8 @@ def main():
                                                   np.abs(m32[2] - m64[2]).max())),
                            "theta_max_rel": float(np.abs(m32[3] - m64[3]).max() / np.abs(m64[3]).max())}}
         s64.close()
+    # initialisation, moments and mass on the same grid (this re-initialises s)
+    out["aux_kernels"] = aux_kernels(s)
     if not args.no_mfma and args.precision == "fp32" and args.workload == "riemann":
         # the same step with the x-pass of the interpolation on the matrix cores
         sm, msm, _ = timed(wl, "fp32", "mfma", args.steps, args.warmup)

@@ -70,10 +70,10 @@ class Solver:
         self.workload = None
 
     @classmethod
-    def from_workload(cls, wl, precision="fp32", path="auto", device=0):
+    def from_workload(cls, wl, precision="fp32", path="auto", device=0, nodes="glc"):
         s = cls(p=wl.p, edges_x=wl.edges_x, edges_y=wl.edges_y, periodic_x=wl.periodic_x,
                 periodic_y=wl.periodic_y, dt=wl.dt, nu=wl.nu, model=wl.model, gamma=wl.gamma,
-                precision=precision, uniform=wl.uniform, path=path, device=device)
+                precision=precision, uniform=wl.uniform, path=path, device=device, nodes=nodes)
         s.workload = wl
         return s
 

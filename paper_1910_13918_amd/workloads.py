@@ -176,6 +176,18 @@ def riemann(ncells=512, p=2, seed=None, t_end=0.25, nu=1.73e-4, gamma=1.4, cfl=0
                     {"seed": seed, "states": [tuple(map(float, s)) for s in states]})
 
 
+def riemann_table3_p4(name=None):
+    """The four-quadrant configuration of Sec. III.D as printed: Table III
+    states, 128 x 128 cells of order 4, t_end = 0.25 in 2091 steps
+    (tau = 1.948 with nu = 1.73e-4), zero-gradient boundaries."""
+    h = 1.0 / 128
+    cfl = 0.25 / 2091 * XI_MAX / (h * GLC_MIN_GAP[4]) * (1.0 + 1e-6)
+    wl = riemann(128, 4, states=RIEMANN_TABLE3_STATES, cfl=cfl,
+                 name=name or "riemann_table3_128x128_p4")
+    assert wl.steps == 2091
+    return wl
+
+
 # ------------------------------------------------------------------ adjoint TGV
 def adjoint_tgv(ncells=128, p=4, U0=0.3, Re=100.0, steps=500, cfl=0.5, name=None):
     return tgv(ncells, p, U0, Re, steps, cfl, "isothermal",
