@@ -207,10 +207,11 @@ int sllbm_step(sllbm_ctx *ctx, int64_t n);
 int sllbm_set_check_interval(sllbm_ctx *ctx, int64_t k);
 
 /* sllbm_step that also records, for each of the n steps, the moments of the
- * streamed (pre-collision) state: moments[s][0..2][ny][nx] = rho, u_x, u_y
- * (float64, device pointer, 3 * nx * ny values per step).  These are the
- * moments the collision Jacobian of step s depends on; the adjoint sweep
- * replays a checkpointed segment with this call. */
+ * streamed (pre-collision) state: moments[s][0..K-1][ny][nx] = rho, u_x, u_y
+ * and, unless isothermal, theta (float64, device pointer, K * nx * ny values
+ * per step, K = 3 or 4).  These are the moments the collision Jacobian of
+ * step s depends on; the adjoint sweep replays a checkpointed segment with
+ * this call. */
 int sllbm_step_record(sllbm_ctx *ctx, int64_t n, double *moments);
 
 /* Synchronise and report the stability flag (1 = raised) and step count. */
@@ -235,33 +236,40 @@ int sllbm_mass(sllbm_ctx *ctx, double *mass);
 int sllbm_get_populations(sllbm_ctx *ctx, void *dst, int on_device);
 int sllbm_set_populations(sllbm_ctx *ctx, const void *src, int on_device);
 
-/* ---- adjoint of the step (isothermal model; SLLBM_E_UNSUPPORTED otherwise) ----
+/* ---- adjoint of the step (every model) ----
  * The paper has no adjoint; these calls differentiate exactly the step above.
  * One step is F' = C(S F) with S the interpolation of every population plane
  * (Sec. II.E, eq. (17)) and C the BGK collision (Sec. II.D, eq. (16)).
  * Reverse sweep:  mu^n = J_C(M^n)^T lambda^{n+1},  lambda^n = S^T mu^n,
  * where M^n are the moments recorded by sllbm_step_record for step n.
  * All arrays are device pointers on the context's device; lambda / mu arrays
- * are [25][ny][nx] in the population type; node fields are float64 [ny][nx].
- * Calls are asynchronous on the bound stream. */
+ * are [S][25][ny][nx] in the population type (S = 2 for the polyatomic
+ * model); node fields are float64 [ny][nx]; a moments record is [K][ny][nx]
+ * with K = 3 (rho, u_x, u_y) for the isothermal model and K = 4 (theta
+ * added) otherwise.  Calls are asynchronous on the bound stream. */
 
 /* lambda = dL/dF of the current populations F for a loss with gradients
- * g_rho, g_ux, g_uy with respect to the node moments rho, u_x, u_y of F. */
+ * g_rho, g_ux, g_uy, g_T with respect to the node moments rho, u_x, u_y and
+ * temperature of F (g_T may be NULL: no temperature term; ignored when
+ * isothermal). */
 int sllbm_adjoint_seed(sllbm_ctx *ctx, const double *g_rho, const double *g_ux, const double *g_uy,
-                       void *lambda);
+                       const double *g_T, void *lambda);
 
-/* mu = J_C(M)^T lambda node by node; moments = [3][ny][nx] rho, u_x, u_y. */
+/* mu = J_C(M)^T lambda node by node; moments = one step's [K][ny][nx] record. */
 int sllbm_adjoint_collide(sllbm_ctx *ctx, const void *lambda, const double *moments, void *mu);
 
 /* out = S^T mu (the transposed interpolation, a gather through transposed
- * departure tables), followed by J_C(M_prev)^T when moments_prev (the moments
- * of the previous step, [3][ny][nx]) is not NULL.  mu and out must differ. */
+ * departure tables), followed by J_C(M_prev)^T when moments_prev (the record
+ * of the previous step) is not NULL.  mu and out must differ. */
 int sllbm_adjoint_step(sllbm_ctx *ctx, const void *mu, const double *moments_prev, void *out);
 
-/* Gradient through the initialisation f = f_eq(rho0, u0) (theta = 1):
- * g_rho0 = sum_i lambda_i df_eq_i/drho0, g_u0 = sum_i lambda_i df_eq_i/du0. */
+/* Gradient through the initialisation f = f_eq(rho0, u0, T0), g = g_eq:
+ * g_rho0 = sum_i lambda_i dF_eq_i/drho0, likewise for u0 and T0.  T0 is
+ * required unless isothermal (where it and g_T0 may be NULL); g_T0 may be
+ * NULL. */
 int sllbm_eq_init_vjp(sllbm_ctx *ctx, const void *lambda0, const double *rho0, const double *ux0,
-                      const double *uy0, double *g_rho0, double *g_ux0, double *g_uy0);
+                      const double *uy0, const double *T0, double *g_rho0, double *g_ux0,
+                      double *g_uy0, double *g_T0);
 
 #ifdef __cplusplus
 }

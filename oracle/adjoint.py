@@ -13,7 +13,8 @@ search depends only on the geometry.
 
 ``kinetic_misfit_loss`` is the loss used for the adjoint workload:
 L = 1/2 sum_v M_v rho |u|^2 + sum_v M_v |u - u_target|^2 at the final step,
-with M_v the exact integral of node v's shape function.
+with M_v the exact integral of node v's shape function; ``thermal_misfit_loss``
+adds sum_v M_v (T - T_target)^2 for the models with a temperature.
 """
 import numpy as np
 
@@ -32,4 +33,21 @@ def complex_step_directional(sim, rho0, ux0, uy0, T0, dux, duy, nsteps, loss, h=
     uy = uy0 + 1j * h * duy
     F = sim.init(rho0.astype(complex), ux, uy, T0.astype(complex))
     F = sim.run(F, nsteps)
+    return float(np.imag(loss(sim, F)) / h)
+
+
+def thermal_misfit_loss(sim, F, u_target, v_target, T_target):
+    rho, ux, uy, T = sim.moments(F)
+    M = sim.grid.node_mass()
+    return (0.5 * np.sum(M * rho * (ux * ux + uy * uy))
+            + np.sum(M * ((ux - u_target) ** 2 + (uy - v_target) ** 2))
+            + np.sum(M * (T - T_target) ** 2))
+
+
+def complex_step_fields(sim, fields0, dfields, nsteps, loss, h=1e-30):
+    """Directional derivative of loss(run(init(fields0 + eps dfields))) for the
+    node fields (rho, u_x, u_y, T)."""
+    rho, ux, uy, T = (np.asarray(f, dtype=complex) + 1j * h * np.asarray(d)
+                      for f, d in zip(fields0, dfields))
+    F = sim.run(sim.init(rho, ux, uy, T), nsteps)
     return float(np.imag(loss(sim, F)) / h)

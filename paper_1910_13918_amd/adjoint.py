@@ -1,22 +1,24 @@
-"""Gradients through an SLLBM rollout (isothermal model) for torch autograd.
+"""Gradients through an SLLBM rollout for torch autograd (every model).
 
-``rollout(rho0, ux0, uy0, solver, nsteps, every)`` initialises the solver at
-equilibrium with the given node fields, advances ``nsteps`` steps and returns
-the final node moments (rho, u_x, u_y).  Its backward pass runs the adjoint
-of every step in the library:
+``rollout(rho0, ux0, uy0, solver, nsteps, every, T0)`` initialises the solver
+at equilibrium with the given node fields, advances ``nsteps`` steps and
+returns the final node moments (rho, u_x, u_y, and T unless isothermal).  Its
+backward pass runs the adjoint of every step in the library:
 
 * forward: a copy of the populations is kept every ``every`` steps;
 * backward: for each segment, newest first, the checkpoint is restored and the
-  segment replayed with ``sllbm_step_record`` (which keeps only the three
-  moments per node and step that the collision Jacobian needs), then
-  ``mu = J_C^T lambda`` and ``lambda = S^T mu`` are applied step by step, and
-  finally the gradient is carried through the initialisation f = f_eq.
+  segment replayed with ``sllbm_step_record`` (which keeps only the moments
+  per node and step that the collision Jacobian needs: rho, u and, unless
+  isothermal, theta), then ``mu = J_C^T lambda`` and ``lambda = S^T mu`` are
+  applied step by step, and finally the gradient is carried through the
+  initialisation F = F_eq.
 
-Memory: one population copy per checkpoint plus 3 float64 per node and step of
-one segment.  With ``every=0`` the forward records the moments of every step
-instead (24 bytes per node and step: 3.1 GB for 500 steps of 512^2 nodes) and
-the backward replays nothing.  Every arithmetic step runs in the HIP kernels;
-this module only sequences the calls and owns the torch buffers.
+Memory: one population copy per checkpoint plus 3 (4) float64 per node and
+step of one segment.  With ``every=0`` the forward records the moments of
+every step instead (24 or 32 bytes per node and step: 3.1 GB for 500
+isothermal steps of 512^2 nodes) and the backward replays nothing.  Every
+arithmetic step runs in the HIP kernels; this module only sequences the calls
+and owns the torch buffers.
 """
 import torch
 
@@ -25,14 +27,15 @@ from . import sllbm as C
 
 class SLLBMRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, rho0, ux0, uy0, solver, nsteps, every):
-        if solver.model != "isothermal":
-            raise ValueError("the adjoint is implemented for the isothermal model")
+    def forward(ctx, rho0, ux0, uy0, T0, solver, nsteps, every):
         dev = solver.device
+        thermal = solver.model != "isothermal"
         rho0 = rho0.detach().to(device=dev, dtype=torch.float64).contiguous()
         ux0 = ux0.detach().to(device=dev, dtype=torch.float64).contiguous()
         uy0 = uy0.detach().to(device=dev, dtype=torch.float64).contiguous()
-        solver.init_macro(rho0, ux0, uy0, torch.ones_like(rho0))
+        T0 = (T0.detach().to(device=dev, dtype=torch.float64).contiguous() if T0 is not None
+              else torch.ones_like(rho0))
+        solver.init_macro(rho0, ux0, uy0, T0)
         checkpoints, lengths, record = [], [], None
         if every == 0:
             record = solver.step_record(nsteps) if nsteps > 0 else None
@@ -45,29 +48,30 @@ class SLLBMRollout(torch.autograd.Function):
                 solver.step(k)
                 done += k
         final = solver.populations_device()
-        rho, ux, uy, _ = solver.moments_device()
-        ctx.save_for_backward(rho0, ux0, uy0)
+        rho, ux, uy, T = solver.moments_device()
+        ctx.save_for_backward(rho0, ux0, uy0, T0)
         ctx.solver = solver
         ctx.checkpoints = checkpoints
         ctx.lengths = lengths
         ctx.record = record
         ctx.final = final
-        return rho, ux, uy
+        ctx.thermal = thermal
+        return rho, ux, uy, T
 
     @staticmethod
-    def backward(ctx, g_rho, g_ux, g_uy):
-        rho0, ux0, uy0 = ctx.saved_tensors
+    def backward(ctx, g_rho, g_ux, g_uy, g_T):
+        rho0, ux0, uy0, T0 = ctx.saved_tensors
         s = ctx.solver
         dev = s.device
         zeros = torch.zeros(s.n, dtype=torch.float64, device=dev)
         g = [t.to(dtype=torch.float64).contiguous() if t is not None else zeros
-             for t in (g_rho, g_ux, g_uy)]
-        lam = torch.empty((s.q, s.n), dtype=s.dtype, device=dev)
+             for t in (g_rho, g_ux, g_uy, g_T)]
+        lam = torch.empty((s.nsets, s.q, s.n), dtype=s.dtype, device=dev)
         mu = torch.empty_like(lam)
         mu2 = torch.empty_like(lam)
         s.set_populations(ctx.final)
         C.sllbm_adjoint_seed(s.ctx, g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(),
-                             lam.data_ptr())
+                             g[3].data_ptr() if ctx.thermal else None, lam.data_ptr())
 
         def reverse_segment(mom, L):
             nonlocal mu, mu2
@@ -82,16 +86,21 @@ class SLLBMRollout(torch.autograd.Function):
         for ck, L in zip(reversed(ctx.checkpoints), reversed(ctx.lengths)):
             s.set_populations(ck)
             reverse_segment(s.step_record(L), L)
-        out = [torch.empty(s.n, dtype=torch.float64, device=dev) for _ in range(3)]
-        C.sllbm_eq_init_vjp(s.ctx, lam.data_ptr(), rho0.data_ptr(), ux0.data_ptr(),
-                            uy0.data_ptr(), *[o.data_ptr() for o in out])
-        return out[0], out[1], out[2], None, None, None
+        out = [torch.empty(s.n, dtype=torch.float64, device=dev) for _ in range(4)]
+        C.sllbm_eq_init_vjp(s.ctx, lam.data_ptr(), rho0.data_ptr(), ux0.data_ptr(), uy0.data_ptr(),
+                            T0.data_ptr(), *[o.data_ptr() for o in out])
+        gT = out[3] if ctx.thermal else None
+        return out[0], out[1], out[2], gT, None, None, None
 
 
-def rollout(rho0, ux0, uy0, solver, nsteps, every=50):
-    """Final (rho, u_x, u_y) after nsteps from f = f_eq(rho0, u0); differentiable
-    in rho0, ux0, uy0.  every > 0: checkpoint interval (the backward replays
-    each segment); every = 0: record every step's moments in the forward."""
+def rollout(rho0, ux0, uy0, solver, nsteps, every=50, T0=None):
+    """Final (rho, u_x, u_y) -- and T for the monatomic and polyatomic models --
+    after nsteps from F = F_eq(rho0, u0, T0); differentiable in rho0, ux0, uy0
+    (and T0).  every > 0: checkpoint interval (the backward replays each
+    segment); every = 0: record every step's moments in the forward."""
     if every < 0:
         raise ValueError("every must be >= 0")
-    return SLLBMRollout.apply(rho0, ux0, uy0, solver, nsteps, every)
+    if solver.model != "isothermal" and T0 is None:
+        raise ValueError("the initial temperature T0 is needed unless isothermal")
+    rho, ux, uy, T = SLLBMRollout.apply(rho0, ux0, uy0, T0, solver, nsteps, every)
+    return (rho, ux, uy) if solver.model == "isothermal" else (rho, ux, uy, T)

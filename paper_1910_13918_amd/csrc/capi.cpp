@@ -410,8 +410,6 @@ void pad_taps(AxisTable &t, const Axis &ax, int taps) {
 int prepare_adjoint(sllbm_ctx *c) {
   int rc = prepare_device(c);
   if (rc) return rc;
-  if (c->model != SLLBM_ISOTHERMAL)
-    return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint step is implemented for the isothermal model");
   if (!c->adj_dirty) return SLLBM_OK;
   int taps = 0;
   for (int a = 0; a < kQ1; ++a) {
@@ -767,6 +765,10 @@ static int read_flag(sllbm_ctx *c, int *flag) {
   return SLLBM_OK;
 }
 
+// Moments per node recorded by sllbm_step_record: rho, u_x, u_y and, unless
+// isothermal, theta.
+static int recorded_moments(const sllbm_ctx *c) { return c->model == SLLBM_ISOTHERMAL ? 3 : 4; }
+
 static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   if (!c) return SLLBM_E_ARG;
   if (n < 0) return fail(c, SLLBM_E_ARG, "n must be >= 0");
@@ -784,7 +786,7 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   const DevTables t = make_tables(c);
   int *flag = static_cast<int *>(c->flag.ptr);
   for (int64_t s = 0; s < n; ++s) {
-    k.mom_out = moments ? moments + s * 3 * k.n : nullptr;
+    k.mom_out = moments ? moments + s * recorded_moments(c) * k.n : nullptr;
     HIP_TRY(c, launch_step(c->fp32, c->model, path, k, t, c->pop[c->cur], c->pop[1 - c->cur],
                            flag, c->stream));
     c->cur ^= 1;
@@ -808,14 +810,14 @@ int sllbm_step_record(sllbm_ctx *c, int64_t n, double *moments) {
 }
 
 int sllbm_adjoint_seed(sllbm_ctx *c, const double *g_rho, const double *g_ux, const double *g_uy,
-                       void *lam) {
+                       const double *g_T, void *lam) {
   if (!c) return SLLBM_E_ARG;
   if (!g_rho || !g_ux || !g_uy || !lam) return fail(c, SLLBM_E_ARG, "null device pointer");
   if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
   int rc = prepare_adjoint(c);
   if (rc) return rc;
-  HIP_TRY(c, launch_adjoint_seed(c->fp32, make_consts(c), c->pop[c->cur], g_rho, g_ux, g_uy, lam,
-                                 c->stream));
+  HIP_TRY(c, launch_adjoint_seed(c->fp32, c->model, make_consts(c), c->pop[c->cur], g_rho, g_ux,
+                                 g_uy, g_T, lam, c->stream));
   return SLLBM_OK;
 }
 
@@ -824,7 +826,8 @@ int sllbm_adjoint_collide(sllbm_ctx *c, const void *lam, const double *moments, 
   if (!lam || !moments || !mu) return fail(c, SLLBM_E_ARG, "null device pointer");
   int rc = prepare_adjoint(c);
   if (rc) return rc;
-  HIP_TRY(c, launch_adjoint_collide(c->fp32, make_consts(c), lam, moments, mu, c->stream));
+  HIP_TRY(c, launch_adjoint_collide(c->fp32, c->model, make_consts(c), lam, moments, mu,
+                                    c->stream));
   return SLLBM_OK;
 }
 
@@ -836,20 +839,23 @@ int sllbm_adjoint_step(sllbm_ctx *c, const void *mu, const double *moments_prev,
   if (rc) return rc;
   const bool tiled = c->path != SLLBM_PATH_DIRECT && c->win_rowsT <= 3 * kTileRows &&
                      c->win_colsT <= kMaxWindowCols;
-  HIP_TRY(c, launch_adjoint_step(c->fp32, tiled, make_consts(c), make_adjoint_tables(c), mu,
-                                 moments_prev, out, c->stream));
+  HIP_TRY(c, launch_adjoint_step(c->fp32, c->model, tiled, make_consts(c),
+                                 make_adjoint_tables(c), mu, moments_prev, out, c->stream));
   return SLLBM_OK;
 }
 
 int sllbm_eq_init_vjp(sllbm_ctx *c, const void *lam0, const double *rho0, const double *ux0,
-                      const double *uy0, double *g_rho0, double *g_ux0, double *g_uy0) {
+                      const double *uy0, const double *T0, double *g_rho0, double *g_ux0,
+                      double *g_uy0, double *g_T0) {
   if (!c) return SLLBM_E_ARG;
   if (!lam0 || !rho0 || !ux0 || !uy0 || !g_rho0 || !g_ux0 || !g_uy0)
     return fail(c, SLLBM_E_ARG, "null device pointer");
+  if (c->model != SLLBM_ISOTHERMAL && !T0)
+    return fail(c, SLLBM_E_ARG, "the initial temperature is needed unless isothermal");
   int rc = prepare_adjoint(c);
   if (rc) return rc;
-  HIP_TRY(c, launch_eq_init_vjp(c->fp32, make_consts(c), lam0, rho0, ux0, uy0, g_rho0, g_ux0,
-                                g_uy0, c->stream));
+  HIP_TRY(c, launch_eq_init_vjp(c->fp32, c->model, make_consts(c), lam0, rho0, ux0, uy0, T0,
+                                g_rho0, g_ux0, g_uy0, g_T0, c->stream));
   return SLLBM_OK;
 }
 

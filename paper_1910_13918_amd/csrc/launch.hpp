@@ -22,7 +22,8 @@ struct StepConsts {
   double rn[5];       // reference support points r_0..r_p
   double lden[5];     // 1 / prod_{n != m} (r_m - r_n)
   int perx, pery;     // periodic axes
-  double *mom_out;    // optional [3][n]: rho, u_x, u_y of the streamed state
+  double *mom_out;    // optional [K][n]: rho, u_x, u_y (and theta unless isothermal) of
+                      // the streamed state
 };
 
 // Device-side departure data.  Per-axis tables are laid out [comp][m][node]
@@ -78,19 +79,24 @@ hipError_t launch_sum(const double *partial, int n, double *out, hipStream_t s);
 // flag = 0 (a kernel, not a memset, so the call can live inside a captured graph)
 hipError_t launch_clear_flag(int *flag, hipStream_t s);
 
-// ---- adjoint of the isothermal step (adjoint.hip) ----
-// lam = d L / d F from d L / d (rho, u_x, u_y) of the current populations
-hipError_t launch_adjoint_seed(int fp32, const StepConsts &c, const void *f, const double *g_rho,
-                               const double *g_ux, const double *g_uy, void *lam, hipStream_t s);
-// mu = J_C(M)^T lam, node by node (M: [3][n] moments of the streamed state)
-hipError_t launch_adjoint_collide(int fp32, const StepConsts &c, const void *lam,
+// ---- adjoint of the step (adjoint.hip), every model ----
+// lam = d L / d F from d L / d (rho, u_x, u_y, theta) of the current populations
+// (g_th may be null: no temperature term)
+hipError_t launch_adjoint_seed(int fp32, int model, const StepConsts &c, const void *f,
+                               const double *g_rho, const double *g_ux, const double *g_uy,
+                               const double *g_th, void *lam, hipStream_t s);
+// mu = J_C(M)^T lam, node by node (M: [K][n] moments of the streamed state,
+// K = 3 isothermal, 4 with theta)
+hipError_t launch_adjoint_collide(int fp32, int model, const StepConsts &c, const void *lam,
                                   const double *mom, void *mu, hipStream_t s);
 // out = S^T mu (transposed tables t), then J_C(M_prev)^T when mom_prev is given
-hipError_t launch_adjoint_step(int fp32, bool tiled, const StepConsts &c, const DevTables &t,
-                               const void *mu, const double *mom_prev, void *out, hipStream_t s);
-// gradients of sum_i lam_i f_eq_i(rho0, u0) with respect to rho0 and u0
-hipError_t launch_eq_init_vjp(int fp32, const StepConsts &c, const void *lam, const double *rho0,
-                              const double *ux0, const double *uy0, double *g_rho,
-                              double *g_ux, double *g_uy, hipStream_t s);
+hipError_t launch_adjoint_step(int fp32, int model, bool tiled, const StepConsts &c,
+                               const DevTables &t, const void *mu, const double *mom_prev,
+                               void *out, hipStream_t s);
+// gradients of sum_i lam_i f_eq_i (+ g_eq_i) with respect to rho0, u0 and theta0
+hipError_t launch_eq_init_vjp(int fp32, int model, const StepConsts &c, const void *lam,
+                              const double *rho0, const double *ux0, const double *uy0,
+                              const double *th0, double *g_rho, double *g_ux, double *g_uy,
+                              double *g_th, hipStream_t s);
 
 }  // namespace sllbm

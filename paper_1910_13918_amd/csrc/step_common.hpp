@@ -199,6 +199,7 @@ __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][25],
     c.mom_out[v] = m[0];
     c.mom_out[c.n + v] = m[1];
     c.mom_out[2 * c.n + v] = m[2];
+    if (MODEL != kIsothermal) c.mom_out[3 * c.n + v] = m[3];
   }
   const bool ok = (m[0] > 0.0) && (m[3] > 0.0) && isfinite(m[0]) && isfinite(m[1]) &&
                   isfinite(m[2]) && isfinite(m[3]);

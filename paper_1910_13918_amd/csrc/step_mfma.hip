@@ -59,17 +59,12 @@ hipError_t launch_mfma(const StepConsts &c, const DevTables &t, const float *in,
   const int ntx = (c.nx + 63) / 64, nty = (c.ny + TY - 1) / TY;
   const int grid = ((ntx * nty + 7) / 8) * 8;
   const dim3 block(64, TY);
-  const size_t lds5 = tiled_lds_bytes(sizeof(float), S, 5, t.win_rows, PITCH, true);
-  if (lds5 <= kTiledLdsBudget) {
-    k_step_mfma<P, MODEL, HALO, 5, R><<<grid, block, lds5, s>>>(
-        in, out, t.xrel, static_cast<const float *>(t.xw), t.xwin, t.yrel,
-        static_cast<const float *>(t.yw), t.ywin, t.win_rows, ntx, nty, c, flag);
-  } else {
-    const size_t lds1 = tiled_lds_bytes(sizeof(float), S, 1, t.win_rows, PITCH, true);
-    k_step_mfma<P, MODEL, HALO, 1, R><<<grid, block, lds1, s>>>(
-        in, out, t.xrel, static_cast<const float *>(t.xw), t.xwin, t.yrel,
-        static_cast<const float *>(t.yw), t.ywin, t.win_rows, ntx, nty, c, flag);
-  }
+  constexpr int G =
+      tiled_lds_bytes(sizeof(float), S, 5, R * TY, PITCH, true) <= kTiledLdsBudget ? 5 : 1;
+  const size_t lds = tiled_lds_bytes(sizeof(float), S, G, t.win_rows, PITCH, true);
+  k_step_mfma<P, MODEL, HALO, G, R><<<grid, block, lds, s>>>(
+      in, out, t.xrel, static_cast<const float *>(t.xw), t.xwin, t.yrel,
+      static_cast<const float *>(t.yw), t.ywin, t.win_rows, ntx, nty, c, flag);
   return hipGetLastError();
 }
 

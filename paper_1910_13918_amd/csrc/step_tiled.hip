@@ -41,21 +41,16 @@ hipError_t launch_tiled(const StepConsts &c, const DevTables &t, const T *in, T 
   constexpr int TY = kTileRowsTY;
   constexpr int S = Sets<MODEL>::S;
   constexpr bool SEP = P + 1 >= kSeparableTaps;
+  // all five x-components per phase when the LDS buffers of the tallest
+  // window this instantiation serves (R TY rows) fit, else one
+  constexpr int G = tiled_lds_bytes(sizeof(T), S, 5, R * TY, 64 + HALO, SEP) <= kTiledLdsBudget
+                        ? 5 : 1;
   const int ntx = (c.nx + 63) / 64, nty = (c.ny + TY - 1) / TY;
   const int grid = ((ntx * nty + 7) / 8) * 8;
-  const dim3 block(64, TY);
-  // all five x-components per phase when the LDS buffers fit, else one
-  const size_t lds5 = tiled_lds_bytes(sizeof(T), S, 5, t.win_rows, 64 + HALO, SEP);
-  if (lds5 <= kTiledLdsBudget) {
-    k_step_tiled<T, P, MODEL, TY, HALO, 5, R><<<grid, block, lds5, s>>>(
-        in, out, t.xrel, static_cast<const T *>(t.xw), t.xwin, t.yrel,
-        static_cast<const T *>(t.yw), t.ywin, t.win_rows, ntx, nty, c, flag);
-  } else {
-    const size_t lds1 = tiled_lds_bytes(sizeof(T), S, 1, t.win_rows, 64 + HALO, SEP);
-    k_step_tiled<T, P, MODEL, TY, HALO, 1, R><<<grid, block, lds1, s>>>(
-        in, out, t.xrel, static_cast<const T *>(t.xw), t.xwin, t.yrel,
-        static_cast<const T *>(t.yw), t.ywin, t.win_rows, ntx, nty, c, flag);
-  }
+  const size_t lds = tiled_lds_bytes(sizeof(T), S, G, t.win_rows, 64 + HALO, SEP);
+  k_step_tiled<T, P, MODEL, TY, HALO, G, R><<<grid, dim3(64, TY), lds, s>>>(
+      in, out, t.xrel, static_cast<const T *>(t.xw), t.xwin, t.yrel, static_cast<const T *>(t.yw),
+      t.ywin, t.win_rows, ntx, nty, c, flag);
   return hipGetLastError();
 }
 

@@ -349,7 +349,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
 // LDS bytes of a tiled launch: two raw window buffers (S G planes of W rows
 // of `pitch` columns), 64 spare slots, and for the separable forms the
 // x-pass buffer.
-inline size_t tiled_lds_bytes(size_t tsize, int S, int G, int W, int pitch, bool sep) {
+constexpr size_t tiled_lds_bytes(size_t tsize, int S, int G, int W, int pitch, bool sep) {
   const size_t planes = size_t(S) * G;
   return (2 * planes * W * pitch + 64 + (sep ? planes * W * 64 : 0)) * tsize;
 }

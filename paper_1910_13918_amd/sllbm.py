@@ -90,10 +90,10 @@ _SIGS = {
     "sllbm_get_populations": ([_vp, _vp, _c], _c),
     "sllbm_set_populations": ([_vp, _vp, _c], _c),
     "sllbm_step_record": ([_vp, _i64, _vp], _c),
-    "sllbm_adjoint_seed": ([_vp, _vp, _vp, _vp, _vp], _c),
+    "sllbm_adjoint_seed": ([_vp, _vp, _vp, _vp, _vp, _vp], _c),
     "sllbm_adjoint_collide": ([_vp, _vp, _vp, _vp], _c),
     "sllbm_adjoint_step": ([_vp, _vp, _vp, _vp], _c),
-    "sllbm_eq_init_vjp": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _c),
+    "sllbm_eq_init_vjp": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _c),
 }
 
 for _name, (_args, _res) in _SIGS.items():
@@ -242,8 +242,8 @@ def sllbm_step_record(ctx, n, moments_ptr):
     return check(ctx, lib.sllbm_step_record(ctx, n, moments_ptr))
 
 
-def sllbm_adjoint_seed(ctx, g_rho_ptr, g_ux_ptr, g_uy_ptr, lam_ptr):
-    return check(ctx, lib.sllbm_adjoint_seed(ctx, g_rho_ptr, g_ux_ptr, g_uy_ptr, lam_ptr))
+def sllbm_adjoint_seed(ctx, g_rho_ptr, g_ux_ptr, g_uy_ptr, g_T_ptr, lam_ptr):
+    return check(ctx, lib.sllbm_adjoint_seed(ctx, g_rho_ptr, g_ux_ptr, g_uy_ptr, g_T_ptr, lam_ptr))
 
 
 def sllbm_adjoint_collide(ctx, lam_ptr, moments_ptr, mu_ptr):
@@ -254,6 +254,7 @@ def sllbm_adjoint_step(ctx, mu_ptr, moments_prev_ptr, out_ptr):
     return check(ctx, lib.sllbm_adjoint_step(ctx, mu_ptr, moments_prev_ptr, out_ptr))
 
 
-def sllbm_eq_init_vjp(ctx, lam0_ptr, rho0_ptr, ux0_ptr, uy0_ptr, g_rho_ptr, g_ux_ptr, g_uy_ptr):
-    return check(ctx, lib.sllbm_eq_init_vjp(ctx, lam0_ptr, rho0_ptr, ux0_ptr, uy0_ptr, g_rho_ptr,
-                                            g_ux_ptr, g_uy_ptr))
+def sllbm_eq_init_vjp(ctx, lam0_ptr, rho0_ptr, ux0_ptr, uy0_ptr, T0_ptr, g_rho_ptr, g_ux_ptr,
+                      g_uy_ptr, g_T_ptr):
+    return check(ctx, lib.sllbm_eq_init_vjp(ctx, lam0_ptr, rho0_ptr, ux0_ptr, uy0_ptr, T0_ptr,
+                                            g_rho_ptr, g_ux_ptr, g_uy_ptr, g_T_ptr))

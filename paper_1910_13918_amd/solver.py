@@ -141,10 +141,17 @@ class Solver:
     def step(self, n=1):
         C.sllbm_step(self.ctx, n)
 
+    @property
+    def recorded_moments(self):
+        """Moments per node and step of step_record: rho, u_x, u_y (+ theta)."""
+        return 3 if self.model == "isothermal" else 4
+
     def step_record(self, n):
-        """Advance n steps and return the moments (rho, u_x, u_y) of each step's
-        streamed state as a device tensor [n, 3, nodes] (float64)."""
-        m = torch.empty((n, 3, self.n), dtype=torch.float64, device=self.device)
+        """Advance n steps and return the moments (rho, u_x, u_y and, unless
+        isothermal, theta) of each step's streamed state as a device tensor
+        [n, K, nodes] (float64)."""
+        m = torch.empty((n, self.recorded_moments, self.n), dtype=torch.float64,
+                        device=self.device)
         C.sllbm_step_record(self.ctx, n, m.data_ptr())
         return m
 

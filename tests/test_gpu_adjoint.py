@@ -200,3 +200,114 @@ def test_adjoint_workload_against_central_differences():
     finally:
         s.close()
     assert isinstance(Solver, type)
+
+
+# ---------------------------------------------------------------- thermal models
+def _thermal(wl, model, periodic=None):
+    wl.model = model
+    if periodic is not None:
+        wl.periodic_x = wl.periodic_y = periodic
+    base = wl.fields
+
+    def fields(x, y):
+        rho, ux, uy, _ = base(x, y)
+        return rho, ux, uy, 1.0 + 0.1 * np.cos(2.0 * x) * np.sin(y)
+
+    wl.fields = fields
+    return wl
+
+
+THERMAL = [
+    ("monatomic", lambda: _thermal(W.tgv(9, 3, U0=0.3), "monatomic")),
+    ("polyatomic", lambda: _thermal(W.riemann(14, 2, states=W.RIEMANN_TABLE3_STATES),
+                                    "polyatomic")),
+]
+
+
+@pytest.mark.parametrize("path", ["tiled", "direct"])
+@pytest.mark.parametrize("name,make", THERMAL, ids=[t[0] for t in THERMAL])
+def test_thermal_transposed_streaming_dot_product(name, make, path):
+    from paper_1910_13918_amd import sllbm as C
+    wl = make()
+    wl.nu = np.inf
+    s = _solver(wl, "fp64", path)
+    try:
+        print(f"[gpu] thermal dot product {name} {path} nodes={s.n}", flush=True)
+        shape = (s.nsets * 25, s.n)
+        v, mu = _rand(shape, 5), _rand(shape, 6)
+        s.set_populations(v)
+        s.step(1)
+        Sv = s.populations_device().reshape(shape)
+        StMu = torch.empty_like(mu)
+        C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, StMu.data_ptr())
+        torch.cuda.synchronize()
+        assert float((mu * Sv).sum()) == pytest.approx(float((StMu * v).sum()), rel=1e-12)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("name,make", THERMAL, ids=[t[0] for t in THERMAL])
+def test_thermal_one_step_adjoint_against_central_differences(name, make):
+    from paper_1910_13918_amd import sllbm as C
+    wl = make()
+    s = _solver(wl, "fp64")
+    try:
+        s.init_from_workload()
+        s.step(3)
+        F = s.populations_device().clone()
+        shape = tuple(F.shape)
+        lam = _rand(shape, 7)
+        v = _rand(shape, 8) * F.abs().mean()
+        s.set_populations(F)
+        mom = s.step_record(1)
+        assert mom.shape[1] == 4
+        mu, out = torch.empty_like(lam), torch.empty_like(lam)
+        C.sllbm_adjoint_collide(s.ctx, lam.data_ptr(), mom[0].data_ptr(), mu.data_ptr())
+        C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, out.data_ptr())
+        torch.cuda.synchronize()
+        adj = float((out * v).sum())
+
+        def g(e):
+            s.set_populations(F + e * v)
+            s.step(1)
+            return float((lam * s.populations_device()).sum())
+
+        fd = (g(1e-6) - g(-1e-6)) / 2e-6
+        assert adj == pytest.approx(fd, rel=1e-6)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("model", ["monatomic", "polyatomic"])
+def test_thermal_rollout_gradient_matches_complex_step(model):
+    """8 x 8 cells p = 2, periodic, 12 steps with checkpoints every 5: the
+    gradient with respect to (rho0, u0, v0, T0) of the kinetic energy + velocity
+    and temperature misfit, along seeded directions, against the oracle's
+    complex-step derivative."""
+    from oracle.adjoint import complex_step_fields, thermal_misfit_loss
+    from paper_1910_13918_amd.adjoint import rollout
+    wl = _thermal(W.tgv(8, 2, U0=0.3, steps=12), model, periodic=True)
+    s = _solver(wl, "fp64")
+    try:
+        X, Y = s.coords()
+        f0 = wl.fields(X, Y)
+        ut, vt = W.fourier_target(X, Y, 0.3, seed=1234)
+        Tt = 1.0 + 0.05 * np.sin(X)
+        t = lambda a: torch.tensor(a, device="cuda")
+        leaves = [t(a).requires_grad_(True) for a in f0]
+        rho, ux, uy, T = rollout(leaves[0], leaves[1], leaves[2], s, 12, 5, T0=leaves[3])
+        M = _mass_weights(s)
+        L = _loss_torch(rho, ux, uy, M, t(ut), t(vt)) + (M * (T - t(Tt)) ** 2).sum()
+        L.backward()
+        grads = [a.grad.detach().cpu().numpy() for a in leaves]
+    finally:
+        s.close()
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, True, True)
+    sim = Sim(g, wl.dt, wl.nu, model, gamma=wl.gamma)
+    loss = lambda sm, F: thermal_misfit_loss(sm, F, ut, vt, Tt)
+    rng = np.random.default_rng(77)
+    for _ in range(3):
+        d = [rng.standard_normal(g.nnodes) for _ in range(4)]
+        ref = complex_step_fields(sim, f0, d, 12, loss)
+        got = sum(float(np.dot(gr, di)) for gr, di in zip(grads, d))
+        assert got == pytest.approx(ref, rel=1e-9, abs=1e-13)

@@ -259,3 +259,28 @@ def test_riemann_default_seed_is_the_accepted_one():
     assert all(not t["stable"] for t in rec["tried"][:-1]) and rec["tried"][-1]["stable"]
     np.testing.assert_array_equal(np.array(rec["states"]), np.array(W.riemann_states(rec["seed"])))
     assert W.riemann(64, 2).meta["states"] == [tuple(map(float, s)) for s in rec["states"]]
+
+
+def test_complex_step_fields_matches_finite_differences():
+    """Polyatomic model: the complex-step derivative along (rho, u, T)
+    perturbations equals central differences of the oracle (to FD accuracy)."""
+    from oracle.adjoint import complex_step_fields, thermal_misfit_loss
+    wl = W.riemann(4, 2, states=W.RIEMANN_TABLE3_STATES)
+    wl.periodic_x = wl.periodic_y = True
+    g = Grid(wl.edges_x, wl.edges_y, 2, True, True)
+    sim = Sim(g, wl.dt, wl.nu, "polyatomic", gamma=1.4)
+    X, Y = g.coords()
+    f0 = (1.0 + 0.1 * np.sin(2 * np.pi * X), 0.1 * np.cos(2 * np.pi * Y),
+          0.05 * np.sin(2 * np.pi * (X + Y)), 1.0 + 0.1 * np.cos(2 * np.pi * X))
+    rng = np.random.default_rng(5)
+    d = [rng.standard_normal(g.nnodes) for _ in range(4)]
+    tgt = (0.05 * np.sin(2 * np.pi * X), 0.0 * X, 1.0 + 0.0 * X)
+    loss = lambda sm, F: thermal_misfit_loss(sm, F, *tgt)
+    cs = complex_step_fields(sim, f0, d, 5, loss)
+
+    def L(e):
+        F = sim.run(sim.init(*(f + e * di for f, di in zip(f0, d))), 5)
+        return loss(sim, F)
+
+    fd = (L(1e-6) - L(-1e-6)) / 2e-6
+    assert cs == pytest.approx(fd, rel=1e-6)
