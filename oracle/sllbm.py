@@ -16,24 +16,31 @@ are values of the interpolant of the nodal post-collision populations):
    population (monatomic gas, C_v = D/2) the g sum is absent; isothermal
    models fix theta = 1 (Sec. III.A);
 4. BGK relaxation toward the 4th-order equilibrium with
-   tau = nu / (c_s^2 dt) + 1/2 (Sec. II.D), Prandtl number 1 so the
-   quasi-equilibrium term of eq. (16) vanishes:
-   f+ = f - (f - f_eq)/tau, g+ = g - (g - g_eq)/tau.
+   tau = nu / (c_s^2 dt) + 1/2 (Sec. II.D), plus the quasi-equilibrium term of
+   eq. (16) with tau_Pr = (tau - 1/2)/Pr + 1/2 (Sec. II.C):
+   f+ = f - (f - f_eq)/tau + (1/tau - 1/tau_Pr) f*, likewise for g; with
+   Pr = 1 the term vanishes.  Reading of the garbled f* of Sec. II.C:
+   f*_i = (w_i / 3!) Qneq : H^(3)(xi_i) with c_s = 1 (the third-order term of
+   the Hermite expansion, whose 1/n! the printed formula drops), and
+   Qneq = Q - Q_eq, Q = sum_i f_i (xi_i - u)^(x3) the centred third moment;
+   g* the same with g and its own Q.
 
 Populations are stored as an array of shape (S, Q, nnodes) with S = 1 (f) or
 S = 2 (f, g) and node index v = iy * nx + ix.
 """
+import math
+
 import numpy as np
 
 from .equilibrium import cv_of_gamma, f_eq, g_eq
 from .grid import lagrange_basis
-from .velocity import D, d1q5, tensor_product
+from .velocity import D, d1q5, hermite_tensor, index_tuples, tensor_product
 
 MODELS = ("isothermal", "monatomic", "polyatomic")
 
 
 class Sim:
-    def __init__(self, grid, dt, nu, model, gamma=1.4, xi1=None, w1=None):
+    def __init__(self, grid, dt, nu, model, gamma=1.4, xi1=None, w1=None, Pr=1.0):
         if model not in MODELS:
             raise ValueError(model)
         self.grid = grid
@@ -48,6 +55,9 @@ class Sim:
         # nu = inf means pure streaming (1/tau = 0)
         self.tau = np.inf if np.isinf(self.nu) else self.nu / self.dt + 0.5
         self.omega = 0.0 if np.isinf(self.tau) else 1.0 / self.tau
+        # Sec. II.D: tau_Pr = (tau - 1/2)/Pr + 1/2
+        self.Pr = float(Pr)
+        self.omega_pr = 0.0 if np.isinf(self.tau) else 1.0 / ((self.tau - 0.5) / self.Pr + 0.5)
         if model == "polyatomic":
             self.gamma = float(gamma)
             self.cv = cv_of_gamma(self.gamma)
@@ -128,11 +138,36 @@ class Sim:
             theta = (two_rho_e - rho * (ux * ux + uy * uy)) / (2.0 * self.cv * rho)
         return rho, ux, uy, theta
 
+    def centred_third_moment(self, f, ux, uy):
+        """Q[a][b][c] = sum_i f_i (xi_i - u)_a (xi_i - u)_b (xi_i - u)_c for
+        every node (Sec. II.C), shape (2, 2, 2, n)."""
+        c = np.stack([self.xi[:, 0, None] - ux[None], self.xi[:, 1, None] - uy[None]])  # (2, Q, n)
+        Q = np.zeros((2, 2, 2) + f.shape[1:], dtype=np.result_type(f, c))
+        for a in range(2):
+            for b in range(2):
+                for d in range(2):
+                    Q[a, b, d] = (f * c[a] * c[b] * c[d]).sum(axis=0)
+        return Q
+
+    def quasi_equilibrium(self, Qneq):
+        """f*_i = (w_i / 3!) Qneq : H^(3)(xi_i) (reading of Sec. II.C), shape (Q, n)."""
+        xT = self.xi.T
+        total = np.zeros((self.Q,) + Qneq.shape[3:], dtype=Qneq.dtype)
+        for idx in index_tuples(3):
+            total = total + np.multiply.outer(hermite_tensor(3, idx, xT), Qneq[idx])
+        return self.w[:, None] * total / math.factorial(3)
+
     def collide(self, F):
-        """BGK relaxation at the nodes (eq. (16) with Pr = 1)."""
+        """BGK relaxation at the nodes with the quasi-equilibrium term, eq. (16)."""
         rho, ux, uy, theta = self.moments(F)
         feq = self.equilibrium(rho, ux, uy, theta)
-        return F - self.omega * (F - feq)
+        out = F - self.omega * (F - feq)
+        if self.Pr != 1.0:
+            for s in range(self.S):
+                Qneq = (self.centred_third_moment(F[s], ux, uy)
+                        - self.centred_third_moment(feq[s], ux, uy))
+                out[s] = out[s] + (self.omega - self.omega_pr) * self.quasi_equilibrium(Qneq)
+        return out
 
     def step(self, F, nodes=None):
         """One full time step; with ``nodes`` only those nodes' new values are returned."""

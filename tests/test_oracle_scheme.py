@@ -284,3 +284,45 @@ def test_complex_step_fields_matches_finite_differences():
 
     fd = (L(1e-6) - L(-1e-6)) / 2e-6
     assert cs == pytest.approx(fd, rel=1e-6)
+
+
+def _pr_state(model, seed=3):
+    wl = W.riemann(3, 2, states=W.RIEMANN_TABLE3_STATES)
+    g = Grid(wl.edges_x, wl.edges_y, 2, False, False)
+    X, Y = g.coords()
+    base = Sim(g, wl.dt, wl.nu, model, gamma=1.4)
+    F = base.init(*wl.fields(X, Y)) * W.population_noise((base.S, 25, g.nnodes), seed, 0.05)
+    return g, wl, F
+
+
+@pytest.mark.parametrize("model", ["monatomic", "polyatomic"])
+def test_prandtl_term_relaxes_the_heat_flux_at_tau_pr(model):
+    """Sec. II.C-D: with Pr != 1 the collision keeps rho, rho u and the energy
+    and relaxes the non-equilibrium centred third moment with 1/tau_Pr instead
+    of 1/tau (pins the 1/3! of the f* reading), for f and for g."""
+    g, wl, F = _pr_state(model)
+    for Pr in (0.75, 1.6):
+        sim = Sim(g, wl.dt, wl.nu, model, gamma=1.4, Pr=Pr)
+        tau_pr = (sim.tau - 0.5) / Pr + 0.5
+        G = sim.collide(F)
+        m0, m1 = sim.moments(F), sim.moments(G)
+        for a, b in zip(m0, m1):
+            np.testing.assert_allclose(b, a, rtol=1e-13, atol=1e-14)
+        rho, ux, uy, theta = m0
+        feq = sim.equilibrium(rho, ux, uy, theta)
+        for s in range(sim.S):
+            Qneq = sim.centred_third_moment(F[s], ux, uy) - sim.centred_third_moment(feq[s], ux, uy)
+            Qout = sim.centred_third_moment(G[s], ux, uy) - sim.centred_third_moment(feq[s], ux, uy)
+            np.testing.assert_allclose(Qout, (1.0 - 1.0 / tau_pr) * Qneq,
+                                       atol=1e-13 * np.abs(Qneq).max())
+
+
+def test_prandtl_one_is_bgk_and_equilibrium_has_no_heat_flux():
+    g, wl, F = _pr_state("polyatomic")
+    a = Sim(g, wl.dt, wl.nu, "polyatomic", gamma=1.4)
+    b = Sim(g, wl.dt, wl.nu, "polyatomic", gamma=1.4, Pr=1.0)
+    np.testing.assert_array_equal(a.collide(F), b.collide(F))
+    rho, ux, uy, theta = a.moments(F)
+    feq = a.equilibrium(rho, ux, uy, theta)
+    # the 4th-order equilibrium reproduces the Gaussian's (zero) centred third moment
+    assert np.abs(a.centred_third_moment(feq[0], ux, uy)).max() < 1e-14
