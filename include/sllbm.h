@@ -16,8 +16,12 @@
  *      the second population g relaxes toward g_eq = (2 C_v - D) theta f_eq
  *      (Sec. II.D, eq. (15)).
  * The collision acts on node values and the interpolant of the post-collision
- * field is what is streamed.  The Prandtl number is 1 (the quasi-equilibrium
- * term of eq. (16) vanishes).  Code units: c_s = R = T0 = 1, D = 2.
+ * field is what is streamed.  For Pr != 1 the collision adds the
+ * quasi-equilibrium term of eq. (16), (1/tau - 1/tau_Pr) f*, with
+ * f*_i = (w_i/3!) Q^neq : H^(3)(xi_i) built from the centred third moment
+ * Q^neq = sum_i (f_i - f_eq_i)(xi_i - u)^3 of each population set and
+ * tau_Pr = (tau - 1/2)/Pr + 1/2 (Sec. II.C-D), so that the heat flux relaxes
+ * at 1/tau_Pr.  Code units: c_s = R = T0 = 1, D = 2.
  *
  * Conventions
  *   - Every function returns an sllbm_status; nothing throws or aborts across
@@ -142,7 +146,13 @@ int sllbm_init_grid_mapped(sllbm_ctx *ctx, int ncx, int ncy, const double *edges
 
 /* Time step dt > 0, kinematic viscosity nu > 0 (nu = +inf: no collision,
  * pure streaming), heat-capacity ratio gamma > 1 (used by SLLBM_POLYATOMIC
- * only), Prandtl number (only 1 is supported), model (sllbm_model). */
+ * only), Prandtl number Pr > 0, model (sllbm_model).  Pr != 1 needs a
+ * thermal model (SLLBM_E_ARG for SLLBM_ISOTHERMAL) and a 1-D
+ * velocity set that integrates the Gaussian's moments exactly up to degree 7
+ * (the default set does), so that the equilibrium has no centred third
+ * moment; SLLBM_E_UNSUPPORTED otherwise (also from a later
+ * sllbm_set_velocity_set that breaks it).  The adjoint calls below refuse
+ * Pr != 1 (SLLBM_E_UNSUPPORTED). */
 int sllbm_set_physics(sllbm_ctx *ctx, double dt, double nu, double gamma, double Pr, int model);
 
 /* Streaming kernel family (sllbm_path).  SLLBM_PATH_TILED needs departures
@@ -236,8 +246,9 @@ int sllbm_mass(sllbm_ctx *ctx, double *mass);
 int sllbm_get_populations(sllbm_ctx *ctx, void *dst, int on_device);
 int sllbm_set_populations(sllbm_ctx *ctx, const void *src, int on_device);
 
-/* ---- adjoint of the step (every model) ----
- * The paper has no adjoint; these calls differentiate exactly the step above.
+/* ---- adjoint of the step (every model, Pr = 1) ----
+ * The paper has no adjoint; these calls differentiate exactly the step above
+ * with Pr = 1 (SLLBM_E_UNSUPPORTED otherwise).
  * One step is F' = C(S F) with S the interpolation of every population plane
  * (Sec. II.E, eq. (17)) and C the BGK collision (Sec. II.D, eq. (16)).
  * Reverse sweep:  mu^n = J_C(M^n)^T lambda^{n+1},  lambda^n = S^T mu^n,

@@ -43,7 +43,7 @@ struct sllbm_ctx {
   bool have_grid = false;
   Axis ax, ay;
   bool have_phys = false;
-  double dt = 0, nu = 0, gamma = 1.4, Pr = 1.0, tau = 0, omega = 0;
+  double dt = 0, nu = 0, gamma = 1.4, Pr = 1.0, tau = 0, omega = 0, omega_pr = 0;
   int model = 0;
   int path = SLLBM_PATH_AUTO;
   int64_t check_interval = 0;
@@ -300,6 +300,7 @@ StepConsts make_consts(const sllbm_ctx *c) {
   k.ncy = c->ay.ncells;
   k.p = c->p;
   k.omega = c->omega;
+  k.omega_pr = c->omega_pr;
   const double D = kDim;
   double cv = D / 2.0;  // monatomic: C_v = D/2 (R = 1)
   if (c->model == SLLBM_POLYATOMIC) cv = 1.0 / (c->gamma - 1.0);
@@ -410,6 +411,8 @@ void pad_taps(AxisTable &t, const Axis &ax, int taps) {
 int prepare_adjoint(sllbm_ctx *c) {
   int rc = prepare_device(c);
   if (rc) return rc;
+  if (c->omega_pr != c->omega)
+    return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers Pr = 1 only");
   if (!c->adj_dirty) return SLLBM_OK;
   int taps = 0;
   for (int a = 0; a < kQ1; ++a) {
@@ -517,6 +520,9 @@ int sllbm_set_velocity_set(sllbm_ctx *c, int q1d, const double *xi1d, const doub
     vs.w[a] = w1d[a];
   }
   fill_hermite_constants(vs);
+  if (c->have_phys && c->Pr != 1.0 && !gaussian_exact_to_degree(vs, 7))
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "Pr != 1 needs a velocity set exact to degree 7 (zero equilibrium heat flux)");
   c->vs = vs;
   invalidate(c);
   return SLLBM_OK;
@@ -603,7 +609,11 @@ int sllbm_set_physics(sllbm_ctx *c, double dt, double nu, double gamma, double P
   if (model == SLLBM_POLYATOMIC && (!is_finite(gamma) || !(gamma > 1.0)))
     return fail(c, SLLBM_E_ARG, "gamma must be finite and > 1");
   if (!is_finite(Pr) || !(Pr > 0)) return fail(c, SLLBM_E_ARG, "Pr must be positive and finite");
-  if (Pr != 1.0) return fail(c, SLLBM_E_UNSUPPORTED, "only Pr = 1 is implemented");
+  if (Pr != 1.0 && model == SLLBM_ISOTHERMAL)
+    return fail(c, SLLBM_E_ARG, "Pr != 1 needs a thermal model (no energy equation otherwise)");
+  if (Pr != 1.0 && !gaussian_exact_to_degree(c->vs, 7))
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "Pr != 1 needs a velocity set exact to degree 7 (zero equilibrium heat flux)");
   c->dt = dt;
   c->nu = nu;
   c->gamma = gamma;
@@ -611,6 +621,8 @@ int sllbm_set_physics(sllbm_ctx *c, double dt, double nu, double gamma, double P
   c->model = model;
   c->tau = std::isinf(nu) ? std::numeric_limits<double>::infinity() : nu / dt + 0.5;
   c->omega = std::isinf(nu) ? 0.0 : 1.0 / c->tau;
+  // tau_Pr = (tau - 1/2)/Pr + 1/2 (Sec. II.D); exactly omega when Pr = 1
+  c->omega_pr = (Pr == 1.0 || std::isinf(nu)) ? c->omega : 1.0 / ((c->tau - 0.5) / Pr + 0.5);
   c->have_phys = true;
   invalidate(c);
   return SLLBM_OK;

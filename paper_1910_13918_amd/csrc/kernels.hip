@@ -114,6 +114,15 @@ hipError_t launch_init_eq(int fp32, int model, const StepConsts &c, const double
 
 hipError_t launch_step(int fp32, int model, int path, const StepConsts &c, const DevTables &t,
                        const void *fin, void *fout, int *flag, hipStream_t s) {
+  if (c.omega_pr != c.omega) {  // Pr != 1: quasi-equilibrium collision
+    switch (path) {
+      case kPathDirect: return launch_step_direct_pr(fp32, model, c, t, fin, fout, flag, s);
+      case kPathTiled: return launch_step_tiled_pr(fp32, model, c, t, fin, fout, flag, s);
+      case kPathRecords: return launch_step_records_pr(fp32, model, c, t, fin, fout, flag, s);
+      case kPathMfma: return launch_step_mfma_pr(fp32, model, c, t, fin, fout, flag, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (path) {
     case kPathDirect: return launch_step_direct(fp32, model, c, t, fin, fout, flag, s);
     case kPathTiled: return launch_step_tiled(fp32, model, c, t, fin, fout, flag, s);

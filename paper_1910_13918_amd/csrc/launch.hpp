@@ -13,6 +13,7 @@ struct StepConsts {
   long long n;        // nx * ny
   int ncx, ncy, p;
   double omega;       // 1 / tau
+  double omega_pr;    // 1 / tau_Pr, tau_Pr = (tau - 1/2)/Pr + 1/2 (= omega when Pr = 1)
   double gfac;        // 2 C_v - D  (g_eq = gfac * theta * f_eq)
   double inv_2cv;     // 1 / (2 C_v)  (theta from the energy moment)
   double xi[5];       // 1-D abscissae
@@ -67,6 +68,15 @@ hipError_t launch_step_records(int fp32, int model, const StepConsts &c, const D
                                const void *fin, void *fout, int *flag, hipStream_t s);
 hipError_t launch_step_mfma(int fp32, int model, const StepConsts &c, const DevTables &t,
                             const void *fin, void *fout, int *flag, hipStream_t s);
+// the same with the quasi-equilibrium (Pr != 1) collision; thermal models only
+hipError_t launch_step_direct_pr(int fp32, int model, const StepConsts &c, const DevTables &t,
+                                 const void *fin, void *fout, int *flag, hipStream_t s);
+hipError_t launch_step_tiled_pr(int fp32, int model, const StepConsts &c, const DevTables &t,
+                                const void *fin, void *fout, int *flag, hipStream_t s);
+hipError_t launch_step_records_pr(int fp32, int model, const StepConsts &c, const DevTables &t,
+                                  const void *fin, void *fout, int *flag, hipStream_t s);
+hipError_t launch_step_mfma_pr(int fp32, int model, const StepConsts &c, const DevTables &t,
+                               const void *fin, void *fout, int *flag, hipStream_t s);
 
 // Moments per node (any output pointer may be null) and per-block partial
 // sums of M_v rho_v into `partial` (mass_blocks(c) entries).

@@ -185,11 +185,121 @@ __device__ __forceinline__ void for_each_equilibrium(double rho, double ux, doub
   }
 }
 
-// Moments, stability flag, equilibrium and BGK relaxation of one node's
+// Centred third moments of one population set about u (Sec. II.C):
+// q[k] = sum_i f_i (xi_a - u_x)^k (xi_b - u_y)^(3-k), k = 0..3
+// (Q_yyy, Q_xyy, Q_xxy, Q_xxx).
+template <typename T>
+__device__ __forceinline__ void centred_third_moments(const T (&f)[25], double ux, double uy,
+                                                      const StepConsts &c, double (&q)[4]) {
+  q[0] = q[1] = q[2] = q[3] = 0.0;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      T fr = f[a + 5 * b];
+      asm volatile("" : "+v"(fr));  // convert again: the moments' doubles are not kept alive
+      const double v = double(fr);
+      const double cx = c.xi[a] - ux;
+      s0 += v;
+      s1 = fma(cx, v, s1);
+      s2 = fma(cx * cx, v, s2);
+      s3 = fma(cx * cx * cx, v, s3);
+    }
+    const double cy = c.xi[b] - uy;
+    q[3] += s3;
+    q[2] = fma(s2, cy, q[2]);
+    q[1] = fma(s1, cy * cy, q[1]);
+    q[0] = fma(s0, cy * cy * cy, q[0]);
+  }
+}
+
+// Quasi-equilibrium population of velocity i = a + 5b from the row factors
+// y[k] = kappa Q_{k,3-k} He_{3-k}(xi_b)/(3-k)!:  kappa f*_i with
+// f*_i = (w_i / 3!) Q : H^(3)(xi_i).  Grouping the 8 index triples by their
+// number k of x indices, H^(3) = He_k(xi_a) He_{3-k}(xi_b) with multiplicity
+// 3!/(k!(3-k)!), so
+// f*_i = w_b sum_k (w_a He_k(xi_a)/k!) (He_{3-k}(xi_b)/(3-k)!) Q_{k,3-k}.
+__device__ __forceinline__ double quasi_equilibrium(const double (&y)[4], int i,
+                                                    const StepConsts &c) {
+  const int a = i % 5, b = i / 5;
+  double s = c.whk[a][0] * y[0];
+#pragma unroll
+  for (int k = 1; k < 4; ++k) s = fma(c.whk[a][k], y[k], s);
+  return c.w[b] * s;
+}
+
+// Relaxation and store of one node (m: its moments).  With PR the heat
+// flux relaxes at 1/tau_Pr instead of 1/tau (Sec. II.C-D, eq. (16)):
+// f+ = f + (f_eq - f)/tau + (1/tau - 1/tau_Pr) f*, f* built from the
+// non-equilibrium centred third moment of the set.  The equilibrium itself
+// has none (the D1Q5 rule integrates degree 7 exactly and the 4th-order
+// expansion carries the Gaussian's moments to order 4; the host refuses
+// Pr != 1 with a rule that does not), so Q^neq is the moment of f.
+template <typename T, int MODEL, bool PR>
+__device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][25],
+                                            const double (&m)[4], const StepConsts &c,
+                                            T *__restrict__ fout, long long v) {
+  constexpr int S = Sets<MODEL>::S;
+  const long long N = c.n;
+  const double om = c.omega;
+  const double gf = c.gfac * m[3];
+  double qf[4], qg[4];
+  if (PR) {
+    const double kq = c.omega - c.omega_pr;
+    centred_third_moments<T>(fs[0], m[1], m[2], c, qf);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qf[k] *= kq;
+    if (S == 2) {
+      centred_third_moments<T>(fs[S - 1], m[1], m[2], c, qg);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) qg[k] *= kq;
+    }
+  }
+  // one 32-bit lane offset for every plane; the plane base lives in the
+  // (scalar) buffer resource
+  const unsigned voff = unsigned(v) * unsigned(sizeof(T));
+  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
+  double yf[4], yg[4];
+  for_each_equilibrium(m[0], m[1], m[2], m[3], c, [&](int i, double feq) {
+    if (PR && i % 5 == 0) {  // row factors of velocity row b, made when the row starts
+      const int b = i / 5;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        yf[k] = qf[k] * c.hk[b][3 - k];
+        asm volatile("" : "+v"(yf[k]));
+        if (S == 2) {
+          yg[k] = qg[k] * c.hk[b][3 - k];
+          asm volatile("" : "+v"(yg[k]));
+        }
+      }
+    }
+    // convert again rather than keep the moments' 25 (50) doubles alive
+    T fr = fs[0][i];
+    asm volatile("" : "+v"(fr));
+    const double f = double(fr);
+    double fo = fma(om, feq - f, f);
+    if (PR) fo += quasi_equilibrium(yf, i, c);
+    buffer_store<T>(T(fo), make_rsrc(fout + i * N, plane_bytes), voff, 0);
+    if (S == 2) {
+      T gr = fs[S - 1][i];
+      asm volatile("" : "+v"(gr));
+      const double g = double(gr);
+      double go = fma(om, gf * feq - g, g);
+      if (PR) go += quasi_equilibrium(yg, i, c);
+      buffer_store<T>(T(go), make_rsrc(fout + (25 + i) * N, plane_bytes), voff, 0);
+    }
+  });
+}
+
+// Moments, stability flag, equilibrium and relaxation of one node's
 // streamed populations; stores the post-collision values at node v
-// (Sec. II.D, eq. (16) with Pr = 1):  f+ = f + (f_eq - f)/tau,
-// g+ = g + (g_eq - g)/tau, g_eq = (2 C_v - D) theta f_eq.
-template <typename T, int MODEL>
+// (Sec. II.D, eq. (16)):  f+ = f + (f_eq - f)/tau, g+ = g + (g_eq - g)/tau,
+// g_eq = (2 C_v - D) theta f_eq, plus the quasi-equilibrium term when PR
+// (Pr != 1).  PR is a kernel template parameter rather than a runtime
+// branch: holding both variants in one kernel costs the Pr = 1 kernels
+// registers and occupancy.
+template <typename T, int MODEL, bool PR = false>
 __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][25],
                                               const StepConsts &c, T *__restrict__ fout,
                                               long long v, int *__restrict__ flag) {
@@ -204,27 +314,7 @@ __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][25],
   const bool ok = (m[0] > 0.0) && (m[3] > 0.0) && isfinite(m[0]) && isfinite(m[1]) &&
                   isfinite(m[2]) && isfinite(m[3]);
   if (!ok) atomicOr(flag, 1);
-  const long long N = c.n;
-  const double om = c.omega;
-  const double gf = c.gfac * m[3];
-  // one 32-bit lane offset for every plane; the plane base lives in the
-  // (scalar) buffer resource
-  const unsigned voff = unsigned(v) * unsigned(sizeof(T));
-  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
-  for_each_equilibrium(m[0], m[1], m[2], m[3], c, [&](int i, double feq) {
-    // convert again rather than keep the moments' 25 (50) doubles alive
-    T fr = fs[0][i];
-    asm volatile("" : "+v"(fr));
-    const double f = double(fr);
-    buffer_store<T>(T(fma(om, feq - f, f)), make_rsrc(fout + i * N, plane_bytes), voff, 0);
-    if (Sets<MODEL>::S == 2) {
-      T gr = fs[1][i];
-      asm volatile("" : "+v"(gr));
-      const double g = double(gr);
-      buffer_store<T>(T(fma(om, gf * feq - g, g)), make_rsrc(fout + (25 + i) * N, plane_bytes),
-                      voff, 0);
-    }
-  });
+  relax_store<T, MODEL, PR>(fs, m, c, fout, v);
 }
 
 // Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
@@ -250,8 +340,9 @@ __device__ __forceinline__ double block_sum_256(double v) {
 }
 
 // Calls f.template operator()<T, P, MODEL>() for the runtime population type
-// (float / double), order p and model.
-template <class F>
+// (float / double), order p and model; THERMAL_ONLY instantiates nothing for
+// the isothermal model (which then gets hipErrorInvalidValue).
+template <bool THERMAL_ONLY = false, class F>
 hipError_t dispatch_step(int fp32, int p, int model, F &&f) {
   auto by_p = [&]<typename T, int MODEL>() -> hipError_t {
     switch (p) {
@@ -264,7 +355,9 @@ hipError_t dispatch_step(int fp32, int p, int model, F &&f) {
   };
   auto by_model = [&]<typename T>() -> hipError_t {
     switch (model) {
-      case kIsothermal: return by_p.template operator()<T, kIsothermal>();
+      case kIsothermal:
+        if constexpr (THERMAL_ONLY) return hipErrorInvalidValue;
+        else return by_p.template operator()<T, kIsothermal>();
       case kMonatomic: return by_p.template operator()<T, kMonatomic>();
       case kPolyatomic: return by_p.template operator()<T, kPolyatomic>();
     }

@@ -1,107 +1,11 @@
-// Stream + collide: general gather through per-(node, velocity) departure
-// records (HIP, gfx950).
-#include <hip/hip_runtime.h>
-
-#include "launch.hpp"
-#include "step_common.hpp"
+// BGK (Pr = 1) instantiation of the records stream + collide kernels.
+#include "step_records.hpp"
 
 namespace sllbm {
 
-// ---------------------------------------------------------------------------
-// stream + collide, general gather through per-(node, velocity) records
-// (departure cell and reference coordinates; weights evaluated here)
-// ---------------------------------------------------------------------------
-// The p+1 stencil columns of a departure cell are consecutive nodes except
-// when the cell is the last one before a periodic seam (its right vertex is
-// node 0): rows are then read one value at a time, in a wave-uniform branch.
-template <typename T, int P1, bool SEAM>
-__device__ __forceinline__ T records_interp(__amdgpu_buffer_rsrc_t rs, const unsigned (&xo)[P1],
-                                            const unsigned (&yo)[P1], const T (&wx)[P1],
-                                            const T (&wy)[P1]) {
-  T acc = T(0);
-#pragma unroll
-  for (int n = 0; n < P1; ++n) {
-    T v[P1];
-    if constexpr (SEAM) {
-#pragma unroll
-      for (int m = 0; m < P1; ++m) v[m] = buffer_load<T>(rs, yo[n] + xo[m], 0);
-    } else {
-      buffer_load_run<T, P1>(rs, yo[n] + xo[0], 0, v);
-    }
-    T row = T(0);
-#pragma unroll
-    for (int m = 0; m < P1; ++m) row = fma(wx[m], v[m], row);
-    acc = fma(wy[n], row, acc);
-  }
-  return acc;
-}
-
-template <typename T, int P, int MODEL>
-__global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
-                                                      T *__restrict__ fout,
-                                                      const int32_t *__restrict__ cell,
-                                                      const T *__restrict__ rr,
-                                                      const T *__restrict__ ss, StepConsts c,
-                                                      int *__restrict__ flag) {
-  constexpr int S = Sets<MODEL>::S;
-  constexpr int P1 = P + 1;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= c.n) return;
-  const long long N = c.n;
-  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
-  const unsigned voff = unsigned(v) * unsigned(sizeof(T));
-  const auto rcell = make_rsrc(cell, unsigned(N * 25 * (long long)sizeof(int32_t)));
-  const unsigned cell_off = unsigned(v) * unsigned(sizeof(int32_t));
-  T rn[P1], den[P1];
-#pragma unroll
-  for (int m = 0; m < P1; ++m) {
-    rn[m] = T(c.rn[m]);
-    den[m] = T(c.lden[m]);
-  }
-  T fs[S][25];
-#pragma unroll
-  for (int i = 0; i < 25; ++i) {
-    const int rec = int(__builtin_amdgcn_raw_buffer_load_b32(rcell, cell_off,
-                                                             unsigned(i) * unsigned(N) * 4u, 0));
-    const int cx = rec & 0xffff, cy = rec >> 16;
-    T wx[P1], wy[P1];
-    lagrange_eval<T, P1>(buffer_load<T>(make_rsrc(rr + i * N, plane_bytes), voff, 0), rn, den, wx);
-    lagrange_eval<T, P1>(buffer_load<T>(make_rsrc(ss + i * N, plane_bytes), voff, 0), rn, den, wy);
-    unsigned xo[P1], yo[P1];
-    bool seam = false;
-#pragma unroll
-    for (int m = 0; m < P1; ++m) {
-      int jx = cx * P + m;
-      seam |= jx >= c.nx;
-      if (jx >= c.nx) jx -= c.nx;  // periodic seam: last vertex is node 0
-      xo[m] = unsigned(jx) * unsigned(sizeof(T));
-      int jy = cy * P + m;
-      if (jy >= c.ny) jy -= c.ny;
-      yo[m] = unsigned(jy) * unsigned(c.nx) * unsigned(sizeof(T));
-    }
-    const bool any_seam = __builtin_amdgcn_ballot_w64(seam) != 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const auto rs = make_rsrc(fin + (long long)(s * 25 + i) * N, plane_bytes);
-      T acc = any_seam ? records_interp<T, P1, true>(rs, xo, yo, wx, wy)
-                       : records_interp<T, P1, false>(rs, xo, yo, wx, wy);
-      // keep the interpolation next to its loads
-      asm volatile("" : "+v"(acc));
-      fs[s][i] = acc;
-    }
-  }
-  collide_store<T, MODEL>(fs, c, fout, v, flag);
-}
-
 hipError_t launch_step_records(int fp32, int model, const StepConsts &c, const DevTables &t,
                                const void *fin, void *fout, int *flag, hipStream_t s) {
-  return dispatch_step(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
-    const unsigned blocks = unsigned((c.n + 255) / 256);
-    k_step_records<T, P, MODEL><<<blocks, 256, 0, s>>>(
-        static_cast<const T *>(fin), static_cast<T *>(fout), t.rec_cell,
-        static_cast<const T *>(t.rec_r), static_cast<const T *>(t.rec_s), c, flag);
-    return hipGetLastError();
-  });
+  return launch_records_family<false>(fp32, model, c, t, fin, fout, flag, s);
 }
 
 }  // namespace sllbm

@@ -33,6 +33,22 @@ void fill_hermite_constants(VelocitySet &vs) {
   }
 }
 
+bool gaussian_exact_to_degree(const VelocitySet &vs, int degree) {
+  double exact = 1.0;  // (n-1)!! for even n
+  for (int n = 0; n <= degree; ++n) {
+    double sum = 0.0, mag = 0.0;
+    for (int a = 0; a < kQ1; ++a) {
+      const double t = vs.w[a] * std::pow(vs.xi[a], n);
+      sum += t;
+      mag += std::fabs(t);
+    }
+    const double want = (n % 2) ? 0.0 : exact;
+    if (!(std::fabs(sum - want) <= 1e-12 * std::max(1.0, mag))) return false;
+    if (n % 2 == 0) exact *= double(n + 1);
+  }
+  return true;
+}
+
 std::vector<double> support_points(int p, bool glc) {
   std::vector<double> r(p + 1);
   const double pi = 3.14159265358979323846;

@@ -27,6 +27,11 @@ struct VelocitySet {
 VelocitySet default_velocity_set();
 void fill_hermite_constants(VelocitySet &vs);
 
+// True when the 1-D rule reproduces the moments of the unit Gaussian,
+// sum_a w_a xi_a^n = (n-1)!! (n even) or 0 (n odd), for every n <= degree
+// (relative tolerance 1e-12).
+bool gaussian_exact_to_degree(const VelocitySet &vs, int degree);
+
 // Reference support points on [0, 1] for order p (Sec. II.E).
 std::vector<double> support_points(int p, bool glc);
 

@@ -27,7 +27,7 @@ def _ptr(a):
 class Solver:
     def __init__(self, *, p, edges_x, edges_y, periodic_x, periodic_y, dt, nu, model,
                  gamma=1.4, precision="fp32", uniform=True, path="auto", device=0,
-                 nodes="glc", xi1d=None, w1d=None):
+                 nodes="glc", xi1d=None, w1d=None, Pr=1.0):
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a HIP device (torch.cuda is not available)")
         self.device = torch.device("cuda", device)
@@ -51,7 +51,7 @@ class Solver:
             else:
                 C.sllbm_init_grid_mapped(self.ctx, len(ex) - 1, len(ey) - 1, _ptr(ex), _ptr(ey),
                                          bcx, bcy)
-            C.sllbm_set_physics(self.ctx, dt, nu, gamma, 1.0, _MODEL[model])
+            C.sllbm_set_physics(self.ctx, dt, nu, gamma, Pr, _MODEL[model])
             C.sllbm_set_path(self.ctx, _PATH[path])
             self.nx, self.ny = C.sllbm_num_nodes(self.ctx)
             self.nsets, self.q, _ = C.sllbm_population_layout(self.ctx)
@@ -73,7 +73,8 @@ class Solver:
     def from_workload(cls, wl, precision="fp32", path="auto", device=0, nodes="glc"):
         s = cls(p=wl.p, edges_x=wl.edges_x, edges_y=wl.edges_y, periodic_x=wl.periodic_x,
                 periodic_y=wl.periodic_y, dt=wl.dt, nu=wl.nu, model=wl.model, gamma=wl.gamma,
-                precision=precision, uniform=wl.uniform, path=path, device=device, nodes=nodes)
+                precision=precision, uniform=wl.uniform, path=path, device=device, nodes=nodes,
+                Pr=wl.Pr)
         s.workload = wl
         return s
 

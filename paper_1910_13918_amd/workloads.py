@@ -61,6 +61,7 @@ class Workload:
     fields: Callable      # (x, y) -> rho, ux, uy, T
     uniform: bool = True
     meta: dict = field(default_factory=dict)
+    Pr: float = 1.0       # Prandtl number (Sec. II.C-D)
 
     @property
     def ncx(self):
@@ -261,12 +262,13 @@ def isentropic_vortex(x, y, xc, yc, radius, mach_v, rho_inf, P_inf, u_inf, gamma
 
 
 def svi(ncx=1024, ncy=512, p=3, steps=2000, mach_s=1.2, mach_v=0.25, radius=0.075, Re=800.0,
-        gamma=1.4, lam=0.95, cfl=0.5, name=None):
+        gamma=1.4, lam=0.95, cfl=0.5, Pr=0.75, name=None):
     """Stationary normal shock at x = 1 on [0, 2] x [0, 1] (x zero-gradient and
     stretched, y periodic), upstream state A (x > 1): rho = 1, T = 1,
     u = -Ma_s sqrt(gamma); downstream state B from Rankine-Hugoniot; an
     isentropic vortex of radius 0.075 centred at (1.15, 0.5) on the upstream
-    flow; nu = c_A * radius / Re."""
+    flow; nu = c_A * radius / Re; Pr = 0.75 as in the paper's shock-vortex
+    case."""
     Lx, Ly = 2.0, 1.0
     hx = Lx / ncx
     dt, n = cfl_time_step(hx * GLC_MIN_GAP[p], cfl, steps=steps)
@@ -287,7 +289,7 @@ def svi(ncx=1024, ncy=512, p=3, steps=2000, mach_s=1.2, mach_v=0.25, radius=0.07
 
     return Workload(name or f"svi_{ncx}x{ncy}_p{p}", stretched_edges(ncx, Lx, lam),
                     uniform_edges(ncy, 0.0, Ly), p, False, True, "polyatomic", gamma, nu, dt,
-                    n, fields, False, {"mach_s": mach_s, "mach_v": mach_v, "Re": Re})
+                    n, fields, False, {"mach_s": mach_s, "mach_v": mach_v, "Re": Re}, Pr)
 
 
 # --------------------------------------------------------------- smooth density

@@ -24,7 +24,7 @@ from paper_1910_13918_amd import workloads as W  # noqa: E402
 def survives(seed, ncells=64):
     wl = W.riemann(ncells, 2, seed=seed)
     g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
-    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, Pr=wl.Pr)
     X, Y = g.coords()
     F = sim.init(*wl.fields(X, Y))
     for n in range(wl.steps):

@@ -81,7 +81,9 @@ def test_setup_validation_and_call_order():
         assert _code(C.sllbm_set_physics, ctx, 0.1, -1.0, 1.4, 1.0, 2) == C.E_ARG
         assert _code(C.sllbm_set_physics, ctx, 0.1, float("nan"), 1.4, 1.0, 2) == C.E_ARG
         assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.0, 1.0, 2) == C.E_ARG
-        assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.4, 0.75, 2) == C.E_UNSUPPORTED
+        assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.4, 0.0, 2) == C.E_ARG
+        assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.4, float("nan"), 2) == C.E_ARG
+        assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.4, float("inf"), 2) == C.E_ARG
         assert _code(C.sllbm_set_physics, ctx, 0.1, 0.1, 1.4, 1.0, 3) == C.E_ARG
         # queries before physics
         assert _code(C.sllbm_relaxation_time, ctx) == C.E_STATE
@@ -120,6 +122,36 @@ def test_resolved_path():
                                  C.ZERO_GRADIENT, C.PERIODIC)
         C.sllbm_set_physics(ctx, 0.05 / W.XI_MAX, 0.01, 1.4, 1.0, C.POLYATOMIC)
         assert C.sllbm_resolved_path(ctx) == C.PATH_DIRECT
+    finally:
+        C.sllbm_destroy(ctx)
+
+
+def test_prandtl_needs_a_rule_exact_to_degree_seven():
+    """Pr != 1 relies on the equilibrium having no centred third moment, which
+    holds for a 1-D rule that integrates the Gaussian exactly to degree 7:
+    the default D1Q5 set and, e.g., nodes 0, +-1, +-sqrt(6) with weights 1/3,
+    3/10, 1/30 (exact to degree 7, not 8); a rule exact only to degree 5 is
+    refused whichever of the two calls comes last."""
+    xi7 = np.array([0.0, 1.0, np.sqrt(6.0), -1.0, -np.sqrt(6.0)])
+    w7 = np.array([1 / 3, 0.3, 1 / 30, 0.3, 1 / 30])
+    # nodes 0, +-1, +-2 with weights matching degrees 0, 2, 4 (degree 6 gives 11)
+    xi5 = np.array([0.0, 1.0, 2.0, -1.0, -2.0])
+    w5 = np.array([1 / 2, 1 / 6, 1 / 12, 1 / 6, 1 / 12])
+    ctx = _ctx()
+    try:
+        C.sllbm_set_order(ctx, 2, C.NODES_GLC)
+        C.sllbm_init_grid_uniform(ctx, 4, 4, 0, 1, 0, 1, 1, 1)
+        C.sllbm_set_physics(ctx, 0.01, 0.02, 1.4, 0.75, C.POLYATOMIC)
+        C.sllbm_set_velocity_set(ctx, 5, xi7.ctypes.data, w7.ctypes.data)
+        assert _code(C.sllbm_set_velocity_set, ctx, 5, xi5.ctypes.data, w5.ctypes.data) == C.E_UNSUPPORTED
+        assert "degree 7" in C.sllbm_last_error(ctx)
+        C.sllbm_set_physics(ctx, 0.01, 0.02, 1.4, 1.0, C.POLYATOMIC)
+        C.sllbm_set_velocity_set(ctx, 5, xi5.ctypes.data, w5.ctypes.data)
+        assert _code(C.sllbm_set_physics, ctx, 0.01, 0.02, 1.4, 0.75, C.POLYATOMIC) == C.E_UNSUPPORTED
+        C.sllbm_set_velocity_set(ctx, 5, None, None)
+        C.sllbm_set_physics(ctx, 0.01, 0.02, 1.4, 0.75, C.MONATOMIC)
+        # the isothermal model has no heat flux to relax
+        assert _code(C.sllbm_set_physics, ctx, 0.01, 0.02, 1.4, 0.75, C.ISOTHERMAL) == C.E_ARG
     finally:
         C.sllbm_destroy(ctx)
 
@@ -165,7 +197,7 @@ def test_init_macro_validates_host_fields_before_device():
 def _oracle_and_lib(wl, kind=C.NODES_GLC):
     g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y,
              "glc" if kind == C.NODES_GLC else "equidistant")
-    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, Pr=wl.Pr)
     ctx = _ctx()
     C.sllbm_set_order(ctx, wl.p, kind)
     bcx = C.PERIODIC if wl.periodic_x else C.ZERO_GRADIENT
@@ -176,7 +208,7 @@ def _oracle_and_lib(wl, kind=C.NODES_GLC):
         C.sllbm_init_grid_uniform(ctx, len(ex) - 1, len(ey) - 1, ex[0], ex[-1], ey[0], ey[-1], bcx, bcy)
     else:
         C.sllbm_init_grid_mapped(ctx, len(ex) - 1, len(ey) - 1, ex.ctypes.data, ey.ctypes.data, bcx, bcy)
-    C.sllbm_set_physics(ctx, wl.dt, wl.nu, wl.gamma, 1.0,
+    C.sllbm_set_physics(ctx, wl.dt, wl.nu, wl.gamma, wl.Pr,
                         {"isothermal": 0, "monatomic": 1, "polyatomic": 2}[wl.model])
     return g, sim, ctx
 

@@ -42,6 +42,7 @@ GRIDS = [
 
 def _iso(wl):
     wl.model = "isothermal"
+    wl.Pr = 1.0
     return wl
 
 

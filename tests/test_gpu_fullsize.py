@@ -35,7 +35,7 @@ class _Case:
     def __init__(self, wl, nsample=4000, seed=7):
         self.wl = wl
         g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
-        self.sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+        self.sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, Pr=wl.Pr)
         X, Y = g.coords()
         self.F0 = self.sim.init(*wl.fields(X, Y))
         rng = np.random.default_rng(seed)
@@ -115,7 +115,7 @@ def test_largest_grid_uniform_state(precision):
     ncells = 2895
     wl = W.riemann(ncells, 2, states=[(1.2, 0.3, -0.2, 0.96)] * 4)
     g = Grid(np.array([0.0, 1.0]), np.array([0.0, 1.0]), 2, False, False)
-    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, Pr=wl.Pr)
     one = np.ones(1)
     ref = sim.init(1.2 * one, 0.3 * one, -0.2 * one, 0.8 * one)[:, :, 0]  # (S, 25)
     s = Solver.from_workload(wl, precision=precision)

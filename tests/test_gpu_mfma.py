@@ -27,7 +27,7 @@ def _solver(wl, precision, path):
 
 def _oracle(wl):
     g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
-    return g, Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+    return g, Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, Pr=wl.Pr)
 
 
 def _wl(model, p, periodic, ncx, ncy):

@@ -27,7 +27,7 @@ def _solver(wl, precision, path):
 
 def _oracle(wl):
     g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
-    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, Pr=wl.Pr)
     return g, sim
 
 

@@ -37,7 +37,7 @@ def _solver(wl, precision, path="auto", nodes="glc"):
 def test_equidistant_nodes_one_step(p, path):
     wl = W.riemann({3: 20, 4: 16}[p], p, states=W.RIEMANN_TABLE3_STATES)
     g = Grid(wl.edges_x, wl.edges_y, p, False, False, kind="equidistant")
-    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, Pr=wl.Pr)
     X, Y = g.coords()
     F0 = sim.init(*wl.fields(X, Y)) * W.population_noise((2, 25, g.nnodes), 31, 0.02)
     F1 = sim.step(F0)
