@@ -62,18 +62,21 @@ def mfma_flops_per_node_update(wl):
     return 5 * 5 * 4 * (16 * 16 * 4 * ks * 2) / (64 * 4)
 
 
-def profiled_traffic(wname, precision, path, launches):
+def profiled_traffic(wname, precision, path):
     """HBM bytes per launch from the committed counter profile of this workload
-    (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when no
-    profile exists or the kernel source has changed since it was taken."""
+    and kernel family (FETCH_SIZE and WRITE_SIZE scaled by a copy of known
+    size), or None when no profile exists or the kernel source has changed
+    since it was taken."""
     import hashlib
     tag = {"riemann2d_512x512cells_p2": "riemann512_p2"}.get(wname)
-    if tag is None or path not in ("auto", "tiled"):
+    if tag is None:
         return None
     f = os.path.join(ROOT, "profiles", f"stream_collide_{tag}_{precision}.json")
     if not os.path.exists(f):
         return None
     prof = json.load(open(f))
+    if prof.get("path") != path:
+        return None
     m = hashlib.sha256()
     for src in prof["source_files"]:
         m.update(open(os.path.join(ROOT, src), "rb").read())
@@ -270,8 +273,9 @@ def main():
     from paper_1910_13918_amd.solver import Solver
     wl, wname = workload(args.workload)
     s, ms, unstable = timed(wl, args.precision, args.path, args.steps, args.warmup)
+    s_path = s.resolved_path()
     nu_s = s.n * args.steps / (ms * 1e-3)
-    bpn = bytes_per_node_update(wl, args.precision, s.resolved_path())
+    bpn = bytes_per_node_update(wl, args.precision, s_path)
     achieved = nu_s * bpn / 1e9
     out = {
         "metric": METRIC, "value": nu_s, "unit": "node-updates/s", "n_gpus": 1,
@@ -280,11 +284,11 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": wname, "nodes": s.n, "populations": wl.nsets * 25,
                    "order": wl.p, "precision": args.precision + ("-pop/f64-moments" if args.precision == "fp32" else ""),
-                   "path": args.path, "path_resolved": s.resolved_path(), "dt": wl.dt,
+                   "path": args.path, "path_resolved": s_path, "dt": wl.dt,
                    "nu": wl.nu, "seed": wl.meta.get("seed"), "unstable_flag": unstable},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(wname, args.precision, args.path, args.steps),
+                     "traffic": profiled_traffic(wname, args.precision, s_path),
                      "bytes_per_node_update": bpn,
                      "kernel": "stream+collide (one launch per step)",
                      "avg_kernel_ms": ms / args.steps},
@@ -294,7 +298,7 @@ def main():
         m32, m64 = s.moments(), s64.moments()
         out["fp64"] = {"value": s64.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps,
                        "bytes_per_node_update": bytes_per_node_update(wl, "fp64", s64.resolved_path()),
-                       "traffic": profiled_traffic(wname, "fp64", args.path, args.steps),
+                       "traffic": profiled_traffic(wname, "fp64", s64.resolved_path()),
                        "fp32_vs_fp64_after_steps": {
                            "steps": args.warmup + args.steps,
                            "rho_max_rel": float(np.abs(m32[0] - m64[0]).max() / np.abs(m64[0]).max()),
@@ -313,6 +317,15 @@ def main():
                               "achieved_gbs": v * bpn / 1e9, "frac": v * bpn / 1e9 / HBM_PEAK_GBS,
                               "mfma_tflops": v * mfma_flops_per_node_update(wl) / 1e12}
         sm.close()
+    if not args.no_mfma and args.workload == "riemann" and args.path == "auto":
+        # the other LDS kernel family on the same workload (AUTO picks by measured speed)
+        other = "tiled" if s_path == "rows" else "rows"
+        so, mso, _ = timed(wl, args.precision, other, args.steps, args.warmup)
+        v = so.n * args.steps / (mso * 1e-3)
+        out[f"{other}_path"] = {"path": other, "value": v, "unit": "node-updates/s",
+                                "ms_per_step": mso / args.steps, "achieved_gbs": v * bpn / 1e9,
+                                "frac": v * bpn / 1e9 / HBM_PEAK_GBS}
+        so.close()
     if not args.no_svi and args.workload == "riemann":
         out["shock_vortex"] = shock_vortex_entry(args.precision)
     if not args.no_adjoint:

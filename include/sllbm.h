@@ -84,8 +84,11 @@ typedef enum {
 } sllbm_model;
 
 typedef enum {
-  SLLBM_PATH_AUTO = 0,    /* library choice: TILED when the departure windows
-                             fit it, else DIRECT (sllbm_resolved_path) */
+  SLLBM_PATH_AUTO = 0,    /* library choice (sllbm_resolved_path): ROWS or
+                             TILED by measured speed where both fit (ROWS for
+                             row segments of >= 48 nodes, except f + g in
+                             float32 at odd p and float64 with Pr != 1), the
+                             one that fits otherwise, else DIRECT */
   SLLBM_PATH_DIRECT = 1,  /* one thread per node, (p+1)^2 gathers per velocity
                              through per-axis departure tables */
   SLLBM_PATH_TILED = 2,   /* raw source windows of each velocity staged in LDS
@@ -93,12 +96,18 @@ typedef enum {
   SLLBM_PATH_RECORDS = 3, /* per-(node, velocity) departure records (cell, r, s)
                              with weights evaluated in the kernel: the general
                              gather for grids that are not axis products */
-  SLLBM_PATH_MFMA = 4     /* as TILED, with the x-pass of the interpolation as
+  SLLBM_PATH_MFMA = 4,    /* as TILED, with the x-pass of the interpolation as
                              16 x 16 x 4 float32 matrix-core products (float32
                              populations, at most 16 population-set x window
                              rows, departures within one node spacing of their
                              cell; SLLBM_E_UNSUPPORTED otherwise); never chosen
                              by AUTO */
+  SLLBM_PATH_ROWS = 5     /* one wavefront per row segment of up to 64 nodes:
+                             the p+1 source rows of each velocity combined in
+                             registers (y-factor), the x-factor from a per-
+                             wavefront LDS row, no workgroup barrier (needs a
+                             segment of >= 32 columns whose x-stencils fit 64
+                             source columns; SLLBM_E_UNSUPPORTED otherwise) */
 } sllbm_path;
 
 /* ---- lifetime ------------------------------------------------------------ */

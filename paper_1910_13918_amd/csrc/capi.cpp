@@ -55,6 +55,8 @@ struct sllbm_ctx {
   int win_rows = 0, win_cols = 0;
   bool mfma_blocks_ok = false;
   std::vector<int32_t> ywin, yrel, xwin, xrel;
+  int rows_tx = 0;  // row-segment path: segment width (0: unavailable)
+  std::vector<int32_t> rows_xwin, rows_xrel;
 
   // adjoint: transposed tables, windows (built on first use)
   bool adj_dirty = true;
@@ -67,6 +69,7 @@ struct sllbm_ctx {
   bool dev_checked = false;
   bool dev_dirty = true;
   bool rec_dirty = true;
+  DeviceBuf rows_xrel_d, rows_xwin_d;
   DeviceBuf xsrc, xw, ysrc, yw, yrel_d, ywin_d, xrel_d, xwin_d, mxd, myd, flag, partial, scalar,
       macro;
   DeviceBuf rec_cell, rec_r, rec_s;
@@ -154,6 +157,22 @@ bool mfma_blocks_fit(const sllbm_ctx *c) {
   return true;
 }
 
+// Widest row segment (at most 64 columns, at least kRowsMinCols) whose
+// x-stencils fit 64 consecutive source columns for every segment and 1-D
+// velocity; its windows go to win / rel.  0 when none does.
+int rows_segment_width(const AxisTable *t, int n, std::vector<int32_t> &win,
+                       std::vector<int32_t> &rel) {
+  int tx = 64;
+  while (tx >= kRowsMinCols) {
+    const int width = build_windows(t, n, tx, win, rel);
+    if (width <= 64) return tx;
+    tx -= width - 64;
+  }
+  win.clear();
+  rel.clear();
+  return 0;
+}
+
 void build_host_tables(sllbm_ctx *c) {
   if (!c->host_dirty) return;
   for (int a = 0; a < kQ1; ++a) {
@@ -166,6 +185,7 @@ void build_host_tables(sllbm_ctx *c) {
   c->win_rows = build_windows(c->yt, c->ay.n, kTileRows, c->ywin, c->yrel);
   c->win_cols = build_windows(c->xt, c->ax.n, kTileCols, c->xwin, c->xrel);
   c->mfma_blocks_ok = mfma_blocks_fit(c);
+  c->rows_tx = rows_segment_width(c->xt, c->ax.n, c->rows_xwin, c->rows_xrel);
   c->host_dirty = false;
   c->dev_dirty = true;
   c->rec_dirty = true;
@@ -183,9 +203,21 @@ bool mfma_fits(const sllbm_ctx *c) {
   return tiled_fits(c) && c->fp32 && nsets(c) * c->win_rows <= 16 && c->mfma_blocks_ok;
 }
 
+// AUTO: the row-segment kernel where it measured faster than the tiled one
+// (1025^2-node grids, p = 1..4, every model): segments of at least 48
+// columns, except f + g in float32 at odd p and float64 with Pr != 1, where
+// the tiled kernel's shared windows won; then tiled, then direct.
+bool rows_preferred(const sllbm_ctx *c) {
+  if (c->rows_tx < 48) return false;
+  if (nsets(c) == 2 && c->fp32 && c->p % 2 == 1) return false;
+  if (!c->fp32 && c->omega_pr != c->omega) return false;
+  return true;
+}
+
 int effective_path(const sllbm_ctx *c) {
-  if (c->path == SLLBM_PATH_AUTO) return tiled_fits(c) ? kPathTiled : kPathDirect;
-  return c->path;
+  if (c->path != SLLBM_PATH_AUTO) return c->path;
+  if (rows_preferred(c) || (!tiled_fits(c) && c->rows_tx >= kRowsMinCols)) return kPathRows;
+  return tiled_fits(c) ? kPathTiled : kPathDirect;
 }
 
 void free_buf(DeviceBuf &b) {
@@ -259,6 +291,8 @@ int prepare_device(sllbm_ctx *c) {
     if (!rc) rc = upload(c, c->ywin_d, c->ywin);
     if (!rc) rc = upload(c, c->xrel_d, c->xrel);
     if (!rc) rc = upload(c, c->xwin_d, c->xwin);
+    if (!rc && c->rows_tx) rc = upload(c, c->rows_xrel_d, c->rows_xrel);
+    if (!rc && c->rows_tx) rc = upload(c, c->rows_xwin_d, c->rows_xwin);
     if (!rc) rc = upload(c, c->mxd, c->mx);
     if (!rc) rc = upload(c, c->myd, c->my);
     if (!rc) rc = alloc_buf(c, c->flag, sizeof(int));
@@ -346,6 +380,9 @@ DevTables make_tables(const sllbm_ctx *c) {
   t.win_cols = c->win_cols;
   t.taps = c->p + 1;
   t.mfma_ok = c->mfma_blocks_ok ? 1 : 0;
+  t.rows_tx = c->rows_tx;
+  t.rows_xrel = c->rows_tx ? static_cast<const int32_t *>(c->rows_xrel_d.ptr) : nullptr;
+  t.rows_xwin = c->rows_tx ? static_cast<const int32_t *>(c->rows_xwin_d.ptr) : nullptr;
   return t;
 }
 
@@ -484,7 +521,7 @@ void sllbm_destroy(sllbm_ctx *c) {
                          &c->xrel_d, &c->xwin_d, &c->xsrcT, &c->xwT, &c->ysrcT, &c->ywT,
                          &c->yrelT_d, &c->ywinT_d, &c->xrelT_d, &c->xwinT_d, &c->mxd,
                          &c->myd, &c->flag, &c->partial, &c->scalar, &c->macro, &c->rec_cell,
-                         &c->rec_r, &c->rec_s};
+                         &c->rec_r, &c->rec_s, &c->rows_xrel_d, &c->rows_xwin_d};
     for (DeviceBuf *b : bufs) free_buf(*b);
     if (c->own_pop) {
       (void)hipFree(c->pop[0]);
@@ -630,7 +667,7 @@ int sllbm_set_physics(sllbm_ctx *c, double dt, double nu, double gamma, double P
 
 int sllbm_set_path(sllbm_ctx *c, int path) {
   if (!c) return SLLBM_E_ARG;
-  if (path < SLLBM_PATH_AUTO || path > SLLBM_PATH_MFMA)
+  if (path < SLLBM_PATH_AUTO || path > SLLBM_PATH_ROWS)
     return fail(c, SLLBM_E_ARG, "unknown path");
   c->path = path;
   return SLLBM_OK;
@@ -790,6 +827,9 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   const int path = effective_path(c);
   if (path == kPathTiled && !tiled_fits(c))
     return fail(c, SLLBM_E_UNSUPPORTED, "departures span too many rows for the tiled kernel");
+  if (path == kPathRows && c->rows_tx == 0)
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "no row segment of at least 32 columns keeps its x-stencils in 64 columns");
   if (path == kPathMfma && !mfma_fits(c))
     return fail(c, SLLBM_E_UNSUPPORTED,
                 "matrix-core path needs float32, at most 16 set x window rows and departures "

@@ -120,6 +120,7 @@ hipError_t launch_step(int fp32, int model, int path, const StepConsts &c, const
       case kPathTiled: return launch_step_tiled_pr(fp32, model, c, t, fin, fout, flag, s);
       case kPathRecords: return launch_step_records_pr(fp32, model, c, t, fin, fout, flag, s);
       case kPathMfma: return launch_step_mfma_pr(fp32, model, c, t, fin, fout, flag, s);
+      case kPathRows: return launch_step_rows_pr(fp32, model, c, t, fin, fout, flag, s);
     }
     return hipErrorInvalidValue;
   }
@@ -128,6 +129,7 @@ hipError_t launch_step(int fp32, int model, int path, const StepConsts &c, const
     case kPathTiled: return launch_step_tiled(fp32, model, c, t, fin, fout, flag, s);
     case kPathRecords: return launch_step_records(fp32, model, c, t, fin, fout, flag, s);
     case kPathMfma: return launch_step_mfma(fp32, model, c, t, fin, fout, flag, s);
+    case kPathRows: return launch_step_rows(fp32, model, c, t, fin, fout, flag, s);
   }
   return hipErrorInvalidValue;
 }

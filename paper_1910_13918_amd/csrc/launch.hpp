@@ -50,9 +50,18 @@ struct DevTables {
   int win_cols;         // source columns staged per tile (max over tiles)
   int taps;             // table entries per node (p+1 forward, more when transposed)
   int mfma_ok;          // every 16-column block's x-stencils fit the matrix-core x-pass
+  // row-segment path: segments of rows_tx columns whose x-stencils fit 64
+  // consecutive source columns starting at rows_xwin[comp][segment]
+  int rows_tx;                 // 0: no such segment width (path unavailable)
+  const int32_t *rows_xrel;    // [5][p+1][nx], relative to the segment's window
+  const int32_t *rows_xwin;    // [5][nsegments]
 };
 
-enum Path { kPathDirect = 1, kPathTiled = 2, kPathRecords = 3, kPathMfma = 4 };
+// Narrowest row segment of the row-segment path (narrower ones leave most
+// lanes idle).
+constexpr int kRowsMinCols = 32;
+
+enum Path { kPathDirect = 1, kPathTiled = 2, kPathRecords = 3, kPathMfma = 4, kPathRows = 5 };
 
 hipError_t launch_init_eq(int fp32, int model, const StepConsts &c, const double *rho,
                           const double *ux, const double *uy, const double *T, void *f,
@@ -68,6 +77,8 @@ hipError_t launch_step_records(int fp32, int model, const StepConsts &c, const D
                                const void *fin, void *fout, int *flag, hipStream_t s);
 hipError_t launch_step_mfma(int fp32, int model, const StepConsts &c, const DevTables &t,
                             const void *fin, void *fout, int *flag, hipStream_t s);
+hipError_t launch_step_rows(int fp32, int model, const StepConsts &c, const DevTables &t,
+                            const void *fin, void *fout, int *flag, hipStream_t s);
 // the same with the quasi-equilibrium (Pr != 1) collision; thermal models only
 hipError_t launch_step_direct_pr(int fp32, int model, const StepConsts &c, const DevTables &t,
                                  const void *fin, void *fout, int *flag, hipStream_t s);
@@ -76,6 +87,8 @@ hipError_t launch_step_tiled_pr(int fp32, int model, const StepConsts &c, const 
 hipError_t launch_step_records_pr(int fp32, int model, const StepConsts &c, const DevTables &t,
                                   const void *fin, void *fout, int *flag, hipStream_t s);
 hipError_t launch_step_mfma_pr(int fp32, int model, const StepConsts &c, const DevTables &t,
+                               const void *fin, void *fout, int *flag, hipStream_t s);
+hipError_t launch_step_rows_pr(int fp32, int model, const StepConsts &c, const DevTables &t,
                                const void *fin, void *fout, int *flag, hipStream_t s);
 
 // Moments per node (any output pointer may be null) and per-block partial

@@ -1,0 +1,143 @@
+// Stream + collide with one independent wavefront per target row segment.
+//
+// On an axis-product grid the departure rows of velocity i = a + 5b depend
+// only on (b, target row) and are therefore the same for every lane of a
+// wavefront that owns one row segment of TX nodes.  For each population
+// plane the wavefront
+//   1. loads its p+1 source rows over a window of 64 consecutive source
+//      columns (one element per lane; the host picks TX so that every
+//      tile's x-stencils fit the 64 columns, so there is no halo);
+//   2. combines them with the uniform y-weights in registers (eq. (17),
+//      y-factor first), writes the one y-interpolated row to its own LDS
+//      row, and
+//   3. evaluates the x-factor from LDS with each lane's p+1 x-weights.
+// No LDS row is shared between wavefronts, so the kernel has no workgroup
+// barrier; loads run a fixed number of planes ahead of the arithmetic.
+// The streamed values stay in registers and the collision is the one of the
+// other paths (collide_store).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "step_common.hpp"
+#include "tiled_common.hpp"
+
+namespace sllbm {
+
+constexpr int kRowsTileRows = 4;  // wavefronts (rows) per workgroup
+
+// Orders this wavefront's LDS accesses: what its lanes wrote before is
+// visible to its lanes after (LDS instructions of one wavefront complete in
+// order; the fences keep the compiler from moving accesses across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// Planes whose loads are in flight ahead of the one being interpolated
+// (measured on the 1025^2-node benchmark, p = 2: float32 is fastest with 2,
+// float64 with 10; both drop by several per cent either way).
+template <typename T, int P1>
+constexpr int rows_lookahead() { return sizeof(T) == 4 ? 2 : (P1 <= 3 ? 10 : 6); }
+
+template <typename T, int P, int MODEL, bool PR>
+__global__ __launch_bounds__(64 * kRowsTileRows) void k_step_rows(
+    const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
+    const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc,
+    const T *__restrict__ yw, int TX, int ntx, int nty, StepConsts c, int *__restrict__ flag) {
+  constexpr int S = Sets<MODEL>::S;
+  constexpr int P1 = P + 1;
+  constexpr int NQ = 25 * S;              // planes, in the order (b, s, a)
+  constexpr int D = rows_lookahead<T, P1>();
+  __shared__ T rows_lds[kRowsTileRows][2][64];
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  if (tile >= ntx * nty) return;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int lane = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int iy = ty * kRowsTileRows + wv;
+  if (iy >= c.ny) return;  // whole wavefront; nothing below waits for others
+  const int ix = tx * TX + lane;
+  // lanes past the segment take the stencil of its last node (in the window)
+  const int ixc = min(tx * TX + min(lane, TX - 1), c.nx - 1);
+  const long long N = c.n;
+  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
+  const unsigned row_bytes = unsigned(c.nx) * unsigned(sizeof(T));
+  T *const lrow = &rows_lds[wv][0][0];
+  int xr0[5];
+  T wx[5][P1];
+  unsigned col_off[5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    xr0[a] = xrel[(a * P1) * c.nx + ixc];
+#pragma unroll
+    for (int m = 0; m < P1; ++m) wx[a][m] = xw[(a * P1 + m) * c.nx + ixc];
+    col_off[a] =
+        unsigned(wrap_or_clamp(xwin[a * ntx + tx] + lane, c.nx, c.perx)) * unsigned(sizeof(T));
+  }
+  // source rows (byte offsets) and weights of the y-factor: wave-uniform
+  unsigned yoff[5][P1];
+  T wy[5][P1];
+#pragma unroll
+  for (int b = 0; b < 5; ++b)
+#pragma unroll
+    for (int m = 0; m < P1; ++m) {
+      yoff[b][m] = unsigned(ysrc[(b * P1 + m) * c.ny + iy]) * row_bytes;
+      wy[b][m] = yw[(b * P1 + m) * c.ny + iy];
+    }
+  auto plane_of = [](int q) {  // q -> (b, s, a)
+    const int b = q / (5 * S), r = q % (5 * S);
+    return int3{b, r / 5, r % 5};
+  };
+  T pre[D + 1][P1];
+  auto load = [&](int q, T (&dst)[P1]) {
+    const int3 p = plane_of(q);
+    const auto rs = make_rsrc(fin + (long long)(p.y * 25 + p.z + 5 * p.x) * N, plane_bytes);
+#pragma unroll
+    for (int m = 0; m < P1; ++m) dst[m] = buffer_load<T>(rs, col_off[p.z], yoff[p.x][m]);
+  };
+  T fs[S][25];
+#pragma unroll
+  for (int q = 0; q < D && q < NQ; ++q) load(q, pre[q % (D + 1)]);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q + D < NQ) load(q + D, pre[(q + D) % (D + 1)]);
+    const int3 p = plane_of(q);
+    const T(&v)[P1] = pre[q % (D + 1)];
+    T y = wy[p.x][0] * v[0];
+#pragma unroll
+    for (int m = 1; m < P1; ++m) y = fma(wy[p.x][m], v[m], y);
+    T *row = lrow + (q & 1) * 64;
+    row[lane] = y;
+    wave_lds_sync();
+    T acc = wx[p.z][0] * row[xr0[p.z]];
+#pragma unroll
+    for (int m = 1; m < P1; ++m) acc = fma(wx[p.z][m], row[xr0[p.z] + m], acc);
+    asm volatile("" : "+v"(acc));  // keep the plane's arithmetic in its place
+    fs[p.y][p.z + 5 * p.x] = acc;
+  }
+  if (ix < c.nx && lane < TX) collide_store<T, MODEL, PR>(fs, c, fout, (long long)iy * c.nx + ix, flag);
+}
+
+// PR: the Pr != 1 collision (thermal models only)
+template <bool PR>
+hipError_t launch_rows_family(int fp32, int model, const StepConsts &c, const DevTables &t,
+                              const void *fin, void *fout, int *flag, hipStream_t s) {
+  if (t.rows_tx < kRowsMinCols || t.rows_tx > 64 || t.rows_xrel == nullptr ||
+      t.rows_xwin == nullptr)
+    return hipErrorInvalidValue;
+  return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
+    const int ntx = (c.nx + t.rows_tx - 1) / t.rows_tx;
+    const int nty = (c.ny + kRowsTileRows - 1) / kRowsTileRows;
+    const int grid = ((ntx * nty + 7) / 8) * 8;
+    k_step_rows<T, P, MODEL, PR><<<grid, dim3(64, kRowsTileRows), 0, s>>>(
+        static_cast<const T *>(fin), static_cast<T *>(fout), t.rows_xrel,
+        static_cast<const T *>(t.xw), t.rows_xwin, t.ysrc, static_cast<const T *>(t.yw),
+        t.rows_tx, ntx, nty, c, flag);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace sllbm

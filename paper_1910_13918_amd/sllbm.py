@@ -43,6 +43,7 @@ PATH_DIRECT = 1
 PATH_TILED = 2
 PATH_RECORDS = 3
 PATH_MFMA = 4
+PATH_ROWS = 5
 
 _STATUS = {OK: "OK", E_ARG: "SLLBM_E_ARG", E_STATE: "SLLBM_E_STATE", E_DEVICE: "SLLBM_E_DEVICE",
            E_OOM: "SLLBM_E_OOM", E_UNSTABLE: "SLLBM_E_UNSTABLE",

@@ -14,7 +14,7 @@ from . import sllbm as C
 _PREC = {"fp64": C.FP64, "fp32": C.FP32}
 _MODEL = {"isothermal": C.ISOTHERMAL, "monatomic": C.MONATOMIC, "polyatomic": C.POLYATOMIC}
 _PATH = {"auto": C.PATH_AUTO, "direct": C.PATH_DIRECT, "tiled": C.PATH_TILED,
-         "records": C.PATH_RECORDS, "mfma": C.PATH_MFMA}
+         "records": C.PATH_RECORDS, "mfma": C.PATH_MFMA, "rows": C.PATH_ROWS}
 
 
 def _ptr(a):

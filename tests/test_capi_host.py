@@ -96,20 +96,33 @@ def test_setup_validation_and_call_order():
         assert _code(C.sllbm_step, ctx, -1) == C.E_ARG
         assert _code(C.sllbm_mass, ctx) == C.E_STATE
         assert _code(C.sllbm_set_path, ctx, 9) == C.E_ARG
-        assert _code(C.sllbm_set_path, ctx, 5) == C.E_ARG
+        assert _code(C.sllbm_set_path, ctx, 6) == C.E_ARG
         assert _code(C.sllbm_set_check_interval, ctx, -2) == C.E_ARG
     finally:
         C.sllbm_destroy(ctx)
 
 
 def test_resolved_path():
-    """AUTO resolves to TILED while every tile's source window fits the LDS
-    staging (at most 3 rows per wavefront, 128 columns), else to DIRECT."""
+    """AUTO resolves to ROWS for row segments of >= 48 nodes (except f + g in
+    float32 at odd p and float64 with Pr != 1), to TILED while every tile's
+    source window fits the LDS staging (at most 3 rows per wavefront, 128
+    columns), else to DIRECT."""
+    for prec, p, Pr, want in ((C.FP64, 2, 1.0, C.PATH_ROWS), (C.FP32, 2, 1.0, C.PATH_ROWS),
+                              (C.FP32, 3, 1.0, C.PATH_TILED), (C.FP64, 3, 1.0, C.PATH_ROWS),
+                              (C.FP64, 2, 0.75, C.PATH_TILED), (C.FP32, 2, 0.75, C.PATH_ROWS)):
+        ctx = _ctx(prec)
+        try:
+            C.sllbm_set_order(ctx, p, C.NODES_GLC)
+            C.sllbm_init_grid_uniform(ctx, 200, 8, 0.0, 1.0, 0.0, 1.0, C.PERIODIC, C.PERIODIC)
+            C.sllbm_set_physics(ctx, 1e-3, 0.01, 1.4, Pr, C.POLYATOMIC)
+            assert C.sllbm_resolved_path(ctx) == want, (prec, p, Pr)
+        finally:
+            C.sllbm_destroy(ctx)
     ctx = _ctx()
     try:
         _setup(ctx, nc=20, dt=1e-3)
-        assert C.sllbm_resolved_path(ctx) == C.PATH_TILED
-        for p in (C.PATH_DIRECT, C.PATH_TILED, C.PATH_RECORDS, C.PATH_MFMA):
+        assert C.sllbm_resolved_path(ctx) == C.PATH_ROWS
+        for p in (C.PATH_DIRECT, C.PATH_TILED, C.PATH_RECORDS, C.PATH_MFMA, C.PATH_ROWS):
             C.sllbm_set_path(ctx, p)
             assert C.sllbm_resolved_path(ctx) == p
         C.sllbm_set_path(ctx, C.PATH_AUTO)

@@ -73,8 +73,8 @@ def _one_step(case, precision, path):
 
 @pytest.mark.parametrize("precision,path", [("fp32", "auto"), ("fp32", "tiled"),
                                             ("fp32", "direct"), ("fp32", "records"),
-                                            ("fp32", "mfma"), ("fp64", "auto"),
-                                            ("fp64", "records")])
+                                            ("fp32", "mfma"), ("fp32", "rows"), ("fp64", "auto"),
+                                            ("fp64", "records"), ("fp64", "rows")])
 def test_riemann_512_one_step_sampled(riemann_case, precision, path):
     G = _one_step(riemann_case, precision, path)
     err = np.abs(G - riemann_case.F1).max() / riemann_case.scale
@@ -99,7 +99,7 @@ def test_riemann_512_two_steps_every_node(riemann_case):
 
 @pytest.mark.parametrize("precision,path", [("fp32", "auto"), ("fp32", "direct"),
                                             ("fp32", "records"), ("fp32", "mfma"),
-                                            ("fp64", "auto")])
+                                            ("fp32", "rows"), ("fp64", "auto")])
 def test_svi_one_step_sampled(svi_case, precision, path):
     G = _one_step(svi_case, precision, path)
     err = np.abs(G - svi_case.F1).max() / svi_case.scale

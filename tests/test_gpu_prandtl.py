@@ -75,7 +75,7 @@ def _ids(c):
     return f"{c[0]}-p{c[1]}-{'per' if c[2] else 'zg'}-Pr{c[3]}"
 
 
-@pytest.mark.parametrize("path", ["direct", "tiled", "records"])
+@pytest.mark.parametrize("path", ["direct", "tiled", "records", "rows"])
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 def test_one_step_fp64(case, path):
     wl = _wl(*case)
@@ -95,7 +95,7 @@ def test_one_step_fp64(case, path):
         s.close()
 
 
-@pytest.mark.parametrize("path", ["tiled", "mfma"])
+@pytest.mark.parametrize("path", ["tiled", "mfma", "rows"])
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 def test_one_step_fp32(case, path):
     wl = _wl(*case)

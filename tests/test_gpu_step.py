@@ -74,7 +74,7 @@ def _wl(model, p, periodic, ncx, ncy):
     return wl
 
 
-@pytest.mark.parametrize("path", ["direct", "tiled", "records"])
+@pytest.mark.parametrize("path", ["direct", "tiled", "records", "rows"])
 @pytest.mark.parametrize("case", _cases(), ids=lambda c: f"{c[0]}-p{c[1]}-{'per' if c[2] else 'zg'}")
 def test_one_step_fp64(case, path):
     wl = _wl(*case)
@@ -93,7 +93,7 @@ def test_one_step_fp64(case, path):
         s.close()
 
 
-@pytest.mark.parametrize("path", ["direct", "tiled", "records"])
+@pytest.mark.parametrize("path", ["direct", "tiled", "records", "rows"])
 def test_one_step_fp64_seeded_extreme_states(path):
     """Seeded quadrant states span theta = P/rho in [0.02, 15]: f_eq has entries
     of both signs, |g| >> |f|, and after one step the temperature at the
@@ -119,7 +119,7 @@ def test_one_step_fp64_seeded_extreme_states(path):
         s.close()
 
 
-@pytest.mark.parametrize("path", ["direct", "tiled", "records"])
+@pytest.mark.parametrize("path", ["direct", "tiled", "records", "rows"])
 @pytest.mark.parametrize("case", [("polyatomic", 2, False, 35, 9), ("polyatomic", 3, True, 23, 6),
                                   ("isothermal", 4, True, 17, 5)],
                          ids=lambda c: f"{c[0]}-p{c[1]}")

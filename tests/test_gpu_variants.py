@@ -32,7 +32,7 @@ def _solver(wl, precision, path="auto", nodes="glc"):
     return Solver.from_workload(wl, precision=precision, path=path, nodes=nodes)
 
 
-@pytest.mark.parametrize("path", ["direct", "tiled", "records"])
+@pytest.mark.parametrize("path", ["direct", "tiled", "records", "rows"])
 @pytest.mark.parametrize("p", [3, 4])
 def test_equidistant_nodes_one_step(p, path):
     wl = W.riemann({3: 20, 4: 16}[p], p, states=W.RIEMANN_TABLE3_STATES)
