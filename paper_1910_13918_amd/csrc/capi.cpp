@@ -61,7 +61,9 @@ struct sllbm_ctx {
   // adjoint: transposed tables, windows (built on first use)
   bool adj_dirty = true;
   AxisTable xtT[kQ1], ytT[kQ1];
-  int taps_T = 0, win_rowsT = 0, win_colsT = 0;
+  int taps_T = 0, win_rowsT = 0, win_colsT = 0, rows_txT = 0;
+  std::vector<int32_t> rows_xwinT, rows_xrelT;
+  DeviceBuf rows_xrelT_d, rows_xwinT_d;
   std::vector<int32_t> ywinT, yrelT, xwinT, xrelT;
   DeviceBuf xsrcT, xwT, ysrcT, ywT, yrelT_d, ywinT_d, xrelT_d, xwinT_d;
 
@@ -465,6 +467,7 @@ int prepare_adjoint(sllbm_ctx *c) {
   c->taps_T = taps;
   c->win_rowsT = build_windows(c->ytT, c->ay.n, kTileRows, c->ywinT, c->yrelT);
   c->win_colsT = build_windows(c->xtT, c->ax.n, kTileCols, c->xwinT, c->xrelT);
+  c->rows_txT = rows_segment_width(c->xtT, c->ax.n, c->rows_xwinT, c->rows_xrelT);
   rc = upload(c, c->xsrcT, comp_major<int32_t>(c->xtT, c->ax.n, taps, false));
   if (!rc) rc = upload_weights(c, c->xwT, comp_major<double>(c->xtT, c->ax.n, taps, true));
   if (!rc) rc = upload(c, c->ysrcT, comp_major<int32_t>(c->ytT, c->ay.n, taps, false));
@@ -473,6 +476,8 @@ int prepare_adjoint(sllbm_ctx *c) {
   if (!rc) rc = upload(c, c->ywinT_d, c->ywinT);
   if (!rc) rc = upload(c, c->xrelT_d, c->xrelT);
   if (!rc) rc = upload(c, c->xwinT_d, c->xwinT);
+  if (!rc && c->rows_txT) rc = upload(c, c->rows_xrelT_d, c->rows_xrelT);
+  if (!rc && c->rows_txT) rc = upload(c, c->rows_xwinT_d, c->rows_xwinT);
   if (rc) return rc;
   c->adj_dirty = false;
   return SLLBM_OK;
@@ -492,6 +497,9 @@ DevTables make_adjoint_tables(const sllbm_ctx *c) {
   t.win_rows = c->win_rowsT;
   t.win_cols = c->win_colsT;
   t.taps = c->taps_T;
+  t.rows_tx = c->rows_txT;
+  t.rows_xrel = c->rows_txT ? static_cast<const int32_t *>(c->rows_xrelT_d.ptr) : nullptr;
+  t.rows_xwin = c->rows_txT ? static_cast<const int32_t *>(c->rows_xwinT_d.ptr) : nullptr;
   return t;
 }
 
@@ -521,7 +529,8 @@ void sllbm_destroy(sllbm_ctx *c) {
                          &c->xrel_d, &c->xwin_d, &c->xsrcT, &c->xwT, &c->ysrcT, &c->ywT,
                          &c->yrelT_d, &c->ywinT_d, &c->xrelT_d, &c->xwinT_d, &c->mxd,
                          &c->myd, &c->flag, &c->partial, &c->scalar, &c->macro, &c->rec_cell,
-                         &c->rec_r, &c->rec_s, &c->rows_xrel_d, &c->rows_xwin_d};
+                         &c->rec_r, &c->rec_s, &c->rows_xrel_d, &c->rows_xwin_d,
+                         &c->rows_xrelT_d, &c->rows_xwinT_d};
     for (DeviceBuf *b : bufs) free_buf(*b);
     if (c->own_pop) {
       (void)hipFree(c->pop[0]);
@@ -889,9 +898,23 @@ int sllbm_adjoint_step(sllbm_ctx *c, const void *mu, const double *moments_prev,
   if (mu == out) return fail(c, SLLBM_E_ARG, "input and output must differ");
   int rc = prepare_adjoint(c);
   if (rc) return rc;
-  const bool tiled = c->path != SLLBM_PATH_DIRECT && c->win_rowsT <= 3 * kTileRows &&
-                     c->win_colsT <= kMaxWindowCols;
-  HIP_TRY(c, launch_adjoint_step(c->fp32, c->model, tiled, make_consts(c),
+  // the forward's path choice carries over: DIRECT and TILED as set (TILED
+  // falling back to DIRECT when its windows do not fit), ROWS when its
+  // segments exist, otherwise row segments of >= 48 nodes, then TILED
+  const bool tiled_ok = c->win_rowsT <= 3 * kTileRows && c->win_colsT <= kMaxWindowCols;
+  const bool rows_ok = c->rows_txT >= kRowsMinCols;
+  int kind = kAdjointDirect;
+  if (c->path == SLLBM_PATH_TILED) {
+    kind = tiled_ok ? kAdjointTiled : kAdjointDirect;
+  } else if (c->path == SLLBM_PATH_ROWS && rows_ok) {
+    kind = kAdjointRows;
+  } else if (c->path != SLLBM_PATH_DIRECT) {
+    kind = c->rows_txT >= 48 ? kAdjointRows
+           : tiled_ok        ? kAdjointTiled
+           : rows_ok         ? kAdjointRows
+                             : kAdjointDirect;
+  }
+  HIP_TRY(c, launch_adjoint_step(c->fp32, c->model, kind, make_consts(c),
                                  make_adjoint_tables(c), mu, moments_prev, out, c->stream));
   return SLLBM_OK;
 }

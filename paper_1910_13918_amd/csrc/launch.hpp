@@ -112,8 +112,10 @@ hipError_t launch_adjoint_seed(int fp32, int model, const StepConsts &c, const v
 // K = 3 isothermal, 4 with theta)
 hipError_t launch_adjoint_collide(int fp32, int model, const StepConsts &c, const void *lam,
                                   const double *mom, void *mu, hipStream_t s);
-// out = S^T mu (transposed tables t), then J_C(M_prev)^T when mom_prev is given
-hipError_t launch_adjoint_step(int fp32, int model, bool tiled, const StepConsts &c,
+// out = S^T mu (transposed tables t), then J_C(M_prev)^T when mom_prev is given;
+// kind: the gather (direct, tiled windows or row segments)
+enum AdjointKind { kAdjointDirect = 0, kAdjointTiled = 1, kAdjointRows = 2 };
+hipError_t launch_adjoint_step(int fp32, int model, int kind, const StepConsts &c,
                                const DevTables &t, const void *mu, const double *mom_prev,
                                void *out, hipStream_t s);
 // gradients of sum_i lam_i f_eq_i (+ g_eq_i) with respect to rho0, u0 and theta0

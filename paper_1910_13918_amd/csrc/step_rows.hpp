@@ -42,30 +42,24 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <typename T, int P1>
 constexpr int rows_lookahead() { return sizeof(T) == 4 ? 2 : (P1 <= 3 ? 10 : 6); }
 
-template <typename T, int P, int MODEL, bool PR>
-__global__ __launch_bounds__(64 * kRowsTileRows) void k_step_rows(
-    const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
-    const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc,
-    const T *__restrict__ yw, int TX, int ntx, int nty, StepConsts c, int *__restrict__ flag) {
-  constexpr int S = Sets<MODEL>::S;
-  constexpr int P1 = P + 1;
-  constexpr int NQ = 25 * S;              // planes, in the order (b, s, a)
-  constexpr int D = rows_lookahead<T, P1>();
-  __shared__ T rows_lds[kRowsTileRows][2][64];
-  const int tile = xcd_tile(blockIdx.x, ntx * nty);
-  if (tile >= ntx * nty) return;
-  const int tx = tile % ntx, ty = tile / ntx;
-  const int lane = threadIdx.x;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
-  const int iy = ty * kRowsTileRows + wv;
-  if (iy >= c.ny) return;  // whole wavefront; nothing below waits for others
-  const int ix = tx * TX + lane;
+// Streams the 25 S planes of `fin` into fs for the node (iy, tx TX + lane):
+// P1 taps per axis (p+1 forward, the transposed width for the adjoint),
+// D planes of loads in flight; lrow = this wavefront's two LDS rows.
+template <typename T, int P1, int S, int D>
+__device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
+                                            const int32_t *__restrict__ xrel,
+                                            const T *__restrict__ xw,
+                                            const int32_t *__restrict__ xwin,
+                                            const int32_t *__restrict__ ysrc,
+                                            const T *__restrict__ yw, int TX, int ntx, int tx,
+                                            int iy, int lane, const StepConsts &c, T *lrow,
+                                            T (&fs)[S][25]) {
+  constexpr int NQ = 25 * S;  // planes, in the order (b, s, a)
   // lanes past the segment take the stencil of its last node (in the window)
   const int ixc = min(tx * TX + min(lane, TX - 1), c.nx - 1);
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   const unsigned row_bytes = unsigned(c.nx) * unsigned(sizeof(T));
-  T *const lrow = &rows_lds[wv][0][0];
   int xr0[5];
   T wx[5][P1];
   unsigned col_off[5];
@@ -98,7 +92,6 @@ __global__ __launch_bounds__(64 * kRowsTileRows) void k_step_rows(
 #pragma unroll
     for (int m = 0; m < P1; ++m) dst[m] = buffer_load<T>(rs, col_off[p.z], yoff[p.x][m]);
   };
-  T fs[S][25];
 #pragma unroll
   for (int q = 0; q < D && q < NQ; ++q) load(q, pre[q % (D + 1)]);
 #pragma unroll
@@ -118,7 +111,28 @@ __global__ __launch_bounds__(64 * kRowsTileRows) void k_step_rows(
     asm volatile("" : "+v"(acc));  // keep the plane's arithmetic in its place
     fs[p.y][p.z + 5 * p.x] = acc;
   }
-  if (ix < c.nx && lane < TX) collide_store<T, MODEL, PR>(fs, c, fout, (long long)iy * c.nx + ix, flag);
+}
+
+template <typename T, int P, int MODEL, bool PR>
+__global__ __launch_bounds__(64 * kRowsTileRows) void k_step_rows(
+    const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
+    const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc,
+    const T *__restrict__ yw, int TX, int ntx, int nty, StepConsts c, int *__restrict__ flag) {
+  constexpr int S = Sets<MODEL>::S;
+  __shared__ T rows_lds[kRowsTileRows][2][64];
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  if (tile >= ntx * nty) return;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int lane = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int iy = ty * kRowsTileRows + wv;
+  if (iy >= c.ny) return;  // whole wavefront; nothing below waits for others
+  T fs[S][25];
+  rows_stream<T, P + 1, S, rows_lookahead<T, P + 1>()>(fin, xrel, xw, xwin, ysrc, yw, TX, ntx,
+                                                       tx, iy, lane, c, &rows_lds[wv][0][0], fs);
+  const int ix = tx * TX + lane;
+  if (ix < c.nx && lane < TX)
+    collide_store<T, MODEL, PR>(fs, c, fout, (long long)iy * c.nx + ix, flag);
 }
 
 // PR: the Pr != 1 collision (thermal models only)

@@ -46,7 +46,7 @@ def _iso(wl):
     return wl
 
 
-@pytest.mark.parametrize("path", ["tiled", "direct"])
+@pytest.mark.parametrize("path", ["tiled", "direct", "rows"])
 @pytest.mark.parametrize("name,make", GRIDS, ids=[g[0] for g in GRIDS])
 def test_transposed_streaming_dot_product(name, make, path):
     from paper_1910_13918_amd import sllbm as C
@@ -225,7 +225,7 @@ THERMAL = [
 ]
 
 
-@pytest.mark.parametrize("path", ["tiled", "direct"])
+@pytest.mark.parametrize("path", ["tiled", "direct", "rows"])
 @pytest.mark.parametrize("name,make", THERMAL, ids=[t[0] for t in THERMAL])
 def test_thermal_transposed_streaming_dot_product(name, make, path):
     from paper_1910_13918_amd import sllbm as C
