@@ -207,11 +207,10 @@ bool mfma_fits(const sllbm_ctx *c) {
 
 // AUTO: the row-segment kernel where it measured faster than the tiled one
 // (1025^2-node grids, p = 1..4, every model): segments of at least 48
-// columns, except f + g in float32 at odd p and float64 with Pr != 1, where
-// the tiled kernel's shared windows won; then tiled, then direct.
+// columns, except float64 with Pr != 1, where the tiled kernel won; then
+// tiled, then direct.
 bool rows_preferred(const sllbm_ctx *c) {
   if (c->rows_tx < 48) return false;
-  if (nsets(c) == 2 && c->fp32 && c->p % 2 == 1) return false;
   if (!c->fp32 && c->omega_pr != c->omega) return false;
   return true;
 }

@@ -36,11 +36,18 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
-// Planes whose loads are in flight ahead of the one being interpolated
-// (measured on the 1025^2-node benchmark, p = 2: float32 is fastest with 2,
-// float64 with 10; both drop by several per cent either way).
-template <typename T, int P1>
-constexpr int rows_lookahead() { return sizeof(T) == 4 ? 2 : (P1 <= 3 ? 10 : 6); }
+// Planes whose loads are in flight ahead of the one being interpolated,
+// measured on 1025^2-node grids: float32 f + g is fastest with 4, 2, 1, 1
+// planes at p = 1..4 (about 6 rows in flight; one plane more or less costs
+// 1-10 %), while a single population set and the heavier Pr != 1 collision
+// want 2 from p = 3 on (1 plane: -6 % and -13 %); float64 with 10 at p <= 2
+// and 6 above (within 5 % from 8 to 20).
+template <typename T, int P1, int S, bool PR>
+constexpr int rows_lookahead() {
+  if (sizeof(T) == 8) return P1 <= 3 ? 10 : 6;
+  if (P1 == 2) return 4;
+  return P1 == 3 || S == 1 || PR ? 2 : 1;
+}
 
 // Streams the 25 S planes of `fin` into fs for the node (iy, tx TX + lane):
 // P1 taps per axis (p+1 forward, the transposed width for the adjoint),
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(64 * kRowsTileRows) void k_step_rows(
   const int iy = ty * kRowsTileRows + wv;
   if (iy >= c.ny) return;  // whole wavefront; nothing below waits for others
   T fs[S][25];
-  rows_stream<T, P + 1, S, rows_lookahead<T, P + 1>()>(fin, xrel, xw, xwin, ysrc, yw, TX, ntx,
+  rows_stream<T, P + 1, S, rows_lookahead<T, P + 1, S, PR>()>(fin, xrel, xw, xwin, ysrc, yw, TX, ntx,
                                                        tx, iy, lane, c, &rows_lds[wv][0][0], fs);
   const int ix = tx * TX + lane;
   if (ix < c.nx && lane < TX)
