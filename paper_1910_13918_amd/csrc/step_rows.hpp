@@ -78,16 +78,20 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
     col_off[a] =
         unsigned(wrap_or_clamp(xwin[a * ntx + tx] + lane, c.nx, c.perx)) * unsigned(sizeof(T));
   }
-  // source rows (byte offsets) and weights of the y-factor: wave-uniform
+  // source rows (byte offsets) and weights of the y-factor: wave-uniform,
+  // fetched one phase (b) at a time, shortly before its first load, so that
+  // only two phases' worth occupy scalar registers
   unsigned yoff[5][P1];
   T wy[5][P1];
-#pragma unroll
-  for (int b = 0; b < 5; ++b)
+  auto fetch_phase = [&](int b) {
+    int z = 0;
+    asm volatile("" : "+s"(z));  // keeps the scalar loads here
 #pragma unroll
     for (int m = 0; m < P1; ++m) {
-      yoff[b][m] = unsigned(ysrc[(b * P1 + m) * c.ny + iy]) * row_bytes;
-      wy[b][m] = yw[(b * P1 + m) * c.ny + iy];
+      yoff[b][m] = unsigned(ysrc[(b * P1 + m) * c.ny + iy + z]) * row_bytes;
+      wy[b][m] = yw[(b * P1 + m) * c.ny + iy + z];
     }
+  };
   auto plane_of = [](int q) {  // q -> (b, s, a)
     const int b = q / (5 * S), r = q % (5 * S);
     return int3{b, r / 5, r % 5};
@@ -99,10 +103,16 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
 #pragma unroll
     for (int m = 0; m < P1; ++m) dst[m] = buffer_load<T>(rs, col_off[p.z], yoff[p.x][m]);
   };
+  constexpr int PH = 5 * S;  // planes per phase
+#pragma unroll
+  for (int b = 0; b <= (D + 1) / PH && b < 5; ++b) fetch_phase(b);
 #pragma unroll
   for (int q = 0; q < D && q < NQ; ++q) load(q, pre[q % (D + 1)]);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
+    // the phase whose first load comes two iterations from now
+    if ((q + D + 2) % PH == 0 && (q + D + 2) / PH < 5 && (q + D + 2) / PH > (D + 1) / PH)
+      fetch_phase((q + D + 2) / PH);
     if (q + D < NQ) load(q + D, pre[(q + D) % (D + 1)]);
     const int3 p = plane_of(q);
     const T(&v)[P1] = pre[q % (D + 1)];

@@ -145,7 +145,7 @@ def test_mapped_grid_one_step_all_paths():
     g, sim = _oracle(wl)
     F0 = _state(wl, sim, g, seed=13, rel=0.02)
     F1 = sim.step(F0)
-    for path in ("direct", "tiled", "records"):
+    for path in ("direct", "tiled", "records", "rows"):
         s = _solver(wl, "fp64", path)
         try:
             s.set_populations(F0)
@@ -258,7 +258,7 @@ def test_pure_streaming_reproduces_polynomials():
     P = 1.0 + 0.3 * X ** 4 - 0.2 * X * Y ** 3 + 0.1 * Y ** 2
     F0 = np.tile(P, (1, 25, 1))
     F1 = sim.stream(F0)
-    for path in ("direct", "tiled", "records"):
+    for path in ("direct", "tiled", "records", "rows"):
         s = _solver(wl, "fp64", path)
         try:
             s.set_populations(F0)
@@ -276,7 +276,7 @@ def test_tiny_grids():
         g, sim = _oracle(wl)
         F0 = _state(wl, sim, g, seed=9, rel=0.05)
         F1 = sim.step(F0)
-        for path in ("direct", "tiled", "records"):
+        for path in ("direct", "tiled", "records", "rows"):
             s = _solver(wl, "fp64", path)
             try:
                 s.set_populations(F0)
