@@ -107,7 +107,8 @@ typedef enum {
                              registers (y-factor), the x-factor from a per-
                              wavefront LDS row, no workgroup barrier (needs a
                              segment of >= 32 columns whose x-stencils fit 64
-                             source columns; SLLBM_E_UNSUPPORTED otherwise) */
+                             source columns and a first 1-D velocity of 0, as
+                             in Table I; SLLBM_E_UNSUPPORTED otherwise) */
 } sllbm_path;
 
 /* ---- lifetime ------------------------------------------------------------ */

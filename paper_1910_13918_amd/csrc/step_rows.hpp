@@ -51,7 +51,10 @@ constexpr int rows_lookahead() {
 
 // Streams the 25 S planes of `fin` into fs for the node (iy, tx TX + lane):
 // P1 taps per axis (p+1 forward, the transposed width for the adjoint),
-// D planes of loads in flight; lrow = this wavefront's two LDS rows.
+// D planes of loads in flight; lrow = this wavefront's two LDS rows.  The
+// first 1-D velocity is 0 (Table I; the host checks that its y-table is the
+// identity on every row), so the phase b = 0 departs from the node itself and
+// loads the target row alone.
 template <typename T, int P1, int S, int D>
 __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
                                             const int32_t *__restrict__ xrel,
@@ -100,12 +103,18 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
   auto load = [&](int q, T (&dst)[P1]) {
     const int3 p = plane_of(q);
     const auto rs = make_rsrc(fin + (long long)(p.y * 25 + p.z + 5 * p.x) * N, plane_bytes);
+    if (p.x == 0) {  // identity y-factor (resolved at compile time)
+      dst[0] = buffer_load<T>(rs, col_off[p.z], unsigned(iy) * row_bytes);
 #pragma unroll
-    for (int m = 0; m < P1; ++m) dst[m] = buffer_load<T>(rs, col_off[p.z], yoff[p.x][m]);
+      for (int m = 1; m < P1; ++m) dst[m] = T(0);
+    } else {
+#pragma unroll
+      for (int m = 0; m < P1; ++m) dst[m] = buffer_load<T>(rs, col_off[p.z], yoff[p.x][m]);
+    }
   };
   constexpr int PH = 5 * S;  // planes per phase
 #pragma unroll
-  for (int b = 0; b <= (D + 1) / PH && b < 5; ++b) fetch_phase(b);
+  for (int b = 1; b <= (D + 1) / PH && b < 5; ++b) fetch_phase(b);
 #pragma unroll
   for (int q = 0; q < D && q < NQ; ++q) load(q, pre[q % (D + 1)]);
 #pragma unroll
@@ -116,9 +125,12 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
     if (q + D < NQ) load(q + D, pre[(q + D) % (D + 1)]);
     const int3 p = plane_of(q);
     const T(&v)[P1] = pre[q % (D + 1)];
-    T y = wy[p.x][0] * v[0];
+    T y = v[0];
+    if (p.x != 0) {
+      y = wy[p.x][0] * v[0];
 #pragma unroll
-    for (int m = 1; m < P1; ++m) y = fma(wy[p.x][m], v[m], y);
+      for (int m = 1; m < P1; ++m) y = fma(wy[p.x][m], v[m], y);
+    }
     T *row = lrow + (q & 1) * 64;
     row[lane] = y;
     wave_lds_sync();
@@ -157,7 +169,7 @@ template <bool PR>
 hipError_t launch_rows_family(int fp32, int model, const StepConsts &c, const DevTables &t,
                               const void *fin, void *fout, int *flag, hipStream_t s) {
   if (t.rows_tx < kRowsMinCols || t.rows_tx > 64 || t.rows_xrel == nullptr ||
-      t.rows_xwin == nullptr)
+      t.rows_xwin == nullptr || !(t.ident_y & 1))
     return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
     const int ntx = (c.nx + t.rows_tx - 1) / t.rows_tx;

@@ -216,6 +216,20 @@ AxisTable build_axis_table(const Axis &ax, double disp) {
   return t;
 }
 
+bool identity_table(const AxisTable &t, int n) {
+  for (int j = 0; j < n; ++j) {
+    int ones = 0;
+    for (int m = 0; m < t.taps; ++m) {
+      const double w = t.w[size_t(j) * t.taps + m];
+      if (w == 0.0) continue;
+      if (w != 1.0 || t.src[size_t(j) * t.taps + m] != j) return false;
+      ++ones;
+    }
+    if (ones != 1) return false;
+  }
+  return true;
+}
+
 AxisTable transpose_axis_table(const Axis &ax, const AxisTable &fwd) {
   const int n = ax.n, P1 = fwd.taps;
   // (virtual target, weight) pairs per source node

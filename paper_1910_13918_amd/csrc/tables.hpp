@@ -85,6 +85,10 @@ struct AxisTable {
 
 AxisTable build_axis_table(const Axis &ax, double disp);
 
+// True when every node's stencil in t is the node itself with weight 1 (all
+// other weights exactly 0): the table of a zero velocity component.
+bool identity_table(const AxisTable &t, int n);
+
 // Transpose of a forward table: entry (j, t) holds the weight with which
 // node j's value enters target start[j] + t.  Targets of one source node are
 // consecutive because departures are monotone along the axis.

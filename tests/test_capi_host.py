@@ -117,6 +117,19 @@ def test_resolved_path():
             assert C.sllbm_resolved_path(ctx) == want, (prec, p, Pr)
         finally:
             C.sllbm_destroy(ctx)
+    # the row-segment kernels load a single row for the first 1-D velocity,
+    # which must be 0: a permuted velocity set resolves to TILED
+    r10 = np.sqrt(10.0)
+    xi = np.array([np.sqrt(5 - r10), 0.0, np.sqrt(5 + r10), -np.sqrt(5 - r10), -np.sqrt(5 + r10)])
+    w = np.array([(7 + 2 * r10) / 60, 8 / 15, (7 - 2 * r10) / 60, (7 + 2 * r10) / 60,
+                  (7 - 2 * r10) / 60])
+    ctx = _ctx()
+    try:
+        C.sllbm_set_velocity_set(ctx, 5, xi.ctypes.data, w.ctypes.data)
+        _setup(ctx, nc=20, dt=1e-3)
+        assert C.sllbm_resolved_path(ctx) == C.PATH_TILED
+    finally:
+        C.sllbm_destroy(ctx)
     ctx = _ctx()
     try:
         _setup(ctx, nc=20, dt=1e-3)

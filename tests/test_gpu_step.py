@@ -284,3 +284,38 @@ def test_tiny_grids():
                 assert _rel(s.populations(), F1) <= 1e-12, (per, path)
             finally:
                 s.close()
+
+
+def test_permuted_velocity_set():
+    """The D1Q5 set in another order (0 second): the same scheme with the
+    velocities renumbered.  The row-segment kernels assume the first 1-D
+    velocity is 0 and refuse; AUTO takes the tiled kernel, which matches the
+    oracle run on the same permuted set."""
+    from paper_1910_13918_amd import sllbm as C
+    from paper_1910_13918_amd.solver import Solver
+    r10 = np.sqrt(10.0)
+    xi1 = np.array([np.sqrt(5 - r10), 0.0, np.sqrt(5 + r10), -np.sqrt(5 - r10), -np.sqrt(5 + r10)])
+    w1 = np.array([(7 + 2 * r10) / 60, 8 / 15, (7 - 2 * r10) / 60, (7 + 2 * r10) / 60,
+                   (7 - 2 * r10) / 60])
+    wl = _wl("polyatomic", 2, True, 35, 9)
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, xi1=xi1, w1=w1)
+    F0 = _state(wl, sim, g, seed=17, rel=0.05)
+    F1 = sim.step(F0)
+    for path in ("auto", "rows"):
+        s = Solver(p=wl.p, edges_x=wl.edges_x, edges_y=wl.edges_y, periodic_x=True, periodic_y=True,
+                   dt=wl.dt, nu=wl.nu, model=wl.model, gamma=wl.gamma, precision="fp64",
+                   path=path, xi1d=xi1, w1d=w1)
+        try:
+            print(f"[gpu] permuted velocity set {path}", flush=True)
+            s.set_populations(F0)
+            if path == "rows":
+                with pytest.raises(C.SllbmError) as e:
+                    s.step(1)
+                assert e.value.code == C.E_UNSUPPORTED
+                continue
+            assert s.resolved_path() == "tiled"
+            s.step(1)
+            assert _rel(s.populations(), F1) <= 1e-12
+        finally:
+            s.close()
