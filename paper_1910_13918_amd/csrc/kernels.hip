@@ -64,6 +64,35 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
+// Mass only: per-block partial sums of M_v rho_v, reading the f planes alone
+// (rho = sum f; the same summation order as node_moments).
+template <typename T>
+__global__ __launch_bounds__(256) void k_mass(const T *__restrict__ f,
+                                              const double *__restrict__ mx,
+                                              const double *__restrict__ my,
+                                              double *__restrict__ partial, StepConsts c) {
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  double mass = 0.0;
+  if (v < c.n) {
+    const long long N = c.n;
+    T fs[25];
+#pragma unroll
+    for (int i = 0; i < 25; ++i) fs[i] = f[i * N + v];
+    double rho = 0.0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      double r_b = 0.0;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) r_b += double(fs[a + 5 * b]);
+      rho += r_b;
+    }
+    const int ix = int(v % c.nx), iy = int(v / c.nx);
+    mass = mx[ix] * my[iy] * rho;
+  }
+  const double tot = block_sum_256(mass);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
 __global__ void k_clear_int(int *__restrict__ p) {
   if (threadIdx.x == 0) p[0] = 0;
 }
@@ -92,6 +121,10 @@ hipError_t init_t(const StepConsts &c, const double *rho, const double *ux, cons
 template <typename T, int MODEL>
 hipError_t moments_t(const StepConsts &c, const DevTables &t, const void *f, double *rho,
                      double *ux, double *uy, double *temp, double *partial, hipStream_t s) {
+  if (!rho && !ux && !uy && !temp) {  // the mass alone needs the f planes only
+    k_mass<T><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, partial, c);
+    return hipGetLastError();
+  }
   k_moments<T, MODEL><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, rho,
                                                      ux, uy, temp, partial, c);
   return hipGetLastError();

@@ -37,16 +37,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Planes whose loads are in flight ahead of the one being interpolated,
-// measured on 1025^2-node grids: float32 f + g is fastest with 4, 2, 1, 1
-// planes at p = 1..4 (about 6 rows in flight; one plane more or less costs
-// 1-10 %), while a single population set and the heavier Pr != 1 collision
-// want 2 from p = 3 on (1 plane: -6 % and -13 %); float64 with 10 at p <= 2
-// and 6 above (within 5 % from 8 to 20).
+// measured on 1025^2-node grids (float32; one plane more or less costs 1-10 %):
+//   p = 1: 4;  p = 2: 3;  p = 3, 4: 3 for a single population set or the
+//   Pr != 1 collision, else 1 (p = 3) and 2 (p = 4).
+// float64: 10 at p <= 2 and 6 above (within 5 % from 8 to 20).
 template <typename T, int P1, int S, bool PR>
 constexpr int rows_lookahead() {
   if (sizeof(T) == 8) return P1 <= 3 ? 10 : 6;
   if (P1 == 2) return 4;
-  return P1 == 3 || S == 1 || PR ? 2 : 1;
+  if (P1 == 3 || S == 1 || PR) return 3;
+  return P1 == 4 ? 1 : 2;
 }
 
 // Streams the 25 S planes of `fin` into fs for the node (iy, tx TX + lane):
