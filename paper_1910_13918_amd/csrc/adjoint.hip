@@ -438,7 +438,7 @@ hipError_t launch_adjoint_step(int fp32, int model, int kind, const StepConsts &
     constexpr int S = Sets<MODEL>::S;
     if (kind == kAdjointRows) {
       if (t.rows_tx < kRowsMinCols || t.rows_tx > 64 || !t.rows_xrel || !t.rows_xwin ||
-          !(t.ident_y & 1))
+          !(t.ident_y & t.ident_x & 1))
         return hipErrorInvalidValue;
       const int ntx = (c.nx + t.rows_tx - 1) / t.rows_tx;
       const int nty = (c.ny + kRowsTileRows - 1) / kRowsTileRows;

@@ -56,7 +56,7 @@ struct sllbm_ctx {
   bool mfma_blocks_ok = false;
   std::vector<int32_t> ywin, yrel, xwin, xrel;
   int rows_tx = 0;  // row-segment path: segment width (0: unavailable)
-  int ident_y = 0, ident_yT = 0;  // identity y-tables (bit per component)
+  int ident_x = 0, ident_y = 0, ident_xT = 0, ident_yT = 0;  // identity tables, bit per component
   std::vector<int32_t> rows_xwin, rows_xrel;
 
   // adjoint: transposed tables, windows (built on first use)
@@ -189,10 +189,12 @@ void build_host_tables(sllbm_ctx *c) {
   c->win_cols = build_windows(c->xt, c->ax.n, kTileCols, c->xwin, c->xrel);
   c->mfma_blocks_ok = mfma_blocks_fit(c);
   c->rows_tx = rows_segment_width(c->xt, c->ax.n, c->rows_xwin, c->rows_xrel);
-  c->ident_y = 0;
-  for (int b = 0; b < kQ1; ++b)
+  c->ident_x = c->ident_y = 0;
+  for (int b = 0; b < kQ1; ++b) {
+    if (identity_table(c->xt[b], c->ax.n)) c->ident_x |= 1 << b;
     if (identity_table(c->yt[b], c->ay.n)) c->ident_y |= 1 << b;
-  if (!(c->ident_y & 1)) c->rows_tx = 0;  // the row-segment kernels need xi_0 = 0
+  }
+  if (!(c->ident_x & c->ident_y & 1)) c->rows_tx = 0;  // the row-segment kernels need xi_0 = 0
   c->host_dirty = false;
   c->dev_dirty = true;
   c->rec_dirty = true;
@@ -389,6 +391,7 @@ DevTables make_tables(const sllbm_ctx *c) {
   t.rows_tx = c->rows_tx;
   t.rows_xrel = c->rows_tx ? static_cast<const int32_t *>(c->rows_xrel_d.ptr) : nullptr;
   t.rows_xwin = c->rows_tx ? static_cast<const int32_t *>(c->rows_xwin_d.ptr) : nullptr;
+  t.ident_x = c->ident_x;
   t.ident_y = c->ident_y;
   return t;
 }
@@ -473,10 +476,12 @@ int prepare_adjoint(sllbm_ctx *c) {
   c->win_rowsT = build_windows(c->ytT, c->ay.n, kTileRows, c->ywinT, c->yrelT);
   c->win_colsT = build_windows(c->xtT, c->ax.n, kTileCols, c->xwinT, c->xrelT);
   c->rows_txT = rows_segment_width(c->xtT, c->ax.n, c->rows_xwinT, c->rows_xrelT);
-  c->ident_yT = 0;
-  for (int b = 0; b < kQ1; ++b)
+  c->ident_xT = c->ident_yT = 0;
+  for (int b = 0; b < kQ1; ++b) {
+    if (identity_table(c->xtT[b], c->ax.n)) c->ident_xT |= 1 << b;
     if (identity_table(c->ytT[b], c->ay.n)) c->ident_yT |= 1 << b;
-  if (!(c->ident_yT & 1)) c->rows_txT = 0;
+  }
+  if (!(c->ident_xT & c->ident_yT & 1)) c->rows_txT = 0;
   rc = upload(c, c->xsrcT, comp_major<int32_t>(c->xtT, c->ax.n, taps, false));
   if (!rc) rc = upload_weights(c, c->xwT, comp_major<double>(c->xtT, c->ax.n, taps, true));
   if (!rc) rc = upload(c, c->ysrcT, comp_major<int32_t>(c->ytT, c->ay.n, taps, false));
@@ -509,6 +514,7 @@ DevTables make_adjoint_tables(const sllbm_ctx *c) {
   t.rows_tx = c->rows_txT;
   t.rows_xrel = c->rows_txT ? static_cast<const int32_t *>(c->rows_xrelT_d.ptr) : nullptr;
   t.rows_xwin = c->rows_txT ? static_cast<const int32_t *>(c->rows_xwinT_d.ptr) : nullptr;
+  t.ident_x = c->ident_xT;
   t.ident_y = c->ident_yT;
   return t;
 }

@@ -55,8 +55,8 @@ struct DevTables {
   int rows_tx;                 // 0: no such segment width (path unavailable)
   const int32_t *rows_xrel;    // [5][p+1][nx], relative to the segment's window
   const int32_t *rows_xwin;    // [5][nsegments]
-  int ident_y;                 // bit b: the y-table of component b is the identity on every row
-                               // (the row-segment kernels need bit 0: xi_0 = 0)
+  int ident_x, ident_y;        // bit a (b): the x- (y-) table of component a (b) is the
+                               // identity (the row-segment kernels need bit 0: xi_0 = 0)
 };
 
 // Narrowest row segment of the row-segment path (narrower ones leave most

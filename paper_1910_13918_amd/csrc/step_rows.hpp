@@ -37,24 +37,26 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Planes whose loads are in flight ahead of the one being interpolated,
-// measured on 1025^2-node grids (float32; one plane more or less costs 1-10 %):
+// measured on 1025^2-node grids (float32; one plane more or less costs
+// 1-10 %, about 5-9 rows in flight is best):
 //   p = 1: 4;  p = 2: 3;  p = 3, 4: 3 for a single population set or the
-//   Pr != 1 collision, else 1 (p = 3) and 2 (p = 4).
+//   Pr != 1 collision, else 2 (p = 3) and 1 (p = 4).
 // float64: 10 at p <= 2 and 6 above (within 5 % from 8 to 20).
 template <typename T, int P1, int S, bool PR>
 constexpr int rows_lookahead() {
   if (sizeof(T) == 8) return P1 <= 3 ? 10 : 6;
   if (P1 == 2) return 4;
   if (P1 == 3 || S == 1 || PR) return 3;
-  return P1 == 4 ? 1 : 2;
+  return P1 == 4 ? 2 : 1;
 }
 
 // Streams the 25 S planes of `fin` into fs for the node (iy, tx TX + lane):
 // P1 taps per axis (p+1 forward, the transposed width for the adjoint),
 // D planes of loads in flight; lrow = this wavefront's two LDS rows.  The
-// first 1-D velocity is 0 (Table I; the host checks that its y-table is the
-// identity on every row), so the phase b = 0 departs from the node itself and
-// loads the target row alone.
+// first 1-D velocity is 0 (Table I; the host checks that its x- and y-tables
+// are the identity), so the phase b = 0 departs from the node itself and
+// loads the target row alone, the x-component a = 0 reads the node's own
+// column, and the rest velocity (0, 0) is the node's own value.
 template <typename T, int P1, int S, int D>
 __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
                                             const int32_t *__restrict__ xrel,
@@ -73,6 +75,8 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
   int xr0[5];
   T wx[5][P1];
   unsigned col_off[5];
+  const int own0 = ixc - xwin[tx];  // the node's column in the a = 0 window
+  const unsigned own_off = unsigned(ixc) * unsigned(sizeof(T));
 #pragma unroll
   for (int a = 0; a < 5; ++a) {
     xr0[a] = xrel[(a * P1) * c.nx + ixc];
@@ -104,7 +108,7 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
     const int3 p = plane_of(q);
     const auto rs = make_rsrc(fin + (long long)(p.y * 25 + p.z + 5 * p.x) * N, plane_bytes);
     if (p.x == 0) {  // identity y-factor (resolved at compile time)
-      dst[0] = buffer_load<T>(rs, col_off[p.z], unsigned(iy) * row_bytes);
+      dst[0] = buffer_load<T>(rs, p.z == 0 ? own_off : col_off[p.z], unsigned(iy) * row_bytes);
 #pragma unroll
       for (int m = 1; m < P1; ++m) dst[m] = T(0);
     } else {
@@ -131,12 +135,19 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
 #pragma unroll
       for (int m = 1; m < P1; ++m) y = fma(wy[p.x][m], v[m], y);
     }
-    T *row = lrow + (q & 1) * 64;
-    row[lane] = y;
-    wave_lds_sync();
-    T acc = wx[p.z][0] * row[xr0[p.z]];
+    T acc = y;  // the rest velocity: loaded at the node's own column
+    if (p.x != 0 || p.z != 0) {
+      T *row = lrow + (q & 1) * 64;
+      row[lane] = y;
+      wave_lds_sync();
+      if (p.z == 0) {  // identity x-factor
+        acc = row[own0];
+      } else {
+        acc = wx[p.z][0] * row[xr0[p.z]];
 #pragma unroll
-    for (int m = 1; m < P1; ++m) acc = fma(wx[p.z][m], row[xr0[p.z] + m], acc);
+        for (int m = 1; m < P1; ++m) acc = fma(wx[p.z][m], row[xr0[p.z] + m], acc);
+      }
+    }
     asm volatile("" : "+v"(acc));  // keep the plane's arithmetic in its place
     fs[p.y][p.z + 5 * p.x] = acc;
   }
@@ -169,7 +180,7 @@ template <bool PR>
 hipError_t launch_rows_family(int fp32, int model, const StepConsts &c, const DevTables &t,
                               const void *fin, void *fout, int *flag, hipStream_t s) {
   if (t.rows_tx < kRowsMinCols || t.rows_tx > 64 || t.rows_xrel == nullptr ||
-      t.rows_xwin == nullptr || !(t.ident_y & 1))
+      t.rows_xwin == nullptr || !(t.ident_y & t.ident_x & 1))
     return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
     const int ntx = (c.nx + t.rows_tx - 1) / t.rows_tx;
