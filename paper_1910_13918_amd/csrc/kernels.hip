@@ -57,7 +57,9 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
     if (ux_o) ux_o[v] = m[1];
     if (uy_o) uy_o[v] = m[2];
     if (T_o) T_o[v] = m[3];
-    const int ix = int(v % c.nx), iy = int(v / c.nx);
+    // 32-bit division (nodes < 2^31): the 64-bit form dominated these kernels
+    const unsigned vv = unsigned(v), nx = unsigned(c.nx);
+    const int ix = int(vv % nx), iy = int(vv / nx);
     mass = mx[ix] * my[iy] * m[0];
   }
   const double tot = block_sum_256(mass);
@@ -86,7 +88,9 @@ __global__ __launch_bounds__(256) void k_mass(const T *__restrict__ f,
       for (int a = 0; a < 5; ++a) r_b += double(fs[a + 5 * b]);
       rho += r_b;
     }
-    const int ix = int(v % c.nx), iy = int(v / c.nx);
+    // 32-bit division (nodes < 2^31): the 64-bit form dominated these kernels
+    const unsigned vv = unsigned(v), nx = unsigned(c.nx);
+    const int ix = int(vv % nx), iy = int(vv / nx);
     mass = mx[ix] * my[iy] * rho;
   }
   const double tot = block_sum_256(mass);
