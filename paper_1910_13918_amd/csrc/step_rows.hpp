@@ -153,8 +153,15 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
   }
 }
 
+// Minimum waves per SIMD the compiler is asked to fit: a single float32
+// population set gets 6 (70-73 VGPRs instead of ~97; Taylor-Green p = 2:
+// +14 %), f + g keeps the default (the same request spills and costs 3-18 %).
+template <typename T, int S>
+constexpr int rows_min_waves() { return sizeof(T) == 4 && S == 1 ? 6 : 1; }
+
 template <typename T, int P, int MODEL, bool PR>
-__global__ __launch_bounds__(64 * kRowsTileRows) void k_step_rows(
+__global__ __launch_bounds__(64 * kRowsTileRows,
+                             (rows_min_waves<T, Sets<MODEL>::S>())) void k_step_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
     const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc,
     const T *__restrict__ yw, int TX, int ntx, int nty, StepConsts c, int *__restrict__ flag) {
