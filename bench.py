@@ -93,6 +93,7 @@ def timed(wl, precision, path, steps, warmup):
     from paper_1910_13918_amd.solver import Solver
     s = Solver.from_workload(wl, precision=precision, path=path)
     s.init_from_workload()
+    s.mass0 = s.mass()  # initial mass, for the drift reported after the run (untimed)
     s.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -298,6 +299,9 @@ def main():
     if not args.no_fp64 and args.precision != "fp64":
         s64, ms64, _ = timed(wl, "fp64", args.path, args.steps, args.warmup)
         m32, m64 = s.moments(), s64.moments()
+
+        def l2_rel(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
         out["fp64"] = {"value": s64.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps,
                        "bytes_per_node_update": bytes_per_node_update(wl, "fp64", s64.resolved_path()),
                        "traffic": profiled_traffic(wname, "fp64", s64.resolved_path()),
@@ -306,7 +310,16 @@ def main():
                            "rho_max_rel": float(np.abs(m32[0] - m64[0]).max() / np.abs(m64[0]).max()),
                            "u_max_abs": float(max(np.abs(m32[1] - m64[1]).max(),
                                                   np.abs(m32[2] - m64[2]).max())),
-                           "theta_max_rel": float(np.abs(m32[3] - m64[3]).max() / np.abs(m64[3]).max())}}
+                           "theta_max_rel": float(np.abs(m32[3] - m64[3]).max() / np.abs(m64[3]).max()),
+                           "rho_l2_rel": l2_rel(m32[0], m64[0]),
+                           "u_l2_rel": float(np.sqrt(((m32[1] - m64[1]) ** 2 + (m32[2] - m64[2]) ** 2).sum()
+                                                     / (m64[1] ** 2 + m64[2] ** 2).sum())),
+                           "theta_l2_rel": l2_rel(m32[3], m64[3]),
+                           # zero-gradient boundaries: mass is not conserved, so these are
+                           # changes over the run, and the FP32 - FP64 difference of the mass
+                           "mass_rel_change_fp32": s.mass() / s.mass0 - 1.0,
+                           "mass_rel_change_fp64": s64.mass() / s64.mass0 - 1.0,
+                           "mass_fp32_vs_fp64_rel": s.mass() / s64.mass() - 1.0}}
         s64.close()
     # initialisation, moments and mass on the same grid (this re-initialises s)
     out["aux_kernels"] = aux_kernels(s)
