@@ -1,0 +1,87 @@
+"""Whole runs of two benchmark configurations on the GPU.
+
+* The seeded four-quadrant Riemann problem on 64 x 64 cells of order 2 to
+  t = 0.25, against the FP64 oracle's moments at every 4th node per axis
+  (tests/golden/riemann64_reference.json, written by the oracle alone):
+  FP64 to 1e-10 relative (rounding-order differences grown over the run's
+  steps through the shocks), FP32 populations with the error stated.
+* The shock-vortex interaction, 1024 x 512 cells of order 3 on the stretched
+  grid at Pr = 0.75, for its 2000 steps in FP32 and FP64 (the vortex crosses
+  the shock): both stay stable and the FP32 result is stated against the
+  FP64 one (measured: rho 3.2e-5 max / 1.0e-5 L2, u 2.5e-5 / 2.5e-6,
+  T 1.5e-5 / 2.4e-6; mass change -6.9e-6 vs 2.5e-7); the bounds leave a
+  factor 4-6 of room.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1910_13918_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a HIP device")]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _run(wl, precision, steps):
+    from paper_1910_13918_amd.solver import Solver
+    s = Solver.from_workload(wl, precision=precision)
+    try:
+        s.init_from_workload()
+        m0 = s.mass()
+        s.step(steps)
+        return s.moments(), s.flags()[0], s.mass() / m0 - 1.0
+    finally:
+        s.close()
+
+
+def _errors(got, ref):
+    """max and L2 relative errors of rho, |u| (vector) and T."""
+    d_rho = got[0] - ref[0]
+    d_u = np.hypot(got[1] - ref[1], got[2] - ref[2])
+    u_ref = np.hypot(ref[1], ref[2])
+    d_t = got[3] - ref[3]
+    return {"rho_max": float(np.abs(d_rho).max() / np.abs(ref[0]).max()),
+            "rho_l2": float(np.linalg.norm(d_rho) / np.linalg.norm(ref[0])),
+            "u_max": float(d_u.max() / u_ref.max()),
+            "u_l2": float(np.linalg.norm(d_u) / np.linalg.norm(u_ref)),
+            "T_max": float(np.abs(d_t).max() / np.abs(ref[3]).max()),
+            "T_l2": float(np.linalg.norm(d_t) / np.linalg.norm(ref[3]))}
+
+
+def _reference():
+    ref = json.load(open(os.path.join(HERE, "golden", "riemann64_reference.json")))
+    nodes = np.array(ref["nodes"])
+    return ref, nodes, [np.array(ref[k]) for k in ("rho", "ux", "uy", "T")]
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_riemann64_to_quarter_time_against_oracle(precision, bound):
+    ref, nodes, want = _reference()
+    wl = W.riemann(64, 2)
+    assert wl.steps == ref["steps"]
+    print(f"[gpu] riemann 64^2 to t = 0.25, {precision}, {wl.steps} steps", flush=True)
+    m, unstable, _ = _run(wl, precision, wl.steps)
+    assert unstable == 0
+    err = _errors([a[nodes] for a in m], want)
+    print(f"[gpu] {precision} error vs FP64 oracle: {err}", flush=True)
+    assert max(err.values()) <= bound, err
+
+
+def test_shock_vortex_full_run_fp32_vs_fp64():
+    wl = W.svi(1024, 512, 3)
+    assert wl.steps == 2000 and wl.Pr == 0.75
+    print("[gpu] shock-vortex 1024x512 p = 3, 2000 steps, fp32 and fp64", flush=True)
+    m32, u32, dm32 = _run(wl, "fp32", wl.steps)
+    m64, u64, dm64 = _run(wl, "fp64", wl.steps)
+    assert u32 == 0 and u64 == 0
+    err = _errors(m32, m64)
+    print(f"[gpu] shock-vortex FP32 vs FP64 after 2000 steps: {err}; mass change "
+          f"{dm32:.3e} (FP32), {dm64:.3e} (FP64)", flush=True)
+    assert max(err["rho_max"], err["u_max"], err["T_max"]) <= 2e-4, err
+    assert max(err["rho_l2"], err["u_l2"], err["T_l2"]) <= 5e-5, err
+    assert abs(dm32 - dm64) <= 4e-5
