@@ -178,7 +178,8 @@ def test_fp32_rollout_gradient_close_to_fp64():
 def test_adjoint_workload_against_central_differences():
     """The 128 x 128-cell, p = 4 Taylor-Green adjoint workload (500 steps,
     checkpoints every 50), FP64 path: the gradient's directional derivatives
-    against central differences with eps = 1e-4 along 4 seeded directions."""
+    against central differences with eps = 1e-4 along 32 seeded directions;
+    the FP32 rollout's gradient against the FP64 one (relative L2)."""
     from paper_1910_13918_amd.solver import Solver
     wl = W.adjoint_tgv()
     L, gu, gv, _, s = _rollout_grad(wl, "fp64", wl.steps, 50)
@@ -194,12 +195,19 @@ def test_adjoint_workload_against_central_differences():
         return float(_loss_torch(rho, ux, uy, M, ut, vt))
 
     try:
-        for d in W.random_directions(s.n, 4, seed=4321):
+        print("[gpu] adjoint workload: 32 central differences (FP64)", flush=True)
+        for d in W.random_directions(s.n, 32, seed=4321):
             fd = (loss(d[0], d[1], 1e-4) - loss(d[0], d[1], -1e-4)) / 2e-4
             got = float(np.dot(gu, d[0]) + np.dot(gv, d[1]))
             assert got == pytest.approx(fd, rel=1e-5)
     finally:
         s.close()
+    _, gu32, gv32, _, s32 = _rollout_grad(wl, "fp32", wl.steps, 50)
+    s32.close()
+    g64, g32 = np.concatenate([gu, gv]), np.concatenate([gu32, gv32])
+    rel = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    print(f"[gpu] adjoint workload FP32 vs FP64 gradient: {rel:.2e} relative L2", flush=True)
+    assert rel <= 1e-4  # measured 8.4e-6
     assert isinstance(Solver, type)
 
 
