@@ -166,8 +166,12 @@ int sllbm_init_grid_mapped(sllbm_ctx *ctx, int ncx, int ncy, const double *edges
 int sllbm_set_physics(sllbm_ctx *ctx, double dt, double nu, double gamma, double Pr, int model);
 
 /* Streaming kernel family (sllbm_path).  SLLBM_PATH_TILED needs departures
- * that stay within a bounded row window (checked; SLLBM_E_UNSUPPORTED
- * otherwise). */
+ * that stay within a bounded row window, SLLBM_PATH_ROWS segments of >= 32
+ * nodes whose x-stencils fit 64 columns and a first 1-D velocity of 0,
+ * SLLBM_PATH_MFMA float32 and narrow stencils (checked at sllbm_step;
+ * SLLBM_E_UNSUPPORTED otherwise).  The adjoint calls use the same family
+ * for their transposed gather (AUTO: row segments, else tiled, else
+ * direct). */
 int sllbm_set_path(sllbm_ctx *ctx, int path);
 
 /* The kernel family the next step runs (sllbm_path, never AUTO), after grid,
