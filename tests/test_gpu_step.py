@@ -319,3 +319,30 @@ def test_permuted_velocity_set():
             assert _rel(s.populations(), F1) <= 1e-12
         finally:
             s.close()
+
+
+@pytest.mark.parametrize("cfl", [1.5, 3.0])
+@pytest.mark.parametrize("path", ["direct", "tiled", "records", "rows"])
+def test_large_cfl_one_step(path, cfl):
+    """Departures several node spacings away (CFL 1.5 and 3 on the smallest
+    GLC gap, p = 3, f + g, Table III states with seeded noise): every gather
+    that accepts the stencil windows matches the oracle; the tiled and
+    row-segment kernels refuse windows they cannot hold."""
+    from paper_1910_13918_amd import sllbm as C
+    wl = W.riemann(40, 3, states=W.RIEMANN_TABLE3_STATES, cfl=cfl)
+    wl.edges_y = wl.edges_y[0] + (wl.edges_x[1] - wl.edges_x[0]) * np.arange(13)
+    g, sim = _oracle(wl)
+    F0 = _state(wl, sim, g, seed=19, rel=0.02)
+    F1 = sim.step(F0)
+    s = _solver(wl, "fp64", path)
+    try:
+        print(f"[gpu] large CFL {cfl} {path} nodes={g.nnodes}", flush=True)
+        s.set_populations(F0)
+        try:
+            s.step(1)
+        except C.SllbmError as e:
+            assert path in ("tiled", "rows") and e.code == C.E_UNSUPPORTED
+            return
+        assert _rel(s.populations(), F1) <= 1e-12
+    finally:
+        s.close()
