@@ -84,11 +84,10 @@ typedef enum {
 } sllbm_model;
 
 typedef enum {
-  SLLBM_PATH_AUTO = 0,    /* library choice (sllbm_resolved_path): ROWS or
-                             TILED by measured speed where both fit (ROWS for
-                             row segments of >= 48 nodes, except float64 with
-                             Pr != 1), the one that fits otherwise, else
-                             DIRECT */
+  SLLBM_PATH_AUTO = 0,    /* library choice (sllbm_resolved_path): ROWS for
+                             row segments of >= 48 nodes (measured at least as
+                             fast as TILED everywhere), else whichever of the
+                             two fits, else DIRECT */
   SLLBM_PATH_DIRECT = 1,  /* one thread per node, (p+1)^2 gathers per velocity
                              through per-axis departure tables */
   SLLBM_PATH_TILED = 2,   /* raw source windows of each velocity staged in LDS

@@ -212,15 +212,11 @@ bool mfma_fits(const sllbm_ctx *c) {
   return tiled_fits(c) && c->fp32 && nsets(c) * c->win_rows <= 16 && c->mfma_blocks_ok;
 }
 
-// AUTO: the row-segment kernel where it measured faster than the tiled one
-// (1025^2-node grids, p = 1..4, every model): segments of at least 48
-// columns, except float64 with Pr != 1, where the tiled kernel won; then
-// tiled, then direct.
-bool rows_preferred(const sllbm_ctx *c) {
-  if (c->rows_tx < 48) return false;
-  if (!c->fp32 && c->omega_pr != c->omega) return false;
-  return true;
-}
+// AUTO: the row-segment kernel where it measured faster than (or as fast
+// as) the tiled one (1025^2-node grids, p = 1..4, every model, Pr = 1 and
+// 0.75, FP32 and FP64): segments of at least 48 columns; then tiled, then
+// direct.
+bool rows_preferred(const sllbm_ctx *c) { return c->rows_tx >= 48; }
 
 int effective_path(const sllbm_ctx *c) {
   if (c->path != SLLBM_PATH_AUTO) return c->path;

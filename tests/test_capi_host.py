@@ -103,12 +103,12 @@ def test_setup_validation_and_call_order():
 
 
 def test_resolved_path():
-    """AUTO resolves to ROWS for row segments of >= 48 nodes (except float64
-    with Pr != 1), to TILED while every tile's source window fits the LDS
-    staging (at most 3 rows per wavefront, 128 columns), else to DIRECT."""
+    """AUTO resolves to ROWS for row segments of >= 48 nodes, to TILED while
+    every tile's source window fits the LDS staging (at most 3 rows per
+    wavefront, 128 columns), else to DIRECT."""
     for prec, p, Pr, want in ((C.FP64, 2, 1.0, C.PATH_ROWS), (C.FP32, 2, 1.0, C.PATH_ROWS),
                               (C.FP32, 3, 1.0, C.PATH_ROWS), (C.FP64, 3, 1.0, C.PATH_ROWS),
-                              (C.FP64, 2, 0.75, C.PATH_TILED), (C.FP32, 2, 0.75, C.PATH_ROWS)):
+                              (C.FP64, 2, 0.75, C.PATH_ROWS), (C.FP32, 2, 0.75, C.PATH_ROWS)):
         ctx = _ctx(prec)
         try:
             C.sllbm_set_order(ctx, p, C.NODES_GLC)
