@@ -11,8 +11,10 @@
 //      y-factor first), writes the one y-interpolated row to its own LDS
 //      row, and
 //   3. evaluates the x-factor from LDS with each lane's p+1 x-weights.
-// No LDS row is shared between wavefronts, so the kernel has no workgroup
-// barrier; loads run a fixed number of planes ahead of the arithmetic.
+// No LDS row is shared between wavefronts; loads run a fixed number of planes
+// ahead of the arithmetic.  A workgroup barrier every few planes only keeps
+// the wavefronts of neighbouring rows, which read overlapping source rows,
+// close enough together for those reads to hit in the L1 cache.
 // The streamed values stay in registers and the collision is the one of the
 // other paths (collide_store).
 #pragma once
@@ -37,27 +39,30 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Planes whose loads are in flight ahead of the one being interpolated,
-// measured on 1025^2-node grids (float32; one plane more or less costs
-// 1-10 %, about 5-9 rows in flight is best):
-//   p = 1: 4;  p = 2: 3;  p = 3, 4: 3 for a single population set or the
-//   Pr != 1 collision, else 2 (p = 3) and 1 (p = 4).
+// measured on 1025^2-node grids (float32):
+//   a single population set: 4 at p = 1, else 3 (one plane more or less
+//   costs 1-10 %);
+//   f + g, with the barrier of rows_sync_planes: 9 - p (8 ... 5; one plane
+//   more or less is within 1 %; without the barrier the best depths were
+//   4, 3, 2, 1 and 5-16 % slower).
 // float64: 10 at p <= 2 and 6 above (within 5 % from 8 to 20).
 template <typename T, int P1, int S, bool PR>
 constexpr int rows_lookahead() {
   if (sizeof(T) == 8) return P1 <= 3 ? 10 : 6;
-  if (P1 == 2) return 4;
-  if (P1 == 3 || S == 1 || PR) return 3;
-  return P1 == 4 ? 2 : 1;
+  if (S == 2) return 10 - P1;
+  return P1 == 2 ? 4 : 3;
 }
 
 // Streams the 25 S planes of `fin` into fs for the node (iy, tx TX + lane):
 // P1 taps per axis (p+1 forward, the transposed width for the adjoint),
-// D planes of loads in flight; lrow = this wavefront's two LDS rows.  The
+// D planes of loads in flight; lrow = this wavefront's two LDS rows.
+// SYNC > 0: a workgroup barrier after every SYNC planes, so every wavefront
+// of the workgroup must call this (none may have returned).  The
 // first 1-D velocity is 0 (Table I; the host checks that its x- and y-tables
 // are the identity), so the phase b = 0 departs from the node itself and
 // loads the target row alone, the x-component a = 0 reads the node's own
 // column, and the rest velocity (0, 0) is the node's own value.
-template <typename T, int P1, int S, int D>
+template <typename T, int P1, int S, int D, int SYNC = 0>
 __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
                                             const int32_t *__restrict__ xrel,
                                             const T *__restrict__ xw,
@@ -123,6 +128,7 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
   for (int q = 0; q < D && q < NQ; ++q) load(q, pre[q % (D + 1)]);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
+    if (SYNC > 0 && q > 0 && q % SYNC == 0) __builtin_amdgcn_s_barrier();
     // the phase whose first load comes two iterations from now
     if ((q + D + 2) % PH == 0 && (q + D + 2) / PH < 5 && (q + D + 2) / PH > (D + 1) / PH)
       fetch_phase((q + D + 2) / PH);
@@ -153,6 +159,14 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
   }
 }
 
+// Planes between workgroup barriers (0: none), measured on 1025^2-node
+// grids: for f + g, every 5 planes (with the deeper lookahead it allows)
+// gives float32 +5-6 % at p = 1-3 and +16 % at p = 4, float64 +-1 %; every
+// 3 or 10 planes is no better.  A single set shows no effect above the
+// run-to-run spread.
+template <int P1, int S>
+constexpr int rows_sync_planes() { return S == 2 ? 5 : 0; }
+
 // Minimum waves per SIMD the compiler is asked to fit: a single float32
 // population set gets 6 (70-73 VGPRs instead of ~97; Taylor-Green p = 2:
 // +14 %), f + g keeps the default (the same request spills and costs 3-18 %).
@@ -172,13 +186,15 @@ __global__ __launch_bounds__(64 * kRowsTileRows,
   const int tx = tile % ntx, ty = tile / ntx;
   const int lane = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
-  const int iy = ty * kRowsTileRows + wv;
-  if (iy >= c.ny) return;  // whole wavefront; nothing below waits for others
+  // rows past the grid stream the last row (every wavefront must reach the
+  // barriers) and store nothing
+  const int iy_t = ty * kRowsTileRows + wv;
+  const int iy = min(iy_t, c.ny - 1);
   T fs[S][25];
-  rows_stream<T, P + 1, S, rows_lookahead<T, P + 1, S, PR>()>(fin, xrel, xw, xwin, ysrc, yw, TX, ntx,
-                                                       tx, iy, lane, c, &rows_lds[wv][0][0], fs);
+  rows_stream<T, P + 1, S, rows_lookahead<T, P + 1, S, PR>(), rows_sync_planes<P + 1, S>()>(
+      fin, xrel, xw, xwin, ysrc, yw, TX, ntx, tx, iy, lane, c, &rows_lds[wv][0][0], fs);
   const int ix = tx * TX + lane;
-  if (ix < c.nx && lane < TX)
+  if (ix < c.nx && lane < TX && iy_t < c.ny)
     collide_store<T, MODEL, PR>(fs, c, fout, (long long)iy * c.nx + ix, flag);
 }
 
