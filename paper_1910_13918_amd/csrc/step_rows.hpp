@@ -45,10 +45,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 //   f + g, with the barrier of rows_sync_planes: 9 - p (8 ... 5; one plane
 //   more or less is within 1 %; without the barrier the best depths were
 //   4, 3, 2, 1 and 5-16 % slower).
-// float64: 10 at p <= 2 and 6 above (within 5 % from 8 to 20).
+// float64: a single set 10 at p <= 2 and 6 above (within 5 % from 8 to 20);
+//   f + g 14 and 9 (+0-3 % over 10 and 6; 18 and 12 are no better).
 template <typename T, int P1, int S, bool PR>
 constexpr int rows_lookahead() {
-  if (sizeof(T) == 8) return P1 <= 3 ? 10 : 6;
+  if (sizeof(T) == 8) return S == 2 ? (P1 <= 3 ? 14 : 9) : (P1 <= 3 ? 10 : 6);
   if (S == 2) return 10 - P1;
   return P1 == 2 ? 4 : 3;
 }
