@@ -153,6 +153,26 @@ int sllbm_init_grid_uniform(sllbm_ctx *ctx, int ncx, int ncy, double x0, double 
 int sllbm_init_grid_mapped(sllbm_ctx *ctx, int ncx, int ncy, const double *edges_x,
                            const double *edges_y, int bcx, int bcy);
 
+/* Curvilinear mesh of ncx x ncy bilinear cells, periodic in x and y: the
+ * cell interpolation of Sec. II.E, eq. (17), on cells that are bilinear
+ * images of the reference square (curved cells are the generalisation the
+ * paper leaves to future work).  vx, vy: host float64 arrays
+ * [ncy + 1][ncx + 1] (copied) of vertex coordinates; vertex column ncx must
+ * be column 0 moved by (Lx, 0) and row ncy row 0 moved by (0, Ly), the
+ * periods, and every cell's Jacobian must be positive at its four corners
+ * (counter-clockwise, not folded), else SLLBM_E_ARG.  Nodes: nx = ncx p,
+ * ny = ncy p; node (ix, iy) is support point (ix mod p, iy mod p) of cell
+ * (ix / p, iy / p) (sllbm_node_coords_2d gives their coordinates).
+ * Departure points are located on the host (Newton's method on the cell
+ * map and a walk across neighbouring cells, at the first step after set-up;
+ * a departure point that is not found fails that step with SLLBM_E_ARG) and
+ * streamed with the records gather: AUTO resolves to SLLBM_PATH_RECORDS and
+ * every other path is refused (SLLBM_E_UNSUPPORTED), as are the per-axis
+ * queries (sllbm_node_coords, sllbm_departure_table, sllbm_mass_weights),
+ * sllbm_mass and the adjoint. */
+int sllbm_init_grid_curvilinear(sllbm_ctx *ctx, int ncx, int ncy, const double *vx,
+                                const double *vy);
+
 /* Time step dt > 0, kinematic viscosity nu > 0 (nu = +inf: no collision,
  * pure streaming), heat-capacity ratio gamma > 1 (used by SLLBM_POLYATOMIC
  * only), Prandtl number Pr > 0, model (sllbm_model).  Pr != 1 needs a
@@ -184,14 +204,26 @@ int sllbm_num_nodes(const sllbm_ctx *ctx, int64_t *nx, int64_t *ny);
 /* Number of population sets S (1 or 2) and bytes per population value. */
 int sllbm_population_layout(const sllbm_ctx *ctx, int *nsets, int *q, int *bytes_per_value);
 
-/* Node coordinates per axis: x[nx], y[ny] (host arrays). */
+/* Node coordinates per axis: x[nx], y[ny] (host arrays); axis-product
+ * grids only. */
 int sllbm_node_coords(const sllbm_ctx *ctx, double *x, double *y);
+
+/* Coordinates of every node, x[ny][nx] and y[ny][nx] (host arrays), on any
+ * grid. */
+int sllbm_node_coords_2d(const sllbm_ctx *ctx, double *x, double *y);
 
 /* Departure table of one axis (0 = x, 1 = y) and 1-D velocity index comp:
  * for each node j of that axis, src[j * (p+1) + m] is the source node along
  * the axis and w[j * (p+1) + m] the Lagrange weight, so that the 1-D value
  * at the departure point is sum_m w * value[src].  Host arrays. */
 int sllbm_departure_table(const sllbm_ctx *ctx, int axis, int comp, int32_t *src, double *w);
+
+/* Departure records of velocity i = a + 5 b (0..24) for every node, as the
+ * records gather reads them: cell[v] = cx | cy << 16 (the departure cell),
+ * r[v], s[v] in [0, 1] its reference coordinates (Sec. II.E, eq. (17)).
+ * Host arrays of nx*ny; any grid.  SLLBM_E_ARG if a departure point of a
+ * curvilinear mesh is not found. */
+int sllbm_departure_records(const sllbm_ctx *ctx, int i, int32_t *cell, double *r, double *s);
 
 /* Integral of each node's shape function per axis (mass weights): the 2-D
  * weight of node (iy, ix) is my[iy] * mx[ix]. */

@@ -119,14 +119,15 @@ class CurviGrid:
 
     def locate(self, px, py, tol=1e-12):
         """Cell (cx, cy) and reference coordinates (r, s) in [0, 1] of each
-        point, by brute force over every cell and the periodic images."""
+        point, by brute force over every cell and the periodic images up to
+        two periods away."""
         n = len(px)
         cx = np.full(n, -1, dtype=np.int64)
         cy = np.full(n, -1, dtype=np.int64)
         r = np.zeros(n)
         s = np.zeros(n)
-        for ky in (-1, 0, 1):
-            for kx in (-1, 0, 1):
+        for ky in (0, -1, 1, -2, 2):
+            for kx in (0, -1, 1, -2, 2):
                 qx, qy = px - kx * self.Lx, py - ky * self.Ly
                 for j in range(self.ncy):
                     for i in range(self.ncx):

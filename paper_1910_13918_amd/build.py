@@ -20,7 +20,7 @@ FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = ["kernels.hip", "step_direct.hip", "step_tiled.hip", "step_records.hip", "step_mfma.hip",
            "step_rows.hip", "step_tiled_pr.hip", "step_prandtl.hip", "adjoint.hip",
-           "adjoint_rows.hip", "capi.cpp", "tables.cpp"]
+           "adjoint_rows.hip", "capi.cpp", "tables.cpp", "curvilinear.cpp"]
 
 
 def build(verbose=False):

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/sllbm.h"
+#include "curvilinear.hpp"
 #include "launch.hpp"
 #include "tables.hpp"
 
@@ -42,6 +43,11 @@ struct sllbm_ctx {
   bool glc = true;
   bool have_grid = false;
   Axis ax, ay;
+  // mesh of bilinear cells (sllbm_init_grid_curvilinear); ax / ay then hold
+  // the logical axes (unit cells), which give the node counts and periodicity
+  bool curvi = false;
+  CurviMesh mesh;
+  std::vector<double> cX, cY;  // node coordinates [ny][nx]
   bool have_phys = false;
   double dt = 0, nu = 0, gamma = 1.4, Pr = 1.0, tau = 0, omega = 0, omega_pr = 0;
   int model = 0;
@@ -176,6 +182,24 @@ int rows_segment_width(const AxisTable *t, int n, std::vector<int32_t> &win,
   return 0;
 }
 
+// Departure records (cell cx | cy << 16, reference coordinates r, s) of
+// velocity i = a + 5 b for every node: from the axis tables, or located on
+// the curvilinear mesh.  Returns "" or an error message.
+std::string departure_records(const sllbm_ctx *c, int i, int32_t *cell, double *r, double *s) {
+  const int a = i % kQ1, b = i / kQ1;
+  if (c->curvi)
+    return curvi_records(c->mesh, support_points(c->p, c->glc), c->cX, c->cY,
+                         -c->dt * c->vs.xi[a], -c->dt * c->vs.xi[b], cell, r, s);
+  for (int iy = 0; iy < c->ay.n; ++iy)
+    for (int ix = 0; ix < c->ax.n; ++ix) {
+      const size_t k = size_t(iy) * c->ax.n + ix;
+      cell[k] = c->xt[a].cell[ix] | (c->yt[b].cell[iy] << 16);
+      r[k] = c->xt[a].rref[ix];
+      s[k] = c->yt[b].rref[iy];
+    }
+  return "";
+}
+
 void build_host_tables(sllbm_ctx *c) {
   if (!c->host_dirty) return;
   for (int a = 0; a < kQ1; ++a) {
@@ -220,6 +244,7 @@ bool rows_preferred(const sllbm_ctx *c) { return c->rows_tx >= 48; }
 
 int effective_path(const sllbm_ctx *c) {
   if (c->path != SLLBM_PATH_AUTO) return c->path;
+  if (c->curvi) return kPathRecords;  // the only gather that takes arbitrary cells
   if (rows_preferred(c) || (!tiled_fits(c) && c->rows_tx >= kRowsMinCols)) return kPathRows;
   return tiled_fits(c) ? kPathTiled : kPathDirect;
 }
@@ -309,17 +334,12 @@ int prepare_device(sllbm_ctx *c) {
     const long long N = nnodes(c);
     std::vector<int32_t> cell(size_t(kQ) * N);
     std::vector<double> r(size_t(kQ) * N), s(size_t(kQ) * N);
-    for (int b = 0; b < kQ1; ++b)
-      for (int a = 0; a < kQ1; ++a) {
-        const int i = a + kQ1 * b;
-        for (int iy = 0; iy < c->ay.n; ++iy)
-          for (int ix = 0; ix < c->ax.n; ++ix) {
-            const size_t k = size_t(i) * N + size_t(iy) * c->ax.n + ix;
-            cell[k] = c->xt[a].cell[ix] | (c->yt[b].cell[iy] << 16);
-            r[k] = c->xt[a].rref[ix];
-            s[k] = c->yt[b].rref[iy];
-          }
-      }
+    for (int i = 0; i < kQ; ++i) {
+      const size_t off = size_t(i) * N;
+      const std::string e =
+          departure_records(c, i, cell.data() + off, r.data() + off, s.data() + off);
+      if (!e.empty()) return fail(c, SLLBM_E_ARG, e);
+    }
     rc = upload(c, c->rec_cell, cell);
     if (!rc) rc = upload_weights(c, c->rec_r, r);
     if (!rc) rc = upload_weights(c, c->rec_s, s);
@@ -456,6 +476,8 @@ int prepare_adjoint(sllbm_ctx *c) {
   if (rc) return rc;
   if (c->omega_pr != c->omega)
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers Pr = 1 only");
+  if (c->curvi)
+    return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers axis-product grids only");
   if (!c->adj_dirty) return SLLBM_OK;
   int taps = 0;
   for (int a = 0; a < kQ1; ++a) {
@@ -608,6 +630,7 @@ static int init_grid(sllbm_ctx *c, int ncx, int ncy, const std::vector<double> &
     return fail(c, SLLBM_E_ARG, "grid too large (nx * ny * 50 must fit in 32 bits)");
   (void)ncx;
   (void)ncy;
+  c->curvi = false;
   c->have_grid = true;
   invalidate(c);
   return SLLBM_OK;
@@ -654,6 +677,27 @@ int sllbm_init_grid_mapped(sllbm_ctx *c, int ncx, int ncy, const double *edges_x
         return fail(c, SLLBM_E_ARG, "cell edges must be strictly increasing");
     }
   return init_grid(c, ncx, ncy, ex, ey, bcx, bcy, false);
+}
+
+int sllbm_init_grid_curvilinear(sllbm_ctx *c, int ncx, int ncy, const double *vx,
+                                const double *vy) {
+  int rc = setup_allowed(c);
+  if (rc) return rc;
+  rc = check_grid_args(c, ncx, ncy, SLLBM_PERIODIC, SLLBM_PERIODIC);
+  if (rc) return rc;
+  if (!vx || !vy) return fail(c, SLLBM_E_ARG, "null vertex array");
+  CurviMesh m;
+  const std::string e = m.setup(ncx, ncy, vx, vy);
+  if (!e.empty()) return fail(c, SLLBM_E_ARG, e);
+  std::vector<double> ex(ncx + 1), ey(ncy + 1);
+  for (int k = 0; k <= ncx; ++k) ex[k] = k;
+  for (int k = 0; k <= ncy; ++k) ey[k] = k;
+  rc = init_grid(c, ncx, ncy, ex, ey, SLLBM_PERIODIC, SLLBM_PERIODIC, true);
+  if (rc) return rc;
+  c->mesh = std::move(m);
+  curvi_node_coords(c->mesh, support_points(c->p, c->glc), c->cX, c->cY);
+  c->curvi = true;
+  return SLLBM_OK;
 }
 
 int sllbm_set_physics(sllbm_ctx *c, double dt, double nu, double gamma, double Pr, int model) {
@@ -724,14 +768,35 @@ int sllbm_population_layout(const sllbm_ctx *c, int *ns, int *q, int *bytes) {
 int sllbm_node_coords(const sllbm_ctx *c, double *x, double *y) {
   if (!c || !x || !y) return SLLBM_E_ARG;
   if (!c->have_grid) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "grid not set");
+  if (c->curvi)
+    return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_UNSUPPORTED,
+                "a curvilinear mesh has no axis coordinates (sllbm_node_coords_2d)");
   for (int j = 0; j < c->ax.n; ++j) x[j] = c->ax.coord(j);
   for (int j = 0; j < c->ay.n; ++j) y[j] = c->ay.coord(j);
+  return SLLBM_OK;
+}
+
+int sllbm_node_coords_2d(const sllbm_ctx *c, double *x, double *y) {
+  if (!c || !x || !y) return SLLBM_E_ARG;
+  if (!c->have_grid) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "grid not set");
+  if (c->curvi) {
+    std::memcpy(x, c->cX.data(), c->cX.size() * sizeof(double));
+    std::memcpy(y, c->cY.data(), c->cY.size() * sizeof(double));
+    return SLLBM_OK;
+  }
+  for (int iy = 0; iy < c->ay.n; ++iy)
+    for (int ix = 0; ix < c->ax.n; ++ix) {
+      x[size_t(iy) * c->ax.n + ix] = c->ax.coord(ix);
+      y[size_t(iy) * c->ax.n + ix] = c->ay.coord(iy);
+    }
   return SLLBM_OK;
 }
 
 int sllbm_departure_table(const sllbm_ctx *cc, int axis, int comp, int32_t *src, double *w) {
   sllbm_ctx *c = const_cast<sllbm_ctx *>(cc);
   if (!c || !src || !w) return SLLBM_E_ARG;
+  if (c->curvi)
+    return fail(c, SLLBM_E_UNSUPPORTED, "a curvilinear mesh has no per-axis departure tables");
   if (axis != 0 && axis != 1) return fail(c, SLLBM_E_ARG, "axis must be 0 or 1");
   if (comp < 0 || comp >= kQ1) return fail(c, SLLBM_E_ARG, "velocity component out of range");
   int rc = ready_for_tables(c);
@@ -743,9 +808,23 @@ int sllbm_departure_table(const sllbm_ctx *cc, int axis, int comp, int32_t *src,
   return SLLBM_OK;
 }
 
+int sllbm_departure_records(const sllbm_ctx *cc, int i, int32_t *cell, double *r, double *s) {
+  sllbm_ctx *c = const_cast<sllbm_ctx *>(cc);
+  if (!c || !cell || !r || !s) return SLLBM_E_ARG;
+  if (i < 0 || i >= kQ) return fail(c, SLLBM_E_ARG, "velocity index out of range");
+  int rc = ready_for_tables(c);
+  if (rc) return rc;
+  build_host_tables(c);
+  const std::string e = departure_records(c, i, cell, r, s);
+  return e.empty() ? SLLBM_OK : fail(c, SLLBM_E_ARG, e);
+}
+
 int sllbm_mass_weights(const sllbm_ctx *c, double *mx, double *my) {
   if (!c || !mx || !my) return SLLBM_E_ARG;
   if (!c->have_grid) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "grid not set");
+  if (c->curvi)
+    return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_UNSUPPORTED,
+                "node masses of a curvilinear mesh are not a product of axis weights");
   const std::vector<double> a = c->ax.node_mass(), b = c->ay.node_mass();
   std::memcpy(mx, a.data(), a.size() * sizeof(double));
   std::memcpy(my, b.data(), b.size() * sizeof(double));
@@ -846,6 +925,8 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   int rc = prepare_device(c);
   if (rc) return rc;
   const int path = effective_path(c);
+  if (c->curvi && path != kPathRecords)
+    return fail(c, SLLBM_E_UNSUPPORTED, "a curvilinear mesh runs on the records path only");
   if (path == kPathTiled && !tiled_fits(c))
     return fail(c, SLLBM_E_UNSUPPORTED, "departures span too many rows for the tiled kernel");
   if (path == kPathRows && c->rows_tx == 0)
@@ -984,6 +1065,9 @@ int sllbm_moments(sllbm_ctx *c, double *rho, double *ux, double *uy, double *T, 
 
 int sllbm_mass(sllbm_ctx *c, double *mass) {
   if (!c || !mass) return SLLBM_E_ARG;
+  if (c->curvi)
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "node masses of a curvilinear mesh are not a product of axis weights");
   if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
   int rc = prepare_device(c);
   if (rc) return rc;

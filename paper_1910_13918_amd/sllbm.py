@@ -72,12 +72,15 @@ _SIGS = {
     "sllbm_set_order": ([_vp, _c, _c], _c),
     "sllbm_init_grid_uniform": ([_vp, _c, _c, _d, _d, _d, _d, _c, _c], _c),
     "sllbm_init_grid_mapped": ([_vp, _c, _c, _vp, _vp, _c, _c], _c),
+    "sllbm_init_grid_curvilinear": ([_vp, _c, _c, _vp, _vp], _c),
     "sllbm_set_physics": ([_vp, _d, _d, _d, _d, _c], _c),
     "sllbm_set_path": ([_vp, _c], _c),
     "sllbm_resolved_path": ([_vp, _ip], _c),
     "sllbm_num_nodes": ([_vp, _i64p, _i64p], _c),
     "sllbm_population_layout": ([_vp, _ip, _ip, _ip], _c),
     "sllbm_node_coords": ([_vp, _vp, _vp], _c),
+    "sllbm_node_coords_2d": ([_vp, _vp, _vp], _c),
+    "sllbm_departure_records": ([_vp, _c, _vp, _vp, _vp], _c),
     "sllbm_departure_table": ([_vp, _c, _c, _vp, _vp], _c),
     "sllbm_mass_weights": ([_vp, _vp, _vp], _c),
     "sllbm_relaxation_time": ([_vp, _dp], _c),
@@ -155,6 +158,10 @@ def sllbm_init_grid_mapped(ctx, ncx, ncy, edges_x_ptr, edges_y_ptr, bcx, bcy):
     return check(ctx, lib.sllbm_init_grid_mapped(ctx, ncx, ncy, edges_x_ptr, edges_y_ptr, bcx, bcy))
 
 
+def sllbm_init_grid_curvilinear(ctx, ncx, ncy, vx_ptr, vy_ptr):
+    return check(ctx, lib.sllbm_init_grid_curvilinear(ctx, ncx, ncy, vx_ptr, vy_ptr))
+
+
 def sllbm_set_physics(ctx, dt, nu, gamma, Pr, model):
     return check(ctx, lib.sllbm_set_physics(ctx, dt, nu, gamma, Pr, model))
 
@@ -183,6 +190,14 @@ def sllbm_population_layout(ctx):
 
 def sllbm_node_coords(ctx, x_ptr, y_ptr):
     return check(ctx, lib.sllbm_node_coords(ctx, x_ptr, y_ptr))
+
+
+def sllbm_node_coords_2d(ctx, x_ptr, y_ptr):
+    return check(ctx, lib.sllbm_node_coords_2d(ctx, x_ptr, y_ptr))
+
+
+def sllbm_departure_records(ctx, i, cell_ptr, r_ptr, s_ptr):
+    return check(ctx, lib.sllbm_departure_records(ctx, i, cell_ptr, r_ptr, s_ptr))
 
 
 def sllbm_departure_table(ctx, axis, comp, src_ptr, w_ptr):

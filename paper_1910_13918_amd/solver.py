@@ -27,7 +27,7 @@ def _ptr(a):
 class Solver:
     def __init__(self, *, p, edges_x, edges_y, periodic_x, periodic_y, dt, nu, model,
                  gamma=1.4, precision="fp32", uniform=True, path="auto", device=0,
-                 nodes="glc", xi1d=None, w1d=None, Pr=1.0):
+                 nodes="glc", xi1d=None, w1d=None, Pr=1.0, vertices=None):
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a HIP device (torch.cuda is not available)")
         self.device = torch.device("cuda", device)
@@ -45,7 +45,12 @@ class Solver:
             bcy = C.PERIODIC if periodic_y else C.ZERO_GRADIENT
             ex = np.ascontiguousarray(edges_x, dtype=np.float64)
             ey = np.ascontiguousarray(edges_y, dtype=np.float64)
-            if uniform:
+            if vertices is not None:
+                self._vx = np.ascontiguousarray(vertices[0], dtype=np.float64)
+                self._vy = np.ascontiguousarray(vertices[1], dtype=np.float64)
+                C.sllbm_init_grid_curvilinear(self.ctx, self._vx.shape[1] - 1,
+                                              self._vx.shape[0] - 1, _ptr(self._vx), _ptr(self._vy))
+            elif uniform:
                 C.sllbm_init_grid_uniform(self.ctx, len(ex) - 1, len(ey) - 1, ex[0], ex[-1], ey[0],
                                           ey[-1], bcx, bcy)
             else:
@@ -74,7 +79,7 @@ class Solver:
         s = cls(p=wl.p, edges_x=wl.edges_x, edges_y=wl.edges_y, periodic_x=wl.periodic_x,
                 periodic_y=wl.periodic_y, dt=wl.dt, nu=wl.nu, model=wl.model, gamma=wl.gamma,
                 precision=precision, uniform=wl.uniform, path=path, device=device, nodes=nodes,
-                Pr=wl.Pr)
+                Pr=wl.Pr, vertices=wl.vertices)
         s.workload = wl
         return s
 
@@ -86,8 +91,11 @@ class Solver:
         return x, y
 
     def coords(self):
-        x, y = self.axis_coords()
-        return np.tile(x, self.ny), np.repeat(y, self.nx)
+        """Coordinates of every node (any grid), flattened [ny * nx]."""
+        x = np.zeros(self.n)
+        y = np.zeros(self.n)
+        C.sllbm_node_coords_2d(self.ctx, _ptr(x), _ptr(y))
+        return x, y
 
     def resolved_path(self):
         """Name of the kernel family the next step runs ("direct", "tiled", "records")."""

@@ -62,6 +62,7 @@ class Workload:
     uniform: bool = True
     meta: dict = field(default_factory=dict)
     Pr: float = 1.0       # Prandtl number (Sec. II.C-D)
+    vertices: tuple = None  # (vx, vy) [ncy + 1][ncx + 1] of a curvilinear mesh, else None
 
     @property
     def ncx(self):
@@ -107,6 +108,32 @@ def tgv(ncells=8, p=2, U0=0.1, Re=100.0, steps=200, cfl=0.5, model="isothermal",
     e = uniform_edges(ncells, 0.0, L)
     return Workload(name or f"tgv_{ncells}x{ncells}_p{p}", e, e.copy(), p, True, True, model,
                     1.4, nu, dt, n, fields, True, {"U0": U0, "Re": Re})
+
+
+# ------------------------------------------------------- Taylor-Green, curved cells
+def wavy_vertices(ncx, ncy, Lx, Ly, amp):
+    """Vertices [ncy + 1][ncx + 1] of a periodic mesh of bilinear cells: the
+    uniform lattice of [0, Lx] x [0, Ly] with both coordinates moved by
+    amp min(Lx, Ly) / (2 pi) sin(2 pi X / Lx) sin(2 pi Y / Ly) (for Lx = Ly the
+    map's Jacobian is >= 1 - 2 amp, so amp < 1/2 keeps the cells unfolded)."""
+    X, Y = np.meshgrid(np.linspace(0.0, Lx, ncx + 1), np.linspace(0.0, Ly, ncy + 1))
+    d = amp * min(Lx, Ly) / (2 * np.pi) * np.sin(2 * np.pi * X / Lx) * np.sin(2 * np.pi * Y / Ly)
+    return X + d, Y + d
+
+
+def tgv_wavy(ncells=8, p=2, amp=0.3, U0=0.1, Re=100.0, steps=200, cfl=0.5, model="isothermal",
+             name=None):
+    """The Taylor-Green vortex of tgv() on a curvilinear periodic mesh of
+    ncells^2 bilinear cells (wavy_vertices of [0, 2 pi]^2); dt from the
+    uniform spacing shrunk by 1 - amp."""
+    wl = tgv(ncells, p, U0=U0, Re=Re, steps=steps, cfl=cfl * (1 - amp), model=model,
+             name=name or f"tgv_wavy_{ncells}x{ncells}_p{p}_a{amp}")
+    L = 2.0 * np.pi
+    wl.vertices = wavy_vertices(ncells, ncells, L, L, amp)
+    wl.edges_x = np.arange(ncells + 1, dtype=float)  # logical cells: node counts only
+    wl.edges_y = wl.edges_x.copy()
+    wl.meta["amp"] = amp
+    return wl
 
 
 # ---------------------------------------------------------------------------- Sod

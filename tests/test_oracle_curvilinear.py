@@ -93,4 +93,4 @@ def test_inverse_of_a_parallelogram_is_linear():
 def test_departure_outside_every_cell_is_an_error():
     cg = _wavy(2)
     with pytest.raises(ValueError):
-        cg.locate(np.array([3 * cg.Lx]), np.array([0.5]))
+        cg.locate(np.array([4 * cg.Lx]), np.array([0.5]))
