@@ -38,6 +38,13 @@ __device__ __forceinline__ T records_interp(__amdgpu_buffer_rsrc_t rs, const uns
   return acc;
 }
 
+// Whether the gather of the next velocity is issued before this velocity's
+// interpolation: float32 f + g, where it measured +13 % on the shock-vortex
+// grid (p = 3) and +3 % at p = 2; a single set and float64 lose 1-3 % to the
+// doubled registers.
+template <typename T, int S>
+constexpr bool records_gather_ahead() { return sizeof(T) == 4 && S == 2; }
+
 template <typename T, int P, int MODEL, bool PR>
 __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
                                                       T *__restrict__ fout,
@@ -61,50 +68,122 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
     den[m] = T(c.lden[m]);
   }
   T fs[S][25];
-  // the next velocity's record is loaded before this one's gather (each
-  // velocity is a separate scheduling region; loading ahead overlaps the
-  // record's latency with the gather: shock-vortex records +18 %, curved
-  // cells p = 2 +9 %, p = 4 +5 %; two or four ahead are no better)
-  constexpr int RD = 1;
-  int recq[RD + 1];
-  T rq[RD + 1], sq[RD + 1];
-  auto load_rec = [&](int i) {
-    recq[i % (RD + 1)] = int(__builtin_amdgcn_raw_buffer_load_b32(rcell, cell_off,
-                                                             unsigned(i) * unsigned(N) * 4u, 0));
-    rq[i % (RD + 1)] = buffer_load<T>(make_rsrc(rr + i * N, plane_bytes), voff, 0);
-    sq[i % (RD + 1)] = buffer_load<T>(make_rsrc(ss + i * N, plane_bytes), voff, 0);
-  };
-#pragma unroll
-  for (int i = 0; i < RD; ++i) load_rec(i);
-#pragma unroll
-  for (int i = 0; i < 25; ++i) {
-    if (i + RD < 25) load_rec(i + RD);
-    const int rec = recq[i % (RD + 1)];
-    const int cx = rec & 0xffff, cy = rec >> 16;
-    T wx[P1], wy[P1];
-    lagrange_eval<T, P1>(rq[i % (RD + 1)], rn, den, wx);
-    lagrange_eval<T, P1>(sq[i % (RD + 1)], rn, den, wy);
-    unsigned xo[P1], yo[P1];
-    bool seam = false;
-#pragma unroll
-    for (int m = 0; m < P1; ++m) {
-      int jx = cx * P + m;
-      seam |= jx >= c.nx;
-      if (jx >= c.nx) jx -= c.nx;  // periodic seam: last vertex is node 0
-      xo[m] = unsigned(jx) * unsigned(sizeof(T));
-      int jy = cy * P + m;
-      if (jy >= c.ny) jy -= c.ny;
-      yo[m] = unsigned(jy) * unsigned(c.nx) * unsigned(sizeof(T));
+  if constexpr (records_gather_ahead<T, S>()) {
+    // f + g in float32: the next velocity's stencil values are loaded
+    // before this one is interpolated (two values in flight per lane and
+    // tap), its record two velocities ahead
+    constexpr int RD = 2;
+    int recq[RD + 1];
+    T rq[RD + 1], sq[RD + 1];
+    auto load_rec = [&](int i) {
+      recq[i % (RD + 1)] = int(__builtin_amdgcn_raw_buffer_load_b32(rcell, cell_off,
+                                                               unsigned(i) * unsigned(N) * 4u, 0));
+      rq[i % (RD + 1)] = buffer_load<T>(make_rsrc(rr + i * N, plane_bytes), voff, 0);
+      sq[i % (RD + 1)] = buffer_load<T>(make_rsrc(ss + i * N, plane_bytes), voff, 0);
+    };
+    T vals[2][S][P1][P1];
+    T wxq[2][P1], wyq[2][P1];
+    auto issue = [&](int i) {
+      const int b = i & 1;
+      const int rec = recq[i % (RD + 1)];
+      const int cx = rec & 0xffff, cy = rec >> 16;
+      lagrange_eval<T, P1>(rq[i % (RD + 1)], rn, den, wxq[b]);
+      lagrange_eval<T, P1>(sq[i % (RD + 1)], rn, den, wyq[b]);
+      unsigned xo[P1], yo[P1];
+      bool seam = false;
+  #pragma unroll
+      for (int m = 0; m < P1; ++m) {
+        int jx = cx * P + m;
+        seam |= jx >= c.nx;
+        if (jx >= c.nx) jx -= c.nx;  // periodic seam: last vertex is node 0
+        xo[m] = unsigned(jx) * unsigned(sizeof(T));
+        int jy = cy * P + m;
+        if (jy >= c.ny) jy -= c.ny;
+        yo[m] = unsigned(jy) * unsigned(c.nx) * unsigned(sizeof(T));
+      }
+      const bool any_seam = __builtin_amdgcn_ballot_w64(seam) != 0;
+  #pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const auto rs = make_rsrc(fin + (long long)(s * 25 + i) * N, plane_bytes);
+  #pragma unroll
+        for (int n = 0; n < P1; ++n) {
+          if (any_seam) {
+  #pragma unroll
+            for (int m = 0; m < P1; ++m) vals[b][s][n][m] = buffer_load<T>(rs, yo[n] + xo[m], 0);
+          } else {
+            buffer_load_run<T, P1>(rs, yo[n] + xo[0], 0, vals[b][s][n]);
+          }
+        }
+      }
+    };
+  #pragma unroll
+    for (int i = 0; i < RD; ++i) load_rec(i);
+    issue(0);
+  #pragma unroll
+    for (int i = 0; i < 25; ++i) {
+      if (i + RD < 25) load_rec(i + RD);
+      if (i + 1 < 25) issue(i + 1);
+      const int b = i & 1;
+  #pragma unroll
+      for (int s = 0; s < S; ++s) {
+        T acc = T(0);
+  #pragma unroll
+        for (int n = 0; n < P1; ++n) {
+          T row = T(0);
+  #pragma unroll
+          for (int m = 0; m < P1; ++m) row = fma(wxq[b][m], vals[b][s][n][m], row);
+          acc = fma(wyq[b][n], row, acc);
+        }
+        asm volatile("" : "+v"(acc));
+        fs[s][i] = acc;
+      }
     }
-    const bool any_seam = __builtin_amdgcn_ballot_w64(seam) != 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const auto rs = make_rsrc(fin + (long long)(s * 25 + i) * N, plane_bytes);
-      T acc = any_seam ? records_interp<T, P1, true>(rs, xo, yo, wx, wy)
-                       : records_interp<T, P1, false>(rs, xo, yo, wx, wy);
-      // keep the interpolation next to its loads
-      asm volatile("" : "+v"(acc));
-      fs[s][i] = acc;
+  } else {
+    // the next velocity's record is loaded before this one's gather (each
+    // velocity is a separate scheduling region; loading ahead overlaps the
+    // record's latency with the gather: shock-vortex records +18 %, curved
+    // cells p = 2 +9 %, p = 4 +5 %; two or four ahead are no better)
+    constexpr int RD = 1;
+    int recq[RD + 1];
+    T rq[RD + 1], sq[RD + 1];
+    auto load_rec = [&](int i) {
+      recq[i % (RD + 1)] = int(__builtin_amdgcn_raw_buffer_load_b32(rcell, cell_off,
+                                                               unsigned(i) * unsigned(N) * 4u, 0));
+      rq[i % (RD + 1)] = buffer_load<T>(make_rsrc(rr + i * N, plane_bytes), voff, 0);
+      sq[i % (RD + 1)] = buffer_load<T>(make_rsrc(ss + i * N, plane_bytes), voff, 0);
+    };
+  #pragma unroll
+    for (int i = 0; i < RD; ++i) load_rec(i);
+  #pragma unroll
+    for (int i = 0; i < 25; ++i) {
+      if (i + RD < 25) load_rec(i + RD);
+      const int rec = recq[i % (RD + 1)];
+      const int cx = rec & 0xffff, cy = rec >> 16;
+      T wx[P1], wy[P1];
+      lagrange_eval<T, P1>(rq[i % (RD + 1)], rn, den, wx);
+      lagrange_eval<T, P1>(sq[i % (RD + 1)], rn, den, wy);
+      unsigned xo[P1], yo[P1];
+      bool seam = false;
+  #pragma unroll
+      for (int m = 0; m < P1; ++m) {
+        int jx = cx * P + m;
+        seam |= jx >= c.nx;
+        if (jx >= c.nx) jx -= c.nx;  // periodic seam: last vertex is node 0
+        xo[m] = unsigned(jx) * unsigned(sizeof(T));
+        int jy = cy * P + m;
+        if (jy >= c.ny) jy -= c.ny;
+        yo[m] = unsigned(jy) * unsigned(c.nx) * unsigned(sizeof(T));
+      }
+      const bool any_seam = __builtin_amdgcn_ballot_w64(seam) != 0;
+  #pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const auto rs = make_rsrc(fin + (long long)(s * 25 + i) * N, plane_bytes);
+        T acc = any_seam ? records_interp<T, P1, true>(rs, xo, yo, wx, wy)
+                         : records_interp<T, P1, false>(rs, xo, yo, wx, wy);
+        // keep the interpolation next to its loads
+        asm volatile("" : "+v"(acc));
+        fs[s][i] = acc;
+      }
     }
   }
   collide_store<T, MODEL, PR>(fs, c, fout, v, flag);
