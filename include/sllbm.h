@@ -314,6 +314,19 @@ int sllbm_adjoint_seed(sllbm_ctx *ctx, const double *g_rho, const double *g_ux, 
 /* mu = J_C(M)^T lambda node by node; moments = one step's [K][ny][nx] record. */
 int sllbm_adjoint_collide(sllbm_ctx *ctx, const void *lambda, const double *moments, void *mu);
 
+/* Viscosity term of the gradient (Pr = 1): acc[0] += <lambda, dC/d(nu)> for
+ * one step, lambda = dL/dF+ of that step's post-collision populations
+ * `populations` (device, the population layout) and `moments` their
+ * [K][ny][nx] record.  The BGK collision of Sec. II.D depends on nu through
+ * 1/tau with tau = nu/dt + 1/2; because the moments are collision
+ * invariants, F - F_eq before the collision is (F+ - F_eq)/(1 - 1/tau), so
+ * the term is sum lambda (F+ - F_eq) / ((1 - 1/tau) tau^2 dt).  Summed over
+ * the steps it is dL/d(nu).  acc: one float64 on the device, accumulated in
+ * stream order.  SLLBM_E_UNSUPPORTED when tau = 1 (F+ = F_eq carries no
+ * non-equilibrium part), with Pr != 1 or on a curvilinear mesh. */
+int sllbm_adjoint_nu_term(sllbm_ctx *ctx, const void *lambda, const void *populations,
+                          const double *moments, double *acc);
+
 /* out = S^T mu (the transposed interpolation, a gather through transposed
  * departure tables), followed by J_C(M_prev)^T when moments_prev (the record
  * of the previous step) is not NULL.  mu and out must differ. */

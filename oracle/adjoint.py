@@ -11,6 +11,11 @@ with geometry-only weights, moments, division by rho, the polynomial
 equilibrium, the relaxation) is analytic in the populations and the cell
 search depends only on the geometry.
 
+The derivative with respect to the viscosity is taken the same way: the BGK
+relaxation rate 1/tau, tau = nu/dt + 1/2 (Sec. II.D), is evaluated at
+nu + i h (Pr = 1, so tau_Pr = tau); the interpolation weights do not depend
+on nu.
+
 ``kinetic_misfit_loss`` is the loss used for the adjoint workload:
 L = 1/2 sum_v M_v rho |u|^2 + sum_v M_v |u - u_target|^2 at the final step,
 with M_v the exact integral of node v's shape function; ``thermal_misfit_loss``
@@ -51,3 +56,16 @@ def complex_step_fields(sim, fields0, dfields, nsteps, loss, h=1e-30):
                       for f, d in zip(fields0, dfields))
     F = sim.run(sim.init(rho, ux, uy, T), nsteps)
     return float(np.imag(loss(sim, F)) / h)
+
+
+def complex_step_nu(sim, fields0, nsteps, loss, h=1e-30):
+    """d loss(run(init(fields0))) / d nu by complex step (Pr = 1)."""
+    if sim.Pr != 1.0:
+        raise ValueError("complex_step_nu covers Pr = 1")
+    saved = sim.omega, sim.omega_pr
+    sim.omega = sim.omega_pr = 1.0 / ((sim.nu + 1j * h) / sim.dt + 0.5)
+    try:
+        F = sim.run(sim.init(*[np.asarray(f, dtype=complex) for f in fields0]), nsteps)
+        return float(np.imag(loss(sim, F)) / h)
+    finally:
+        sim.omega, sim.omega_pr = saved

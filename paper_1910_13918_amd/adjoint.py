@@ -104,3 +104,44 @@ def rollout(rho0, ux0, uy0, solver, nsteps, every=50, T0=None):
         raise ValueError("the initial temperature T0 is needed unless isothermal")
     rho, ux, uy, T = SLLBMRollout.apply(rho0, ux0, uy0, T0, solver, nsteps, every)
     return (rho, ux, uy) if solver.model == "isothermal" else (rho, ux, uy, T)
+
+
+def nu_gradient(solver, rho0, ux0, uy0, nsteps, loss_grad, T0=None):
+    """dL/d(nu) of a loss L of the final node moments after nsteps from
+    F = F_eq(rho0, u0, T0) (Pr = 1, tau != 1).  loss_grad(rho, ux, uy[, T])
+    receives the final moments (float64 device tensors; T unless isothermal)
+    and returns dL/d of each, in the same order.
+
+    The forward keeps every step's post-collision populations and moments
+    (one population copy per step: for short rollouts); the backward runs the
+    adjoint step by step and adds each step's viscosity term
+    (sllbm_adjoint_nu_term) on the device.  Returns (L-independent) dL/d(nu)
+    as a Python float."""
+    dev = solver.device
+    thermal = solver.model != "isothermal"
+    if thermal and T0 is None:
+        raise ValueError("the initial temperature T0 is needed unless isothermal")
+    f64 = dict(device=dev, dtype=torch.float64)
+    fields = [torch.as_tensor(a, **f64).contiguous() for a in (rho0, ux0, uy0)]
+    fields.append(torch.as_tensor(T0, **f64).contiguous() if thermal
+                  else torch.ones_like(fields[0]))
+    solver.init_macro(*fields)
+    states, moments = [], []
+    for _ in range(nsteps):
+        moments.append(solver.step_record(1)[0])
+        states.append(solver.populations_device())
+    rho, ux, uy, T = solver.moments_device()
+    g = loss_grad(rho, ux, uy, T) if thermal else loss_grad(rho, ux, uy)
+    g = [t.to(**f64).contiguous() for t in g]
+    lam = torch.empty((solver.nsets, solver.q, solver.n), dtype=solver.dtype, device=dev)
+    mu = torch.empty_like(lam)
+    acc = torch.zeros(1, **f64)
+    C.sllbm_adjoint_seed(solver.ctx, g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(),
+                         g[3].data_ptr() if thermal else None, lam.data_ptr())
+    for n in range(nsteps - 1, -1, -1):
+        C.sllbm_adjoint_nu_term(solver.ctx, lam.data_ptr(), states[n].data_ptr(),
+                                moments[n].data_ptr(), acc.data_ptr())
+        C.sllbm_adjoint_collide(solver.ctx, lam.data_ptr(), moments[n].data_ptr(), mu.data_ptr())
+        C.sllbm_adjoint_step(solver.ctx, mu.data_ptr(), None, lam.data_ptr())
+    torch.cuda.synchronize(dev)
+    return float(acc.item())

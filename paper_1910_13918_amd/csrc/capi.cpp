@@ -998,6 +998,26 @@ int sllbm_adjoint_collide(sllbm_ctx *c, const void *lam, const double *moments, 
   return SLLBM_OK;
 }
 
+int sllbm_adjoint_nu_term(sllbm_ctx *c, const void *lam, const void *pop, const double *moments,
+                          double *acc) {
+  if (!c) return SLLBM_E_ARG;
+  if (!lam || !pop || !moments || !acc) return fail(c, SLLBM_E_ARG, "null device pointer");
+  int rc = prepare_adjoint(c);
+  if (rc) return rc;
+  if (c->omega == 1.0)
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "tau = 1: post-collision populations are at equilibrium and do not give the "
+                "pre-collision non-equilibrium part");
+  // f - f_eq before the collision is (f+ - f_eq) / (1 - omega) (the moments
+  // are collision invariants), d(omega)/d(nu) = -1 / (tau^2 dt), and
+  // dC/d(omega) = -(f - f_eq)
+  const double scale = std::isinf(c->tau) ? 0.0 : 1.0 / ((1.0 - c->omega) * c->tau * c->tau * c->dt);
+  HIP_TRY(c, launch_nu_term(c->fp32, c->model, make_consts(c), lam, pop, moments,
+                            static_cast<double *>(c->partial.ptr),
+                            static_cast<double *>(c->scalar.ptr), scale, acc, c->stream));
+  return SLLBM_OK;
+}
+
 int sllbm_adjoint_step(sllbm_ctx *c, const void *mu, const double *moments_prev, void *out) {
   if (!c) return SLLBM_E_ARG;
   if (!mu || !out) return fail(c, SLLBM_E_ARG, "null device pointer");

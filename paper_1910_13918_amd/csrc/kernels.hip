@@ -110,9 +110,47 @@ __global__ __launch_bounds__(256) void k_sum(const double *__restrict__ partial,
 }
 
 // ---------------------------------------------------------------------------
+// viscosity term of the adjoint: per block, sum over nodes, sets and
+// velocities of lambda (F - F_eq(M)), F a post-collision state and M its
+// moments [K][n] (rho, u_x, u_y, theta); scaled and added on the host's
+// behalf by k_add_scaled
+// ---------------------------------------------------------------------------
+template <typename T, int MODEL>
+__global__ __launch_bounds__(256) void k_nu_term(const T *__restrict__ lam,
+                                                 const T *__restrict__ f,
+                                                 const double *__restrict__ mom,
+                                                 double *__restrict__ partial, StepConsts c) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long N = c.n;
+  double acc = 0.0;
+  if (v < N) {  // no early return: every thread takes part in the block sum
+    const double th = MODEL == kIsothermal ? 1.0 : mom[3 * N + v];
+    for_each_equilibrium(mom[v], mom[N + v], mom[2 * N + v], th, c, [&](int i, double feq) {
+      acc += double(lam[i * N + v]) * (double(f[i * N + v]) - feq);
+      if (Sets<MODEL>::S == 2)
+        acc += double(lam[(25 + i) * N + v]) * (double(f[(25 + i) * N + v]) - c.gfac * th * feq);
+    });
+  }
+  const double tot = block_sum_256(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ void k_add_scaled(const double *__restrict__ s, double a, double *__restrict__ acc) {
+  if (threadIdx.x == 0) acc[0] += a * s[0];
+}
+
+// ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
 namespace {
+
+template <typename T, int MODEL>
+hipError_t nu_term_t(const StepConsts &c, const void *lam, const void *f, const double *mom,
+                     double *partial, hipStream_t s) {
+  k_nu_term<T, MODEL><<<mass_blocks(c), 256, 0, s>>>(
+      static_cast<const T *>(lam), static_cast<const T *>(f), mom, partial, c);
+  return hipGetLastError();
+}
 
 template <typename T, int MODEL>
 hipError_t init_t(const StepConsts &c, const double *rho, const double *ux, const double *uy,
@@ -184,6 +222,25 @@ hipError_t launch_moments(int fp32, int model, const StepConsts &c, const DevTab
   if (model == kIsothermal) return moments_t<double, kIsothermal>(c, t, f, rho, ux, uy, T, partial, s);
   if (model == kMonatomic) return moments_t<double, kMonatomic>(c, t, f, rho, ux, uy, T, partial, s);
   return moments_t<double, kPolyatomic>(c, t, f, rho, ux, uy, T, partial, s);
+}
+
+hipError_t launch_nu_term(int fp32, int model, const StepConsts &c, const void *lam,
+                          const void *f, const double *mom, double *partial, double *scalar,
+                          double scale, double *acc, hipStream_t s) {
+  hipError_t e;
+  if (fp32) {
+    if (model == kIsothermal) e = nu_term_t<float, kIsothermal>(c, lam, f, mom, partial, s);
+    else if (model == kMonatomic) e = nu_term_t<float, kMonatomic>(c, lam, f, mom, partial, s);
+    else e = nu_term_t<float, kPolyatomic>(c, lam, f, mom, partial, s);
+  } else {
+    if (model == kIsothermal) e = nu_term_t<double, kIsothermal>(c, lam, f, mom, partial, s);
+    else if (model == kMonatomic) e = nu_term_t<double, kMonatomic>(c, lam, f, mom, partial, s);
+    else e = nu_term_t<double, kPolyatomic>(c, lam, f, mom, partial, s);
+  }
+  if (e != hipSuccess) return e;
+  k_sum<<<1, 256, 0, s>>>(partial, mass_blocks(c), scalar);
+  k_add_scaled<<<1, 64, 0, s>>>(scalar, scale, acc);
+  return hipGetLastError();
 }
 
 hipError_t launch_clear_flag(int *flag, hipStream_t s) {

@@ -100,6 +100,11 @@ hipError_t launch_moments(int fp32, int model, const StepConsts &c, const DevTab
                           const void *f, double *rho, double *ux, double *uy, double *T,
                           double *partial, hipStream_t s);
 hipError_t launch_sum(const double *partial, int n, double *out, hipStream_t s);
+// acc += scale * sum lambda (F - F_eq(M)) (partial: mass_blocks doubles,
+// scalar: one double of scratch)
+hipError_t launch_nu_term(int fp32, int model, const StepConsts &c, const void *lam,
+                          const void *f, const double *mom, double *partial, double *scalar,
+                          double scale, double *acc, hipStream_t s);
 
 // flag = 0 (a kernel, not a memset, so the call can live inside a captured graph)
 hipError_t launch_clear_flag(int *flag, hipStream_t s);

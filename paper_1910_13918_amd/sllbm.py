@@ -81,6 +81,7 @@ _SIGS = {
     "sllbm_node_coords": ([_vp, _vp, _vp], _c),
     "sllbm_node_coords_2d": ([_vp, _vp, _vp], _c),
     "sllbm_departure_records": ([_vp, _c, _vp, _vp, _vp], _c),
+    "sllbm_adjoint_nu_term": ([_vp, _vp, _vp, _vp, _vp], _c),
     "sllbm_departure_table": ([_vp, _c, _c, _vp, _vp], _c),
     "sllbm_mass_weights": ([_vp, _vp, _vp], _c),
     "sllbm_relaxation_time": ([_vp, _dp], _c),
@@ -194,6 +195,10 @@ def sllbm_node_coords(ctx, x_ptr, y_ptr):
 
 def sllbm_node_coords_2d(ctx, x_ptr, y_ptr):
     return check(ctx, lib.sllbm_node_coords_2d(ctx, x_ptr, y_ptr))
+
+
+def sllbm_adjoint_nu_term(ctx, lam_ptr, pop_ptr, moments_ptr, acc_ptr):
+    return check(ctx, lib.sllbm_adjoint_nu_term(ctx, lam_ptr, pop_ptr, moments_ptr, acc_ptr))
 
 
 def sllbm_departure_records(ctx, i, cell_ptr, r_ptr, s_ptr):

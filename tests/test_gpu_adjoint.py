@@ -320,3 +320,67 @@ def test_thermal_rollout_gradient_matches_complex_step(model):
         ref = complex_step_fields(sim, f0, d, 12, loss)
         got = sum(float(np.dot(gr, di)) for gr, di in zip(grads, d))
         assert got == pytest.approx(ref, rel=1e-9, abs=1e-13)
+
+
+# ------------------------------------------------------------ viscosity gradient
+@pytest.mark.parametrize("model", ["isothermal", "monatomic", "polyatomic"])
+def test_nu_gradient_matches_complex_step(model):
+    """dL/d(nu) through 10 steps (8 x 8 cells p = 3, periodic; Pr = 1) against
+    the oracle's complex-step derivative in nu, and against central
+    differences of the GPU loss itself."""
+    from oracle.adjoint import complex_step_nu, thermal_misfit_loss
+    from paper_1910_13918_amd.adjoint import nu_gradient
+    wl = W.tgv(8, 3, U0=0.3, steps=10)
+    if model != "isothermal":
+        wl = _thermal(wl, model, periodic=True)
+    wl.nu = 0.3 * wl.dt  # tau = 0.8
+    s = _solver(wl, "fp64")
+    try:
+        X, Y = s.coords()
+        f0 = wl.fields(X, Y)
+        ut, vt = W.fourier_target(X, Y, 0.3, seed=99)
+        Tt = 1.0 + 0.05 * np.sin(X)
+        M = _mass_weights(s)
+        t = lambda a: torch.tensor(a, device="cuda")
+
+        def torch_loss(rho, ux, uy, T=None):
+            L = _loss_torch(rho, ux, uy, M, t(ut), t(vt))
+            return L if T is None else L + (M * (T - t(Tt)) ** 2).sum()
+
+        def loss_grad(*m):
+            leaves = [a.detach().clone().requires_grad_(True) for a in m]
+            torch_loss(*leaves).backward()
+            return [a.grad for a in leaves]
+
+        T0 = f0[3] if model != "isothermal" else None
+        got = nu_gradient(s, f0[0], f0[1], f0[2], 10, loss_grad, T0=T0)
+        print(f"[gpu] nu gradient {model}: {got}", flush=True)
+    finally:
+        s.close()
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, True, True)
+    sim = Sim(g, wl.dt, wl.nu, model, gamma=wl.gamma)
+    if model == "isothermal":
+        loss = lambda sm, F: kinetic_misfit_loss(sm, F, ut, vt)
+    else:
+        loss = lambda sm, F: thermal_misfit_loss(sm, F, ut, vt, Tt)
+    ref = complex_step_nu(sim, f0, 10, loss)
+    assert abs(ref) > 1e-3
+    assert got == pytest.approx(ref, rel=1e-9)
+
+
+def test_nu_term_refused_at_tau_one():
+    from paper_1910_13918_amd import sllbm as C
+    wl = W.tgv(4, 2, U0=0.1)
+    wl.nu = 0.5 * wl.dt  # tau = 1
+    s = _solver(wl, "fp64")
+    try:
+        s.init_from_workload()
+        lam = torch.zeros(s.nsets * s.q * s.n, dtype=torch.float64, device="cuda")
+        mom = torch.ones(3 * s.n, dtype=torch.float64, device="cuda")
+        acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+        with pytest.raises(C.SllbmError) as e:
+            C.sllbm_adjoint_nu_term(s.ctx, lam.data_ptr(), lam.data_ptr(), mom.data_ptr(),
+                                    acc.data_ptr())
+        assert e.value.code == C.E_UNSUPPORTED
+    finally:
+        s.close()

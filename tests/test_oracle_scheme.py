@@ -326,3 +326,28 @@ def test_prandtl_one_is_bgk_and_equilibrium_has_no_heat_flux():
     feq = a.equilibrium(rho, ux, uy, theta)
     # the 4th-order equilibrium reproduces the Gaussian's (zero) centred third moment
     assert np.abs(a.centred_third_moment(feq[0], ux, uy)).max() < 1e-14
+
+
+@pytest.mark.parametrize("model", ["isothermal", "polyatomic"])
+def test_complex_step_in_nu_matches_finite_differences(model):
+    """The oracle's complex-step derivative in the viscosity (through the
+    relaxation rate 1/tau, tau = nu/dt + 1/2) against central differences of
+    independent runs at nu +- eps."""
+    from oracle.adjoint import complex_step_nu, thermal_misfit_loss
+    g = Grid(uniform_edges(5, 0.0, 2 * np.pi), uniform_edges(5, 0.0, 2 * np.pi), 2, True, True)
+    X, Y = g.coords()
+    f0 = (1 + 0.05 * np.cos(X), 0.3 * np.sin(X) * np.cos(Y), -0.3 * np.cos(X) * np.sin(Y),
+          1 + 0.1 * np.sin(Y))
+    ut, vt, Tt = 0.1 * np.sin(Y), 0.1 * np.cos(X), 1 + 0.05 * np.cos(X)
+    loss = lambda sm, F: thermal_misfit_loss(sm, F, ut, vt, Tt)
+    dt, nu = 0.05, 0.02
+
+    def run(n):
+        sm = Sim(g, dt, n, model)
+        return loss(sm, sm.run(sm.init(*f0), 6))
+
+    cs = complex_step_nu(Sim(g, dt, nu, model), f0, 6, loss)
+    eps = 1e-6 * nu
+    cd = (run(nu + eps) - run(nu - eps)) / (2 * eps)
+    assert abs(cs) > 1e-3
+    assert cs == pytest.approx(cd, rel=1e-6)
