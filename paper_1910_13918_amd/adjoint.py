@@ -27,7 +27,7 @@ from . import sllbm as C
 
 class SLLBMRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, rho0, ux0, uy0, T0, solver, nsteps, every):
+    def forward(ctx, rho0, ux0, uy0, T0, nu, solver, nsteps, every):
         dev = solver.device
         thermal = solver.model != "isothermal"
         rho0 = rho0.detach().to(device=dev, dtype=torch.float64).contiguous()
@@ -56,6 +56,8 @@ class SLLBMRollout(torch.autograd.Function):
         ctx.record = record
         ctx.final = final
         ctx.thermal = thermal
+        ctx.nu_dtype = nu.dtype if nu is not None else None
+        ctx.nu_device = nu.device if nu is not None else None
         return rho, ux, uy, T
 
     @staticmethod
@@ -73,36 +75,70 @@ class SLLBMRollout(torch.autograd.Function):
         C.sllbm_adjoint_seed(s.ctx, g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(),
                              g[3].data_ptr() if ctx.thermal else None, lam.data_ptr())
 
-        def reverse_segment(mom, L):
+        want_nu = ctx.needs_input_grad[4]
+        acc = torch.zeros(1, dtype=torch.float64, device=dev)
+
+        def reverse_segment(mom, L, states=None):
+            # states (dL/d(nu) wanted): the post-collision populations of the
+            # segment's steps; lambda is then formed at every step (S^T and
+            # J_C^T as two calls) so that each step's viscosity term can use it
             nonlocal mu, mu2
+            if states is not None:
+                C.sllbm_adjoint_nu_term(s.ctx, lam.data_ptr(), states[L - 1].data_ptr(),
+                                        mom[L - 1].data_ptr(), acc.data_ptr())
             C.sllbm_adjoint_collide(s.ctx, lam.data_ptr(), mom[L - 1].data_ptr(), mu.data_ptr())
             for t in range(L - 1, 0, -1):
-                C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), mom[t - 1].data_ptr(), mu2.data_ptr())
-                mu, mu2 = mu2, mu
+                if states is None:
+                    C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), mom[t - 1].data_ptr(),
+                                         mu2.data_ptr())
+                    mu, mu2 = mu2, mu
+                else:
+                    C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, lam.data_ptr())
+                    C.sllbm_adjoint_nu_term(s.ctx, lam.data_ptr(), states[t - 1].data_ptr(),
+                                            mom[t - 1].data_ptr(), acc.data_ptr())
+                    C.sllbm_adjoint_collide(s.ctx, lam.data_ptr(), mom[t - 1].data_ptr(),
+                                            mu.data_ptr())
             C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, lam.data_ptr())
 
         if ctx.record is not None:
             reverse_segment(ctx.record, ctx.record.shape[0])
         for ck, L in zip(reversed(ctx.checkpoints), reversed(ctx.lengths)):
             s.set_populations(ck)
-            reverse_segment(s.step_record(L), L)
+            if want_nu:
+                mom, states = [], []
+                for _ in range(L):
+                    mom.append(s.step_record(1)[0])
+                    states.append(s.populations_device())
+                reverse_segment(mom, L, states)
+            else:
+                reverse_segment(s.step_record(L), L)
         out = [torch.empty(s.n, dtype=torch.float64, device=dev) for _ in range(4)]
         C.sllbm_eq_init_vjp(s.ctx, lam.data_ptr(), rho0.data_ptr(), ux0.data_ptr(), uy0.data_ptr(),
                             T0.data_ptr(), *[o.data_ptr() for o in out])
         gT = out[3] if ctx.thermal else None
-        return out[0], out[1], out[2], gT, None, None, None
+        gnu = acc.reshape(()).to(device=ctx.nu_device, dtype=ctx.nu_dtype) if want_nu else None
+        return out[0], out[1], out[2], gT, gnu, None, None, None
 
 
-def rollout(rho0, ux0, uy0, solver, nsteps, every=50, T0=None):
+def rollout(rho0, ux0, uy0, solver, nsteps, every=50, T0=None, nu=None):
     """Final (rho, u_x, u_y) -- and T for the monatomic and polyatomic models --
     after nsteps from F = F_eq(rho0, u0, T0); differentiable in rho0, ux0, uy0
     (and T0).  every > 0: checkpoint interval (the backward replays each
-    segment); every = 0: record every step's moments in the forward."""
+    segment); every = 0: record every step's moments in the forward.
+
+    nu: optional 0-dim tensor holding the solver's viscosity; when it requires
+    grad, the backward also gives dL/d(nu) (Pr = 1, tau != 1, every > 0; each
+    replayed segment then keeps its steps' populations)."""
     if every < 0:
         raise ValueError("every must be >= 0")
     if solver.model != "isothermal" and T0 is None:
         raise ValueError("the initial temperature T0 is needed unless isothermal")
-    rho, ux, uy, T = SLLBMRollout.apply(rho0, ux0, uy0, T0, solver, nsteps, every)
+    if nu is not None:
+        if every == 0 and nu.requires_grad:
+            raise ValueError("the viscosity gradient needs checkpoints (every > 0)")
+        if abs(float(nu) - solver.nu) > 1e-12 * abs(solver.nu):
+            raise ValueError("nu must hold the solver's viscosity")
+    rho, ux, uy, T = SLLBMRollout.apply(rho0, ux0, uy0, T0, nu, solver, nsteps, every)
     return (rho, ux, uy) if solver.model == "isothermal" else (rho, ux, uy, T)
 
 

@@ -33,6 +33,7 @@ class Solver:
         self.device = torch.device("cuda", device)
         self.precision = precision
         self.model = model
+        self.nu = float(nu)
         self.dtype = torch.float32 if precision == "fp32" else torch.float64
         self.ctx = C.sllbm_create(device, _PREC[precision])
         try:

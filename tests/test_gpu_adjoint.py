@@ -384,3 +384,50 @@ def test_nu_term_refused_at_tau_one():
         assert e.value.code == C.E_UNSUPPORTED
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("model", ["isothermal", "polyatomic"])
+def test_checkpointed_rollout_nu_gradient(model):
+    """rollout(..., nu=tensor) with checkpoints every 4 of 10 steps (uneven
+    last segment) gives the same dL/d(nu) as the oracle's complex step, and
+    the same field gradients as without the viscosity input."""
+    from oracle.adjoint import complex_step_nu, thermal_misfit_loss
+    from paper_1910_13918_amd.adjoint import rollout
+    wl = W.tgv(8, 3, U0=0.3, steps=10)
+    if model != "isothermal":
+        wl = _thermal(wl, model, periodic=True)
+    wl.nu = 0.3 * wl.dt
+    s = _solver(wl, "fp64")
+    try:
+        X, Y = s.coords()
+        f0 = wl.fields(X, Y)
+        ut, vt = W.fourier_target(X, Y, 0.3, seed=99)
+        Tt = 1.0 + 0.05 * np.sin(X)
+        M = _mass_weights(s)
+        t = lambda a: torch.tensor(a, device="cuda")
+
+        def run(with_nu):
+            leaves = [t(a).requires_grad_(True) for a in f0[:3]]
+            T0 = t(f0[3]) if model != "isothermal" else None
+            nu = torch.tensor(wl.nu, dtype=torch.float64, requires_grad=True) if with_nu else None
+            out = rollout(*leaves, s, 10, 4, T0=T0, nu=nu)
+            L = _loss_torch(*out[:3], M, t(ut), t(vt))
+            if model != "isothermal":
+                L = L + (M * (out[3] - t(Tt)) ** 2).sum()
+            L.backward()
+            return [a.grad.cpu().numpy() for a in leaves], (float(nu.grad) if with_nu else None)
+
+        g_plain, _ = run(False)
+        g_nu, dnu = run(True)
+        print(f"[gpu] checkpointed nu gradient {model}: {dnu}", flush=True)
+    finally:
+        s.close()
+    for a, b in zip(g_plain, g_nu):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, True, True)
+    sim = Sim(g, wl.dt, wl.nu, model, gamma=wl.gamma)
+    if model == "isothermal":
+        loss = lambda sm, F: kinetic_misfit_loss(sm, F, ut, vt)
+    else:
+        loss = lambda sm, F: thermal_misfit_loss(sm, F, ut, vt, Tt)
+    assert dnu == pytest.approx(complex_step_nu(sim, f0, 10, loss), rel=1e-9)
