@@ -27,7 +27,12 @@
 
 namespace sllbm {
 
-constexpr int kRowsTileRows = 4;  // wavefronts (rows) per workgroup
+constexpr int kRowsTileRows = 4;  // wavefronts (rows) per workgroup: adjoint, float32 step
+
+// Rows per workgroup of the forward step: float64 takes 8 (+1-3 % over 4 on
+// 1025^2-node grids, f + g and Pr = 0.75 alike); float32 loses 5 % with 8.
+template <typename T>
+constexpr int rows_tile_rows() { return sizeof(T) == 8 ? 8 : kRowsTileRows; }
 
 // Orders this wavefront's LDS accesses: what its lanes wrote before is
 // visible to its lanes after (LDS instructions of one wavefront complete in
@@ -175,13 +180,14 @@ template <typename T, int S>
 constexpr int rows_min_waves() { return sizeof(T) == 4 && S == 1 ? 6 : 1; }
 
 template <typename T, int P, int MODEL, bool PR>
-__global__ __launch_bounds__(64 * kRowsTileRows,
+__global__ __launch_bounds__(64 * rows_tile_rows<T>(),
                              (rows_min_waves<T, Sets<MODEL>::S>())) void k_step_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
     const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc,
     const T *__restrict__ yw, int TX, int ntx, int nty, StepConsts c, int *__restrict__ flag) {
   constexpr int S = Sets<MODEL>::S;
-  __shared__ T rows_lds[kRowsTileRows][2][64];
+  constexpr int R = rows_tile_rows<T>();
+  __shared__ T rows_lds[R][2][64];
   const int tile = xcd_tile(blockIdx.x, ntx * nty);
   if (tile >= ntx * nty) return;
   const int tx = tile % ntx, ty = tile / ntx;
@@ -189,7 +195,7 @@ __global__ __launch_bounds__(64 * kRowsTileRows,
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
   // rows past the grid stream the last row (every wavefront must reach the
   // barriers) and store nothing
-  const int iy_t = ty * kRowsTileRows + wv;
+  const int iy_t = ty * R + wv;
   const int iy = min(iy_t, c.ny - 1);
   T fs[S][25];
   rows_stream<T, P + 1, S, rows_lookahead<T, P + 1, S, PR>(), rows_sync_planes<P + 1, S>()>(
@@ -207,10 +213,11 @@ hipError_t launch_rows_family(int fp32, int model, const StepConsts &c, const De
       t.rows_xwin == nullptr || !(t.ident_y & t.ident_x & 1))
     return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
+    constexpr int R = rows_tile_rows<T>();
     const int ntx = (c.nx + t.rows_tx - 1) / t.rows_tx;
-    const int nty = (c.ny + kRowsTileRows - 1) / kRowsTileRows;
+    const int nty = (c.ny + R - 1) / R;
     const int grid = ((ntx * nty + 7) / 8) * 8;
-    k_step_rows<T, P, MODEL, PR><<<grid, dim3(64, kRowsTileRows), 0, s>>>(
+    k_step_rows<T, P, MODEL, PR><<<grid, dim3(64, R), 0, s>>>(
         static_cast<const T *>(fin), static_cast<T *>(fout), t.rows_xrel,
         static_cast<const T *>(t.xw), t.rows_xwin, t.ysrc, static_cast<const T *>(t.yw),
         t.rows_tx, ntx, nty, c, flag);
