@@ -29,10 +29,11 @@ namespace sllbm {
 
 constexpr int kRowsTileRows = 4;  // wavefronts (rows) per workgroup: adjoint, float32 step
 
-// Rows per workgroup of the forward step: float64 takes 8 (+1-3 % over 4 on
-// 1025^2-node grids, f + g and Pr = 0.75 alike); float32 loses 5 % with 8.
-template <typename T>
-constexpr int rows_tile_rows() { return sizeof(T) == 8 ? 8 : kRowsTileRows; }
+// Rows per workgroup of the forward step: float64 f + g takes 8 (+1-3 % over
+// 4 on 1025^2-node grids, Pr = 0.75 alike); a single float64 set (-3 %) and
+// float32 (-5 %) keep 4.
+template <typename T, int S>
+constexpr int rows_tile_rows() { return sizeof(T) == 8 && S == 2 ? 8 : kRowsTileRows; }
 
 // Orders this wavefront's LDS accesses: what its lanes wrote before is
 // visible to its lanes after (LDS instructions of one wavefront complete in
@@ -180,13 +181,13 @@ template <typename T, int S>
 constexpr int rows_min_waves() { return sizeof(T) == 4 && S == 1 ? 6 : 1; }
 
 template <typename T, int P, int MODEL, bool PR>
-__global__ __launch_bounds__(64 * rows_tile_rows<T>(),
+__global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
                              (rows_min_waves<T, Sets<MODEL>::S>())) void k_step_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
     const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc,
     const T *__restrict__ yw, int TX, int ntx, int nty, StepConsts c, int *__restrict__ flag) {
   constexpr int S = Sets<MODEL>::S;
-  constexpr int R = rows_tile_rows<T>();
+  constexpr int R = rows_tile_rows<T, Sets<MODEL>::S>();
   __shared__ T rows_lds[R][2][64];
   const int tile = xcd_tile(blockIdx.x, ntx * nty);
   if (tile >= ntx * nty) return;
@@ -213,7 +214,7 @@ hipError_t launch_rows_family(int fp32, int model, const StepConsts &c, const De
       t.rows_xwin == nullptr || !(t.ident_y & t.ident_x & 1))
     return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
-    constexpr int R = rows_tile_rows<T>();
+    constexpr int R = rows_tile_rows<T, Sets<MODEL>::S>();
     const int ntx = (c.nx + t.rows_tx - 1) / t.rows_tx;
     const int nty = (c.ny + R - 1) / R;
     const int grid = ((ntx * nty + 7) / 8) * 8;
