@@ -952,8 +952,16 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   StepConsts k = make_consts(c);
   const DevTables t = make_tables(c);
   int *flag = static_cast<int *>(c->flag.ptr);
+  const bool big_state =
+      2.0 * double(nsets(c)) * kQ * double(nnodes(c)) * double(pop_size(c)) > 256.0 * (1 << 20);
   for (int64_t s = 0; s < n; ++s) {
     k.mom_out = moments ? moments + s * recorded_moments(c) * k.n : nullptr;
+    // when the two population arrays exceed the 256 MB last-level cache
+    // (MALL) of the MI355X, every other step walks the grid backwards, so
+    // that it starts on the tiles the previous step wrote last, which are
+    // still cached (Riemann 1025^2 f + g: +7 % float32, +1-4 % float64); a
+    // state that fits keeps one order (backwards cost 3 % there)
+    k.reverse = big_state ? int(c->steps_done & 1) : 0;
     HIP_TRY(c, launch_step(c->fp32, c->model, path, k, t, c->pop[c->cur], c->pop[1 - c->cur],
                            flag, c->stream));
     c->cur ^= 1;

@@ -189,8 +189,9 @@ __global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
   constexpr int S = Sets<MODEL>::S;
   constexpr int R = rows_tile_rows<T, Sets<MODEL>::S>();
   __shared__ T rows_lds[R][2][64];
-  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  int tile = xcd_tile(blockIdx.x, ntx * nty);
   if (tile >= ntx * nty) return;
+  if (c.reverse) tile = ntx * nty - 1 - tile;
   const int tx = tile % ntx, ty = tile / ntx;
   const int lane = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
