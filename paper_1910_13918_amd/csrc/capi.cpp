@@ -952,12 +952,16 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   StepConsts k = make_consts(c);
   const DevTables t = make_tables(c);
   int *flag = static_cast<int *>(c->flag.ptr);
-  const bool big_state =
-      2.0 * double(nsets(c)) * kQ * double(nnodes(c)) * double(pop_size(c)) > 256.0 * (1 << 20);
+  // bytes each step streams: both population arrays, plus the records the
+  // records gather re-reads every step
+  const double state_bytes =
+      2.0 * double(nsets(c)) * kQ * double(nnodes(c)) * double(pop_size(c)) +
+      (path == kPathRecords ? double(kQ) * double(nnodes(c)) * double(4 + 2 * pop_size(c)) : 0.0);
+  const bool big_state = state_bytes > 256.0 * (1 << 20);
   for (int64_t s = 0; s < n; ++s) {
     k.mom_out = moments ? moments + s * recorded_moments(c) * k.n : nullptr;
-    // when the two population arrays exceed the 256 MB last-level cache
-    // (MALL) of the MI355X, every other step walks the grid backwards, so
+    // when what a step streams exceeds the 256 MB last-level cache (MALL)
+    // of the MI355X, every other step walks the grid backwards, so
     // that it starts on the tiles the previous step wrote last, which are
     // still cached (Riemann 1025^2 f + g: +7 % float32, +1-4 % float64); a
     // state that fits keeps one order (backwards cost 3 % there)

@@ -23,7 +23,7 @@ struct StepConsts {
   double rn[5];       // reference support points r_0..r_p
   double lden[5];     // 1 / prod_{n != m} (r_m - r_n)
   int perx, pery;     // periodic axes
-  int reverse;        // row-segment step: visit the tiles in reverse order (set per step)
+  int reverse;        // row-segment and records steps: visit the tiles / blocks in reverse order
   double *mom_out;    // optional [K][n]: rho, u_x, u_y (and theta unless isothermal) of
                       // the streamed state
 };

@@ -54,7 +54,9 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
                                                       int *__restrict__ flag) {
   constexpr int S = Sets<MODEL>::S;
   constexpr int P1 = P + 1;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // every other step may visit the blocks backwards (see StepConsts::reverse)
+  const unsigned bid = c.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
+  const long long v = (long long)bid * blockDim.x + threadIdx.x;
   if (v >= c.n) return;
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
