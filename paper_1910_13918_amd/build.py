@@ -1,8 +1,13 @@
 """Build libsllbm.so in-tree with hipcc for gfx950.
 
-    python -m paper_1910_13918_amd.build
+    python -m paper_1910_13918_amd.build [--incremental]
+
+build() compiles every source.  With incremental=True an object is only
+recompiled when it is older than its source or any header that source
+includes (directly or through other headers).
 """
 import os
+import re
 import subprocess
 import sys
 import time
@@ -20,10 +25,24 @@ FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = ["kernels.hip", "step_direct.hip", "step_tiled.hip", "step_records.hip", "step_mfma.hip",
            "step_rows.hip", "step_tiled_pr.hip", "step_prandtl.hip", "adjoint.hip",
-           "adjoint_rows.hip", "capi.cpp", "tables.cpp", "curvilinear.cpp"]
+           "adjoint_rows.hip", "adjoint_tiled_f32.hip", "adjoint_tiled_f64.hip", "capi.cpp",
+           "tables.cpp", "curvilinear.cpp"]
+
+_INCLUDE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
 
 
-def build(verbose=False):
+def _deps(path, seen=None):
+    """The file and every quoted include it reaches."""
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for inc in _INCLUDE.findall(open(path, errors="replace").read()):
+        _deps(os.path.normpath(os.path.join(os.path.dirname(path), inc)), seen)
+    return seen
+
+
+def build(verbose=False, incremental=False):
     os.makedirs(OBJ, exist_ok=True)
     t0 = time.time()
     procs = []
@@ -34,6 +53,10 @@ def build(verbose=False):
             continue
         obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
+        if incremental and os.path.exists(obj):
+            newest = max(os.path.getmtime(d) for d in _deps(path))
+            if os.path.getmtime(obj) >= newest:
+                continue
         cmd = [HIPCC] + FLAGS + ["-c", path, "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
@@ -52,9 +75,9 @@ def build(verbose=False):
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f} s")
+        print(f"built {LIB} in {time.time() - t0:.1f} s ({len(procs)} units compiled)")
     return LIB
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])

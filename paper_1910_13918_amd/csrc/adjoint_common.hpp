@@ -193,6 +193,12 @@ hipError_t dispatch_taps(int fp32, int model, int taps, F &&f) {
 }
 
 
+// S^T through LDS-staged windows (adjoint_tiled.hpp; T = float or double).
+template <typename T>
+hipError_t launch_adjoint_step_tiled_t(int model, const StepConsts &c, const DevTables &t,
+                                       const void *mu, const double *mom_prev, void *out,
+                                       hipStream_t s);
+
 // S^T through row segments (adjoint_rows.hip).
 hipError_t launch_adjoint_step_rows(int fp32, int model, const StepConsts &c, const DevTables &t,
                                     const void *mu, const double *mom_prev, void *out,
