@@ -8,6 +8,10 @@ Sec. II.B, Table I: the D1Q5 abscissae are 0, +-sqrt(5 - sqrt(10)),
 y-component index.  The lattice speed of sound is 1 (Sec. II.B: c_s = 1 unless
 scaled), so normalised and physical velocities coincide.
 
+The D1Q3 rule (roots of He_3) and its tensor product D2Q9 are the on-lattice
+set that Sec. III.A compares D2Q25 against, streamed by the same
+semi-Lagrangian step and with the same 4th-order equilibrium at theta = 1.
+
 Sec. II.A: the scaled Hermite tensors up to 4th order, with the symmetrising
 "overbrace" operator written out as the explicit sum over the distinct index
 permutations (3 terms for xi I at 3rd order, 6 terms for xi^2 I and 3 terms
@@ -31,6 +35,15 @@ def d1q5():
     return xi, w
 
 
+def d1q3():
+    """The three-point Gauss-Hermite rule (roots of He_3, x^3 - 3x): abscissae
+    0, +sqrt(3), -sqrt(3) and weights 2/3, 1/6, 1/6, in the index order of
+    Table I (zero first, then the positive and the negative value).  Its tensor
+    product is the D2Q9 set with which Sec. III.A compares D2Q25 (c_s = 1)."""
+    r3 = np.sqrt(3.0)
+    return np.array([0.0, r3, -r3]), np.array([2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0])
+
+
 def tensor_product(xi1, w1):
     """2-D velocity set from a 1-D one: xi_i = (xi_a, xi_b), w_i = w_a w_b, i = a + q b."""
     q = len(xi1)
@@ -47,6 +60,10 @@ def tensor_product(xi1, w1):
 
 def d2q25():
     return tensor_product(*d1q5())
+
+
+def d2q9():
+    return tensor_product(*d1q3())
 
 
 def delta(a, b):

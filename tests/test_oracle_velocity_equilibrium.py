@@ -12,7 +12,7 @@ import pytest
 from numpy.polynomial import hermite_e as He
 
 from oracle.equilibrium import f_eq, g_eq
-from oracle.velocity import d1q5, d2q25, hermite_tensor, index_tuples
+from oracle.velocity import d1q3, d1q5, d2q9, d2q25, hermite_tensor, index_tuples
 from tests.conftest import GOLDEN
 
 
@@ -137,3 +137,75 @@ def test_g_equilibrium_carries_internal_energy():
     cv = 1.0 / (gamma - 1.0)
     two_rho_e = np.sum((xi[:, 0] ** 2 + xi[:, 1] ** 2) * f[:, 0]) + g.sum()
     assert two_rho_e == pytest.approx(rho * (ux * ux + uy * uy) + 2 * cv * rho * th, rel=1e-14)
+
+
+# ---- D2Q9 (the on-lattice set Sec. III.A compares against) --------------------------
+def test_d1q3_is_gauss_hermite_rule_exact_to_degree_five():
+    """Nodes = roots of He_3 = x^3 - 3x, weights = numpy's Gauss-Hermite
+    weights over sqrt(2 pi) (2/3, 1/6, 1/6); the rule integrates the unit
+    Gaussian's moments exactly to degree 5 and not at degree 6 (9 vs 15)."""
+    xi, w = d1q3()
+    assert xi[0] == 0.0 and xi[1] > 0 > xi[2]
+    ref_x, ref_w = He.hermegauss(3)
+    order = np.argsort(xi)
+    np.testing.assert_allclose(xi[order], ref_x, atol=1e-15)
+    np.testing.assert_allclose(w[order], ref_w / np.sqrt(2.0 * np.pi), atol=1e-15)
+    gauss = [1, 0, 1, 0, 3, 0, 15]
+    for n in range(6):
+        assert np.sum(w * xi ** n) == pytest.approx(gauss[n], abs=1e-14)
+    assert np.sum(w * xi ** 6) == pytest.approx(9.0, abs=1e-13)
+
+
+def test_d2q9_second_order_equilibrium_is_the_textbook_one():
+    """Truncated at second order, the Hermite equilibrium on D2Q9 is the
+    textbook f_eq = w rho (1 + xi.u + ((xi.u)^2 - |u|^2)/2) (c_s = 1)."""
+    xi, w = d2q9()
+    rho = np.array([1.0, 0.7, 1.3])
+    ux = np.array([0.0, 0.05, -0.12])
+    uy = np.array([0.0, -0.08, 0.03])
+    got = f_eq(xi, w, rho, ux, uy, np.ones(3), order=2)
+    xu = xi[:, 0, None] * ux + xi[:, 1, None] * uy
+    want = w[:, None] * rho * (1 + xu + 0.5 * (xu ** 2 - (ux ** 2 + uy ** 2)))
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-16)
+
+
+def test_d2q9_fourth_order_equilibrium_moments():
+    """The 4th-order equilibrium at theta = 1 on D2Q9 (the paper's D2Q9 runs,
+    Sec. III.A): mass and momentum exact; per axis, the quadrature of
+    He_4(xi) xi^2 gives -6 instead of 0 and He_3 vanishes at the nodes, so
+    sum f_eq xi_x^2 = rho (1 + u_x^2 - u_x^4 / 4) (Gaussian: rho (1 + u_x^2))
+    and sum f_eq xi_x^3 = 3 rho u_x (Gaussian: rho (3 u_x + u_x^3)) -- the
+    missing u^3 of the on-lattice set's Galilean error."""
+    xi, w = d2q9()
+    rho, ux, uy = 1.1, 0.21, -0.13
+    f = f_eq(xi, w, rho, ux, uy, 1.0)[:, 0]
+    X, Y = xi[:, 0], xi[:, 1]
+    assert np.sum(f) == pytest.approx(rho, rel=1e-14)
+    assert np.sum(f * X) == pytest.approx(rho * ux, rel=1e-14)
+    assert np.sum(f * Y) == pytest.approx(rho * uy, rel=1e-14)
+    assert np.sum(f * X * X) == pytest.approx(rho * (1 + ux ** 2 - ux ** 4 / 4), rel=1e-14)
+    assert np.sum(f * Y * Y) == pytest.approx(rho * (1 + uy ** 2 - uy ** 4 / 4), rel=1e-14)
+    assert np.sum(f * X ** 3) == pytest.approx(3 * rho * ux, rel=1e-14)
+    # the mixed second moment keeps the Gaussian's rho u_x u_y: the terms
+    # He_k(xi_x) He_m(xi_y) with k + m <= 4 and k, m <= 3 integrate exactly
+    assert np.sum(f * X * Y) == pytest.approx(rho * ux * uy, rel=1e-13)
+
+
+def test_d2q9_equilibrium_factorises_per_axis():
+    """The factorised form the kernels evaluate,
+    f_eq_{a+3b} = rho w_a w_b sum_{k+m<=4} A_k(u_x) He_k(xi_a)/k! A_m(u_y) He_m(xi_b)/m!
+    with A_k = u^k at theta = 1, equals the literal contraction on D2Q9."""
+    x1, w1 = d1q3()
+    xi, w = d2q9()
+    rho, ux, uy = 0.9, -0.3, 0.17
+    lit = f_eq(xi, w, rho, ux, uy, 1.0)[:, 0]
+    fac = np.zeros(9)
+    for b in range(3):
+        for a in range(3):
+            s = 0.0
+            for k in range(5):
+                for m in range(5 - k):
+                    s += (ux ** k * _he(k, x1[a]) / math.factorial(k)
+                          * uy ** m * _he(m, x1[b]) / math.factorial(m))
+            fac[a + 3 * b] = rho * w1[a] * w1[b] * s
+    np.testing.assert_allclose(fac, lit, rtol=1e-14, atol=1e-16)
