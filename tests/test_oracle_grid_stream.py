@@ -141,3 +141,25 @@ def test_interpolation_error_order():
         errs.append(np.abs(out[0, 1] - np.sin(X - sim.dt * sim.xi[1, 0])).max())
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders > 3.5), (errs, orders)
+
+
+def test_dependency_cone_steps_equal_full_steps():
+    """The cone helper (several steps evaluated only on the samples'
+    dependency sets) returns the full run's values at the samples, bit for
+    bit: a stream sums the same terms in the same order whichever nodes are
+    evaluated.  A cone missing a node would leave a NaN instead."""
+    from paper_1910_13918_amd import workloads as W
+    from tests.oracle_cone import dependencies, steps_at
+    wl = W.riemann(10, 2, states=W.RIEMANN_TABLE3_STATES)
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, Pr=0.75)
+    X, Y = g.coords()
+    F0 = sim.init(*wl.fields(X, Y))
+    nodes = np.array([0, 37, 200, g.nnodes - 1])
+    full = sim.run(F0, 3)[:, :, nodes]
+    np.testing.assert_array_equal(steps_at(sim, F0, nodes, 3), full)
+    # the cone of a node holds its own departure stencils and stays local
+    dep = dependencies(sim, np.array([200]))
+    assert 200 in dep and len(dep) <= 25
+    iy, ix = np.divmod(dep, g.nx)
+    assert np.abs(ix - 200 % g.nx).max() <= 2 and np.abs(iy - 200 // g.nx).max() <= 2
