@@ -110,6 +110,8 @@ int fail(sllbm_ctx *c, int code, const std::string &msg) {
 bool is_finite(double v) { return std::isfinite(v); }
 
 int nsets(const sllbm_ctx *c) { return c->model == SLLBM_POLYATOMIC ? 2 : 1; }
+int q1(const sllbm_ctx *c) { return c->vs.q1; }             // 1-D velocities
+int nvel(const sllbm_ctx *c) { return c->vs.q1 * c->vs.q1; }  // 2-D velocities
 size_t pop_size(const sllbm_ctx *c) { return c->fp32 ? 4 : 8; }
 long long nnodes(const sllbm_ctx *c) { return (long long)c->ax.n * c->ay.n; }
 
@@ -126,14 +128,14 @@ int ready_for_tables(sllbm_ctx *c) {
 // holds each node's stencil relative to its tile's window ([comp][m][node]).
 // Unwrapped indices keep the window contiguous across a periodic seam.
 // Returns the widest window.
-int build_windows(const AxisTable *t, int n, int tile, std::vector<int32_t> &win,
+int build_windows(const AxisTable *t, int nq1, int n, int tile, std::vector<int32_t> &win,
                   std::vector<int32_t> &rel) {
   const int taps = t[0].taps;
   const int ntiles = (n + tile - 1) / tile;
-  win.assign(size_t(kQ1) * ntiles, 0);
-  rel.assign(size_t(kQ1) * taps * n, 0);
+  win.assign(size_t(nq1) * ntiles, 0);
+  rel.assign(size_t(nq1) * taps * n, 0);
   int width = 0;
-  for (int a = 0; a < kQ1; ++a) {
+  for (int a = 0; a < nq1; ++a) {
     for (int k = 0; k < ntiles; ++k) {
       const int j0 = k * tile, j1 = std::min(j0 + tile, n);
       long lo = std::numeric_limits<long>::max(), hi = std::numeric_limits<long>::min();
@@ -157,7 +159,7 @@ int build_windows(const AxisTable *t, int n, int tile, std::vector<int32_t> &win
 bool mfma_blocks_fit(const sllbm_ctx *c) {
   const int P1 = c->p + 1, n = c->ax.n;
   const int K = 4 * ((16 + 2 * c->p + 3) / 4);
-  for (int a = 0; a < kQ1; ++a)
+  for (int a = 0; a < q1(c); ++a)
     for (int n0 = 0; n0 < n; n0 += 16) {
       const int32_t base = c->xrel[(size_t(a) * P1) * n + n0];
       for (int j = n0; j < std::min(n0 + 16, n); ++j) {
@@ -171,11 +173,11 @@ bool mfma_blocks_fit(const sllbm_ctx *c) {
 // Widest row segment (at most 64 columns, at least kRowsMinCols) whose
 // x-stencils fit 64 consecutive source columns for every segment and 1-D
 // velocity; its windows go to win / rel.  0 when none does.
-int rows_segment_width(const AxisTable *t, int n, std::vector<int32_t> &win,
+int rows_segment_width(const AxisTable *t, int nq1, int n, std::vector<int32_t> &win,
                        std::vector<int32_t> &rel) {
   int tx = 64;
   while (tx >= kRowsMinCols) {
-    const int width = build_windows(t, n, tx, win, rel);
+    const int width = build_windows(t, nq1, n, tx, win, rel);
     if (width <= 64) return tx;
     tx -= width - 64;
   }
@@ -188,14 +190,14 @@ int rows_segment_width(const AxisTable *t, int n, std::vector<int32_t> &win,
 // velocity i = a + 5 b for every node: from the axis tables, or located on
 // the curvilinear mesh.  Returns "" or an error message.
 std::string departure_records(const sllbm_ctx *c, int i, int32_t *cell, double *r, double *s) {
-  const int a = i % kQ1, b = i / kQ1;
+  const int a = i % q1(c), b = i / q1(c);
   if (c->curvi)
     return curvi_records(c->mesh, support_points(c->p, c->glc), c->cX, c->cY,
                          -c->dt * c->vs.xi[a], -c->dt * c->vs.xi[b], cell, r, s);
   for (int iy = 0; iy < c->ay.n; ++iy)
     for (int ix = 0; ix < c->ax.n; ++ix) {
       const size_t k = size_t(iy) * c->ax.n + ix;
-      cell[k] = c->xt[a].cell[ix] | (c->yt[b].cell[iy] << 16);
+      cell[k] = int32_t(uint32_t(c->xt[a].cell[ix]) | (uint32_t(c->yt[b].cell[iy]) << 16));
       r[k] = c->xt[a].rref[ix];
       s[k] = c->yt[b].rref[iy];
     }
@@ -204,19 +206,19 @@ std::string departure_records(const sllbm_ctx *c, int i, int32_t *cell, double *
 
 void build_host_tables(sllbm_ctx *c) {
   if (!c->host_dirty) return;
-  for (int a = 0; a < kQ1; ++a) {
+  for (int a = 0; a < q1(c); ++a) {
     c->xt[a] = build_axis_table(c->ax, -c->dt * c->vs.xi[a]);
     c->yt[a] = build_axis_table(c->ay, -c->dt * c->vs.xi[a]);
   }
   c->mx = c->ax.node_mass();
   c->my = c->ay.node_mass();
   // windows of the tiled kernel: tiles of kTileCols columns by kTileRows rows
-  c->win_rows = build_windows(c->yt, c->ay.n, kTileRows, c->ywin, c->yrel);
-  c->win_cols = build_windows(c->xt, c->ax.n, kTileCols, c->xwin, c->xrel);
+  c->win_rows = build_windows(c->yt, q1(c), c->ay.n, kTileRows, c->ywin, c->yrel);
+  c->win_cols = build_windows(c->xt, q1(c), c->ax.n, kTileCols, c->xwin, c->xrel);
   c->mfma_blocks_ok = mfma_blocks_fit(c);
-  c->rows_tx = rows_segment_width(c->xt, c->ax.n, c->rows_xwin, c->rows_xrel);
+  c->rows_tx = rows_segment_width(c->xt, q1(c), c->ax.n, c->rows_xwin, c->rows_xrel);
   c->ident_x = c->ident_y = 0;
-  for (int b = 0; b < kQ1; ++b) {
+  for (int b = 0; b < q1(c); ++b) {
     if (identity_table(c->xt[b], c->ax.n)) c->ident_x |= 1 << b;
     if (identity_table(c->yt[b], c->ay.n)) c->ident_y |= 1 << b;
   }
@@ -229,7 +231,7 @@ void build_host_tables(sllbm_ctx *c) {
 // The tiled kernel stages window rows (up to 3 per wavefront) of
 // up to 128 columns; LDS always fits (one x-component per phase if need be).
 bool tiled_fits(const sllbm_ctx *c) {
-  return c->win_rows <= 3 * kTileRows && c->win_cols <= kMaxWindowCols;
+  return q1(c) == kQ1 && c->win_rows <= 3 * kTileRows && c->win_cols <= kMaxWindowCols;
 }
 
 // The matrix-core path: tiled windows, float32, at most 16 (set, row) pairs
@@ -244,6 +246,8 @@ bool mfma_fits(const sllbm_ctx *c) {
 // direct.
 bool rows_preferred(const sllbm_ctx *c) { return c->rows_tx >= 48; }
 
+// (The 3-velocity set has row-segment, direct and records kernels only:
+// tiled_fits is false for it.)
 int effective_path(const sllbm_ctx *c) {
   if (c->path != SLLBM_PATH_AUTO) return c->path;
   if (c->curvi) return kPathRecords;  // the only gather that takes arbitrary cells
@@ -296,9 +300,9 @@ int check_device(sllbm_ctx *c) {
 
 // Per-axis tables in [comp][m][node] order.
 template <typename V>
-std::vector<V> comp_major(const AxisTable *t, int n, int P1, bool weights) {
-  std::vector<V> out(size_t(kQ1) * P1 * n);
-  for (int a = 0; a < kQ1; ++a)
+std::vector<V> comp_major(const AxisTable *t, int nq1, int n, int P1, bool weights) {
+  std::vector<V> out(size_t(nq1) * P1 * n);
+  for (int a = 0; a < nq1; ++a)
     for (int m = 0; m < P1; ++m)
       for (int j = 0; j < n; ++j)
         out[(size_t(a) * P1 + m) * n + j] =
@@ -314,10 +318,11 @@ int prepare_device(sllbm_ctx *c) {
   build_host_tables(c);
   if (c->dev_dirty) {
     const int P1 = c->p + 1;
-    rc = upload(c, c->xsrc, comp_major<int32_t>(c->xt, c->ax.n, P1, false));
-    if (!rc) rc = upload_weights(c, c->xw, comp_major<double>(c->xt, c->ax.n, P1, true));
-    if (!rc) rc = upload(c, c->ysrc, comp_major<int32_t>(c->yt, c->ay.n, P1, false));
-    if (!rc) rc = upload_weights(c, c->yw, comp_major<double>(c->yt, c->ay.n, P1, true));
+    const int nq1 = q1(c);
+    rc = upload(c, c->xsrc, comp_major<int32_t>(c->xt, nq1, c->ax.n, P1, false));
+    if (!rc) rc = upload_weights(c, c->xw, comp_major<double>(c->xt, nq1, c->ax.n, P1, true));
+    if (!rc) rc = upload(c, c->ysrc, comp_major<int32_t>(c->yt, nq1, c->ay.n, P1, false));
+    if (!rc) rc = upload_weights(c, c->yw, comp_major<double>(c->yt, nq1, c->ay.n, P1, true));
     if (!rc) rc = upload(c, c->yrel_d, c->yrel);
     if (!rc) rc = upload(c, c->ywin_d, c->ywin);
     if (!rc) rc = upload(c, c->xrel_d, c->xrel);
@@ -334,17 +339,18 @@ int prepare_device(sllbm_ctx *c) {
   }
   if (effective_path(c) == kPathRecords && c->rec_dirty) {
     const long long N = nnodes(c);
-    std::vector<int32_t> cell(size_t(kQ) * N);
-    std::vector<double> r(size_t(kQ) * N), s(size_t(kQ) * N);
+    const int nq = nvel(c);
+    std::vector<int32_t> cell(size_t(nq) * N);
+    std::vector<double> r(size_t(nq) * N), s(size_t(nq) * N);
     // one velocity per task, over up to 16 host threads (locating departure
     // points on a curvilinear mesh takes ~0.5 s per velocity at 1e6 nodes)
-    std::vector<std::string> errs(kQ);
+    std::vector<std::string> errs(nq);
     const int nthreads =
-        std::max(1, std::min({kQ, 16, int(std::thread::hardware_concurrency())}));
+        std::max(1, std::min({nq, 16, int(std::thread::hardware_concurrency())}));
     std::vector<std::thread> pool;
     for (int t = 0; t < nthreads; ++t)
       pool.emplace_back([&, t] {
-        for (int i = t; i < kQ; i += nthreads) {
+        for (int i = t; i < nq; i += nthreads) {
           const size_t off = size_t(i) * N;
           errs[i] = departure_records(c, i, cell.data() + off, r.data() + off, s.data() + off);
         }
@@ -376,7 +382,8 @@ StepConsts make_consts(const sllbm_ctx *c) {
   if (c->model == SLLBM_POLYATOMIC) cv = 1.0 / (c->gamma - 1.0);
   k.gfac = 2.0 * cv - D;
   k.inv_2cv = 1.0 / (2.0 * cv);
-  for (int a = 0; a < kQ1; ++a) {
+  k.q1 = q1(c);
+  for (int a = 0; a < q1(c); ++a) {
     k.xi[a] = c->vs.xi[a];
     k.w[a] = c->vs.w[a];
     for (int j = 0; j < 5; ++j) {
@@ -425,7 +432,7 @@ DevTables make_tables(const sllbm_ctx *c) {
 }
 
 int ensure_populations(sllbm_ctx *c) {
-  const size_t bytes = size_t(nsets(c)) * kQ * size_t(nnodes(c)) * pop_size(c);
+  const size_t bytes = size_t(nsets(c)) * nvel(c) * size_t(nnodes(c)) * pop_size(c);
   if (c->pop[0] && c->pop_bytes == bytes) return SLLBM_OK;
   if (c->pop[0] && !c->own_pop)
     return fail(c, SLLBM_E_STATE, "bound population buffers do not match the current set-up");
@@ -490,6 +497,8 @@ int prepare_adjoint(sllbm_ctx *c) {
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers Pr = 1 only");
   if (c->curvi)
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers axis-product grids only");
+  if (q1(c) != kQ1)
+    return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers the 5-velocity set (D2Q25) only");
   if (!c->adj_dirty) return SLLBM_OK;
   int taps = 0;
   for (int a = 0; a < kQ1; ++a) {
@@ -503,19 +512,19 @@ int prepare_adjoint(sllbm_ctx *c) {
     pad_taps(c->ytT[a], c->ay, taps);
   }
   c->taps_T = taps;
-  c->win_rowsT = build_windows(c->ytT, c->ay.n, kTileRows, c->ywinT, c->yrelT);
-  c->win_colsT = build_windows(c->xtT, c->ax.n, kTileCols, c->xwinT, c->xrelT);
-  c->rows_txT = rows_segment_width(c->xtT, c->ax.n, c->rows_xwinT, c->rows_xrelT);
+  c->win_rowsT = build_windows(c->ytT, kQ1, c->ay.n, kTileRows, c->ywinT, c->yrelT);
+  c->win_colsT = build_windows(c->xtT, kQ1, c->ax.n, kTileCols, c->xwinT, c->xrelT);
+  c->rows_txT = rows_segment_width(c->xtT, kQ1, c->ax.n, c->rows_xwinT, c->rows_xrelT);
   c->ident_xT = c->ident_yT = 0;
   for (int b = 0; b < kQ1; ++b) {
     if (identity_table(c->xtT[b], c->ax.n)) c->ident_xT |= 1 << b;
     if (identity_table(c->ytT[b], c->ay.n)) c->ident_yT |= 1 << b;
   }
   if (!(c->ident_xT & c->ident_yT & 1)) c->rows_txT = 0;
-  rc = upload(c, c->xsrcT, comp_major<int32_t>(c->xtT, c->ax.n, taps, false));
-  if (!rc) rc = upload_weights(c, c->xwT, comp_major<double>(c->xtT, c->ax.n, taps, true));
-  if (!rc) rc = upload(c, c->ysrcT, comp_major<int32_t>(c->ytT, c->ay.n, taps, false));
-  if (!rc) rc = upload_weights(c, c->ywT, comp_major<double>(c->ytT, c->ay.n, taps, true));
+  rc = upload(c, c->xsrcT, comp_major<int32_t>(c->xtT, kQ1, c->ax.n, taps, false));
+  if (!rc) rc = upload_weights(c, c->xwT, comp_major<double>(c->xtT, kQ1, c->ax.n, taps, true));
+  if (!rc) rc = upload(c, c->ysrcT, comp_major<int32_t>(c->ytT, kQ1, c->ay.n, taps, false));
+  if (!rc) rc = upload_weights(c, c->ywT, comp_major<double>(c->ytT, kQ1, c->ay.n, taps, true));
   if (!rc) rc = upload(c, c->yrelT_d, c->yrelT);
   if (!rc) rc = upload(c, c->ywinT_d, c->ywinT);
   if (!rc) rc = upload(c, c->xrelT_d, c->xrelT);
@@ -597,21 +606,25 @@ int sllbm_set_stream(sllbm_ctx *c, void *stream) {
 int sllbm_set_velocity_set(sllbm_ctx *c, int q1d, const double *xi1d, const double *w1d) {
   int rc = setup_allowed(c);
   if (rc) return rc;
-  if (!xi1d && !w1d) {
-    c->vs = default_velocity_set();
-    invalidate(c);
-    return SLLBM_OK;
-  }
-  if (!xi1d || !w1d) return fail(c, SLLBM_E_ARG, "xi1d and w1d must both be given or both NULL");
-  if (q1d != kQ1) return fail(c, SLLBM_E_UNSUPPORTED, "only 5 velocities per axis are supported");
+  if (q1d != 5 && q1d != 3)
+    return fail(c, SLLBM_E_UNSUPPORTED, "5 (D2Q25) or 3 (D2Q9) velocities per axis");
+  if (q1d == 3 && c->have_phys && c->model != SLLBM_ISOTHERMAL)
+    return fail(c, SLLBM_E_UNSUPPORTED, "the 3-velocity set (D2Q9) runs the isothermal model only");
   VelocitySet vs{};
-  for (int a = 0; a < kQ1; ++a) {
-    if (!is_finite(xi1d[a]) || !is_finite(w1d[a]) || !(w1d[a] > 0))
-      return fail(c, SLLBM_E_ARG, "velocities must be finite and weights positive");
-    vs.xi[a] = xi1d[a];
-    vs.w[a] = w1d[a];
+  if (!xi1d && !w1d) {
+    vs = q1d == 3 ? d1q3_velocity_set() : default_velocity_set();
+  } else {
+    if (!xi1d || !w1d)
+      return fail(c, SLLBM_E_ARG, "xi1d and w1d must both be given or both NULL");
+    vs.q1 = q1d;
+    for (int a = 0; a < q1d; ++a) {
+      if (!is_finite(xi1d[a]) || !is_finite(w1d[a]) || !(w1d[a] > 0))
+        return fail(c, SLLBM_E_ARG, "velocities must be finite and weights positive");
+      vs.xi[a] = xi1d[a];
+      vs.w[a] = w1d[a];
+    }
+    fill_hermite_constants(vs);
   }
-  fill_hermite_constants(vs);
   if (c->have_phys && c->Pr != 1.0 && !gaussian_exact_to_degree(vs, 7))
     return fail(c, SLLBM_E_UNSUPPORTED,
                 "Pr != 1 needs a velocity set exact to degree 7 (zero equilibrium heat flux)");
@@ -725,6 +738,8 @@ int sllbm_set_physics(sllbm_ctx *c, double dt, double nu, double gamma, double P
   if (!is_finite(Pr) || !(Pr > 0)) return fail(c, SLLBM_E_ARG, "Pr must be positive and finite");
   if (Pr != 1.0 && model == SLLBM_ISOTHERMAL)
     return fail(c, SLLBM_E_ARG, "Pr != 1 needs a thermal model (no energy equation otherwise)");
+  if (q1(c) == 3 && model != SLLBM_ISOTHERMAL)
+    return fail(c, SLLBM_E_UNSUPPORTED, "the 3-velocity set (D2Q9) runs the isothermal model only");
   if (Pr != 1.0 && !gaussian_exact_to_degree(c->vs, 7))
     return fail(c, SLLBM_E_UNSUPPORTED,
                 "Pr != 1 needs a velocity set exact to degree 7 (zero equilibrium heat flux)");
@@ -772,7 +787,7 @@ int sllbm_population_layout(const sllbm_ctx *c, int *ns, int *q, int *bytes) {
   if (!c || !ns || !q || !bytes) return SLLBM_E_ARG;
   if (!c->have_phys) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "physics not set");
   *ns = nsets(c);
-  *q = kQ;
+  *q = nvel(c);
   *bytes = int(pop_size(c));
   return SLLBM_OK;
 }
@@ -810,7 +825,7 @@ int sllbm_departure_table(const sllbm_ctx *cc, int axis, int comp, int32_t *src,
   if (c->curvi)
     return fail(c, SLLBM_E_UNSUPPORTED, "a curvilinear mesh has no per-axis departure tables");
   if (axis != 0 && axis != 1) return fail(c, SLLBM_E_ARG, "axis must be 0 or 1");
-  if (comp < 0 || comp >= kQ1) return fail(c, SLLBM_E_ARG, "velocity component out of range");
+  if (comp < 0 || comp >= q1(c)) return fail(c, SLLBM_E_ARG, "velocity component out of range");
   int rc = ready_for_tables(c);
   if (rc) return rc;
   build_host_tables(c);
@@ -823,7 +838,7 @@ int sllbm_departure_table(const sllbm_ctx *cc, int axis, int comp, int32_t *src,
 int sllbm_departure_records(const sllbm_ctx *cc, int i, int32_t *cell, double *r, double *s) {
   sllbm_ctx *c = const_cast<sllbm_ctx *>(cc);
   if (!c || !cell || !r || !s) return SLLBM_E_ARG;
-  if (i < 0 || i >= kQ) return fail(c, SLLBM_E_ARG, "velocity index out of range");
+  if (i < 0 || i >= nvel(c)) return fail(c, SLLBM_E_ARG, "velocity index out of range");
   int rc = ready_for_tables(c);
   if (rc) return rc;
   build_host_tables(c);
@@ -862,7 +877,7 @@ int sllbm_bind_populations(sllbm_ctx *c, void *a, void *b) {
   c->pop[0] = a;
   c->pop[1] = b;
   c->own_pop = false;
-  c->pop_bytes = size_t(nsets(c)) * kQ * size_t(nnodes(c)) * pop_size(c);
+  c->pop_bytes = size_t(nsets(c)) * nvel(c) * size_t(nnodes(c)) * pop_size(c);
   c->cur = 0;
   c->initialised = false;
   return SLLBM_OK;
@@ -939,6 +954,9 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   const int path = effective_path(c);
   if (c->curvi && path != kPathRecords)
     return fail(c, SLLBM_E_UNSUPPORTED, "a curvilinear mesh runs on the records path only");
+  if ((path == kPathTiled || path == kPathMfma) && q1(c) != kQ1)
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "the 3-velocity set (D2Q9) runs on the row-segment, direct and records kernels");
   if (path == kPathTiled && !tiled_fits(c))
     return fail(c, SLLBM_E_UNSUPPORTED, "departures span too many rows for the tiled kernel");
   if (path == kPathRows && c->rows_tx == 0)
@@ -955,8 +973,9 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   // bytes each step streams: both population arrays, plus the records the
   // records gather re-reads every step
   const double state_bytes =
-      2.0 * double(nsets(c)) * kQ * double(nnodes(c)) * double(pop_size(c)) +
-      (path == kPathRecords ? double(kQ) * double(nnodes(c)) * double(4 + 2 * pop_size(c)) : 0.0);
+      2.0 * double(nsets(c)) * nvel(c) * double(nnodes(c)) * double(pop_size(c)) +
+      (path == kPathRecords ? double(nvel(c)) * double(nnodes(c)) * double(4 + 2 * pop_size(c))
+                            : 0.0);
   const bool big_state = state_bytes > 256.0 * (1 << 20);
   for (int64_t s = 0; s < n; ++s) {
     k.mom_out = moments ? moments + s * recorded_moments(c) * k.n : nullptr;

@@ -163,7 +163,7 @@ std::string curvi_records(const CurviMesh &m, const std::vector<double> &pts,
         return "departure point of node (" + std::to_string(ix) + ", " + std::to_string(iy) +
                ") not found in the mesh";
       const long cx = ux - floor_div(ux, m.ncx) * m.ncx, cy = uy - floor_div(uy, m.ncy) * m.ncy;
-      cell[v] = int32_t(cx | (cy << 16));
+      cell[v] = int32_t(uint32_t(cx) | (uint32_t(cy) << 16));
       r[v] = std::clamp(rr, 0.0, 1.0);
       s[v] = std::clamp(ss, 0.0, 1.0);
     }

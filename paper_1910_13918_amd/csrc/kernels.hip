@@ -15,7 +15,7 @@ namespace sllbm {
 // ---------------------------------------------------------------------------
 // initialisation: f = f_eq(rho, u, theta), g = g_eq
 // ---------------------------------------------------------------------------
-template <typename T, int MODEL>
+template <typename T, int MODEL, int Q1 = 5>
 __global__ __launch_bounds__(256) void k_init_eq(const double *__restrict__ rho,
                                                  const double *__restrict__ ux,
                                                  const double *__restrict__ uy,
@@ -26,33 +26,34 @@ __global__ __launch_bounds__(256) void k_init_eq(const double *__restrict__ rho,
   const double r = rho[v], u = ux[v], w = uy[v];
   const double th = (MODEL == kIsothermal) ? 1.0 : temp[v];
   const long long N = c.n;
-  for_each_equilibrium(r, u, w, th, c, [&](int i, double feq) {
+  for_each_equilibrium<Q1>(r, u, w, th, c, [&](int i, double feq) {
     f[i * N + v] = T(feq);
-    if (Sets<MODEL>::S == 2) f[(25 + i) * N + v] = T(c.gfac * th * feq);
+    if (Sets<MODEL>::S == 2) f[(Q1 * Q1 + i) * N + v] = T(c.gfac * th * feq);
   });
 }
 
 // ---------------------------------------------------------------------------
 // moments and mass
 // ---------------------------------------------------------------------------
-template <typename T, int MODEL>
+template <typename T, int MODEL, int Q1 = 5>
 __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const double *__restrict__ mx,
                                                  const double *__restrict__ my,
                                                  double *__restrict__ rho_o, double *__restrict__ ux_o,
                                                  double *__restrict__ uy_o, double *__restrict__ T_o,
                                                  double *__restrict__ partial, StepConsts c) {
   constexpr int S = Sets<MODEL>::S;
+  constexpr int Q = Q1 * Q1;
   const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
   double mass = 0.0;
   if (v < c.n) {
     const long long N = c.n;
     double m[4];
-    T fs[S][25];
+    T fs[S][Q];
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
-      for (int i = 0; i < 25; ++i) fs[s][i] = f[(s * 25 + i) * N + v];
-    node_moments<T, MODEL>(fs, c, m);
+      for (int i = 0; i < Q; ++i) fs[s][i] = f[(s * Q + i) * N + v];
+    node_moments<T, MODEL, Q1>(fs, c, m);
     if (rho_o) rho_o[v] = m[0];
     if (ux_o) ux_o[v] = m[1];
     if (uy_o) uy_o[v] = m[2];
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
 
 // Mass only: per-block partial sums of M_v rho_v, reading the f planes alone
 // (rho = sum f; the same summation order as node_moments).
-template <typename T>
+template <typename T, int Q1 = 5>
 __global__ __launch_bounds__(256) void k_mass(const T *__restrict__ f,
                                               const double *__restrict__ mx,
                                               const double *__restrict__ my,
@@ -77,15 +78,15 @@ __global__ __launch_bounds__(256) void k_mass(const T *__restrict__ f,
   double mass = 0.0;
   if (v < c.n) {
     const long long N = c.n;
-    T fs[25];
+    T fs[Q1 * Q1];
 #pragma unroll
-    for (int i = 0; i < 25; ++i) fs[i] = f[i * N + v];
+    for (int i = 0; i < Q1 * Q1; ++i) fs[i] = f[i * N + v];
     double rho = 0.0;
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
+    for (int b = 0; b < Q1; ++b) {
       double r_b = 0.0;
 #pragma unroll
-      for (int a = 0; a < 5; ++a) r_b += double(fs[a + 5 * b]);
+      for (int a = 0; a < Q1; ++a) r_b += double(fs[a + Q1 * b]);
       rho += r_b;
     }
     // 32-bit division (nodes < 2^31): the 64-bit form dominated these kernels
@@ -156,7 +157,12 @@ template <typename T, int MODEL>
 hipError_t init_t(const StepConsts &c, const double *rho, const double *ux, const double *uy,
                   const double *temp, void *f, hipStream_t s) {
   const unsigned blocks = unsigned((c.n + 255) / 256);
-  k_init_eq<T, MODEL><<<blocks, 256, 0, s>>>(rho, ux, uy, temp, static_cast<T *>(f), c);
+  if (c.q1 == 3) {  // D2Q9 (isothermal only; the host refuses the rest)
+    if constexpr (MODEL != kIsothermal) return hipErrorInvalidValue;
+    else k_init_eq<T, MODEL, 3><<<blocks, 256, 0, s>>>(rho, ux, uy, temp, static_cast<T *>(f), c);
+  } else {
+    k_init_eq<T, MODEL><<<blocks, 256, 0, s>>>(rho, ux, uy, temp, static_cast<T *>(f), c);
+  }
   return hipGetLastError();
 }
 
@@ -164,7 +170,16 @@ template <typename T, int MODEL>
 hipError_t moments_t(const StepConsts &c, const DevTables &t, const void *f, double *rho,
                      double *ux, double *uy, double *temp, double *partial, hipStream_t s) {
   if (!rho && !ux && !uy && !temp) {  // the mass alone needs the f planes only
-    k_mass<T><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, partial, c);
+    if (c.q1 == 3)
+      k_mass<T, 3><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, partial, c);
+    else
+      k_mass<T><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, partial, c);
+    return hipGetLastError();
+  }
+  if (c.q1 == 3) {
+    if constexpr (MODEL != kIsothermal) return hipErrorInvalidValue;
+    else k_moments<T, MODEL, 3><<<mass_blocks(c), 256, 0, s>>>(
+        static_cast<const T *>(f), t.mx, t.my, rho, ux, uy, temp, partial, c);
     return hipGetLastError();
   }
   k_moments<T, MODEL><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, rho,

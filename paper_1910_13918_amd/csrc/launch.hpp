@@ -16,12 +16,13 @@ struct StepConsts {
   double omega_pr;    // 1 / tau_Pr, tau_Pr = (tau - 1/2)/Pr + 1/2 (= omega when Pr = 1)
   double gfac;        // 2 C_v - D  (g_eq = gfac * theta * f_eq)
   double inv_2cv;     // 1 / (2 C_v)  (theta from the energy moment)
-  double xi[5];       // 1-D abscissae
+  double xi[5];       // 1-D abscissae (the first q1 entries are used)
   double w[5];        // 1-D weights
   double hk[5][5];    // He_k(xi_a) / k!
   double whk[5][5];   // w_a He_k(xi_a) / k!
   double rn[5];       // reference support points r_0..r_p
   double lden[5];     // 1 / prod_{n != m} (r_m - r_n)
+  int q1;             // 1-D velocities (5: D2Q25; 3: D2Q9, isothermal only)
   int perx, pery;     // periodic axes
   int reverse;        // row-segment and records steps: visit the tiles / blocks in reverse order
   double *mom_out;    // optional [K][n]: rho, u_x, u_y (and theta unless isothermal) of

@@ -114,16 +114,17 @@ __device__ __forceinline__ void lagrange_eval(T r, const T (&rn)[P1], const T (&
 // rho, u_x, u_y, theta of one node's populations (Sec. II, eqs. (3)-(5)):
 // rho = sum f, rho u = sum xi f, 2 rho E = sum |xi|^2 f + sum g, and
 // theta = (2 rho E - rho |u|^2) / (2 C_v rho) (theta = 1 when isothermal).
-template <typename T, int MODEL>
-__device__ __forceinline__ void node_moments(const T (&fs)[Sets<MODEL>::S][25],
+// Q1: velocities per axis of the tensor-product set (5: D2Q25; 3: D2Q9).
+template <typename T, int MODEL, int Q1 = 5>
+__device__ __forceinline__ void node_moments(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
                                              const StepConsts &c, double (&m)[4]) {
   double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
 #pragma unroll
-  for (int b = 0; b < 5; ++b) {
+  for (int b = 0; b < Q1; ++b) {
     double r_b = 0.0, jx_b = 0.0, e_b = 0.0;
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      const double v = double(fs[0][a + 5 * b]);
+    for (int a = 0; a < Q1; ++a) {
+      const double v = double(fs[0][a + Q1 * b]);
       r_b += v;
       jx_b = fma(c.xi[a], v, jx_b);
       if (MODEL != kIsothermal) e_b = fma(c.xi[a] * c.xi[a], v, e_b);
@@ -135,7 +136,7 @@ __device__ __forceinline__ void node_moments(const T (&fs)[Sets<MODEL>::S][25],
   }
   if (MODEL == kPolyatomic) {
 #pragma unroll
-    for (int i = 0; i < 25; ++i) e += double(fs[Sets<MODEL>::S - 1][i]);
+    for (int i = 0; i < Q1 * Q1; ++i) e += double(fs[Sets<MODEL>::S - 1][i]);
   }
   const double ux = jx / rho, uy = jy / rho;
   double theta = 1.0;
@@ -146,7 +147,7 @@ __device__ __forceinline__ void node_moments(const T (&fs)[Sets<MODEL>::S][25],
   m[3] = theta;
 }
 
-// Calls fn(i, f_eq_i) for the 25 velocities.  Factorised form of the
+// Calls fn(i, f_eq_i) for the Q1^2 velocities (i = a + Q1 b).  Factorised form of the
 // 4th-order Hermite equilibrium (Sec. II.A): with t = theta - 1 and
 // A_0 = 1, A_1 = u, A_2 = u^2 + t, A_3 = u^3 + 3ut, A_4 = u^4 + 6u^2 t + 3t^2
 // (the Hermite moments of a Gaussian of mean u and variance theta),
@@ -155,7 +156,7 @@ __device__ __forceinline__ void node_moments(const T (&fs)[Sets<MODEL>::S][25],
 // Evaluated per b as Z_k = A_k(u_x) sum_{m<=4-k} A_m(u_y) He_m(xi_b)/m! and
 // f_eq_{a+5b} = rho w_b sum_k (w_a He_k(xi_a)/k!) Z_k, the bracket a kernel
 // constant: five live values per b instead of 25 hoisted products.
-template <class Fn>
+template <int Q1 = 5, class Fn>
 __device__ __forceinline__ void for_each_equilibrium(double rho, double ux, double uy,
                                                      double theta, const StepConsts &c, Fn &&fn) {
   const double t = theta - 1.0;
@@ -165,7 +166,7 @@ __device__ __forceinline__ void for_each_equilibrium(double rho, double ux, doub
   const double Ay[5] = {1.0, uy, uy2 + t, uy * (uy2 + 3.0 * t),
                         uy2 * uy2 + 6.0 * uy2 * t + 3.0 * t * t};
 #pragma unroll
-  for (int b = 0; b < 5; ++b) {
+  for (int b = 0; b < Q1; ++b) {
     // Z[k] = A_k(u_x) sum_{m <= 4-k} A_m(u_y) He_m(xi_b)/m!
     double Z[5];
     double acc = 0.0;
@@ -176,11 +177,11 @@ __device__ __forceinline__ void for_each_equilibrium(double rho, double ux, doub
     }
     const double rw = rho * c.w[b];
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
+    for (int a = 0; a < Q1; ++a) {
       double s = c.whk[a][0] * Z[0];
 #pragma unroll
       for (int k = 1; k < 5; ++k) s = fma(c.whk[a][k], Z[k], s);
-      fn(a + 5 * b, rw * s);
+      fn(a + Q1 * b, rw * s);
     }
   }
 }
@@ -236,16 +237,18 @@ __device__ __forceinline__ double quasi_equilibrium(const double (&y)[4], int i,
 // has none (the D1Q5 rule integrates degree 7 exactly and the 4th-order
 // expansion carries the Gaussian's moments to order 4; the host refuses
 // Pr != 1 with a rule that does not), so Q^neq is the moment of f.
-template <typename T, int MODEL, bool PR>
-__device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][25],
+template <typename T, int MODEL, bool PR, int Q1 = 5>
+__device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
                                             const double (&m)[4], const StepConsts &c,
                                             T *__restrict__ fout, long long v) {
+  static_assert(!PR || Q1 == 5, "the quasi-equilibrium term needs a set exact to degree 7");
   constexpr int S = Sets<MODEL>::S;
+  constexpr int Q = Q1 * Q1;
   const long long N = c.n;
   const double om = c.omega;
   const double gf = c.gfac * m[3];
   double qf[4], qg[4];
-  if (PR) {
+  if constexpr (PR) {
     const double kq = c.omega - c.omega_pr;
     centred_third_moments<T>(fs[0], m[1], m[2], c, qf);
 #pragma unroll
@@ -261,7 +264,7 @@ __device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][25],
   const unsigned voff = unsigned(v) * unsigned(sizeof(T));
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   double yf[4], yg[4];
-  for_each_equilibrium(m[0], m[1], m[2], m[3], c, [&](int i, double feq) {
+  for_each_equilibrium<Q1>(m[0], m[1], m[2], m[3], c, [&](int i, double feq) {
     if (PR && i % 5 == 0) {  // row factors of velocity row b, made when the row starts
       const int b = i / 5;
 #pragma unroll
@@ -287,7 +290,7 @@ __device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][25],
       const double g = double(gr);
       double go = fma(om, gf * feq - g, g);
       if (PR) go += quasi_equilibrium(yg, i, c);
-      buffer_store<T>(T(go), make_rsrc(fout + (25 + i) * N, plane_bytes), voff, 0);
+      buffer_store<T>(T(go), make_rsrc(fout + (Q + i) * N, plane_bytes), voff, 0);
     }
   });
 }
@@ -299,12 +302,12 @@ __device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][25],
 // (Pr != 1).  PR is a kernel template parameter rather than a runtime
 // branch: holding both variants in one kernel costs the Pr = 1 kernels
 // registers and occupancy.
-template <typename T, int MODEL, bool PR = false>
-__device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][25],
+template <typename T, int MODEL, bool PR = false, int Q1 = 5>
+__device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
                                               const StepConsts &c, T *__restrict__ fout,
                                               long long v, int *__restrict__ flag) {
   double m[4];
-  node_moments<T, MODEL>(fs, c, m);
+  node_moments<T, MODEL, Q1>(fs, c, m);
   if (c.mom_out) {  // recorded for the adjoint (uniform branch)
     c.mom_out[v] = m[0];
     c.mom_out[c.n + v] = m[1];
@@ -314,7 +317,7 @@ __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][25],
   const bool ok = (m[0] > 0.0) && (m[3] > 0.0) && isfinite(m[0]) && isfinite(m[1]) &&
                   isfinite(m[2]) && isfinite(m[3]);
   if (!ok) atomicOr(flag, 1);
-  relax_store<T, MODEL, PR>(fs, m, c, fout, v);
+  relax_store<T, MODEL, PR, Q1>(fs, m, c, fout, v);
 }
 
 // Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
@@ -364,6 +367,24 @@ hipError_t dispatch_step(int fp32, int p, int model, F &&f) {
     return hipErrorInvalidValue;
   };
   return fp32 ? by_model.template operator()<float>() : by_model.template operator()<double>();
+}
+
+// The D2Q9 (three velocities per axis) variants: isothermal, Pr = 1 only
+// (the set carries the Gaussian's moments to degree 5, too few for the
+// energy equation); calls f.template operator()<T, P>().
+template <class F>
+hipError_t dispatch_q3(int fp32, int p, int model, F &&f) {
+  if (model != kIsothermal) return hipErrorInvalidValue;
+  auto by_p = [&]<typename T>() -> hipError_t {
+    switch (p) {
+      case 1: return f.template operator()<T, 1>();
+      case 2: return f.template operator()<T, 2>();
+      case 3: return f.template operator()<T, 3>();
+      case 4: return f.template operator()<T, 4>();
+    }
+    return hipErrorInvalidValue;
+  };
+  return fp32 ? by_p.template operator()<float>() : by_p.template operator()<double>();
 }
 
 }  // namespace sllbm

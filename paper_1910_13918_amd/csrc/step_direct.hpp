@@ -17,19 +17,20 @@ namespace sllbm {
 // (dwordx2..x4 runs); only lanes whose stencil wraps around a periodic seam
 // re-read their values one by one.
 // ---------------------------------------------------------------------------
-template <typename T, int P1, int S, bool SEAM>
+template <typename T, int P1, int S, bool SEAM, int Q1>
 __device__ __forceinline__ void direct_stream(const T *__restrict__ fin,
                                               const int32_t *__restrict__ xsrc,
                                               const T *__restrict__ ysrc_w,
                                               const int32_t *__restrict__ ysrc,
-                                              const unsigned (&x0)[5], const T (&wx)[5][P1],
+                                              const unsigned (&x0)[Q1], const T (&wx)[Q1][P1],
                                               int ix, int iy, const StepConsts &c,
-                                              T (&fs)[S][25]) {
+                                              T (&fs)[S][Q1 * Q1]) {
+  constexpr int Q = Q1 * Q1;
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   const unsigned row_bytes = unsigned(c.nx) * unsigned(sizeof(T));
 #pragma unroll
-  for (int b = 0; b < 5; ++b) {
+  for (int b = 0; b < Q1; ++b) {
     unsigned yo[P1];
     T wy[P1];
 #pragma unroll
@@ -38,8 +39,8 @@ __device__ __forceinline__ void direct_stream(const T *__restrict__ fin,
       wy[n] = ysrc_w[(b * P1 + n) * c.ny + iy];
     }
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      const int i = a + 5 * b;
+    for (int a = 0; a < Q1; ++a) {
+      const int i = a + Q1 * b;
       unsigned xs[P1];
       if constexpr (SEAM) {
 #pragma unroll
@@ -48,7 +49,7 @@ __device__ __forceinline__ void direct_stream(const T *__restrict__ fin,
       }
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const auto rs = make_rsrc(fin + (long long)(s * 25 + i) * N, plane_bytes);
+        const auto rs = make_rsrc(fin + (long long)(s * Q + i) * N, plane_bytes);
         T acc = T(0);
 #pragma unroll
         for (int n = 0; n < P1; ++n) {
@@ -73,7 +74,7 @@ __device__ __forceinline__ void direct_stream(const T *__restrict__ fin,
   }
 }
 
-template <typename T, int P, int MODEL, bool PR>
+template <typename T, int P, int MODEL, bool PR, int Q1 = 5>
 __global__ __launch_bounds__(256) void k_step_direct(const T *__restrict__ fin,
                                                      T *__restrict__ fout,
                                                      const int32_t *__restrict__ xsrc,
@@ -86,11 +87,11 @@ __global__ __launch_bounds__(256) void k_step_direct(const T *__restrict__ fin,
   const int ix = blockIdx.x * 64 + threadIdx.x;
   const int iy = blockIdx.y * 4 + threadIdx.y;
   if (ix >= c.nx || iy >= c.ny) return;
-  unsigned x0[5];  // byte offset of the first stencil column
+  unsigned x0[Q1];  // byte offset of the first stencil column
   bool seam = false;
-  T wx[5][P1];
+  T wx[Q1][P1];
 #pragma unroll
-  for (int a = 0; a < 5; ++a) {
+  for (int a = 0; a < Q1; ++a) {
     const int first = xsrc[(a * P1) * c.nx + ix];
     const int last = xsrc[(a * P1 + P) * c.nx + ix];
     x0[a] = unsigned(first) * unsigned(sizeof(T));
@@ -98,19 +99,33 @@ __global__ __launch_bounds__(256) void k_step_direct(const T *__restrict__ fin,
 #pragma unroll
     for (int m = 0; m < P1; ++m) wx[a][m] = xw[(a * P1 + m) * c.nx + ix];
   }
-  T fs[S][25];
+  T fs[S][Q1 * Q1];
   // one uniform branch: wavefronts touching a seam gather element by element
   if (__builtin_amdgcn_ballot_w64(seam))
-    direct_stream<T, P1, S, true>(fin, xsrc, yw, ysrc, x0, wx, ix, iy, c, fs);
+    direct_stream<T, P1, S, true, Q1>(fin, xsrc, yw, ysrc, x0, wx, ix, iy, c, fs);
   else
-    direct_stream<T, P1, S, false>(fin, xsrc, yw, ysrc, x0, wx, ix, iy, c, fs);
-  collide_store<T, MODEL, PR>(fs, c, fout, (long long)iy * c.nx + ix, flag);
+    direct_stream<T, P1, S, false, Q1>(fin, xsrc, yw, ysrc, x0, wx, ix, iy, c, fs);
+  collide_store<T, MODEL, PR, Q1>(fs, c, fout, (long long)iy * c.nx + ix, flag);
 }
 
 // PR: the Pr != 1 collision (thermal models only)
 template <bool PR>
 hipError_t launch_direct_family(int fp32, int model, const StepConsts &c, const DevTables &t,
                                 const void *fin, void *fout, int *flag, hipStream_t s) {
+  if (c.q1 == 3) {  // D2Q9: isothermal BGK
+    if constexpr (PR) {
+      return hipErrorInvalidValue;
+    } else {
+      return dispatch_q3(fp32, c.p, model, [&]<typename T, int P>() {
+        dim3 grid((c.nx + 63) / 64, (c.ny + 3) / 4);
+        k_step_direct<T, P, kIsothermal, false, 3><<<grid, dim3(64, 4), 0, s>>>(
+            static_cast<const T *>(fin), static_cast<T *>(fout), t.xsrc,
+            static_cast<const T *>(t.xw), t.ysrc, static_cast<const T *>(t.yw), c, flag);
+        return hipGetLastError();
+      });
+    }
+  }
+  if (c.q1 != 5) return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
     dim3 grid((c.nx + 63) / 64, (c.ny + 3) / 4);
     k_step_direct<T, P, MODEL, PR><<<grid, dim3(64, 4), 0, s>>>(

@@ -77,6 +77,7 @@ hipError_t launch_mfma_family(int fp32, int model, const StepConsts &c, const De
     return hipErrorInvalidValue;
   const int halo = tiled_halo(t.win_cols, c.nx, c.ny);
   if (halo == 0) return hipErrorInvalidValue;
+  if (c.q1 != 5) return hipErrorInvalidValue;  // D2Q25 only
   return dispatch_step<PR>(1, c.p, model, [&]<typename T, int P, int MODEL>() -> hipError_t {
     if constexpr (!std::is_same_v<T, float>) {
       return hipErrorInvalidValue;

@@ -45,7 +45,7 @@ __device__ __forceinline__ T records_interp(__amdgpu_buffer_rsrc_t rs, const uns
 template <typename T, int S>
 constexpr bool records_gather_ahead() { return sizeof(T) == 4 && S == 2; }
 
-template <typename T, int P, int MODEL, bool PR>
+template <typename T, int P, int MODEL, bool PR, int Q1 = 5>
 __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
                                                       T *__restrict__ fout,
                                                       const int32_t *__restrict__ cell,
@@ -54,6 +54,7 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
                                                       int *__restrict__ flag) {
   constexpr int S = Sets<MODEL>::S;
   constexpr int P1 = P + 1;
+  constexpr int Q = Q1 * Q1;
   // every other step may visit the blocks backwards (see StepConsts::reverse)
   const unsigned bid = c.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
   const long long v = (long long)bid * blockDim.x + threadIdx.x;
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   const unsigned voff = unsigned(v) * unsigned(sizeof(T));
-  const auto rcell = make_rsrc(cell, unsigned(N * 25 * (long long)sizeof(int32_t)));
+  const auto rcell = make_rsrc(cell, unsigned(N * Q * (long long)sizeof(int32_t)));
   const unsigned cell_off = unsigned(v) * unsigned(sizeof(int32_t));
   T rn[P1], den[P1];
 #pragma unroll
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
     rn[m] = T(c.rn[m]);
     den[m] = T(c.lden[m]);
   }
-  T fs[S][25];
+  T fs[S][Q];
   if constexpr (records_gather_ahead<T, S>()) {
     // f + g in float32: the next velocity's stencil values are loaded
     // before this one is interpolated (two values in flight per lane and
@@ -88,7 +89,9 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
     auto issue = [&](int i) {
       const int b = i & 1;
       const int rec = recq[i % (RD + 1)];
-      const int cx = rec & 0xffff, cy = rec >> 16;
+      // unsigned shift: cell rows up to 65535 (an arithmetic shift would make
+      // rows >= 32768 negative)
+      const int cx = rec & 0xffff, cy = int(unsigned(rec) >> 16);
       lagrange_eval<T, P1>(rq[i % (RD + 1)], rn, den, wxq[b]);
       lagrange_eval<T, P1>(sq[i % (RD + 1)], rn, den, wyq[b]);
       unsigned xo[P1], yo[P1];
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
       const bool any_seam = __builtin_amdgcn_ballot_w64(seam) != 0;
   #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const auto rs = make_rsrc(fin + (long long)(s * 25 + i) * N, plane_bytes);
+        const auto rs = make_rsrc(fin + (long long)(s * Q + i) * N, plane_bytes);
   #pragma unroll
         for (int n = 0; n < P1; ++n) {
           if (any_seam) {
@@ -122,9 +125,9 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
     for (int i = 0; i < RD; ++i) load_rec(i);
     issue(0);
   #pragma unroll
-    for (int i = 0; i < 25; ++i) {
-      if (i + RD < 25) load_rec(i + RD);
-      if (i + 1 < 25) issue(i + 1);
+    for (int i = 0; i < Q; ++i) {
+      if (i + RD < Q) load_rec(i + RD);
+      if (i + 1 < Q) issue(i + 1);
       const int b = i & 1;
   #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -157,10 +160,12 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
   #pragma unroll
     for (int i = 0; i < RD; ++i) load_rec(i);
   #pragma unroll
-    for (int i = 0; i < 25; ++i) {
-      if (i + RD < 25) load_rec(i + RD);
+    for (int i = 0; i < Q; ++i) {
+      if (i + RD < Q) load_rec(i + RD);
       const int rec = recq[i % (RD + 1)];
-      const int cx = rec & 0xffff, cy = rec >> 16;
+      // unsigned shift: cell rows up to 65535 (an arithmetic shift would make
+      // rows >= 32768 negative)
+      const int cx = rec & 0xffff, cy = int(unsigned(rec) >> 16);
       T wx[P1], wy[P1];
       lagrange_eval<T, P1>(rq[i % (RD + 1)], rn, den, wx);
       lagrange_eval<T, P1>(sq[i % (RD + 1)], rn, den, wy);
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
       const bool any_seam = __builtin_amdgcn_ballot_w64(seam) != 0;
   #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const auto rs = make_rsrc(fin + (long long)(s * 25 + i) * N, plane_bytes);
+        const auto rs = make_rsrc(fin + (long long)(s * Q + i) * N, plane_bytes);
         T acc = any_seam ? records_interp<T, P1, true>(rs, xo, yo, wx, wy)
                          : records_interp<T, P1, false>(rs, xo, yo, wx, wy);
         // keep the interpolation next to its loads
@@ -188,13 +193,27 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
       }
     }
   }
-  collide_store<T, MODEL, PR>(fs, c, fout, v, flag);
+  collide_store<T, MODEL, PR, Q1>(fs, c, fout, v, flag);
 }
 
 // PR: the Pr != 1 collision (thermal models only)
 template <bool PR>
 hipError_t launch_records_family(int fp32, int model, const StepConsts &c, const DevTables &t,
                                  const void *fin, void *fout, int *flag, hipStream_t s) {
+  if (c.q1 == 3) {  // D2Q9: isothermal BGK
+    if constexpr (PR) {
+      return hipErrorInvalidValue;
+    } else {
+      return dispatch_q3(fp32, c.p, model, [&]<typename T, int P>() {
+        const unsigned blocks = unsigned((c.n + 255) / 256);
+        k_step_records<T, P, kIsothermal, false, 3><<<blocks, 256, 0, s>>>(
+            static_cast<const T *>(fin), static_cast<T *>(fout), t.rec_cell,
+            static_cast<const T *>(t.rec_r), static_cast<const T *>(t.rec_s), c, flag);
+        return hipGetLastError();
+      });
+    }
+  }
+  if (c.q1 != 5) return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
     const unsigned blocks = unsigned((c.n + 255) / 256);
     k_step_records<T, P, MODEL, PR><<<blocks, 256, 0, s>>>(

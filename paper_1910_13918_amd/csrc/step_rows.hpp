@@ -69,7 +69,7 @@ constexpr int rows_lookahead() {
 // are the identity), so the phase b = 0 departs from the node itself and
 // loads the target row alone, the x-component a = 0 reads the node's own
 // column, and the rest velocity (0, 0) is the node's own value.
-template <typename T, int P1, int S, int D, int SYNC = 0>
+template <typename T, int P1, int S, int D, int SYNC = 0, int Q1 = 5>
 __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
                                             const int32_t *__restrict__ xrel,
                                             const T *__restrict__ xw,
@@ -77,20 +77,21 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
                                             const int32_t *__restrict__ ysrc,
                                             const T *__restrict__ yw, int TX, int ntx, int tx,
                                             int iy, int lane, const StepConsts &c, T *lrow,
-                                            T (&fs)[S][25]) {
-  constexpr int NQ = 25 * S;  // planes, in the order (b, s, a)
+                                            T (&fs)[S][Q1 * Q1]) {
+  constexpr int Q = Q1 * Q1;
+  constexpr int NQ = Q * S;  // planes, in the order (b, s, a)
   // lanes past the segment take the stencil of its last node (in the window)
   const int ixc = min(tx * TX + min(lane, TX - 1), c.nx - 1);
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   const unsigned row_bytes = unsigned(c.nx) * unsigned(sizeof(T));
-  int xr0[5];
-  T wx[5][P1];
-  unsigned col_off[5];
+  int xr0[Q1];
+  T wx[Q1][P1];
+  unsigned col_off[Q1];
   const int own0 = ixc - xwin[tx];  // the node's column in the a = 0 window
   const unsigned own_off = unsigned(ixc) * unsigned(sizeof(T));
 #pragma unroll
-  for (int a = 0; a < 5; ++a) {
+  for (int a = 0; a < Q1; ++a) {
     xr0[a] = xrel[(a * P1) * c.nx + ixc];
 #pragma unroll
     for (int m = 0; m < P1; ++m) wx[a][m] = xw[(a * P1 + m) * c.nx + ixc];
@@ -100,8 +101,8 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
   // source rows (byte offsets) and weights of the y-factor: wave-uniform,
   // fetched one phase (b) at a time, shortly before its first load, so that
   // only two phases' worth occupy scalar registers
-  unsigned yoff[5][P1];
-  T wy[5][P1];
+  unsigned yoff[Q1][P1];
+  T wy[Q1][P1];
   auto fetch_phase = [&](int b) {
     int z = 0;
     asm volatile("" : "+s"(z));  // keeps the scalar loads here
@@ -112,13 +113,13 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
     }
   };
   auto plane_of = [](int q) {  // q -> (b, s, a)
-    const int b = q / (5 * S), r = q % (5 * S);
-    return int3{b, r / 5, r % 5};
+    const int b = q / (Q1 * S), r = q % (Q1 * S);
+    return int3{b, r / Q1, r % Q1};
   };
   T pre[D + 1][P1];
   auto load = [&](int q, T (&dst)[P1]) {
     const int3 p = plane_of(q);
-    const auto rs = make_rsrc(fin + (long long)(p.y * 25 + p.z + 5 * p.x) * N, plane_bytes);
+    const auto rs = make_rsrc(fin + (long long)(p.y * Q + p.z + Q1 * p.x) * N, plane_bytes);
     if (p.x == 0) {  // identity y-factor (resolved at compile time)
       dst[0] = buffer_load<T>(rs, p.z == 0 ? own_off : col_off[p.z], unsigned(iy) * row_bytes);
 #pragma unroll
@@ -128,16 +129,16 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
       for (int m = 0; m < P1; ++m) dst[m] = buffer_load<T>(rs, col_off[p.z], yoff[p.x][m]);
     }
   };
-  constexpr int PH = 5 * S;  // planes per phase
+  constexpr int PH = Q1 * S;  // planes per phase
 #pragma unroll
-  for (int b = 1; b <= (D + 1) / PH && b < 5; ++b) fetch_phase(b);
+  for (int b = 1; b <= (D + 1) / PH && b < Q1; ++b) fetch_phase(b);
 #pragma unroll
   for (int q = 0; q < D && q < NQ; ++q) load(q, pre[q % (D + 1)]);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     if (SYNC > 0 && q > 0 && q % SYNC == 0) __builtin_amdgcn_s_barrier();
     // the phase whose first load comes two iterations from now
-    if ((q + D + 2) % PH == 0 && (q + D + 2) / PH < 5 && (q + D + 2) / PH > (D + 1) / PH)
+    if ((q + D + 2) % PH == 0 && (q + D + 2) / PH < Q1 && (q + D + 2) / PH > (D + 1) / PH)
       fetch_phase((q + D + 2) / PH);
     if (q + D < NQ) load(q + D, pre[(q + D) % (D + 1)]);
     const int3 p = plane_of(q);
@@ -162,7 +163,7 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
       }
     }
     asm volatile("" : "+v"(acc));  // keep the plane's arithmetic in its place
-    fs[p.y][p.z + 5 * p.x] = acc;
+    fs[p.y][p.z + Q1 * p.x] = acc;
   }
 }
 
@@ -180,7 +181,7 @@ constexpr int rows_sync_planes() { return S == 2 ? 5 : 0; }
 template <typename T, int S>
 constexpr int rows_min_waves() { return sizeof(T) == 4 && S == 1 ? 6 : 1; }
 
-template <typename T, int P, int MODEL, bool PR>
+template <typename T, int P, int MODEL, bool PR, int Q1 = 5>
 __global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
                              (rows_min_waves<T, Sets<MODEL>::S>())) void k_step_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
@@ -199,12 +200,12 @@ __global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
   // barriers) and store nothing
   const int iy_t = ty * R + wv;
   const int iy = min(iy_t, c.ny - 1);
-  T fs[S][25];
-  rows_stream<T, P + 1, S, rows_lookahead<T, P + 1, S, PR>(), rows_sync_planes<P + 1, S>()>(
+  T fs[S][Q1 * Q1];
+  rows_stream<T, P + 1, S, rows_lookahead<T, P + 1, S, PR>(), rows_sync_planes<P + 1, S>(), Q1>(
       fin, xrel, xw, xwin, ysrc, yw, TX, ntx, tx, iy, lane, c, &rows_lds[wv][0][0], fs);
   const int ix = tx * TX + lane;
   if (ix < c.nx && lane < TX && iy_t < c.ny)
-    collide_store<T, MODEL, PR>(fs, c, fout, (long long)iy * c.nx + ix, flag);
+    collide_store<T, MODEL, PR, Q1>(fs, c, fout, (long long)iy * c.nx + ix, flag);
 }
 
 // PR: the Pr != 1 collision (thermal models only)
@@ -214,6 +215,24 @@ hipError_t launch_rows_family(int fp32, int model, const StepConsts &c, const De
   if (t.rows_tx < kRowsMinCols || t.rows_tx > 64 || t.rows_xrel == nullptr ||
       t.rows_xwin == nullptr || !(t.ident_y & t.ident_x & 1))
     return hipErrorInvalidValue;
+  if (c.q1 == 3) {  // D2Q9: isothermal BGK
+    if constexpr (PR) {
+      return hipErrorInvalidValue;
+    } else {
+      return dispatch_q3(fp32, c.p, model, [&]<typename T, int P>() {
+        constexpr int R = rows_tile_rows<T, 1>();
+        const int ntx = (c.nx + t.rows_tx - 1) / t.rows_tx;
+        const int nty = (c.ny + R - 1) / R;
+        const int grid = ((ntx * nty + 7) / 8) * 8;
+        k_step_rows<T, P, kIsothermal, false, 3><<<grid, dim3(64, R), 0, s>>>(
+            static_cast<const T *>(fin), static_cast<T *>(fout), t.rows_xrel,
+            static_cast<const T *>(t.xw), t.rows_xwin, t.ysrc, static_cast<const T *>(t.yw),
+            t.rows_tx, ntx, nty, c, flag);
+        return hipGetLastError();
+      });
+    }
+  }
+  if (c.q1 != 5) return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
     constexpr int R = rows_tile_rows<T, Sets<MODEL>::S>();
     const int ntx = (c.nx + t.rows_tx - 1) / t.rows_tx;

@@ -70,6 +70,7 @@ hipError_t launch_tiled_family(int fp32, int model, const StepConsts &c, const D
   if (t.tile_rows != kTileRowsTY || t.yrel == nullptr || t.xrel == nullptr)
     return hipErrorInvalidValue;
   if (!tiled_window_ok(t.win_rows, t.win_cols)) return hipErrorInvalidValue;
+  if (c.q1 != 5) return hipErrorInvalidValue;  // D2Q25 only
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
     const T *in = static_cast<const T *>(fin);
     T *out = static_cast<T *>(fout);

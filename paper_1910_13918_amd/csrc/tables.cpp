@@ -18,12 +18,25 @@ VelocitySet default_velocity_set() {
   const double xi[kQ1] = {0.0, c1, c2, -c1, -c2};
   const double w[kQ1] = {8.0 / 15.0, w1, w2, w1, w2};
   for (int a = 0; a < kQ1; ++a) { vs.xi[a] = xi[a]; vs.w[a] = w[a]; }
+  vs.q1 = kQ1;
+  fill_hermite_constants(vs);
+  return vs;
+}
+
+VelocitySet d1q3_velocity_set() {
+  // roots of He_3 = x^3 - 3x and their Gauss-Hermite weights
+  VelocitySet vs{};
+  vs.q1 = 3;
+  const double r3 = std::sqrt(3.0);
+  const double xi[3] = {0.0, r3, -r3};
+  const double w[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
+  for (int a = 0; a < 3; ++a) { vs.xi[a] = xi[a]; vs.w[a] = w[a]; }
   fill_hermite_constants(vs);
   return vs;
 }
 
 void fill_hermite_constants(VelocitySet &vs) {
-  for (int a = 0; a < kQ1; ++a) {
+  for (int a = 0; a < vs.q1; ++a) {
     const double x = vs.xi[a], x2 = x * x;
     vs.hk[a][0] = 1.0;
     vs.hk[a][1] = x;
@@ -37,7 +50,7 @@ bool gaussian_exact_to_degree(const VelocitySet &vs, int degree) {
   double exact = 1.0;  // (n-1)!! for even n
   for (int n = 0; n <= degree; ++n) {
     double sum = 0.0, mag = 0.0;
-    for (int a = 0; a < kQ1; ++a) {
+    for (int a = 0; a < vs.q1; ++a) {
       const double t = vs.w[a] * std::pow(vs.xi[a], n);
       sum += t;
       mag += std::fabs(t);

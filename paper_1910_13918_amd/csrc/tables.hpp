@@ -12,12 +12,14 @@
 namespace sllbm {
 
 constexpr int kMaxOrder = 4;
-constexpr int kQ1 = 5;           // 1-D velocities of the tensor-product set
-constexpr int kQ = kQ1 * kQ1;    // 2-D velocities
+constexpr int kQ1 = 5;           // most 1-D velocities of a tensor-product set
+constexpr int kQ = kQ1 * kQ1;    // most 2-D velocities
 constexpr int kDim = 2;
 
-// 1-D velocity set (Sec. II.B, Table I) and per-velocity Hermite constants.
+// 1-D velocity set (Sec. II.B, Table I) and per-velocity Hermite constants;
+// q1 = 5 (D1Q5, whose product is D2Q25) or 3 (D1Q3: D2Q9, Sec. III.A).
 struct VelocitySet {
+  int q1 = kQ1;
   double xi[kQ1];
   double w[kQ1];
   // hk[a][k] = He_k(xi_a) / k!  (probabilists' Hermite polynomials, k <= 4)
@@ -25,6 +27,8 @@ struct VelocitySet {
 };
 
 VelocitySet default_velocity_set();
+// Three-point Gauss-Hermite rule: 0, +sqrt(3), -sqrt(3); 2/3, 1/6, 1/6.
+VelocitySet d1q3_velocity_set();
 void fill_hermite_constants(VelocitySet &vs);
 
 // True when the 1-D rule reproduces the moments of the unit Gaussian,

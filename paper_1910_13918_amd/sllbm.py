@@ -18,8 +18,9 @@ except ImportError:  # the C ABI itself does not need torch
     pass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# SLLBM_LIBRARY may name another build of the same library (e.g. a tuning build)
-LIB_PATH = os.environ.get("SLLBM_LIBRARY") or os.path.join(_HERE, "libsllbm.so")
+# always the library built in this package (no override: every caller runs
+# the product build)
+LIB_PATH = os.path.join(_HERE, "libsllbm.so")
 
 OK = 0
 E_ARG = -1

@@ -63,6 +63,7 @@ class Workload:
     meta: dict = field(default_factory=dict)
     Pr: float = 1.0       # Prandtl number (Sec. II.C-D)
     vertices: tuple = None  # (vx, vy) [ncy + 1][ncx + 1] of a curvilinear mesh, else None
+    q1: int = 5           # velocities per axis of the tensor-product set (5: D2Q25, 3: D2Q9)
 
     @property
     def ncx(self):
@@ -108,6 +109,41 @@ def tgv(ncells=8, p=2, U0=0.1, Re=100.0, steps=200, cfl=0.5, model="isothermal",
     e = uniform_edges(ncells, 0.0, L)
     return Workload(name or f"tgv_{ncells}x{ncells}_p{p}", e, e.copy(), p, True, True, model,
                     1.4, nu, dt, n, fields, True, {"U0": U0, "Re": Re})
+
+
+# ------------------------------------------ Taylor-Green on a moving frame (Fig. 3)
+def tgv_moving(ncells=4, p=4, ma_h=0.0, q1=5, ma_v=0.01, Re=10.0, name=None):
+    """The Taylor-Green comparison of Sec. III.A (D2Q9 against D2Q25, Fig. 3):
+    vortex Mach number 0.01 (U0 = 0.01 with c_s = 1), Re = U0 2 pi / nu = 10,
+    a uniform horizontal velocity u_h = ma_h, and the paper's time step,
+    dt = 0.0008 in the paper's time unit (vortex speed 1, length 2 pi) at 4
+    cells of order 4 per direction and halved with the cell size, i.e.
+    dt = 0.0008 / U0 * 4 / ncells in code units.  The end time is the
+    paper's t = 1.83 (vortex speed decayed to 0.1 U0), t = 1.83 / U0 in code
+    units, rounded to whole steps.  Isothermal; the exact solution is the
+    decaying vortex advected by u_h:
+    u = u_h + U0 e^(-2 nu t) sin(x - u_h t) cos y, v = -U0 e^(-2 nu t) cos(x - u_h t) sin y."""
+    L = 2.0 * np.pi
+    U0 = ma_v
+    nu = U0 * L / Re
+    dt = 0.0008 / U0 * 4.0 / ncells
+    steps = int(round(1.83 / U0 / dt))
+
+    def fields(x, y):
+        ux = ma_h + U0 * np.sin(x) * np.cos(y)
+        uy = -U0 * np.cos(x) * np.sin(y)
+        rho = 1.0 + 0.25 * U0 * U0 * (np.cos(2 * x) + np.cos(2 * y))
+        return rho, ux, uy, np.ones_like(x)
+
+    def exact(x, y, t):
+        d = U0 * np.exp(-2.0 * nu * t)
+        return ma_h + d * np.sin(x - ma_h * t) * np.cos(y), -d * np.cos(x - ma_h * t) * np.sin(y)
+
+    e = uniform_edges(ncells, 0.0, L)
+    wl = Workload(name or f"tgv_moving_{ncells}x{ncells}_p{p}_mah{ma_h}_q{q1 * q1}", e, e.copy(),
+                  p, True, True, "isothermal", 1.4, nu, dt, steps, fields, True,
+                  {"U0": U0, "Re": Re, "ma_h": ma_h, "exact": exact}, q1=q1)
+    return wl
 
 
 # ------------------------------------------------------- Taylor-Green, curved cells

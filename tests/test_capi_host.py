@@ -186,7 +186,8 @@ def test_velocity_set_validation():
     try:
         xi = np.zeros(5)
         w = np.ones(5)
-        assert _code(C.sllbm_set_velocity_set, ctx, 3, xi.ctypes.data, w.ctypes.data) == C.E_UNSUPPORTED
+        assert _code(C.sllbm_set_velocity_set, ctx, 4, xi.ctypes.data, w.ctypes.data) == C.E_UNSUPPORTED
+        assert _code(C.sllbm_set_velocity_set, ctx, 7, None, None) == C.E_UNSUPPORTED
         w[2] = -1.0
         assert _code(C.sllbm_set_velocity_set, ctx, 5, xi.ctypes.data, w.ctypes.data) == C.E_ARG
         assert _code(C.sllbm_set_velocity_set, ctx, 5, xi.ctypes.data, None) == C.E_ARG
@@ -315,5 +316,42 @@ def test_equidistant_nodes_tables():
         y = np.zeros(g.ny)
         C.sllbm_node_coords(ctx, x.ctypes.data, y.ctypes.data)
         np.testing.assert_allclose(x, g.ax.node_coords(), atol=1e-14)
+    finally:
+        C.sllbm_destroy(ctx)
+
+
+def test_records_pack_cell_rows_above_32767():
+    """Departure records of a 4 x 40000-cell strip: the packed cell
+    (cx | cy << 16) read as an unsigned 32-bit word gives back the oracle's
+    departure cell for rows up to 39999 (a signed read would turn rows of
+    32768 and more negative)."""
+    h = 1.0 / 4000
+    ctx = _ctx()
+    try:
+        C.sllbm_set_order(ctx, 1, C.NODES_GLC)
+        C.sllbm_init_grid_uniform(ctx, 4, 40000, 0.0, 4 * h, 0.0, 40000 * h, C.PERIODIC,
+                                  C.ZERO_GRADIENT)
+        dt = 0.5 * h / W.XI_MAX
+        C.sllbm_set_physics(ctx, dt, 1e-3, 1.4, 1.0, C.MONATOMIC)
+        nx, ny = C.sllbm_num_nodes(ctx)
+        g = Grid(W.uniform_edges(4, 0.0, 4 * h), W.uniform_edges(40000, 0.0, 40000 * h), 1,
+                 True, False)
+        sim = Sim(g, dt, 1e-3, "monatomic")
+        nodes = np.arange(nx * (ny - 700), nx * ny)  # rows 39301 .. 40000
+        n = nx * ny
+        for i in (0, 6, 13, 24):  # the rest velocity and three others
+            cell = np.zeros(n, dtype=np.int32)
+            r = np.zeros(n)
+            s = np.zeros(n)
+            C.sllbm_departure_records(ctx, i, cell.ctypes.data, r.ctypes.data, s.ctypes.data)
+            u = cell.view(np.uint32)[nodes]
+            xd = g.ax.apply_boundary(sim.X[nodes] - dt * sim.xi[i, 0])
+            yd = g.ay.apply_boundary(sim.Y[nodes] - dt * sim.xi[i, 1])
+            cx, _ = g.ax.locate(xd)
+            cy, ry = g.ay.locate(yd)
+            assert (cell[nodes] < 0).any()  # rows >= 32768 fill the sign bit
+            np.testing.assert_array_equal(u >> 16, cy)
+            np.testing.assert_array_equal(u & 0xFFFF, cx)
+            np.testing.assert_allclose(s[nodes], ry, atol=1e-9)
     finally:
         C.sllbm_destroy(ctx)
