@@ -232,28 +232,73 @@ def adjoint_cost(precision="fp32", every=50, reps=3):
             "checkpoint_every": every, "forward_ms": f, "backward_ms": b, "ratio": b / f}
 
 
-def cpu_baseline(wl, solver_state, sample_nodes=250000, seed=0):
-    """Time the FP64 oracle on a bounded sample of the same workload: one step
-    at `sample_nodes` seeded nodes, from the same initial state.  Also returns
-    the GPU's error against it at those nodes."""
-    import numpy as np
+# ---- CPU baseline: the FP64 oracle on the host's cores ---------------------------
+_ORACLE = {}
 
+
+def _oracle_setup(wname):
+    """Oracle simulation and initial state of a bench workload (in a worker)."""
     from oracle.grid import Grid
     from oracle.sllbm import Sim
+    wl, _ = workload(wname)
     g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
     sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, Pr=wl.Pr)
     X, Y = g.coords()
-    F0 = sim.init(*wl.fields(X, Y))
+    _ORACLE["sim"] = sim
+    _ORACLE["F0"] = sim.init(*wl.fields(X, Y))
+
+
+def _oracle_chunk(nodes):
+    """One oracle step at `nodes` (worker side); returns the chunk's size."""
+    _ORACLE["sim"].step(_ORACLE["F0"], nodes)
+    return len(nodes)
+
+
+def cpu_baseline(wname, solver_state, sample_nodes=250000, seed=0):
+    """Time the FP64 oracle on the host: one full step of the workload (every
+    node) split over worker processes on all host cores the box grants (at
+    most 16), and one step at `sample_nodes` seeded nodes on one core, from
+    the same initial state as the GPU.  The single-core sample also gives the
+    GPU's one-step error at those nodes."""
+    import multiprocessing as mp
+
+    import numpy as np
+    _oracle_setup(wname)
+    sim, F0 = _ORACLE["sim"], _ORACLE["F0"]
+    n_all = sim.grid.nnodes
     rng = np.random.default_rng(seed)
-    nodes = np.sort(rng.choice(g.nnodes, size=min(sample_nodes, g.nnodes), replace=False))
+    nodes = np.sort(rng.choice(n_all, size=min(sample_nodes, n_all), replace=False))
     t0 = time.perf_counter()
     F1 = sim.step(F0, nodes)
-    dt = time.perf_counter() - t0
-    G1 = solver_state[:, :, nodes]
-    err = float(np.abs(G1 - F1).max() / np.abs(F1).max())
-    return {"value": len(nodes) / dt, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 oracle step at {len(nodes)} seeded nodes of the same workload "
-                      f"({dt:.1f} s, numpy, single thread)"}, err
+    t1 = time.perf_counter() - t0
+    err = float(np.abs(solver_state[:, :, nodes] - F1).max() / np.abs(F1).max())
+    host_cores = os.cpu_count() or 1
+    workers = max(1, min(host_cores, 16))
+    # one thread per worker process (set before the workers import numpy)
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        with mp.get_context("spawn").Pool(workers, initializer=_oracle_setup,
+                                          initargs=(wname,)) as pool:
+            pool.map(_oracle_chunk, [np.arange(1)] * workers)  # every worker set up
+            chunks = np.array_split(np.arange(n_all), 8 * workers)
+            t0 = time.perf_counter()
+            done = sum(pool.map(_oracle_chunk, chunks, chunksize=1))
+            tw = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    assert done == n_all
+    return {"value": n_all / tw, "unit": "node-updates/s", "cores": workers, "kind": "oracle",
+            "host_cores": host_cores,
+            "sample": f"one FP64 oracle step at all {n_all} nodes of the same workload over "
+                      f"{workers} worker processes ({tw:.1f} s; numpy, one thread each)",
+            "single_core": {"value": len(nodes) / t1, "unit": "node-updates/s", "cores": 1,
+                            "sample": f"one step at {len(nodes)} seeded nodes ({t1:.1f} s)"}}, err
 
 
 def main():
@@ -380,7 +425,7 @@ def main():
         s1.step(1)
         G1 = s1.populations().astype(np.float64)
         s1.close()
-        cb, err = cpu_baseline(wl, G1)
+        cb, err = cpu_baseline(args.workload, G1)
         out["cpu_baseline"] = cb
         out["accuracy"] = {"one_step_max_rel_err_vs_fp64_oracle": err,
                            "sample_nodes": 250000}
