@@ -285,6 +285,21 @@ int sllbm_moments(sllbm_ctx *ctx, double *rho, double *ux, double *uy, double *T
  * reduction; synchronises. */
 int sllbm_mass(sllbm_ctx *ctx, double *mass);
 
+/* sllbm_mass for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same reduction, written to mass_dev (a caller-owned float64 on the
+ * context's device), asynchronously on the bound stream; nothing is
+ * allocated and nothing synchronises.  The per-block partial sums go to a
+ * fixed device array of 2^17 float64 (1 MiB) that the library holds on each
+ * GPU it runs on until the process ends; it covers every grid the library
+ * accepts (up to 2^25 nodes; SLLBM_E_ARG beyond).  Every context on a GPU
+ * shares that array: calls that overlap on one GPU (other streams, other
+ * threads) race on it, and each call overwrites what the last one left.
+ * Needs initialised populations (SLLBM_E_STATE otherwise, as the device
+ * tables are built by sllbm_init_macro / sllbm_set_populations);
+ * SLLBM_E_UNSUPPORTED on a curvilinear mesh, as sllbm_mass. */
+int sllbm_mass_noalloc(sllbm_ctx *ctx, double *mass_dev);
+
 /* Copy the current populations out / in ([S][Q][ny][nx], population type).
  * set_populations makes the given state current (step counter unchanged,
  * stability flag cleared). */

@@ -1145,6 +1145,30 @@ int sllbm_mass(sllbm_ctx *c, double *mass) {
   return SLLBM_OK;
 }
 
+int sllbm_mass_noalloc(sllbm_ctx *c, double *mass_dev) {
+  if (!c || !mass_dev) return SLLBM_E_ARG;
+  if (c->curvi)
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "node masses of a curvilinear mesh are not a product of axis weights");
+  // no set-up work here: the device tables must already exist (they are
+  // built by init_macro / set_populations and stay valid until the set-up
+  // changes, which is refused once initialised)
+  if (!c->initialised || c->dev_dirty || !c->mxd.ptr || !c->myd.ptr)
+    return fail(c, SLLBM_E_STATE,
+                "populations not initialised (sllbm_init_macro or sllbm_set_populations first)");
+  const StepConsts k = make_consts(c);
+  if (mass_blocks(k) > kScratchDoubles)
+    return fail(c, SLLBM_E_ARG, "grid larger than the fixed scratch (" +
+                                    std::to_string(int64_t(kScratchDoubles) * 256) + " nodes)");
+  HIP_TRY(c, hipSetDevice(c->device));
+  double *part = nullptr;
+  HIP_TRY(c, scratch_buffer(c->device, &part));
+  HIP_TRY(c, launch_moments(c->fp32, c->model, k, make_tables(c), c->pop[c->cur], nullptr,
+                            nullptr, nullptr, nullptr, part, c->stream));
+  HIP_TRY(c, launch_sum(part, mass_blocks(k), mass_dev, c->stream));
+  return SLLBM_OK;
+}
+
 int sllbm_get_populations(sllbm_ctx *c, void *dst, int on_device) {
   if (!c || !dst) return SLLBM_E_ARG;
   if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");

@@ -7,10 +7,38 @@
 // and relaxation are evaluated in float64 for both population types.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "launch.hpp"
 #include "step_common.hpp"
 
 namespace sllbm {
+
+// ---------------------------------------------------------------------------
+// fixed device scratch for callers that cannot allocate: per-block partial
+// sums of the mass reduction (one float64 per 256 nodes, so 2^17 entries
+// cover the library's largest grid of 2^25 nodes).  Every GPU the library
+// runs on holds one copy for the life of the process.  In host code the
+// array's name is not a device address: its address on each device comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t scratch_buffer(int device, double **ptr) {
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    // the caller has made `device` current
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<double *>(p);
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // initialisation: f = f_eq(rho, u, theta), g = g_eq

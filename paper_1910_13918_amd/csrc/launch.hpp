@@ -108,6 +108,13 @@ hipError_t launch_nu_term(int fp32, int model, const StepConsts &c, const void *
                           const void *f, const double *mom, double *partial, double *scalar,
                           double scale, double *acc, hipStream_t s);
 
+// Fixed per-device scratch of kScratchDoubles float64 (kernels.hip) for the
+// entry points that allocate nothing; *ptr receives its address on `device`,
+// which must be the current device.  Shared by every call on that device.
+constexpr int kScratchDoubles = 1 << 17;  // mass partials of up to 2^25 nodes
+constexpr int kMaxDevices = 64;
+hipError_t scratch_buffer(int device, double **ptr);
+
 // flag = 0 (a kernel, not a memset, so the call can live inside a captured graph)
 hipError_t launch_clear_flag(int *flag, hipStream_t s);
 

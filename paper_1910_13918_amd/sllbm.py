@@ -93,6 +93,7 @@ _SIGS = {
     "sllbm_status_flags": ([_vp, _ip, _i64p], _c),
     "sllbm_moments": ([_vp, _vp, _vp, _vp, _vp, _c], _c),
     "sllbm_mass": ([_vp, _dp], _c),
+    "sllbm_mass_noalloc": ([_vp, _vp], _c),
     "sllbm_get_populations": ([_vp, _vp, _c], _c),
     "sllbm_set_populations": ([_vp, _vp, _c], _c),
     "sllbm_step_record": ([_vp, _i64, _vp], _c),
@@ -250,6 +251,10 @@ def sllbm_mass(ctx):
     m = ctypes.c_double()
     check(ctx, lib.sllbm_mass(ctx, ctypes.byref(m)))
     return m.value
+
+
+def sllbm_mass_noalloc(ctx, mass_dev_ptr):
+    return check(ctx, lib.sllbm_mass_noalloc(ctx, mass_dev_ptr))
 
 
 def sllbm_get_populations(ctx, dst_ptr, on_device):
