@@ -191,6 +191,66 @@ def aux_kernels(s, reps=20):
     return res
 
 
+def mfma_bf16_flops_per_node_update(wl):
+    """Matrix-core flops of the bfloat16 x-pass per node update: per tile of
+    64 x 4 nodes and x-component, 4 blocks of one 16 x 16 x 32 product, 5
+    components per phase, 5 phases."""
+    return 5 * 5 * 4 * (16 * 16 * 32 * 2) / (64 * 4)
+
+
+def _moment_errors(got, ref):
+    """max and L2 relative errors of rho, u (vector) and theta."""
+    import numpy as np
+    d_u = np.hypot(got[1] - ref[1], got[2] - ref[2])
+    u_ref = np.hypot(ref[1], ref[2])
+    out = {}
+    for name, d, r in (("rho", got[0] - ref[0], ref[0]), ("u", d_u, u_ref),
+                       ("T", got[3] - ref[3], ref[3])):
+        out[name + "_max_rel"] = float(np.abs(d).max() / np.abs(r).max())
+        out[name + "_l2_rel"] = float(np.linalg.norm(d) / np.linalg.norm(r))
+    return out
+
+
+def bf16_experiment(wl, steps, warmup, fp64_run):
+    """The bfloat16 x-pass (SLLBM_BF16X) on the benchmark grid: throughput,
+    HBM fraction and matrix-core rate, its moments after the same steps
+    against the FP64 GPU run, and the seeded Riemann problem on 64 x 64 cells
+    to t = 0.25 against the FP64 oracle's moments (committed golden written by
+    the oracle alone).  Errors are reported, not bounded."""
+    import numpy as np
+
+    from paper_1910_13918_amd import workloads as W
+    from paper_1910_13918_amd.solver import Solver
+    sb, msb, unstable = timed(wl, "bf16x", "auto", steps, warmup)
+    v = sb.n * steps / (msb * 1e-3)
+    bpn = bytes_per_node_update(wl, "fp32", "mfma")
+    flops = v * mfma_bf16_flops_per_node_update(wl)
+    res = {"path": sb.resolved_path(), "value": v, "unit": "node-updates/s",
+           "ms_per_step": msb / steps, "achieved_gbs": v * bpn / 1e9,
+           "frac": v * bpn / 1e9 / HBM_PEAK_GBS, "mfma_tflops": flops / 1e12,
+           "mfma_frac_of_bf16_dense_peak": flops / 2.5e15, "unstable_flag": unstable}
+    if fp64_run is not None:
+        m64, dm64 = fp64_run
+        res["vs_fp64_gpu_after_steps"] = dict(_moment_errors(sb.moments(), m64),
+                                             steps=steps + warmup,
+                                             mass_rel_change=sb.mass() / sb.mass0 - 1.0,
+                                             mass_rel_change_fp64=dm64)
+    sb.close()
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "riemann64_reference.json")))
+    nodes = np.array(ref["nodes"])
+    want = [np.array(ref[k]) for k in ("rho", "ux", "uy", "T")]
+    w64 = W.riemann(64, 2)
+    s = Solver.from_workload(w64, precision="bf16x")
+    s.init_from_workload()
+    m0 = s.mass()
+    s.step(w64.steps)
+    got = [a[nodes] for a in s.moments()]
+    res["riemann64_t0.25_vs_fp64_oracle"] = dict(_moment_errors(got, want), steps=w64.steps,
+                                                 mass_rel_change=s.mass() / m0 - 1.0)
+    s.close()
+    return res
+
+
 def adjoint_cost(precision="fp32", every=50, reps=3):
     """Forward and backward time of the checkpointed rollout on the adjoint
     workload (Taylor-Green, 128 x 128 cells, p = 4, 500 steps, loss = kinetic
@@ -388,7 +448,10 @@ def main():
                            "mass_rel_change_fp32": s.mass() / s.mass0 - 1.0,
                            "mass_rel_change_fp64": s64.mass() / s64.mass0 - 1.0,
                            "mass_fp32_vs_fp64_rel": s.mass() / s64.mass() - 1.0}}
+        s64_moments = (m64, s64.mass() / s64.mass0 - 1.0)
         s64.close()
+    else:
+        s64_moments = None
     # initialisation, moments and mass on the same grid (this re-initialises s)
     out["aux_kernels"] = aux_kernels(s)
     if not args.no_mfma and args.precision == "fp32" and args.workload == "riemann":
@@ -400,6 +463,8 @@ def main():
                               "achieved_gbs": v * bpn / 1e9, "frac": v * bpn / 1e9 / HBM_PEAK_GBS,
                               "mfma_tflops": v * mfma_flops_per_node_update(wl) / 1e12}
         sm.close()
+    if not args.no_mfma and args.precision == "fp32" and args.workload == "riemann":
+        out["bf16_experiment"] = bf16_experiment(wl, args.steps, args.warmup, s64_moments)
     if not args.no_mfma and args.workload == "riemann" and args.path == "auto":
         # the other LDS kernel family on the same workload (AUTO picks by measured speed)
         other = "tiled" if s_path == "rows" else "rows"

@@ -68,9 +68,18 @@ typedef enum {
 } sllbm_status;
 
 typedef enum {
-  SLLBM_FP64 = 0, /* float64 populations, interpolation, moments, equilibrium */
-  SLLBM_FP32 = 1  /* float32 populations and interpolation; float64 moments,
-                     temperature, equilibrium and relaxation */
+  SLLBM_FP64 = 0,  /* float64 populations, interpolation, moments, equilibrium */
+  SLLBM_FP32 = 1,  /* float32 populations and interpolation; float64 moments,
+                      temperature, equilibrium and relaxation */
+  SLLBM_BF16X = 3  /* experiment: as SLLBM_FP32 (float32 populations in
+                      memory, same layout), with the x-pass of the
+                      interpolation (eq. (17)) on the matrix cores taking
+                      bfloat16 Lagrange weights and bfloat16 staged values
+                      (round to nearest even) with float32 accumulation
+                      (v_mfma_f32_16x16x32_bf16); runs on SLLBM_PATH_MFMA
+                      only (AUTO resolves to it; other paths and the adjoint
+                      return SLLBM_E_UNSUPPORTED).  Its error is a measured
+                      result, not a bound. */
 } sllbm_precision;
 
 typedef enum { SLLBM_PERIODIC = 0, SLLBM_ZERO_GRADIENT = 1 } sllbm_bc;
@@ -99,8 +108,9 @@ typedef enum {
                              16 x 16 x 4 float32 matrix-core products (float32
                              populations, at most 16 population-set x window
                              rows, departures within one node spacing of their
-                             cell; SLLBM_E_UNSUPPORTED otherwise); never chosen
-                             by AUTO */
+                             cell; SLLBM_E_UNSUPPORTED otherwise); chosen by
+                             AUTO only for SLLBM_BF16X, whose x-pass is one
+                             16 x 16 x 32 bfloat16 product per block */
   SLLBM_PATH_ROWS = 5     /* one wavefront per row segment of up to 64 nodes:
                              the p+1 source rows of each velocity combined in
                              registers (y-factor), the x-factor from a per-

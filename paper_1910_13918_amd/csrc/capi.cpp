@@ -37,6 +37,7 @@ struct DeviceBuf {
 struct sllbm_ctx {
   int device = 0;
   int fp32 = 0;
+  int bf16x = 0;  // SLLBM_BF16X: float32 populations, bfloat16 matrix-core x-pass
   std::string err;
   hipStream_t stream = nullptr;
 
@@ -158,7 +159,8 @@ int build_windows(const AxisTable *t, int nq1, int n, int tile, std::vector<int3
 // ks = (16 + 2p + 3) / 4 (as in the kernel).
 bool mfma_blocks_fit(const sllbm_ctx *c) {
   const int P1 = c->p + 1, n = c->ax.n;
-  const int K = 4 * ((16 + 2 * c->p + 3) / 4);
+  // float32: k-steps of 4 columns; bfloat16: one product of 32 columns
+  const int K = c->bf16x ? 32 : 4 * ((16 + 2 * c->p + 3) / 4);
   for (int a = 0; a < q1(c); ++a)
     for (int n0 = 0; n0 < n; n0 += 16) {
       const int32_t base = c->xrel[(size_t(a) * P1) * n + n0];
@@ -249,6 +251,7 @@ bool rows_preferred(const sllbm_ctx *c) { return c->rows_tx >= 48; }
 // (The 3-velocity set has row-segment, direct and records kernels only:
 // tiled_fits is false for it.)
 int effective_path(const sllbm_ctx *c) {
+  if (c->bf16x && c->path == SLLBM_PATH_AUTO) return kPathMfma;  // the experiment's only kernel
   if (c->path != SLLBM_PATH_AUTO) return c->path;
   if (c->curvi) return kPathRecords;  // the only gather that takes arbitrary cells
   if (rows_preferred(c) || (!tiled_fits(c) && c->rows_tx >= kRowsMinCols)) return kPathRows;
@@ -383,6 +386,7 @@ StepConsts make_consts(const sllbm_ctx *c) {
   k.gfac = 2.0 * cv - D;
   k.inv_2cv = 1.0 / (2.0 * cv);
   k.q1 = q1(c);
+  k.bf16x = c->bf16x;
   for (int a = 0; a < q1(c); ++a) {
     k.xi[a] = c->vs.xi[a];
     k.w[a] = c->vs.w[a];
@@ -499,6 +503,8 @@ int prepare_adjoint(sllbm_ctx *c) {
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers axis-product grids only");
   if (q1(c) != kQ1)
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers the 5-velocity set (D2Q25) only");
+  if (c->bf16x)
+    return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint differentiates the float32/float64 step");
   if (!c->adj_dirty) return SLLBM_OK;
   int taps = 0;
   for (int a = 0; a < kQ1; ++a) {
@@ -566,11 +572,13 @@ int sllbm_create(sllbm_ctx **out, int hip_device, int precision) {
   if (!out) return SLLBM_E_ARG;
   *out = nullptr;
   if (hip_device < 0) return SLLBM_E_ARG;
-  if (precision != SLLBM_FP64 && precision != SLLBM_FP32) return SLLBM_E_ARG;
+  if (precision != SLLBM_FP64 && precision != SLLBM_FP32 && precision != SLLBM_BF16X)
+    return SLLBM_E_ARG;
   sllbm_ctx *c = new (std::nothrow) sllbm_ctx();
   if (!c) return SLLBM_E_OOM;
   c->device = hip_device;
-  c->fp32 = precision == SLLBM_FP32;
+  c->fp32 = precision != SLLBM_FP64;
+  c->bf16x = precision == SLLBM_BF16X;
   *out = c;
   return SLLBM_OK;
 }
@@ -963,6 +971,9 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
     return fail(c, SLLBM_E_UNSUPPORTED,
                 "row segments need a first 1-D velocity of 0 and a segment of at least 32 "
                 "columns whose x-stencils fit 64 columns");
+  if (c->bf16x && path != kPathMfma)
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "the bfloat16 experiment runs on the matrix-core path (SLLBM_PATH_MFMA) only");
   if (path == kPathMfma && !mfma_fits(c))
     return fail(c, SLLBM_E_UNSUPPORTED,
                 "matrix-core path needs float32, at most 16 set x window rows and departures "

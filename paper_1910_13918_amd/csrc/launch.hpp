@@ -23,6 +23,7 @@ struct StepConsts {
   double rn[5];       // reference support points r_0..r_p
   double lden[5];     // 1 / prod_{n != m} (r_m - r_n)
   int q1;             // 1-D velocities (5: D2Q25; 3: D2Q9, isothermal only)
+  int bf16x;          // matrix-core x-pass with bfloat16 operands (the experiment)
   int perx, pery;     // periodic axes
   int reverse;        // row-segment and records steps: visit the tiles / blocks in reverse order
   double *mom_out;    // optional [K][n]: rho, u_x, u_y (and theta unless isothermal) of

@@ -230,21 +230,22 @@ __device__ __forceinline__ double quasi_equilibrium(const double (&y)[4], int i,
   return c.w[b] * s;
 }
 
-// Relaxation and store of one node (m: its moments).  With PR the heat
-// flux relaxes at 1/tau_Pr instead of 1/tau (Sec. II.C-D, eq. (16)):
+// Relaxation of one node (m: its moments): calls sink(s, i, value) with the
+// post-collision value of set s and velocity i.  With PR the heat flux
+// relaxes at 1/tau_Pr instead of 1/tau (Sec. II.C-D, eq. (16)):
 // f+ = f + (f_eq - f)/tau + (1/tau - 1/tau_Pr) f*, f* built from the
 // non-equilibrium centred third moment of the set.  The equilibrium itself
 // has none (the D1Q5 rule integrates degree 7 exactly and the 4th-order
 // expansion carries the Gaussian's moments to order 4; the host refuses
 // Pr != 1 with a rule that does not), so Q^neq is the moment of f.
-template <typename T, int MODEL, bool PR, int Q1 = 5>
-__device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
-                                            const double (&m)[4], const StepConsts &c,
-                                            T *__restrict__ fout, long long v) {
+// fs[s][i] is read before sink(s, i, .) is called and not after, so a sink
+// may overwrite fs in place.
+template <typename T, int MODEL, bool PR, int Q1 = 5, class Sink>
+__device__ __forceinline__ void relax_each(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
+                                           const double (&m)[4], const StepConsts &c,
+                                           Sink &&sink) {
   static_assert(!PR || Q1 == 5, "the quasi-equilibrium term needs a set exact to degree 7");
   constexpr int S = Sets<MODEL>::S;
-  constexpr int Q = Q1 * Q1;
-  const long long N = c.n;
   const double om = c.omega;
   const double gf = c.gfac * m[3];
   double qf[4], qg[4];
@@ -259,10 +260,6 @@ __device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][Q1 * Q
       for (int k = 0; k < 4; ++k) qg[k] *= kq;
     }
   }
-  // one 32-bit lane offset for every plane; the plane base lives in the
-  // (scalar) buffer resource
-  const unsigned voff = unsigned(v) * unsigned(sizeof(T));
-  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   double yf[4], yg[4];
   for_each_equilibrium<Q1>(m[0], m[1], m[2], m[3], c, [&](int i, double feq) {
     if (PR && i % 5 == 0) {  // row factors of velocity row b, made when the row starts
@@ -283,16 +280,52 @@ __device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][Q1 * Q
     const double f = double(fr);
     double fo = fma(om, feq - f, f);
     if (PR) fo += quasi_equilibrium(yf, i, c);
-    buffer_store<T>(T(fo), make_rsrc(fout + i * N, plane_bytes), voff, 0);
+    sink(0, i, T(fo));
     if (S == 2) {
       T gr = fs[S - 1][i];
       asm volatile("" : "+v"(gr));
       const double g = double(gr);
       double go = fma(om, gf * feq - g, g);
       if (PR) go += quasi_equilibrium(yg, i, c);
-      buffer_store<T>(T(go), make_rsrc(fout + (Q + i) * N, plane_bytes), voff, 0);
+      sink(1, i, T(go));
     }
   });
+}
+
+// Relaxation and store of one node at node index v.
+template <typename T, int MODEL, bool PR, int Q1 = 5>
+__device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
+                                            const double (&m)[4], const StepConsts &c,
+                                            T *__restrict__ fout, long long v) {
+  constexpr int Q = Q1 * Q1;
+  const long long N = c.n;
+  // one 32-bit lane offset for every plane; the plane base lives in the
+  // (scalar) buffer resource
+  const unsigned voff = unsigned(v) * unsigned(sizeof(T));
+  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
+  relax_each<T, MODEL, PR, Q1>(fs, m, c, [&](int s, int i, T val) {
+    buffer_store<T>(val, make_rsrc(fout + (s * Q + i) * N, plane_bytes), voff, 0);
+  });
+}
+
+// Moments of one node's streamed populations; when `valid`, records them for
+// the adjoint (if asked) and raises the stability flag on rho <= 0,
+// theta <= 0 or a non-finite moment.
+template <typename T, int MODEL, int Q1 = 5>
+__device__ __forceinline__ void collide_moments(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
+                                                const StepConsts &c, long long v, bool valid,
+                                                int *__restrict__ flag, double (&m)[4]) {
+  node_moments<T, MODEL, Q1>(fs, c, m);
+  if (!valid) return;
+  if (c.mom_out) {  // recorded for the adjoint (uniform branch)
+    c.mom_out[v] = m[0];
+    c.mom_out[c.n + v] = m[1];
+    c.mom_out[2 * c.n + v] = m[2];
+    if (MODEL != kIsothermal) c.mom_out[3 * c.n + v] = m[3];
+  }
+  const bool ok = (m[0] > 0.0) && (m[3] > 0.0) && isfinite(m[0]) && isfinite(m[1]) &&
+                  isfinite(m[2]) && isfinite(m[3]);
+  if (!ok) atomicOr(flag, 1);
 }
 
 // Moments, stability flag, equilibrium and relaxation of one node's
@@ -307,16 +340,7 @@ __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][Q1 *
                                               const StepConsts &c, T *__restrict__ fout,
                                               long long v, int *__restrict__ flag) {
   double m[4];
-  node_moments<T, MODEL, Q1>(fs, c, m);
-  if (c.mom_out) {  // recorded for the adjoint (uniform branch)
-    c.mom_out[v] = m[0];
-    c.mom_out[c.n + v] = m[1];
-    c.mom_out[2 * c.n + v] = m[2];
-    if (MODEL != kIsothermal) c.mom_out[3 * c.n + v] = m[3];
-  }
-  const bool ok = (m[0] > 0.0) && (m[3] > 0.0) && isfinite(m[0]) && isfinite(m[1]) &&
-                  isfinite(m[2]) && isfinite(m[3]);
-  if (!ok) atomicOr(flag, 1);
+  collide_moments<T, MODEL, Q1>(fs, c, v, true, flag, m);
   relax_store<T, MODEL, PR, Q1>(fs, m, c, fout, v);
 }
 

@@ -63,8 +63,15 @@ __device__ __forceinline__ int wrap_or_clamp_near(int j, int n, int periodic) {
 
 // Interpolation from the staged windows: the direct 2-D form; the separable
 // form (x-pass per staged row into LDS, then y); or the separable form with
-// the x-pass on the matrix cores (float32).
-enum InterpMode { kInterp2D = 0, kInterpSep = 1, kInterpMfma = 2 };
+// the x-pass on the matrix cores, in float32 or (the bfloat16 experiment)
+// with bfloat16 weights and staged values and float32 accumulation.
+enum InterpMode { kInterp2D = 0, kInterpSep = 1, kInterpMfma = 2, kInterpMfmaBf16 = 3 };
+
+constexpr bool is_mfma_mode(int im) { return im == kInterpMfma || im == kInterpMfmaBf16; }
+
+// Staged columns one bfloat16 x-pass product spans (v_mfma_f32_16x16x32_bf16:
+// K = 32 >= the 16 + 2p columns of a 16-column block).
+constexpr int kMfmaBf16Cols = 32;
 
 // k-steps of 4 of the matrix-core x-pass: 16 target columns need at most
 // 16 + 2 (P1 - 1) staged columns (departures within one node spacing of the
@@ -75,7 +82,10 @@ constexpr int mfma_ksteps() { return (16 + 2 * (P1 - 1) + 3) / 4; }
 // Row pitch of the staged windows: 64 + halo columns, plus (for the
 // matrix-core x-pass) zero columns that the last k-steps may read.
 template <int P1, int HALO, int IM>
-constexpr int tiled_pitch() { return 64 + HALO + (IM == kInterpMfma ? 4 * mfma_ksteps<P1>() : 0); }
+constexpr int tiled_pitch() {
+  return 64 + HALO + (IM == kInterpMfma ? 4 * mfma_ksteps<P1>()
+                                        : (IM == kInterpMfmaBf16 ? kMfmaBf16Cols : 0));
+}
 
 // P1 = taps per axis: p+1 for the forward step, the transposed table width
 // for the adjoint.  R = staged rows per wavefront (W <= R * TY).  The
@@ -93,7 +103,7 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
                                              int wv, const StepConsts &c, T *lds,
                                              T (&fs)[S][25]) {
   static_assert(HALO == 4 || HALO == 8 || HALO == 64, "halo of 4, 8 or 64 columns");
-  static_assert(IM != kInterpMfma || sizeof(T) == 4, "matrix-core x-pass in float32");
+  static_assert(!is_mfma_mode(IM) || sizeof(T) == 4, "matrix-core x-pass on float32 populations");
   constexpr bool SEP = IM != kInterp2D;
   constexpr int WX = tiled_pitch<P1, HALO, IM>();        // staged row pitch
   constexpr int NQ = S * G;                              // planes staged per phase
@@ -205,9 +215,33 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
   // weights of target column 16 wv + lane % 16 against staged column
   // base_a + 4 k + lane / 16, base_a = stencil start of the block's first
   // column), and zeros in the pad columns of both raw buffers
+  typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
   constexpr int KS = IM == kInterpMfma ? mfma_ksteps<P1>() : 1;
   float amat[IM == kInterpMfma ? 5 : 1][KS];
+  bf8 amat16[IM == kInterpMfmaBf16 ? 5 : 1];  // bfloat16: A[n][8 (l / 16) + e], e = 0..7
   int xbase[5];
+  if constexpr (IM == kInterpMfmaBf16) {
+    const int n = 16 * wv + (lane & 15), kq = lane >> 4;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      xbase[a] = __shfl(xr0[a], 16 * wv);
+      const int d0 = xbase[a] + 8 * kq - __shfl(xr0[a], n);
+      float wn[P1];
+#pragma unroll
+      for (int m = 0; m < P1; ++m) wn[m] = __shfl(float(wx[a][m]), n);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int d = d0 + e;
+        float v = 0.0f;
+#pragma unroll
+        for (int m = 0; m < P1; ++m) v = d == m ? wn[m] : v;
+        amat16[a][e] = __bf16(v);  // round to nearest even
+      }
+    }
+    constexpr int PADC = WX - 64 - HALO;  // pad columns of every staged row
+    for (int e = wv * 64 + lane; e < 2 * NQ * W * PADC; e += TY * 64)
+      lds[(e / PADC) * WX + 64 + HALO + e % PADC] = T(0);  // rows of both buffers in turn
+  }
   if constexpr (IM == kInterpMfma) {
     const int n = 16 * wv + (lane & 15), kq = lane >> 4;
 #pragma unroll
@@ -261,6 +295,27 @@ __device__ __forceinline__ void tiled_stream(const T *__restrict__ fin,
               xb[((s * G + g) * W + row) * 64 + lane] = xv;
             }
           }
+        }
+      } else if constexpr (IM == kInterpMfmaBf16) {
+        // X[16 columns of block wv][(set, row) pairs] = A_a (16 x 32) x
+        // staged columns (32 x pairs) in one bfloat16 product: lane l
+        // supplies A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16]
+        // (e = 0..7) and receives X[4 (l / 16) + t][l % 16]
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const int j = lane & 15, kq = lane >> 4;
+        const bool jok = j < S * W;
+        const int jc = jok ? j : 0, js = jc / W, jr = jc % W;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int a = a0 + g;
+          const float *src = cur + (js * G + g) * PLANE + jr * WX + xbase[a] + 8 * kq;
+          bf8 bv;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bv[e] = __bf16(jok ? src[e] : 0.0f);
+          const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+          const f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amat16[a], bv, zero, 0, 0, 0);
+          if (jok)
+            *reinterpret_cast<f4 *>(xb + ((js * G + g) * W + jr) * 64 + 16 * wv + 4 * kq) = acc;
         }
       } else {
         // X[16 columns of block wv][(set, row) pairs] = A_a (16 x 4 KS) x

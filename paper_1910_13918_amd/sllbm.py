@@ -32,6 +32,7 @@ E_UNSUPPORTED = -6
 
 FP64 = 0
 FP32 = 1
+BF16X = 3
 PERIODIC = 0
 ZERO_GRADIENT = 1
 NODES_GLC = 0

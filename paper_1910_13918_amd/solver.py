@@ -11,7 +11,8 @@ import torch
 
 from . import sllbm as C
 
-_PREC = {"fp64": C.FP64, "fp32": C.FP32}
+# "bf16x": float32 populations with the bfloat16 matrix-core x-pass (experiment)
+_PREC = {"fp64": C.FP64, "fp32": C.FP32, "bf16x": C.BF16X}
 _MODEL = {"isothermal": C.ISOTHERMAL, "monatomic": C.MONATOMIC, "polyatomic": C.POLYATOMIC}
 _PATH = {"auto": C.PATH_AUTO, "direct": C.PATH_DIRECT, "tiled": C.PATH_TILED,
          "records": C.PATH_RECORDS, "mfma": C.PATH_MFMA, "rows": C.PATH_ROWS}
@@ -34,7 +35,7 @@ class Solver:
         self.precision = precision
         self.model = model
         self.nu = float(nu)
-        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.ctx = C.sllbm_create(device, _PREC[precision])
         try:
             if xi1d is not None:
@@ -132,7 +133,7 @@ class Solver:
             C.sllbm_set_populations(self.ctx, t.data_ptr(), 1)
             torch.cuda.synchronize(self.device)
             return
-        a = np.ascontiguousarray(F, dtype=np.float32 if self.precision == "fp32" else np.float64)
+        a = np.ascontiguousarray(F, dtype=np.float64 if self.precision == "fp64" else np.float32)
         if a.size != self.nsets * self.q * self.n:
             raise ValueError("population array size does not match the grid")
         C.sllbm_set_populations(self.ctx, _ptr(a), 0)
@@ -145,7 +146,7 @@ class Solver:
 
     def populations(self):
         a = np.empty(self.nsets * self.q * self.n,
-                     dtype=np.float32 if self.precision == "fp32" else np.float64)
+                     dtype=np.float64 if self.precision == "fp64" else np.float32)
         C.sllbm_get_populations(self.ctx, _ptr(a), 0)
         return a.reshape(self.nsets, self.q, self.n)
 

@@ -49,6 +49,8 @@ def _rel(a, b):
 
 CASES = [(p, per, {1: 70, 2: 35, 3: 23, 4: 17}[p], {1: 19, 2: 9, 3: 6, 4: 5}[p])
          for p in (1, 2, 3, 4) for per in (True, False)]
+# rows of several 64-column row segments
+CASES += [(2, True, 97, 4), (3, False, 61, 3)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

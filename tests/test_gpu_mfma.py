@@ -132,3 +132,77 @@ def test_refuses_fp64_and_wide_departures():
         assert e.value.code == C.E_UNSUPPORTED
     finally:
         s.close()
+
+
+# ---- the bfloat16 experiment (SLLBM_BF16X) --------------------------------------
+# bfloat16 weights and staged values, float32 accumulation: each operand is
+# rounded once (relative 2^-9), the x-pass sums p+1 products whose weights have
+# |w| summing to the Lebesgue constant (<= 1.25 up to p = 4 on these points),
+# so a step moves a value by at most about 2 * 2^-9 * 1.25 of max |F| against
+# the exact interpolation (5e-3); a wrong operand layout gives O(1) errors.
+BF16_STEP_REL = 1e-2
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-p{c[1]}-{'per' if c[2] else 'zg'}")
+def test_one_step_bf16x(case):
+    wl = _wl(*case)
+    g, sim = _oracle(wl)
+    F0 = _state32(wl, sim, g, seed=21)
+    F1 = sim.step(F0)
+    s = _solver(wl, "bf16x", "auto")
+    try:
+        print(f"[gpu] bf16x one step {case} nodes={g.nnodes}", flush=True)
+        assert s.resolved_path() == "mfma"
+        s.set_populations(F0)
+        if case[0] == "polyatomic" and case[1] == 4:
+            from paper_1910_13918_amd import sllbm as C
+            with pytest.raises(C.SllbmError) as e:
+                s.step(1)
+            assert e.value.code == C.E_UNSUPPORTED
+            return
+        s.step(1)
+        err = _rel(s.populations().astype(np.float64), F1)
+        print(f"[gpu] bf16x one step {case}: max |dF| / max |F| = {err:.3e}", flush=True)
+        assert err <= BF16_STEP_REL
+        assert s.flags() == (0, 1)
+    finally:
+        s.close()
+
+
+def test_bf16x_riemann64_against_oracle_reported():
+    """The seeded Riemann problem on 64 x 64 cells of order 2 to t = 0.25 with
+    the bfloat16 x-pass, against the FP64 oracle's moments
+    (tests/golden/riemann64_reference.json): the errors are reported, not
+    bounded (the experiment).  Measured: L2 7.1e-2 rho, 7.1e-2 u, 1.9e-2 T
+    (max 0.33, 0.41, 0.096) and a mass change of +31.8 % against the FP64
+    run's +24.6 %: the bfloat16 weights of a departure point do not sum to
+    one (by up to 2^-9), the same bias every step.  The run must stay stable;
+    the L2 errors are held below twice the measured ones as a guard against
+    regressions."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "riemann64_reference.json")))
+    nodes = np.array(ref["nodes"])
+    want = [np.array(ref[k]) for k in ("rho", "ux", "uy", "T")]
+    wl = W.riemann(64, 2)
+    out = {}
+    for prec in ("bf16x", "fp64"):
+        s = _solver(wl, prec, "auto")
+        try:
+            s.init_from_workload()
+            m0 = s.mass()
+            s.step(wl.steps)
+            assert s.flags()[0] == 0
+            out[prec] = ([a[nodes] for a in s.moments()], s.mass() / m0 - 1.0)
+        finally:
+            s.close()
+    got, dm = out["bf16x"]
+    errs = {}
+    for k, name in enumerate(("rho", "ux", "uy", "T")):
+        d = got[k] - want[k]
+        errs[name + "_max"] = float(np.abs(d).max() / np.abs(want[k]).max())
+        errs[name + "_l2"] = float(np.linalg.norm(d) / np.linalg.norm(want[k]))
+    print(f"[gpu] bf16x riemann 64^2 t = 0.25 vs FP64 oracle: {errs}; mass change {dm:.3e} "
+          f"(FP64 GPU {out['fp64'][1]:.3e})", flush=True)
+    assert max(v for k, v in errs.items() if k.endswith("_l2")) < 0.15

@@ -346,3 +346,26 @@ def test_large_cfl_one_step(path, cfl):
         assert _rel(s.populations(), F1) <= 1e-12
     finally:
         s.close()
+
+
+def test_row_segments_pr_and_record():
+    """Pr = 0.75 (quasi-equilibrium collision) with the moments record of
+    step_record on the row-segment kernel (float32), 163 x 5 cells of order 2:
+    the recorded rho, u, theta are those of the streamed state."""
+    wl = _wl("polyatomic", 2, False, 163, 5)
+    wl.Pr = 0.75
+    g, sim = _oracle(wl)
+    F0 = _state(wl, sim, g, seed=17, rel=0.05)
+    Fs = sim.stream(F0)
+    F1 = sim.collide(Fs)
+    rho, ux, uy, th = sim.moments(Fs)
+    s = _solver(wl, "fp32", "rows")
+    try:
+        s.set_populations(F0)
+        M = s.step_record(1)[0].cpu().numpy()
+        G1 = s.populations().astype(np.float64)
+    finally:
+        s.close()
+    assert _rel(G1, F1) <= 2e-6
+    for k, want in enumerate((rho, ux, uy, th)):
+        assert np.abs(M[k] - want).max() <= 2e-6 * max(1.0, np.abs(want).max())
