@@ -140,6 +140,35 @@ class CurviGrid:
             raise ValueError("departure point outside every cell and periodic image")
         return cx, cy, np.clip(r, 0.0, 1.0), np.clip(s, 0.0, 1.0)
 
+    def node_mass(self, nquad=8):
+        """Integral of each node's shape function over the mesh (the mass
+        weights of the mass monitor, Sec. III.E): on every cell the local
+        basis l_a(r) l_b(s) times the Jacobian determinant of the bilinear
+        map, integrated over the reference square by tensor Gauss-Legendre
+        quadrature (nquad points per axis), summed over the cells that share
+        the node."""
+        g, gw = np.polynomial.legendre.leggauss(nquad)
+        q = 0.5 * (g + 1.0)
+        qw = 0.5 * gw
+        R, S = np.meshgrid(q, q, indexing="ij")
+        Wq = np.outer(qw, qw)
+        lr = lagrange_basis(self.r, R)  # (p+1, nquad, nquad)
+        ls = lagrange_basis(self.r, S)
+        M = np.zeros(self.nnodes)
+        for cy in range(self.ncy):
+            for cx in range(self.ncx):
+                (x00, y00), (x10, y10), (x01, y01), (x11, y11) = self.cell_vertices(cx, cy)
+                # partial derivatives of the bilinear map at the quadrature points
+                dxdr = (1 - S) * (x10 - x00) + S * (x11 - x01)
+                dydr = (1 - S) * (y10 - y00) + S * (y11 - y01)
+                dxds = (1 - R) * (x01 - x00) + R * (x11 - x10)
+                dyds = (1 - R) * (y01 - y00) + R * (y11 - y10)
+                J = np.abs(dxdr * dyds - dxds * dydr)
+                for a in range(self.p + 1):
+                    for b in range(self.p + 1):
+                        M[self.node_of(cx, cy, a, b)] += np.sum(lr[a] * ls[b] * J * Wq)
+        return M
+
     def stencil(self, px, py):
         """Source nodes (p+1, p+1, n) and weights (p+1, p+1, n) of the cell
         interpolant at the points, eq. (17) on the reference square."""

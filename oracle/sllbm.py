@@ -25,6 +25,10 @@ are values of the interpolant of the nodal post-collision populations):
    Qneq = Q - Q_eq, Q = sum_i f_i (xi_i - u)^(x3) the centred third moment;
    g* the same with g and its own Q.
 
+A scaled velocity set (Sec. II.B, c_s != 1) streams with xi = c_s xi_hat and
+expands the equilibrium in xi_hat, u / c_s and theta = T / T0 with T0 = c_s^2
+(readings S3/S4); every input and output here is in physical units.
+
 Populations are stored as an array of shape (S, Q, nnodes) with S = 1 (f) or
 S = 2 (f, g) and node index v = iy * nx + ix.
 """
@@ -40,7 +44,7 @@ MODELS = ("isothermal", "monatomic", "polyatomic")
 
 
 class Sim:
-    def __init__(self, grid, dt, nu, model, gamma=1.4, xi1=None, w1=None, Pr=1.0):
+    def __init__(self, grid, dt, nu, model, gamma=1.4, xi1=None, w1=None, Pr=1.0, cs=1.0):
         if model not in MODELS:
             raise ValueError(model)
         self.grid = grid
@@ -49,11 +53,19 @@ class Sim:
         self.model = model
         if xi1 is None:
             xi1, w1 = d1q5()
-        self.xi, self.w = tensor_product(np.asarray(xi1, float), np.asarray(w1, float))
+        # Sec. II.B: the abscissae are given for c_s = 1 "unless scaled"; a
+        # scaled set has physical velocities xi = c_s xi_hat, and the Hermite
+        # expansion of Sec. II.A is in the normalised velocity xi_hat with the
+        # reference temperature T0 = c_s^2 (c_s^2 = R T0, R = 1)
+        self.cs = float(cs)
+        self.T0 = self.cs ** 2
+        xi_hat, self.w = tensor_product(np.asarray(xi1, float), np.asarray(w1, float))
+        self.xi_hat = xi_hat
+        self.xi = self.cs * xi_hat
         self.Q = len(self.w)
-        # relaxation time tau = nu/(c_s^2 dt) + 1/2 with c_s = 1 (Sec. II.D);
+        # relaxation time tau = nu/(c_s^2 dt) + 1/2 (Sec. II.D);
         # nu = inf means pure streaming (1/tau = 0)
-        self.tau = np.inf if np.isinf(self.nu) else self.nu / self.dt + 0.5
+        self.tau = np.inf if np.isinf(self.nu) else self.nu / (self.cs ** 2 * self.dt) + 0.5
         self.omega = 0.0 if np.isinf(self.tau) else 1.0 / self.tau
         # Sec. II.D: tau_Pr = (tau - 1/2)/Pr + 1/2
         self.Pr = float(Pr)
@@ -73,17 +85,21 @@ class Sim:
         self.X, self.Y = grid.coords()
 
     # ---- equilibrium and initialisation -------------------------------------------
-    def equilibrium(self, rho, ux, uy, theta):
-        feq = f_eq(self.xi, self.w, rho, ux, uy, theta)
+    def equilibrium(self, rho, ux, uy, T):
+        """f_eq of eq. (9) in the normalised variables xi_hat = xi / c_s,
+        u / c_s and theta = T / T0, and g_eq = (2 C_v - D) T f_eq (R = 1)."""
+        c = self.cs
+        feq = f_eq(self.xi_hat, self.w, rho, ux / c, uy / c, T / self.T0)
         if self.S == 1:
             return feq[None]
-        return np.stack([feq, g_eq(feq, theta, self.gamma)])
+        return np.stack([feq, g_eq(feq, T, self.gamma)])
 
     def init(self, rho, ux, uy, T):
         """Populations at equilibrium with the given node fields (the paper is
-        silent on initialisation; f = f_eq and g = g_eq is the reading used)."""
-        theta = np.ones_like(rho) if self.model == "isothermal" else T
-        return self.equilibrium(rho, ux, uy, theta)
+        silent on initialisation; f = f_eq and g = g_eq is the reading used).
+        The isothermal model sits at the reference temperature T0."""
+        T = self.T0 * np.ones_like(rho) if self.model == "isothermal" else T
+        return self.equilibrium(rho, ux, uy, T)
 
     # ---- streaming ------------------------------------------------------------
     def departure_stencil(self, i, nodes):
@@ -130,7 +146,7 @@ class Sim:
         ux = jx / rho
         uy = jy / rho
         if self.model == "isothermal":
-            theta = np.ones_like(rho)
+            theta = self.T0 * np.ones_like(rho)
         else:
             two_rho_e = ((self.xi[:, 0] ** 2 + self.xi[:, 1] ** 2)[:, None] * f).sum(axis=0)
             if self.S == 2:
@@ -150,11 +166,13 @@ class Sim:
         return Q
 
     def quasi_equilibrium(self, Qneq):
-        """f*_i = (w_i / 3!) Qneq : H^(3)(xi_i) (reading of Sec. II.C), shape (Q, n)."""
-        xT = self.xi.T
+        """f*_i = (w_i / 3!) Qneq : H^(3)(xi_i) (reading of Sec. II.C) in the
+        normalised velocities (Qneq / c_s^3 against H^(3)(xi_hat)), shape (Q, n)."""
+        xT = self.xi_hat.T
+        Qh = Qneq / self.cs ** 3
         total = np.zeros((self.Q,) + Qneq.shape[3:], dtype=Qneq.dtype)
         for idx in index_tuples(3):
-            total = total + np.multiply.outer(hermite_tensor(3, idx, xT), Qneq[idx])
+            total = total + np.multiply.outer(hermite_tensor(3, idx, xT), Qh[idx])
         return self.w[:, None] * total / math.factorial(3)
 
     def collide(self, F):
@@ -180,7 +198,7 @@ class Sim:
 
     # ---- outputs ---------------------------------------------------------------
     def macro(self, F):
-        """rho, u_x, u_y, T per node (T = theta with T0 = R = 1)."""
+        """rho, u_x, u_y, T per node (physical units; R = 1)."""
         return self.moments(F)
 
     def mass(self, F):

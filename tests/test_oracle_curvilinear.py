@@ -94,3 +94,32 @@ def test_departure_outside_every_cell_is_an_error():
     cg = _wavy(2)
     with pytest.raises(ValueError):
         cg.locate(np.array([4 * cg.Lx]), np.array([0.5]))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_node_mass_rectangles_equal_axis_product(p):
+    """On rectangular cells the curvilinear node masses are the axis-product
+    weights of the grid oracle (Clenshaw-Curtis weights times the cell size,
+    pinned in test_oracle_grid_stream.py)."""
+    ex = np.array([0.0, 0.7, 1.5, 2.0, 3.1])
+    ey = np.array([0.0, 1.1, 1.9, 3.0])
+    VX, VY = np.meshgrid(ex, ey)
+    M = CurviGrid(VX, VY, p).node_mass()
+    np.testing.assert_allclose(M, Grid(ex, ey, p, True, True).node_mass(), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_node_mass_wavy_area_and_smooth_integral(p):
+    """On a genuinely curved periodic mesh: the masses sum to the area of the
+    periodic box (the shape functions sum to one and the cells tile one
+    period), and sum_v M_v f(x_v) of a smooth periodic f converges to its
+    exact integral (cos^2(2 pi x / Lx) integrates to half the area)."""
+    L = 2 * np.pi
+    errs = []
+    for n in (8, 16):
+        cg = CurviGrid(*wavy_vertices(n, n, L, L, 0.3), p)
+        M = cg.node_mass()
+        assert abs(M.sum() - L * L) <= 1e-12 * L * L
+        X, Y = cg.coords()
+        errs.append(abs(np.sum(M * np.cos(X) ** 2) - 0.5 * L * L))
+    assert errs[1] < errs[0] * 2.0 ** (-p) or errs[1] < 1e-11, errs

@@ -385,3 +385,53 @@ def test_smooth_density_convergence_order():
         assert np.abs(rho * T - 1.0).max() < 20 * errs[-1]
     order = np.log2(errs[0] / errs[1])
     assert errs[0] < 5e-3 and order >= 3.5, (errs, order)
+
+
+def test_scaled_velocity_set_equilibrium_is_maxwellian_in_physical_units():
+    """Sec. II.B: a velocity set scaled by c_s (xi = c_s xi_hat, T0 = c_s^2)
+    carries the moments of the Maxwellian of the physical u and T up to
+    order 4: sum f_eq xi_x^a xi_y^b = rho E[X^a] E[Y^b], X ~ N(u_x, T),
+    Y ~ N(u_y, T), a + b <= 4; g_eq carries (2 C_v - D) rho T."""
+    from math import comb
+    g = Grid(uniform_edges(2, 0.0, 1.0), uniform_edges(2, 0.0, 1.0), 1, True, True)
+    sim = Sim(g, 0.01, 0.01, "polyatomic", gamma=1.4, cs=1.7)
+    rho, ux, uy, T = np.array([1.3]), np.array([0.9]), np.array([-0.4]), np.array([2.2])
+    F = sim.equilibrium(rho, ux, uy, T)[:, :, 0]
+
+    def gauss(m, mu, var):  # E[X^m], X ~ N(mu, var)
+        return sum(comb(m, k) * mu ** (m - k) * (0 if k % 2 else np.prod(
+            np.arange(k - 1, 0, -2, dtype=float)) * var ** (k // 2)) for k in range(m + 1))
+    X, Y = sim.xi[:, 0], sim.xi[:, 1]
+    for a in range(5):
+        for b in range(5 - a):
+            want = rho[0] * gauss(a, ux[0], T[0]) * gauss(b, uy[0], T[0])
+            assert np.sum(F[0] * X ** a * Y ** b) == pytest.approx(want, rel=1e-13, abs=1e-13)
+    cv = 1.0 / 0.4
+    assert np.sum(F[1]) == pytest.approx((2 * cv - 2) * rho[0] * T[0], rel=1e-13)
+
+
+@pytest.mark.parametrize("model,Pr", [("polyatomic", 0.75), ("isothermal", 1.0)])
+def test_scaled_velocity_set_is_the_unscaled_run_in_other_units(model, Pr):
+    """A run with the set scaled by c_s equals the unscaled run with
+    dt' = c_s dt, nu' = nu / c_s, u' = u / c_s, T' = T / c_s^2 (departures
+    x - dt c_s xi_hat, tau = nu / (c_s^2 dt) + 1/2): rho and f are the same,
+    u = c_s u', T = c_s^2 T', g = c_s^2 g'."""
+    cs, dt, nu = 1.6, 0.07, 0.02
+    e = uniform_edges(5, 0.0, 2 * np.pi)
+    g = Grid(e, e, 3, True, True)
+    X, Y = g.coords()
+    rho = 1 + 0.1 * np.sin(X) * np.cos(Y)
+    ux, uy = 0.3 * np.cos(Y), 0.2 * np.sin(X)
+    T = 1.5 + 0.2 * np.cos(X + Y)
+    a = Sim(g, dt, nu, model, Pr=Pr, cs=cs)
+    b = Sim(g, cs * dt, nu / cs, model, Pr=Pr)
+    Fa = a.run(a.init(rho, ux, uy, T), 3)
+    Fb = b.run(b.init(rho, ux / cs, uy / cs, T / cs ** 2), 3)
+    np.testing.assert_allclose(Fa[0], Fb[0], rtol=1e-12, atol=1e-15)
+    if a.S == 2:
+        np.testing.assert_allclose(Fa[1], cs ** 2 * Fb[1], rtol=1e-12, atol=1e-15)
+    ma, mb = a.macro(Fa), b.macro(Fb)
+    np.testing.assert_allclose(ma[0], mb[0], rtol=1e-12)
+    np.testing.assert_allclose(ma[1], cs * mb[1], rtol=1e-11, atol=1e-14)
+    np.testing.assert_allclose(ma[3], cs ** 2 * mb[3], rtol=1e-12)
+    assert a.tau == pytest.approx(b.tau, rel=1e-15)
