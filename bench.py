@@ -47,7 +47,7 @@ def bytes_per_node_update(wl, precision, path):
     """Algorithmic HBM bytes per node update: every population read once and
     written once (tables excluded); per-(node, velocity) departure records add
     a 4-byte cell index and two reference coordinates per velocity."""
-    size = 4 if precision == "fp32" else 8
+    size = 8 if precision == "fp64" else 4
     b = 2 * wl.nsets * 25 * size
     if path == "records":
         b += 25 * (4 + 2 * size)
@@ -68,10 +68,13 @@ def profiled_traffic(wname, precision, path):
     size), or None when no profile exists or the kernel source has changed
     since it was taken."""
     import hashlib
-    tag = {"riemann2d_512x512cells_p2": "riemann512_p2"}.get(wname)
+    tag = {"riemann2d_512x512cells_p2": "riemann512_p2",
+           "shock_vortex_1024x512cells_p3_stretched": "svi1024x512_p3"}.get(wname)
     if tag is None:
         return None
-    f = os.path.join(ROOT, "profiles", f"stream_collide_{tag}_{precision}.json")
+    f = os.path.join(ROOT, "profiles", f"stream_collide_{tag}_{precision}_{path}.json")
+    if not os.path.exists(f):
+        f = os.path.join(ROOT, "profiles", f"stream_collide_{tag}_{precision}.json")
     if not os.path.exists(f):
         return None
     prof = json.load(open(f))
@@ -128,6 +131,10 @@ def shock_vortex_entry(precision, steps=20, warmup=3):
                       "ms_per_step": ms / steps, "bytes_per_node_update": bpn,
                       "achieved_gbs": nu_s * bpn / 1e9, "frac": nu_s * bpn / 1e9 / HBM_PEAK_GBS,
                       "unstable_flag": unstable}
+        if label != "axis_tables_pr1":  # counters taken at Pr = 0.75
+            tr = profiled_traffic(wname, precision, s.resolved_path())
+            out[label]["traffic"] = tr
+            out[label]["traffic_over_algorithmic"] = (tr / (s.n * bpn)) if tr else None
         s.close()
     return out
 
@@ -165,7 +172,7 @@ def aux_kernels(s, reps=20):
     X, Y = s.coords()
     fields = [torch.tensor(a, device=s.device) for a in s.workload.fields(X, Y)]
     outs = [torch.empty(s.n, dtype=torch.float64, device=s.device) for _ in range(4)]
-    size = 4 if s.precision == "fp32" else 8
+    size = 8 if s.precision == "fp64" else 4
     pops = s.nsets * 25 * size
 
     def timed_call(fn):
@@ -286,10 +293,41 @@ def adjoint_cost(precision="fp32", every=50, reps=3):
         torch.cuda.synchronize()
         fwd.append(e0.elapsed_time(e1))
         bwd.append(e1.elapsed_time(e2))
+    kern = adjoint_step_kernel(s)
     s.close()
     f, b = min(fwd[1:]), min(bwd[1:])
     return {"workload": "tgv_128x128cells_p4_500steps", "precision": precision,
-            "checkpoint_every": every, "forward_ms": f, "backward_ms": b, "ratio": b / f}
+            "checkpoint_every": every, "forward_ms": f, "backward_ms": b, "ratio": b / f,
+            "adjoint_step_kernel": kern}
+
+
+def adjoint_step_kernel(s, reps=50):
+    """Average duration of one fused adjoint step (the transposed gather S^T
+    fused with the previous step's collision Jacobian, sllbm_adjoint_step
+    with a moments record) on the solver's grid, with its algorithmic bytes
+    per node: mu read and lambda written (S 25 values each) plus the K
+    recorded float64 moments read."""
+    import torch
+
+    from paper_1910_13918_amd import sllbm as C
+    size = 4 if s.precision != "fp64" else 8
+    K = s.recorded_moments
+    s.init_from_workload()
+    mom = s.step_record(1)[0].contiguous()
+    mu = s.populations_device().contiguous()
+    out = torch.empty_like(mu)
+    C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), mom.data_ptr(), out.data_ptr())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    for _ in range(reps):
+        C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), mom.data_ptr(), out.data_ptr())
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    bpn = 2 * s.nsets * 25 * size + 8 * K
+    return {"ms": ms, "bytes_per_node": bpn, "nodes": s.n,
+            "achieved_gbs": s.n * bpn / (ms * 1e6), "frac": s.n * bpn / (ms * 1e6) / HBM_PEAK_GBS}
 
 
 # ---- CPU baseline: the FP64 oracle on the host's cores ---------------------------
@@ -412,7 +450,7 @@ def main():
         "metric": METRIC, "value": nu_s, "unit": "node-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": wname, "nodes": s.n, "populations": wl.nsets * 25,
                    "order": wl.p, "precision": args.precision + ("-pop/f64-moments" if args.precision == "fp32" else ""),
                    "path": args.path, "path_resolved": s_path, "dt": wl.dt,

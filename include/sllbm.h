@@ -39,7 +39,8 @@
  *   - Populations are structure-of-arrays [S][Q][ny][nx] of the population
  *     type (float64 for SLLBM_FP64, float32 for SLLBM_FP32), with S = 2 for
  *     the polyatomic model (f then g) and 1 otherwise, and i = a + q1 * b
- *     for the velocity (xi_a, xi_b).
+ *     for the velocity (xi_a, xi_b) (g divided by cs^2 for a scaled
+ *     velocity set, sllbm_set_velocity_set).
  *   - Device pointers are HIP device addresses on the context's device.
  *     Kernels run asynchronously on the bound stream (default: the null
  *     stream); calls that return host data synchronise that stream.
@@ -139,11 +140,21 @@ int sllbm_set_stream(sllbm_ctx *ctx, void *hip_stream);
 /* ---- set-up (host only) -------------------------------------------------- */
 
 /* 1-D velocity set of the tensor-product 2-D set (Sec. II.B).  xi1d/w1d hold
- * q1d abscissae and weights in code units (c_s = 1).  NULL/NULL selects the
- * D1Q5 Gauss-Hermite set of Table I: 0, +sqrt(5-sqrt(10)), +sqrt(5+sqrt(10)),
- * -sqrt(5-sqrt(10)), -sqrt(5+sqrt(10)).  Only q1d = 5 is supported
- * (SLLBM_E_UNSUPPORTED otherwise).  Weights must be positive and finite. */
-int sllbm_set_velocity_set(sllbm_ctx *ctx, int q1d, const double *xi1d, const double *w1d);
+ * q1d abscissae and weights of the unscaled set (c_s = 1); NULL/NULL selects
+ * the set of that size: for q1d = 5 the D1Q5 Gauss-Hermite set of Table I
+ * (0, +sqrt(5-sqrt(10)), +sqrt(5+sqrt(10)), -sqrt(5-sqrt(10)),
+ * -sqrt(5+sqrt(10))), for q1d = 3 the D1Q3 one (0, +sqrt(3), -sqrt(3);
+ * 2/3, 1/6, 1/6), whose product D2Q9 is the comparison set of Sec. III.A
+ * (isothermal model only, on the row-segment, direct and records kernels).
+ * Other sizes: SLLBM_E_UNSUPPORTED.  Weights must be positive and finite.
+ * cs > 0 scales the set (Sec. II.B: "unless scaled", c_s = 1): the
+ * physical velocities are cs * xi1d, the reference temperature is
+ * T0 = cs^2 (c_s^2 = R T0, R = 1), tau = nu / (cs^2 dt) + 1/2, and the
+ * equilibrium is the Hermite expansion in xi / cs, u / cs and T / T0.  All
+ * node fields in and out (init_macro, moments) are physical; inside, the
+ * second population is held as g / cs^2.  The adjoint calls need cs = 1. */
+int sllbm_set_velocity_set(sllbm_ctx *ctx, int q1d, const double *xi1d, const double *w1d,
+                           double cs);
 
 /* Interpolation order p in 1..4 and support-point family (Sec. II.E:
  * Gauss-Lobatto-Chebyshev points; equidistant points as the unstable
@@ -178,8 +189,9 @@ int sllbm_init_grid_mapped(sllbm_ctx *ctx, int ncx, int ncy, const double *edges
  * a departure point that is not found fails that step with SLLBM_E_ARG) and
  * streamed with the records gather: AUTO resolves to SLLBM_PATH_RECORDS and
  * every other path is refused (SLLBM_E_UNSUPPORTED), as are the per-axis
- * queries (sllbm_node_coords, sllbm_departure_table, sllbm_mass_weights),
- * sllbm_mass and the adjoint. */
+ * queries (sllbm_node_coords, sllbm_departure_table, sllbm_mass_weights)
+ * and the adjoint.  sllbm_mass integrates the interpolated density with the
+ * node masses of the bilinear cells (sllbm_node_masses). */
 int sllbm_init_grid_curvilinear(sllbm_ctx *ctx, int ncx, int ncy, const double *vx,
                                 const double *vy);
 
@@ -239,6 +251,15 @@ int sllbm_departure_records(const sllbm_ctx *ctx, int i, int32_t *cell, double *
  * weight of node (iy, ix) is my[iy] * mx[ix]. */
 int sllbm_mass_weights(const sllbm_ctx *ctx, double *mx, double *my);
 
+/* Mass weight of every node, m[ny][nx] (host array), on any grid: the
+ * integral of the node's shape function, i.e. the sum over the cells sharing
+ * the node of the integral of its local basis l_a(r) l_b(s) times the cell
+ * map's Jacobian (Sec. II.E; the weights of the mass monitor of Sec. III.E).
+ * On axis-product grids the product my[iy] mx[ix] of sllbm_mass_weights; on
+ * a curvilinear mesh of bilinear cells from the Jacobian, which is linear in
+ * (r, s) there. */
+int sllbm_node_masses(const sllbm_ctx *ctx, double *m);
+
 /* Relaxation time tau = nu/(c_s^2 dt) + 1/2 (Sec. II.D); +inf for nu = +inf. */
 int sllbm_relaxation_time(const sllbm_ctx *ctx, double *tau);
 
@@ -284,15 +305,16 @@ int sllbm_status_flags(sllbm_ctx *ctx, int *unstable, int64_t *steps_done);
 
 /* ---- outputs ----------------------------------------------------------------- */
 
-/* rho, ux, uy, T per node (T = theta; T0 = 1) from the current populations.
+/* rho, ux, uy, T per node (physical units: T = theta T0 with T0 = cs^2, so
+ * T = theta for the unscaled set) from the current populations.
  * rho, ux, uy, T and the collision invariants they derive from are equal
  * before and after the collision, so these are the post-streaming moments.
  * Arrays of nx*ny float64, host (synchronises) or device (async). */
 int sllbm_moments(sllbm_ctx *ctx, double *rho, double *ux, double *uy, double *T, int on_device);
 
 /* Total mass sum_v M_v rho_v with M_v the integral of node v's shape function
- * (relative mass m/m0 is the monitor of Sec. III.E).  Deterministic FP64
- * reduction; synchronises. */
+ * (sllbm_node_masses; relative mass m/m0 is the monitor of Sec. III.E), on
+ * every grid.  Deterministic FP64 reduction; synchronises. */
 int sllbm_mass(sllbm_ctx *ctx, double *mass);
 
 /* sllbm_mass for callers that cannot allocate device memory (code under HIP
@@ -307,7 +329,7 @@ int sllbm_mass(sllbm_ctx *ctx, double *mass);
  * threads) race on it, and each call overwrites what the last one left.
  * Needs initialised populations (SLLBM_E_STATE otherwise, as the device
  * tables are built by sllbm_init_macro / sllbm_set_populations);
- * SLLBM_E_UNSUPPORTED on a curvilinear mesh, as sllbm_mass. */
+ * on every grid, as sllbm_mass. */
 int sllbm_mass_noalloc(sllbm_ctx *ctx, double *mass_dev);
 
 /* Copy the current populations out / in ([S][Q][ny][nx], population type).

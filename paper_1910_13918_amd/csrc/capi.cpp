@@ -42,6 +42,7 @@ struct sllbm_ctx {
   hipStream_t stream = nullptr;
 
   VelocitySet vs = default_velocity_set();
+  double cs = 1.0;  // the set's scale (Sec. II.B): physical velocities cs * xi
   int p = 0;
   bool glc = true;
   bool have_grid = false;
@@ -61,6 +62,7 @@ struct sllbm_ctx {
   bool host_dirty = true;
   AxisTable xt[kQ1], yt[kQ1];
   std::vector<double> mx, my;
+  std::vector<double> mnode;  // curvilinear mesh: node masses [ny][nx]
   int win_rows = 0, win_cols = 0;
   bool mfma_blocks_ok = false;
   std::vector<int32_t> ywin, yrel, xwin, xrel;
@@ -82,6 +84,7 @@ struct sllbm_ctx {
   bool dev_dirty = true;
   bool rec_dirty = true;
   DeviceBuf rows_xrel_d, rows_xwin_d;
+  DeviceBuf mnode_d;
   DeviceBuf xsrc, xw, ysrc, yw, yrel_d, ywin_d, xrel_d, xwin_d, mxd, myd, flag, partial, scalar,
       macro;
   DeviceBuf rec_cell, rec_r, rec_s;
@@ -195,7 +198,8 @@ std::string departure_records(const sllbm_ctx *c, int i, int32_t *cell, double *
   const int a = i % q1(c), b = i / q1(c);
   if (c->curvi)
     return curvi_records(c->mesh, support_points(c->p, c->glc), c->cX, c->cY,
-                         -c->dt * c->vs.xi[a], -c->dt * c->vs.xi[b], cell, r, s);
+                         -c->dt * c->cs * c->vs.xi[a], -c->dt * c->cs * c->vs.xi[b], cell, r,
+                         s);
   for (int iy = 0; iy < c->ay.n; ++iy)
     for (int ix = 0; ix < c->ax.n; ++ix) {
       const size_t k = size_t(iy) * c->ax.n + ix;
@@ -209,11 +213,13 @@ std::string departure_records(const sllbm_ctx *c, int i, int32_t *cell, double *
 void build_host_tables(sllbm_ctx *c) {
   if (!c->host_dirty) return;
   for (int a = 0; a < q1(c); ++a) {
-    c->xt[a] = build_axis_table(c->ax, -c->dt * c->vs.xi[a]);
-    c->yt[a] = build_axis_table(c->ay, -c->dt * c->vs.xi[a]);
+    // departure x - dt xi with the physical velocity xi = cs xi_hat
+    c->xt[a] = build_axis_table(c->ax, -c->dt * c->cs * c->vs.xi[a]);
+    c->yt[a] = build_axis_table(c->ay, -c->dt * c->cs * c->vs.xi[a]);
   }
   c->mx = c->ax.node_mass();
   c->my = c->ay.node_mass();
+  if (c->curvi) c->mnode = curvi_node_mass(c->mesh, support_points(c->p, c->glc));
   // windows of the tiled kernel: tiles of kTileCols columns by kTileRows rows
   c->win_rows = build_windows(c->yt, q1(c), c->ay.n, kTileRows, c->ywin, c->yrel);
   c->win_cols = build_windows(c->xt, q1(c), c->ax.n, kTileCols, c->xwin, c->xrel);
@@ -334,6 +340,7 @@ int prepare_device(sllbm_ctx *c) {
     if (!rc && c->rows_tx) rc = upload(c, c->rows_xwin_d, c->rows_xwin);
     if (!rc) rc = upload(c, c->mxd, c->mx);
     if (!rc) rc = upload(c, c->myd, c->my);
+    if (!rc && c->curvi) rc = upload(c, c->mnode_d, c->mnode);
     if (!rc) rc = alloc_buf(c, c->flag, sizeof(int));
     if (!rc) rc = alloc_buf(c, c->scalar, 2 * sizeof(double));
     if (!rc) rc = alloc_buf(c, c->partial, sizeof(double) * (size_t(nnodes(c)) / 256 + 2));
@@ -386,6 +393,8 @@ StepConsts make_consts(const sllbm_ctx *c) {
   k.gfac = 2.0 * cv - D;
   k.inv_2cv = 1.0 / (2.0 * cv);
   k.q1 = q1(c);
+  k.cs = c->cs;
+  k.inv_cs = 1.0 / c->cs;
   k.bf16x = c->bf16x;
   for (int a = 0; a < q1(c); ++a) {
     k.xi[a] = c->vs.xi[a];
@@ -418,6 +427,7 @@ DevTables make_tables(const sllbm_ctx *c) {
   t.rec_s = c->rec_s.ptr;
   t.mx = static_cast<const double *>(c->mxd.ptr);
   t.my = static_cast<const double *>(c->myd.ptr);
+  t.mnode = c->curvi ? static_cast<const double *>(c->mnode_d.ptr) : nullptr;
   t.yrel = static_cast<const int32_t *>(c->yrel_d.ptr);
   t.ywin = static_cast<const int32_t *>(c->ywin_d.ptr);
   t.xrel = static_cast<const int32_t *>(c->xrel_d.ptr);
@@ -455,6 +465,18 @@ int ensure_populations(sllbm_ctx *c) {
 int clear_flag(sllbm_ctx *c) {
   HIP_TRY(c, launch_clear_flag(static_cast<int *>(c->flag.ptr), c->stream));
   return SLLBM_OK;
+}
+
+// tau = nu / (c_s^2 dt) + 1/2 (Sec. II.D) and tau_Pr = (tau - 1/2)/Pr + 1/2
+// (omega_pr exactly omega when Pr = 1); nu = +inf: no collision.
+void update_relaxation(sllbm_ctx *c) {
+  if (!c->have_phys) return;
+  const double nu = c->nu;
+  c->tau = std::isinf(nu) ? std::numeric_limits<double>::infinity()
+                          : nu / (c->cs * c->cs * c->dt) + 0.5;
+  c->omega = std::isinf(nu) ? 0.0 : 1.0 / c->tau;
+  c->omega_pr = (c->Pr == 1.0 || std::isinf(nu)) ? c->omega
+                                                  : 1.0 / ((c->tau - 0.5) / c->Pr + 0.5);
 }
 
 int setup_allowed(sllbm_ctx *c) {
@@ -505,6 +527,8 @@ int prepare_adjoint(sllbm_ctx *c) {
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers the 5-velocity set (D2Q25) only");
   if (c->bf16x)
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint differentiates the float32/float64 step");
+  if (c->cs != 1.0)
+    return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers the unscaled velocity set (c_s = 1)");
   if (!c->adj_dirty) return SLLBM_OK;
   int taps = 0;
   for (int a = 0; a < kQ1; ++a) {
@@ -591,7 +615,8 @@ void sllbm_destroy(sllbm_ctx *c) {
     DeviceBuf *bufs[] = {&c->xsrc, &c->xw, &c->ysrc, &c->yw, &c->yrel_d, &c->ywin_d,
                          &c->xrel_d, &c->xwin_d, &c->xsrcT, &c->xwT, &c->ysrcT, &c->ywT,
                          &c->yrelT_d, &c->ywinT_d, &c->xrelT_d, &c->xwinT_d, &c->mxd,
-                         &c->myd, &c->flag, &c->partial, &c->scalar, &c->macro, &c->rec_cell,
+                         &c->myd, &c->mnode_d, &c->flag, &c->partial, &c->scalar, &c->macro,
+                         &c->rec_cell,
                          &c->rec_r, &c->rec_s, &c->rows_xrel_d, &c->rows_xwin_d,
                          &c->rows_xrelT_d, &c->rows_xwinT_d};
     for (DeviceBuf *b : bufs) free_buf(*b);
@@ -611,9 +636,11 @@ int sllbm_set_stream(sllbm_ctx *c, void *stream) {
   return SLLBM_OK;
 }
 
-int sllbm_set_velocity_set(sllbm_ctx *c, int q1d, const double *xi1d, const double *w1d) {
+int sllbm_set_velocity_set(sllbm_ctx *c, int q1d, const double *xi1d, const double *w1d,
+                           double cs) {
   int rc = setup_allowed(c);
   if (rc) return rc;
+  if (!is_finite(cs) || !(cs > 0)) return fail(c, SLLBM_E_ARG, "cs must be positive and finite");
   if (q1d != 5 && q1d != 3)
     return fail(c, SLLBM_E_UNSUPPORTED, "5 (D2Q25) or 3 (D2Q9) velocities per axis");
   if (q1d == 3 && c->have_phys && c->model != SLLBM_ISOTHERMAL)
@@ -637,6 +664,8 @@ int sllbm_set_velocity_set(sllbm_ctx *c, int q1d, const double *xi1d, const doub
     return fail(c, SLLBM_E_UNSUPPORTED,
                 "Pr != 1 needs a velocity set exact to degree 7 (zero equilibrium heat flux)");
   c->vs = vs;
+  c->cs = cs;
+  update_relaxation(c);
   invalidate(c);
   return SLLBM_OK;
 }
@@ -756,11 +785,8 @@ int sllbm_set_physics(sllbm_ctx *c, double dt, double nu, double gamma, double P
   c->gamma = gamma;
   c->Pr = Pr;
   c->model = model;
-  c->tau = std::isinf(nu) ? std::numeric_limits<double>::infinity() : nu / dt + 0.5;
-  c->omega = std::isinf(nu) ? 0.0 : 1.0 / c->tau;
-  // tau_Pr = (tau - 1/2)/Pr + 1/2 (Sec. II.D); exactly omega when Pr = 1
-  c->omega_pr = (Pr == 1.0 || std::isinf(nu)) ? c->omega : 1.0 / ((c->tau - 0.5) / Pr + 0.5);
   c->have_phys = true;
+  update_relaxation(c);
   invalidate(c);
   return SLLBM_OK;
 }
@@ -863,6 +889,21 @@ int sllbm_mass_weights(const sllbm_ctx *c, double *mx, double *my) {
   const std::vector<double> a = c->ax.node_mass(), b = c->ay.node_mass();
   std::memcpy(mx, a.data(), a.size() * sizeof(double));
   std::memcpy(my, b.data(), b.size() * sizeof(double));
+  return SLLBM_OK;
+}
+
+int sllbm_node_masses(const sllbm_ctx *cc, double *m) {
+  sllbm_ctx *c = const_cast<sllbm_ctx *>(cc);
+  if (!c || !m) return SLLBM_E_ARG;
+  if (!c->have_grid) return fail(c, SLLBM_E_STATE, "grid not set");
+  if (c->curvi) {
+    const std::vector<double> M = curvi_node_mass(c->mesh, support_points(c->p, c->glc));
+    std::memcpy(m, M.data(), M.size() * sizeof(double));
+    return SLLBM_OK;
+  }
+  const std::vector<double> a = c->ax.node_mass(), b = c->ay.node_mass();
+  for (int iy = 0; iy < c->ay.n; ++iy)
+    for (int ix = 0; ix < c->ax.n; ++ix) m[size_t(iy) * c->ax.n + ix] = b[iy] * a[ix];
   return SLLBM_OK;
 }
 
@@ -1139,9 +1180,6 @@ int sllbm_moments(sllbm_ctx *c, double *rho, double *ux, double *uy, double *T, 
 
 int sllbm_mass(sllbm_ctx *c, double *mass) {
   if (!c || !mass) return SLLBM_E_ARG;
-  if (c->curvi)
-    return fail(c, SLLBM_E_UNSUPPORTED,
-                "node masses of a curvilinear mesh are not a product of axis weights");
   if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
   int rc = prepare_device(c);
   if (rc) return rc;
@@ -1158,13 +1196,11 @@ int sllbm_mass(sllbm_ctx *c, double *mass) {
 
 int sllbm_mass_noalloc(sllbm_ctx *c, double *mass_dev) {
   if (!c || !mass_dev) return SLLBM_E_ARG;
-  if (c->curvi)
-    return fail(c, SLLBM_E_UNSUPPORTED,
-                "node masses of a curvilinear mesh are not a product of axis weights");
   // no set-up work here: the device tables must already exist (they are
   // built by init_macro / set_populations and stay valid until the set-up
   // changes, which is refused once initialised)
-  if (!c->initialised || c->dev_dirty || !c->mxd.ptr || !c->myd.ptr)
+  if (!c->initialised || c->dev_dirty || !c->mxd.ptr || !c->myd.ptr ||
+      (c->curvi && !c->mnode_d.ptr))
     return fail(c, SLLBM_E_STATE,
                 "populations not initialised (sllbm_init_macro or sllbm_set_populations first)");
   const StepConsts k = make_consts(c);

@@ -1,4 +1,5 @@
 #include "curvilinear.hpp"
+#include "tables.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -168,6 +169,32 @@ std::string curvi_records(const CurviMesh &m, const std::vector<double> &pts,
       s[v] = std::clamp(ss, 0.0, 1.0);
     }
   return "";
+}
+
+std::vector<double> curvi_node_mass(const CurviMesh &m, const std::vector<double> &pts) {
+  const int p = int(pts.size()) - 1;
+  const int nx = m.ncx * p, ny = m.ncy * p;
+  const std::vector<double> W0 = lagrange_moments(pts, 0), W1 = lagrange_moments(pts, 1);
+  std::vector<double> M(size_t(nx) * ny, 0.0);
+  for (int cy = 0; cy < m.ncy; ++cy)
+    for (int cx = 0; cx < m.ncx; ++cx) {
+      double x[4], y[4];  // corners 00, 10, 01, 11
+      m.corners(cx, cy, x, y);
+      // x(r, s) = A0 + A1 r + A2 s + A3 r s; det of [x_r x_s] is
+      // A1 x A2 + (A1 x A3) r + (A3 x A2) s (the r s terms cancel)
+      const double a1x = x[1] - x[0], a1y = y[1] - y[0];
+      const double a2x = x[2] - x[0], a2y = y[2] - y[0];
+      const double a3x = x[0] - x[1] - x[2] + x[3], a3y = y[0] - y[1] - y[2] + y[3];
+      const double J0 = a1x * a2y - a1y * a2x;
+      const double Jr = a1x * a3y - a1y * a3x;
+      const double Js = a3x * a2y - a3y * a2x;
+      for (int b = 0; b <= p; ++b)
+        for (int a = 0; a <= p; ++a) {
+          const int ix = (cx * p + a) % nx, iy = (cy * p + b) % ny;
+          M[size_t(iy) * nx + ix] += J0 * W0[a] * W0[b] + Jr * W1[a] * W0[b] + Js * W0[a] * W1[b];
+        }
+    }
+  return M;
 }
 
 }  // namespace sllbm

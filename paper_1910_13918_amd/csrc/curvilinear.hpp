@@ -40,6 +40,13 @@ void bilinear_map(const double (&x)[4], const double (&y)[4], double r, double s
 void curvi_node_coords(const CurviMesh &m, const std::vector<double> &pts, std::vector<double> &X,
                        std::vector<double> &Y);
 
+// Integral of each node's shape function over the mesh, [ny][nx]: on a cell
+// the local basis l_a(r) l_b(s) times the Jacobian determinant of the
+// bilinear map, which is linear in (r, s) (J = J0 + Jr r + Js s), so the
+// integral is J0 W_a W_b + Jr W1_a W_b + Js W_a W1_b with W = int l and
+// W1 = int r l over [0, 1]; summed over the cells sharing the node.
+std::vector<double> curvi_node_mass(const CurviMesh &m, const std::vector<double> &pts);
+
 // Departure records of every node for the displacement (dx, dy) (the
 // departure point is x + (dx, dy)): cell[v] = cx | cy << 16, r[v], s[v] in
 // [0, 1].  The point is found by a walk from the node's own cell to the

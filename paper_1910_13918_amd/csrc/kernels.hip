@@ -51,8 +51,9 @@ __global__ __launch_bounds__(256) void k_init_eq(const double *__restrict__ rho,
                                                  T *__restrict__ f, StepConsts c) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c.n) return;
-  const double r = rho[v], u = ux[v], w = uy[v];
-  const double th = (MODEL == kIsothermal) ? 1.0 : temp[v];
+  // normalised by the velocity-set scale: u / c_s, theta = T / c_s^2
+  const double r = rho[v], u = ux[v] * c.inv_cs, w = uy[v] * c.inv_cs;
+  const double th = (MODEL == kIsothermal) ? 1.0 : temp[v] * (c.inv_cs * c.inv_cs);
   const long long N = c.n;
   for_each_equilibrium<Q1>(r, u, w, th, c, [&](int i, double feq) {
     f[i * N + v] = T(feq);
@@ -66,6 +67,7 @@ __global__ __launch_bounds__(256) void k_init_eq(const double *__restrict__ rho,
 template <typename T, int MODEL, int Q1 = 5>
 __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const double *__restrict__ mx,
                                                  const double *__restrict__ my,
+                                                 const double *__restrict__ mnode,
                                                  double *__restrict__ rho_o, double *__restrict__ ux_o,
                                                  double *__restrict__ uy_o, double *__restrict__ T_o,
                                                  double *__restrict__ partial, StepConsts c) {
@@ -82,14 +84,15 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
 #pragma unroll
       for (int i = 0; i < Q; ++i) fs[s][i] = f[(s * Q + i) * N + v];
     node_moments<T, MODEL, Q1>(fs, c, m);
+    // physical units: u = c_s u_hat, T = c_s^2 theta
     if (rho_o) rho_o[v] = m[0];
-    if (ux_o) ux_o[v] = m[1];
-    if (uy_o) uy_o[v] = m[2];
-    if (T_o) T_o[v] = m[3];
+    if (ux_o) ux_o[v] = m[1] * c.cs;
+    if (uy_o) uy_o[v] = m[2] * c.cs;
+    if (T_o) T_o[v] = m[3] * (c.cs * c.cs);
     // 32-bit division (nodes < 2^31): the 64-bit form dominated these kernels
     const unsigned vv = unsigned(v), nx = unsigned(c.nx);
     const int ix = int(vv % nx), iy = int(vv / nx);
-    mass = mx[ix] * my[iy] * m[0];
+    mass = (mnode ? mnode[v] : mx[ix] * my[iy]) * m[0];
   }
   const double tot = block_sum_256(mass);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -101,6 +104,7 @@ template <typename T, int Q1 = 5>
 __global__ __launch_bounds__(256) void k_mass(const T *__restrict__ f,
                                               const double *__restrict__ mx,
                                               const double *__restrict__ my,
+                                              const double *__restrict__ mnode,
                                               double *__restrict__ partial, StepConsts c) {
   const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
   double mass = 0.0;
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(256) void k_mass(const T *__restrict__ f,
     // 32-bit division (nodes < 2^31): the 64-bit form dominated these kernels
     const unsigned vv = unsigned(v), nx = unsigned(c.nx);
     const int ix = int(vv % nx), iy = int(vv / nx);
-    mass = mx[ix] * my[iy] * rho;
+    mass = (mnode ? mnode[v] : mx[ix] * my[iy]) * rho;
   }
   const double tot = block_sum_256(mass);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -199,19 +203,21 @@ hipError_t moments_t(const StepConsts &c, const DevTables &t, const void *f, dou
                      double *ux, double *uy, double *temp, double *partial, hipStream_t s) {
   if (!rho && !ux && !uy && !temp) {  // the mass alone needs the f planes only
     if (c.q1 == 3)
-      k_mass<T, 3><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, partial, c);
+      k_mass<T, 3><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, t.mnode,
+                                                  partial, c);
     else
-      k_mass<T><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, partial, c);
+      k_mass<T><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, t.mnode,
+                                               partial, c);
     return hipGetLastError();
   }
   if (c.q1 == 3) {
     if constexpr (MODEL != kIsothermal) return hipErrorInvalidValue;
     else k_moments<T, MODEL, 3><<<mass_blocks(c), 256, 0, s>>>(
-        static_cast<const T *>(f), t.mx, t.my, rho, ux, uy, temp, partial, c);
+        static_cast<const T *>(f), t.mx, t.my, t.mnode, rho, ux, uy, temp, partial, c);
     return hipGetLastError();
   }
-  k_moments<T, MODEL><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my, rho,
-                                                     ux, uy, temp, partial, c);
+  k_moments<T, MODEL><<<mass_blocks(c), 256, 0, s>>>(static_cast<const T *>(f), t.mx, t.my,
+                                                     t.mnode, rho, ux, uy, temp, partial, c);
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ struct StepConsts {
   double lden[5];     // 1 / prod_{n != m} (r_m - r_n)
   int q1;             // 1-D velocities (5: D2Q25; 3: D2Q9, isothermal only)
   int bf16x;          // matrix-core x-pass with bfloat16 operands (the experiment)
+  double cs, inv_cs;  // velocity-set scale: the kernels work in xi / cs, u / cs and T / cs^2
   int perx, pery;     // periodic axes
   int reverse;        // row-segment and records steps: visit the tiles / blocks in reverse order
   double *mom_out;    // optional [K][n]: rho, u_x, u_y (and theta unless isothermal) of
@@ -43,6 +44,7 @@ struct DevTables {
   const double *rnodes;     // p + 1 reference support points (records path)
   const double *mx;     // [nx] mass weights
   const double *my;     // [ny]
+  const double *mnode;  // [n] node mass weights of a curvilinear mesh (else null)
   // tiled path: per-tile source windows (tiles of 64 columns by tile_rows rows)
   const int32_t *yrel;  // [5][p+1][ny]: source row relative to the tile's window
   const int32_t *ywin;  // [5][ntiles_y]: first (unwrapped) source row of the window

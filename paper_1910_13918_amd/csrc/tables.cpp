@@ -90,6 +90,10 @@ void lagrange_weights(const std::vector<double> &pts, double r, double *out) {
 }
 
 std::vector<double> lagrange_integrals(const std::vector<double> &pts) {
+  return lagrange_moments(pts, 0);
+}
+
+std::vector<double> lagrange_moments(const std::vector<double> &pts, int k) {
   const int n = int(pts.size());
   std::vector<double> out(n);
   for (int m = 0; m < n; ++m) {
@@ -105,8 +109,9 @@ std::vector<double> lagrange_integrals(const std::vector<double> &pts) {
       }
       c.swap(nc);
     }
+    // int_0^1 r^k r^t dr = 1 / (t + k + 1)
     double s = 0.0;
-    for (size_t t = 0; t < c.size(); ++t) s += c[t] / double(t + 1);
+    for (size_t t = 0; t < c.size(); ++t) s += c[t] / double(t + k + 1);
     out[m] = s;
   }
   return out;

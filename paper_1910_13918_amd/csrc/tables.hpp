@@ -45,6 +45,9 @@ void lagrange_weights(const std::vector<double> &pts, double r, double *out);
 // Integrals over [0, 1] of each Lagrange polynomial, by exact integration of
 // the monomial expansion.
 std::vector<double> lagrange_integrals(const std::vector<double> &pts);
+// Moments int_0^1 r^k l_m(r) dr of each Lagrange polynomial (k = 0: the
+// integrals above).
+std::vector<double> lagrange_moments(const std::vector<double> &pts, int k);
 
 // One grid direction.
 struct Axis {

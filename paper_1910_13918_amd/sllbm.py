@@ -70,7 +70,7 @@ _SIGS = {
     "sllbm_destroy": ([_vp], None),
     "sllbm_last_error": ([_vp], ctypes.c_char_p),
     "sllbm_set_stream": ([_vp, _vp], _c),
-    "sllbm_set_velocity_set": ([_vp, _c, _vp, _vp], _c),
+    "sllbm_set_velocity_set": ([_vp, _c, _vp, _vp, _d], _c),
     "sllbm_set_order": ([_vp, _c, _c], _c),
     "sllbm_init_grid_uniform": ([_vp, _c, _c, _d, _d, _d, _d, _c, _c], _c),
     "sllbm_init_grid_mapped": ([_vp, _c, _c, _vp, _vp, _c, _c], _c),
@@ -86,6 +86,7 @@ _SIGS = {
     "sllbm_adjoint_nu_term": ([_vp, _vp, _vp, _vp, _vp], _c),
     "sllbm_departure_table": ([_vp, _c, _c, _vp, _vp], _c),
     "sllbm_mass_weights": ([_vp, _vp, _vp], _c),
+    "sllbm_node_masses": ([_vp, _vp], _c),
     "sllbm_relaxation_time": ([_vp, _dp], _c),
     "sllbm_bind_populations": ([_vp, _vp, _vp], _c),
     "sllbm_init_macro": ([_vp, _vp, _vp, _vp, _vp, _c], _c),
@@ -146,8 +147,8 @@ def sllbm_set_stream(ctx, stream):
     return check(ctx, lib.sllbm_set_stream(ctx, stream))
 
 
-def sllbm_set_velocity_set(ctx, q1d, xi1d_ptr, w1d_ptr):
-    return check(ctx, lib.sllbm_set_velocity_set(ctx, q1d, xi1d_ptr, w1d_ptr))
+def sllbm_set_velocity_set(ctx, q1d, xi1d_ptr, w1d_ptr, cs=1.0):
+    return check(ctx, lib.sllbm_set_velocity_set(ctx, q1d, xi1d_ptr, w1d_ptr, cs))
 
 
 def sllbm_set_order(ctx, p, nodes):
@@ -214,6 +215,10 @@ def sllbm_departure_table(ctx, axis, comp, src_ptr, w_ptr):
 
 def sllbm_mass_weights(ctx, mx_ptr, my_ptr):
     return check(ctx, lib.sllbm_mass_weights(ctx, mx_ptr, my_ptr))
+
+
+def sllbm_node_masses(ctx, m_ptr):
+    return check(ctx, lib.sllbm_node_masses(ctx, m_ptr))
 
 
 def sllbm_relaxation_time(ctx):

@@ -28,7 +28,7 @@ def _ptr(a):
 class Solver:
     def __init__(self, *, p, edges_x, edges_y, periodic_x, periodic_y, dt, nu, model,
                  gamma=1.4, precision="fp32", uniform=True, path="auto", device=0,
-                 nodes="glc", xi1d=None, w1d=None, Pr=1.0, vertices=None, q1d=5):
+                 nodes="glc", xi1d=None, w1d=None, Pr=1.0, vertices=None, q1d=5, cs=1.0):
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a HIP device (torch.cuda is not available)")
         self.device = torch.device("cuda", device)
@@ -41,9 +41,10 @@ class Solver:
             if xi1d is not None:
                 self._xi = np.ascontiguousarray(xi1d, dtype=np.float64)
                 self._w = np.ascontiguousarray(w1d, dtype=np.float64)
-                C.sllbm_set_velocity_set(self.ctx, len(self._xi), _ptr(self._xi), _ptr(self._w))
-            elif q1d != 5:  # the library's default set of that size (3: D2Q9)
-                C.sllbm_set_velocity_set(self.ctx, q1d, None, None)
+                C.sllbm_set_velocity_set(self.ctx, len(self._xi), _ptr(self._xi), _ptr(self._w),
+                                         cs)
+            elif q1d != 5 or cs != 1.0:  # the library's default set of that size (3: D2Q9)
+                C.sllbm_set_velocity_set(self.ctx, q1d, None, None, cs)
             C.sllbm_set_order(self.ctx, p, C.NODES_GLC if nodes == "glc" else C.NODES_EQUIDISTANT)
             bcx = C.PERIODIC if periodic_x else C.ZERO_GRADIENT
             bcy = C.PERIODIC if periodic_y else C.ZERO_GRADIENT
@@ -83,7 +84,7 @@ class Solver:
         s = cls(p=wl.p, edges_x=wl.edges_x, edges_y=wl.edges_y, periodic_x=wl.periodic_x,
                 periodic_y=wl.periodic_y, dt=wl.dt, nu=wl.nu, model=wl.model, gamma=wl.gamma,
                 precision=precision, uniform=wl.uniform, path=path, device=device, nodes=nodes,
-                Pr=wl.Pr, vertices=wl.vertices, q1d=wl.q1)
+                Pr=wl.Pr, vertices=wl.vertices, q1d=wl.q1, cs=wl.cs)
         s.workload = wl
         return s
 

@@ -64,6 +64,7 @@ class Workload:
     Pr: float = 1.0       # Prandtl number (Sec. II.C-D)
     vertices: tuple = None  # (vx, vy) [ncy + 1][ncx + 1] of a curvilinear mesh, else None
     q1: int = 5           # velocities per axis of the tensor-product set (5: D2Q25, 3: D2Q9)
+    cs: float = 1.0       # scale of the velocity set (Sec. II.B; 1: unscaled)
 
     @property
     def ncx(self):

@@ -153,3 +153,33 @@ def test_records_of_an_axis_grid_match_its_tables():
                      s.ctypes.data) == C.E_ARG
     finally:
         C.sllbm_destroy(ctx)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_node_masses_match_the_oracle(p):
+    """The library's node masses on wavy bilinear cells (closed form of the
+    Jacobian, which is linear in (r, s)) against the oracle's tensor
+    Gauss-Legendre quadrature of l_a l_b |J|; on an axis grid the same query
+    gives the product of the per-axis weights."""
+    vx, vy = _mesh()
+    ctx = _ctx(vx, vy, p)
+    try:
+        nx, ny = C.sllbm_num_nodes(ctx)
+        m = np.zeros(nx * ny)
+        C.sllbm_node_masses(ctx, m.ctypes.data)
+        want = CurviGrid(vx, vy, p).node_mass()
+        np.testing.assert_allclose(m, want, rtol=1e-13, atol=1e-15)
+    finally:
+        C.sllbm_destroy(ctx)
+    ctx = C.sllbm_create(0, C.FP64)
+    try:
+        C.sllbm_set_order(ctx, p, C.NODES_GLC)
+        C.sllbm_init_grid_uniform(ctx, 5, 4, 0.0, 1.0, 0.0, 2.0, C.PERIODIC, C.ZERO_GRADIENT)
+        nx, ny = C.sllbm_num_nodes(ctx)
+        m = np.zeros(nx * ny)
+        mx, my = np.zeros(nx), np.zeros(ny)
+        C.sllbm_node_masses(ctx, m.ctypes.data)
+        C.sllbm_mass_weights(ctx, mx.ctypes.data, my.ctypes.data)
+        np.testing.assert_allclose(m, np.outer(my, mx).reshape(-1), rtol=1e-15)
+    finally:
+        C.sllbm_destroy(ctx)

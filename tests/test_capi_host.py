@@ -191,6 +191,9 @@ def test_velocity_set_validation():
         w[2] = -1.0
         assert _code(C.sllbm_set_velocity_set, ctx, 5, xi.ctypes.data, w.ctypes.data) == C.E_ARG
         assert _code(C.sllbm_set_velocity_set, ctx, 5, xi.ctypes.data, None) == C.E_ARG
+        assert _code(C.sllbm_set_velocity_set, ctx, 5, None, None, 0.0) == C.E_ARG
+        assert _code(C.sllbm_set_velocity_set, ctx, 5, None, None, float("nan")) == C.E_ARG
+        assert _code(C.sllbm_set_velocity_set, ctx, 5, None, None, -1.0) == C.E_ARG
         C.sllbm_set_velocity_set(ctx, 5, None, None)
     finally:
         C.sllbm_destroy(ctx)
@@ -353,5 +356,43 @@ def test_records_pack_cell_rows_above_32767():
             np.testing.assert_array_equal(u >> 16, cy)
             np.testing.assert_array_equal(u & 0xFFFF, cx)
             np.testing.assert_allclose(s[nodes], ry, atol=1e-9)
+    finally:
+        C.sllbm_destroy(ctx)
+
+
+def test_scaled_velocity_set_tables_and_tau():
+    """A velocity set scaled by c_s = 1.7 (Sec. II.B): departure weights of
+    the library's tables against the oracle's brute-force stencils of the
+    scaled set, and tau = nu / (c_s^2 dt) + 1/2, whichever of the set-up
+    calls comes last."""
+    wl = W.riemann(6, 3, states=W.RIEMANN_TABLE3_STATES)
+    cs = 1.7
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, cs=cs)
+    ctx = _ctx()
+    try:
+        C.sllbm_set_order(ctx, wl.p, C.NODES_GLC)
+        C.sllbm_init_grid_uniform(ctx, 6, 6, 0.0, 1.0, 0.0, 1.0, C.ZERO_GRADIENT, C.ZERO_GRADIENT)
+        C.sllbm_set_physics(ctx, wl.dt, wl.nu, wl.gamma, 1.0, C.POLYATOMIC)
+        C.sllbm_set_velocity_set(ctx, 5, None, None, cs)
+        assert C.sllbm_relaxation_time(ctx) == pytest.approx(sim.tau, rel=1e-15)
+        P1 = wl.p + 1
+        nodes = np.arange(g.nnodes)
+        for i in (1, 7, 18, 24):
+            a, b = i % 5, i // 5
+            sx, wx = np.zeros(g.nx * P1, dtype=np.int32), np.zeros(g.nx * P1)
+            sy, wy = np.zeros(g.ny * P1, dtype=np.int32), np.zeros(g.ny * P1)
+            C.sllbm_departure_table(ctx, 0, a, sx.ctypes.data, wx.ctypes.data)
+            C.sllbm_departure_table(ctx, 1, b, sy.ctypes.data, wy.ctypes.data)
+            sx, wx, sy, wy = sx.reshape(-1, P1), wx.reshape(-1, P1), sy.reshape(-1, P1), wy.reshape(-1, P1)
+            osrc, owgt = sim.departure_stencil(i, nodes)
+            ix, iy = nodes % g.nx, nodes // g.nx
+            M_o = np.zeros((g.nnodes, g.nnodes))
+            M_l = np.zeros((g.nnodes, g.nnodes))
+            for m in range(P1):
+                for k in range(P1):
+                    np.add.at(M_o, (nodes, osrc[m, k]), owgt[m, k])
+                    np.add.at(M_l, (nodes, sy[iy, k] * g.nx + sx[ix, m]), wx[ix, m] * wy[iy, k])
+            np.testing.assert_allclose(M_l, M_o, rtol=0, atol=2e-13)
     finally:
         C.sllbm_destroy(ctx)

@@ -368,6 +368,51 @@ def test_nu_gradient_matches_complex_step(model):
     assert got == pytest.approx(ref, rel=1e-9)
 
 
+@pytest.mark.parametrize("model,tau", [("isothermal", 0.8), ("polyatomic", 0.8),
+                                       ("monatomic", 1.5)])
+def test_nu_gradient_fp32_against_fp64(model, tau):
+    """dL/d(nu) with float32 populations against the float64 path (10 steps,
+    8 x 8 cells p = 3).  The term rebuilds f - f_eq before the collision as
+    (f+ - f_eq) / (1 - 1/tau) from stored post-collision values: float32
+    rounding of f+ (2^-24 relative) divided by the non-equilibrium part
+    (about 1e-3 of f here) and amplified by 1 / |1 - 1/tau| (4 at tau = 0.8,
+    3 at tau = 1.5; unbounded as tau -> 1, where the library refuses the
+    exact value tau = 1).  Measured: 8.7e-7 (isothermal, tau = 0.8), 8.3e-7
+    (polyatomic, 0.8), 1.2e-7 (monatomic, 1.5); bound 1e-5 relative."""
+    from paper_1910_13918_amd.adjoint import nu_gradient
+    wl = W.tgv(8, 3, U0=0.3, steps=10)
+    if model != "isothermal":
+        wl = _thermal(wl, model, periodic=True)
+    wl.nu = (tau - 0.5) * wl.dt
+    out = {}
+    for prec in ("fp64", "fp32"):
+        s = _solver(wl, prec)
+        try:
+            X, Y = s.coords()
+            f0 = wl.fields(X, Y)
+            ut, vt = W.fourier_target(X, Y, 0.3, seed=99)
+            Tt = 1.0 + 0.05 * np.sin(X)
+            M = _mass_weights(s)
+            t = lambda a: torch.tensor(a, device="cuda")
+
+            def loss_grad(*m):
+                leaves = [a.detach().clone().requires_grad_(True) for a in m]
+                L = _loss_torch(leaves[0], leaves[1], leaves[2], M, t(ut), t(vt))
+                if len(leaves) == 4:
+                    L = L + (M * (leaves[3] - t(Tt)) ** 2).sum()
+                L.backward()
+                return [a.grad for a in leaves]
+
+            T0 = f0[3] if model != "isothermal" else None
+            out[prec] = nu_gradient(s, f0[0], f0[1], f0[2], 10, loss_grad, T0=T0)
+        finally:
+            s.close()
+    rel = abs(out["fp32"] - out["fp64"]) / abs(out["fp64"])
+    print(f"[gpu] nu gradient {model} tau={tau}: fp32 {out['fp32']:.9e} fp64 {out['fp64']:.9e} "
+          f"rel {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+
+
 def test_nu_term_refused_at_tau_one():
     from paper_1910_13918_amd import sllbm as C
     wl = W.tgv(4, 2, U0=0.1)

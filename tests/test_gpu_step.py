@@ -114,9 +114,19 @@ def test_one_step_fp64_seeded_extreme_states(path):
     try:
         s.set_populations(F0)
         s.step(1)
-        assert _rel(s.populations(), F1) <= 1e-12 * max(1.0, kappa.max())
+        G1 = s.populations()
     finally:
         s.close()
+    bound = 1e-12 * max(1.0, kappa.max())  # seed 5: kappa = 131, bound 1.3e-10
+    err = _rel(G1, F1)
+    # every plane against its own magnitude as well (the smallest-weight
+    # planes are ~1e-4 of the largest, so the global ratio alone would not
+    # see an error confined to them)
+    plane = np.abs(G1 - F1).max(axis=2) / np.abs(F1).max(axis=2)
+    print(f"[gpu] extreme states {path}: kappa {kappa.max():.1f}, bound {bound:.2e}, "
+          f"error {err:.2e}, worst plane {plane.max():.2e}", flush=True)
+    assert err <= bound
+    assert plane.max() <= bound
 
 
 @pytest.mark.parametrize("path", ["direct", "tiled", "records", "rows"])

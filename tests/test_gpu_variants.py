@@ -108,3 +108,53 @@ def test_order_sweep_taylor_green():
     print("[gpu] Taylor-Green order sweep errors", errs, flush=True)
     assert errs[0] > 10 * errs[1] > 0 and errs[1] > 3 * errs[2]
     assert errs[3] <= 1.5 * errs[2]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("model,cs,path", [("polyatomic", 1.7, "auto"), ("polyatomic", 1.15, "records"),
+                                           ("monatomic", 1.3, "tiled"), ("isothermal", 0.8, "direct"),
+                                           ("polyatomic", 1.7, "rows")])
+def test_scaled_velocity_set_one_step_and_trajectory(model, cs, path, precision):
+    """A velocity set scaled by c_s (Sec. II.B): one step from perturbed
+    populations and a 20-step trajectory of the moments (physical units)
+    against the oracle's scaled set.  The library holds the second population
+    as g / c_s^2.  (The scale moves theta = T / c_s^2: c_s = 0.6 puts the
+    Table III states at theta up to 3.5, where the equilibrium has entries of
+    both signs and the run blows up on either side.)"""
+    from oracle.grid import Grid
+    from oracle.sllbm import Sim
+    from paper_1910_13918_amd.solver import Solver
+    wl = W.riemann(21, 2, states=W.RIEMANN_TABLE3_STATES) if model == "polyatomic" else \
+        W.tgv(21, 2, U0=0.2, model=model)
+    wl.cs = cs
+    wl.dt = wl.dt / cs  # the same CFL number with the faster velocities
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, wl.periodic_x, wl.periodic_y)
+    sim = Sim(g, wl.dt, wl.nu, wl.model, gamma=wl.gamma, cs=cs)
+    X, Y = g.coords()
+    rho, ux, uy, T = wl.fields(X, Y)
+    if model == "monatomic":
+        T = 0.8 + 0.3 * np.cos(X) * np.sin(Y)
+    F0 = sim.init(rho, ux, uy, T)
+    scale = np.ones((F0.shape[0], 1, 1))
+    scale[-1] = 1.0 / cs ** 2 if sim.S == 2 else 1.0  # g held as g / cs^2
+    Fp = F0 * W.population_noise(F0.shape, 5, 0.05)
+    F1 = sim.step(Fp)
+    F20 = sim.run(F0, 20)
+    s = Solver.from_workload(wl, precision=precision, path=path)
+    try:
+        print(f"[gpu] scaled set cs={cs} {model} {path} {precision}", flush=True)
+        assert s.relaxation_time() == pytest.approx(sim.tau, rel=1e-14)
+        s.set_populations(Fp * scale)
+        s.step(1)
+        G1 = s.populations().astype(np.float64) / scale
+        s.init_macro(rho, ux, uy, T)
+        s.step(20)
+        got = s.moments()
+        assert s.flags()[0] == 0
+    finally:
+        s.close()
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    assert np.abs(G1 - F1).max() / np.abs(F1).max() <= tol
+    want = sim.macro(F20)
+    for k in range(4):
+        assert np.abs(got[k] - want[k]).max() <= 50 * tol * max(1.0, np.abs(want[k]).max()), k
