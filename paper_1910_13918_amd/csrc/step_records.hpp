@@ -6,6 +6,7 @@
 
 #include "launch.hpp"
 #include "step_common.hpp"
+#include "tiled_common.hpp"
 
 namespace sllbm {
 
@@ -45,20 +46,29 @@ __device__ __forceinline__ T records_interp(__amdgpu_buffer_rsrc_t rs, const uns
 template <typename T, int S>
 constexpr bool records_gather_ahead() { return sizeof(T) == 4 && S == 2; }
 
+// Nodes per workgroup: tiles of 64 x 4 nodes (one wavefront per row), so
+// that the stencils a workgroup reads from neighbouring rows overlap.
+constexpr int kRecTileRows = 4;
+
 template <typename T, int P, int MODEL, bool PR, int Q1 = 5>
-__global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
-                                                      T *__restrict__ fout,
-                                                      const int32_t *__restrict__ cell,
-                                                      const T *__restrict__ rr,
-                                                      const T *__restrict__ ss, StepConsts c,
-                                                      int *__restrict__ flag) {
+__global__ __launch_bounds__(64 * kRecTileRows) void k_step_records(
+    const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ cell,
+    const T *__restrict__ rr, const T *__restrict__ ss, int ntx, int nty, int strip,
+    StepConsts c, int *__restrict__ flag) {
   constexpr int S = Sets<MODEL>::S;
   constexpr int P1 = P + 1;
   constexpr int Q = Q1 * Q1;
-  // every other step may visit the blocks backwards (see StepConsts::reverse)
-  const unsigned bid = c.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
-  const long long v = (long long)bid * blockDim.x + threadIdx.x;
-  if (v >= c.n) return;
+  // XCD-aware, strip-major tile order; every other step may visit the tiles
+  // backwards (see StepConsts::reverse)
+  int tile = xcd_tile(blockIdx.x, ntx * nty);
+  if (tile >= ntx * nty) return;
+  if (c.reverse) tile = ntx * nty - 1 - tile;
+  int tx, ty;
+  strip_tile(tile, ntx, nty, strip, tx, ty);
+  const int ix = tx * 64 + (threadIdx.x & 63);
+  const int iy = ty * kRecTileRows + (threadIdx.x >> 6);
+  if (ix >= c.nx || iy >= c.ny) return;
+  const long long v = (long long)iy * c.nx + ix;
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   const unsigned voff = unsigned(v) * unsigned(sizeof(T));
@@ -200,25 +210,32 @@ __global__ __launch_bounds__(256) void k_step_records(const T *__restrict__ fin,
 template <bool PR>
 hipError_t launch_records_family(int fp32, int model, const StepConsts &c, const DevTables &t,
                                  const void *fin, void *fout, int *flag, hipStream_t s) {
+  const int ntx = (c.nx + 63) / 64, nty = (c.ny + kRecTileRows - 1) / kRecTileRows;
+  const int grid = ((ntx * nty + 7) / 8) * 8;
+  // strip-major order on wide grids (strip_tile); with the 64 x 4 tiles it
+  // took the shock-vortex records gather from 1.45x to 1.10x the algorithmic
+  // HBM bytes (the one-dimensional order of 256-node blocks put vertical
+  // neighbours on other XCDs), step time -3 %
+  const int strip = ntx <= 24 ? ntx : 16;
   if (c.q1 == 3) {  // D2Q9: isothermal BGK
     if constexpr (PR) {
       return hipErrorInvalidValue;
     } else {
       return dispatch_q3(fp32, c.p, model, [&]<typename T, int P>() {
-        const unsigned blocks = unsigned((c.n + 255) / 256);
-        k_step_records<T, P, kIsothermal, false, 3><<<blocks, 256, 0, s>>>(
+        k_step_records<T, P, kIsothermal, false, 3><<<grid, 64 * kRecTileRows, 0, s>>>(
             static_cast<const T *>(fin), static_cast<T *>(fout), t.rec_cell,
-            static_cast<const T *>(t.rec_r), static_cast<const T *>(t.rec_s), c, flag);
+            static_cast<const T *>(t.rec_r), static_cast<const T *>(t.rec_s), ntx, nty, strip, c,
+            flag);
         return hipGetLastError();
       });
     }
   }
   if (c.q1 != 5) return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
-    const unsigned blocks = unsigned((c.n + 255) / 256);
-    k_step_records<T, P, MODEL, PR><<<blocks, 256, 0, s>>>(
+    k_step_records<T, P, MODEL, PR><<<grid, 64 * kRecTileRows, 0, s>>>(
         static_cast<const T *>(fin), static_cast<T *>(fout), t.rec_cell,
-        static_cast<const T *>(t.rec_r), static_cast<const T *>(t.rec_s), c, flag);
+        static_cast<const T *>(t.rec_r), static_cast<const T *>(t.rec_s), ntx, nty, strip, c,
+        flag);
     return hipGetLastError();
   });
 }

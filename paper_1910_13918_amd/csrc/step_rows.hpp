@@ -186,14 +186,16 @@ __global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
                              (rows_min_waves<T, Sets<MODEL>::S>())) void k_step_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
     const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc,
-    const T *__restrict__ yw, int TX, int ntx, int nty, StepConsts c, int *__restrict__ flag) {
+    const T *__restrict__ yw, int TX, int ntx, int nty, int strip, StepConsts c,
+    int *__restrict__ flag) {
   constexpr int S = Sets<MODEL>::S;
   constexpr int R = rows_tile_rows<T, Sets<MODEL>::S>();
   __shared__ T rows_lds[R][2][64];
   int tile = xcd_tile(blockIdx.x, ntx * nty);
   if (tile >= ntx * nty) return;
   if (c.reverse) tile = ntx * nty - 1 - tile;
-  const int tx = tile % ntx, ty = tile / ntx;
+  int tx, ty;
+  strip_tile(tile, ntx, nty, strip, tx, ty);
   const int lane = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
   // rows past the grid stream the last row (every wavefront must reach the
@@ -207,6 +209,15 @@ __global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
   if (ix < c.nx && lane < TX && iy_t < c.ny)
     collide_store<T, MODEL, PR, Q1>(fs, c, fout, (long long)iy * c.nx + ix, flag);
 }
+
+// Segments per strip of the strip-major tile order (strip_tile): rows of up
+// to 24 segments keep the row-major order; wider ones (the 3073-node rows of
+// the shock-vortex grid: 68 segments) go in strips of 16, so that a tile's
+// vertical neighbours, which re-read its source rows, run 16 tiles later on
+// the same XCD rather than a whole row later, when those rows have left its
+// L2 cache.  Measured on the shock-vortex grid (float32, Pr = 0.75): HBM
+// traffic 1.34x -> 1.06x the algorithmic bytes, step time -2 %.
+inline int rows_strip(int ntx) { return ntx <= 24 ? ntx : 16; }
 
 // PR: the Pr != 1 collision (thermal models only)
 template <bool PR>
@@ -227,7 +238,7 @@ hipError_t launch_rows_family(int fp32, int model, const StepConsts &c, const De
         k_step_rows<T, P, kIsothermal, false, 3><<<grid, dim3(64, R), 0, s>>>(
             static_cast<const T *>(fin), static_cast<T *>(fout), t.rows_xrel,
             static_cast<const T *>(t.xw), t.rows_xwin, t.ysrc, static_cast<const T *>(t.yw),
-            t.rows_tx, ntx, nty, c, flag);
+            t.rows_tx, ntx, nty, rows_strip(ntx), c, flag);
         return hipGetLastError();
       });
     }
@@ -241,7 +252,7 @@ hipError_t launch_rows_family(int fp32, int model, const StepConsts &c, const De
     k_step_rows<T, P, MODEL, PR><<<grid, dim3(64, R), 0, s>>>(
         static_cast<const T *>(fin), static_cast<T *>(fout), t.rows_xrel,
         static_cast<const T *>(t.xw), t.rows_xwin, t.ysrc, static_cast<const T *>(t.yw),
-        t.rows_tx, ntx, nty, c, flag);
+        t.rows_tx, ntx, nty, rows_strip(ntx), c, flag);
     return hipGetLastError();
   });
 }

@@ -401,6 +401,27 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
   return (bid & 7) * per + (bid >> 3);
 }
 
+// Tile (tx, ty) of position t of the strip-major order: the columns of tiles
+// are grouped in strips of `strip` columns (the last one may be narrower),
+// each strip is walked row by row, and the strips follow each other.  Tiles
+// that read the same source rows (vertical neighbours) then run `strip`
+// positions apart instead of ntx; strip >= ntx is the row-major order.
+__device__ __forceinline__ void strip_tile(int t, int ntx, int nty, int strip, int &tx, int &ty) {
+  const int full = ntx / strip;               // strips of full width
+  const int per_strip = strip * nty;
+  const int s = t / per_strip;
+  if (s < full) {
+    const int r = t - s * per_strip;
+    ty = r / strip;
+    tx = s * strip + r % strip;
+  } else {                                    // the narrower last strip
+    const int w = ntx - full * strip;
+    const int r = t - full * per_strip;
+    ty = r / w;
+    tx = full * strip + r % w;
+  }
+}
+
 // LDS bytes of a tiled launch: two raw window buffers (S G planes of W rows
 // of `pitch` columns), 64 spare slots, and for the separable forms the
 // x-pass buffer.
