@@ -36,11 +36,17 @@
  *     step / moments / mass / get_populations.  Changing the order, grid or
  *     physics after initialisation returns SLLBM_E_STATE.
  *   - Node arrays are node-major: element (iy, ix) at iy * nx + ix, float64.
- *   - Populations are structure-of-arrays [S][Q][ny][nx] of the population
- *     type (float64 for SLLBM_FP64, float32 for SLLBM_FP32), with S = 2 for
- *     the polyatomic model (f then g) and 1 otherwise, and i = a + q1 * b
- *     for the velocity (xi_a, xi_b) (g divided by cs^2 for a scaled
- *     velocity set, sllbm_set_velocity_set).
+ *   - Populations cross the boundary (get / set_populations, the adjoint's
+ *     arrays) as structure-of-arrays [S][Q][ny][nx] of the population type
+ *     (float64 for SLLBM_FP64, float32 for SLLBM_FP32), with S = 2 for the
+ *     polyatomic model (f then g) and 1 otherwise, and i = a + q1 * b for
+ *     the velocity (xi_a, xi_b) (g divided by cs^2 for a scaled velocity
+ *     set, sllbm_set_velocity_set).  Inside the two state buffers (bound or
+ *     the library's own) the order depends on the kernel family that runs:
+ *     the row-segment step keeps the q1 - 1 values a = 1 .. q1-1 of each
+ *     velocity row b together per node (then the planes of a = 0), the
+ *     other gathers the order above; the library converts on a change of
+ *     path.  Read and write the state through get / set_populations only.
  *   - Device pointers are HIP device addresses on the context's device.
  *     Kernels run asynchronously on the bound stream (default: the null
  *     stream); calls that return host data synchronise that stream.
@@ -267,8 +273,10 @@ int sllbm_relaxation_time(const sllbm_ctx *ctx, double *tau);
 
 /* Use two caller-owned device buffers of S*Q*nx*ny population values each
  * as the ping-pong pair.  The caller keeps ownership and must keep them
- * alive while the context uses them.  Without this call the library
- * allocates the pair itself. */
+ * alive while the context uses them; their contents are the library's (in
+ * its internal order, see the header comment), to be read and written
+ * through sllbm_get_populations / sllbm_set_populations.  Without this call
+ * the library allocates the pair itself. */
 int sllbm_bind_populations(sllbm_ctx *ctx, void *dev_a, void *dev_b);
 
 /* Initialise populations at equilibrium: f = f_eq(rho, u, theta) and, for
@@ -332,9 +340,11 @@ int sllbm_mass(sllbm_ctx *ctx, double *mass);
  * on every grid, as sllbm_mass. */
 int sllbm_mass_noalloc(sllbm_ctx *ctx, double *mass_dev);
 
-/* Copy the current populations out / in ([S][Q][ny][nx], population type).
- * set_populations makes the given state current (step counter unchanged,
- * stability flag cleared). */
+/* Copy the current populations out / in ([S][Q][ny][nx], population type,
+ * whatever order the state buffers hold).  set_populations makes the given
+ * state current (step counter unchanged, stability flag cleared).  A device
+ * pointer must not be one of the context's two state buffers (SLLBM_E_ARG);
+ * both calls may use the buffer that does not hold the state as staging. */
 int sllbm_get_populations(sllbm_ctx *ctx, void *dst, int on_device);
 int sllbm_set_populations(sllbm_ctx *ctx, const void *src, int on_device);
 

@@ -41,7 +41,8 @@ namespace sllbm {
 
 
 // ---------------------------------------------------------------------------
-// lambda^N = dL/dF from dL/d(rho, u, theta) of the current populations:
+// lambda^N = dL/dF from dL/d(rho, u, theta) of the current populations (f in
+// the storage order c.layout; lambda, like every adjoint array, planar):
 //   lam_f_k = g_rho + g_u . (xi_k - u) / rho
 //             + g_theta (|xi_k - u|^2 - 2 C_v theta) / (2 C_v rho),
 //   lam_g_k = g_theta / (2 C_v rho)                 (g_theta = 0 if absent)
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(256) void k_adjoint_seed(const T *__restrict__ f,
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int i = 0; i < 25; ++i) fs[s][i] = f[(s * 25 + i) * c.n + v];
+    for (int i = 0; i < 25; ++i) fs[s][i] = f[pop_elem(c.layout, 5, s, i % 5, i / 5, v, c.n)];
   double m[4];
   node_moments<T, MODEL>(fs, c, m);
   const double inv_rho = 1.0 / m[0];

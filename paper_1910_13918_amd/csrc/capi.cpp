@@ -92,6 +92,7 @@ struct sllbm_ctx {
   bool own_pop = false;
   size_t pop_bytes = 0;
   int cur = 0;
+  int layout = kPlanar;  // storage order (PopLayout) of pop[cur]
   bool initialised = false;
   int64_t steps_done = 0;
 };
@@ -133,20 +134,24 @@ int ready_for_tables(sllbm_ctx *c) {
 // Unwrapped indices keep the window contiguous across a periodic seam.
 // Returns the widest window.
 int build_windows(const AxisTable *t, int nq1, int n, int tile, std::vector<int32_t> &win,
-                  std::vector<int32_t> &rel) {
+                  std::vector<int32_t> &rel, bool shared_moving = false) {
   const int taps = t[0].taps;
   const int ntiles = (n + tile - 1) / tile;
   win.assign(size_t(nq1) * ntiles, 0);
   rel.assign(size_t(nq1) * taps * n, 0);
   int width = 0;
   for (int a = 0; a < nq1; ++a) {
+    // shared_moving: components 1 .. nq1-1 share one window per tile (the
+    // union of their stencils)
+    const int a0 = shared_moving && a > 0 ? 1 : a, a1 = shared_moving && a > 0 ? nq1 : a + 1;
     for (int k = 0; k < ntiles; ++k) {
       const int j0 = k * tile, j1 = std::min(j0 + tile, n);
       long lo = std::numeric_limits<long>::max(), hi = std::numeric_limits<long>::min();
-      for (int j = j0; j < j1; ++j) {
-        lo = std::min(lo, t[a].start[j]);
-        hi = std::max(hi, t[a].start[j] + taps - 1);
-      }
+      for (int b = a0; b < a1; ++b)
+        for (int j = j0; j < j1; ++j) {
+          lo = std::min(lo, t[b].start[j]);
+          hi = std::max(hi, t[b].start[j] + taps - 1);
+        }
       win[size_t(a) * ntiles + k] = int32_t(lo);
       width = std::max<int>(width, int(hi - lo + 1));
       for (int j = j0; j < j1; ++j)
@@ -179,10 +184,10 @@ bool mfma_blocks_fit(const sllbm_ctx *c) {
 // x-stencils fit 64 consecutive source columns for every segment and 1-D
 // velocity; its windows go to win / rel.  0 when none does.
 int rows_segment_width(const AxisTable *t, int nq1, int n, std::vector<int32_t> &win,
-                       std::vector<int32_t> &rel) {
+                       std::vector<int32_t> &rel, bool shared_moving = false) {
   int tx = 64;
   while (tx >= kRowsMinCols) {
-    const int width = build_windows(t, nq1, n, tx, win, rel);
+    const int width = build_windows(t, nq1, n, tx, win, rel, shared_moving);
     if (width <= 64) return tx;
     tx -= width - 64;
   }
@@ -224,7 +229,9 @@ void build_host_tables(sllbm_ctx *c) {
   c->win_rows = build_windows(c->yt, q1(c), c->ay.n, kTileRows, c->ywin, c->yrel);
   c->win_cols = build_windows(c->xt, q1(c), c->ax.n, kTileCols, c->xwin, c->xrel);
   c->mfma_blocks_ok = mfma_blocks_fit(c);
-  c->rows_tx = rows_segment_width(c->xt, q1(c), c->ax.n, c->rows_xwin, c->rows_xrel);
+  // the forward step reads the moving x-components of a node with one wide
+  // load, so they share a window per segment
+  c->rows_tx = rows_segment_width(c->xt, q1(c), c->ax.n, c->rows_xwin, c->rows_xrel, true);
   c->ident_x = c->ident_y = 0;
   for (int b = 0; b < q1(c); ++b) {
     if (identity_table(c->xt[b], c->ax.n)) c->ident_x |= 1 << b;
@@ -413,6 +420,7 @@ StepConsts make_consts(const sllbm_ctx *c) {
   }
   k.perx = c->ax.periodic;
   k.pery = c->ay.periodic;
+  k.layout = c->layout;
   return k;
 }
 
@@ -443,6 +451,21 @@ DevTables make_tables(const sllbm_ctx *c) {
   t.ident_x = c->ident_x;
   t.ident_y = c->ident_y;
   return t;
+}
+
+// Storage order a path streams: the row-segment step the grouped order
+// (PopLayout), every other gather the planar one.
+int path_layout(int path) { return path == kPathRows ? kGrouped : kPlanar; }
+
+// Brings the state pop[cur] into `layout`, through the other buffer (which
+// holds nothing between steps).
+int to_layout(sllbm_ctx *c, int layout) {
+  if (c->layout == layout) return SLLBM_OK;
+  HIP_TRY(c, launch_relayout(c->fp32, nsets(c), make_consts(c), c->pop[c->cur],
+                             c->pop[1 - c->cur], layout == kGrouped, c->stream));
+  c->cur ^= 1;
+  c->layout = layout;
+  return SLLBM_OK;
 }
 
 int ensure_populations(sllbm_ctx *c) {
@@ -967,6 +990,7 @@ int sllbm_init_macro(sllbm_ctx *c, const double *rho, const double *ux, const do
     }
   }
   c->cur = 0;
+  c->layout = path_layout(effective_path(c));  // written in the order the next step reads
   HIP_TRY(c, launch_init_eq(c->fp32, c->model, make_consts(c), d[0], d[1], d[2], d[3],
                             c->pop[0], c->stream));
   rc = clear_flag(c);
@@ -1019,6 +1043,8 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
     return fail(c, SLLBM_E_UNSUPPORTED,
                 "matrix-core path needs float32, at most 16 set x window rows and departures "
                 "within one node spacing of their cell");
+  rc = to_layout(c, path_layout(path));  // after a change of path
+  if (rc) return rc;
   StepConsts k = make_consts(c);
   const DevTables t = make_tables(c);
   int *flag = static_cast<int *>(c->flag.ptr);
@@ -1219,8 +1245,17 @@ int sllbm_mass_noalloc(sllbm_ctx *c, double *mass_dev) {
 int sllbm_get_populations(sllbm_ctx *c, void *dst, int on_device) {
   if (!c || !dst) return SLLBM_E_ARG;
   if (!c->initialised) return fail(c, SLLBM_E_STATE, "populations not initialised");
+  if (on_device && (dst == c->pop[0] || dst == c->pop[1]))
+    return fail(c, SLLBM_E_ARG, "destination is one of the context's population buffers");
   HIP_TRY(c, hipSetDevice(c->device));
-  HIP_TRY(c, hipMemcpyAsync(dst, c->pop[c->cur], c->pop_bytes,
+  const void *src = c->pop[c->cur];
+  if (c->layout != kPlanar) {  // to the planar order of the ABI
+    void *planar = on_device ? dst : c->pop[1 - c->cur];
+    HIP_TRY(c, launch_relayout(c->fp32, nsets(c), make_consts(c), src, planar, 0, c->stream));
+    if (on_device) return SLLBM_OK;
+    src = planar;
+  }
+  HIP_TRY(c, hipMemcpyAsync(dst, src, c->pop_bytes,
                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                             c->stream));
   if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1234,10 +1269,25 @@ int sllbm_set_populations(sllbm_ctx *c, const void *src, int on_device) {
   rc = prepare_device(c);
   if (!rc) rc = ensure_populations(c);
   if (rc) return rc;
+  if (on_device && (src == c->pop[0] || src == c->pop[1]))
+    return fail(c, SLLBM_E_ARG, "source is one of the context's population buffers");
+  // stored in the order the next step reads
+  const int layout = path_layout(effective_path(c));
   c->cur = 0;
-  HIP_TRY(c, hipMemcpyAsync(c->pop[0], src, c->pop_bytes,
-                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                            c->stream));
+  c->layout = layout;
+  if (layout == kPlanar) {
+    HIP_TRY(c, hipMemcpyAsync(c->pop[0], src, c->pop_bytes,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              c->stream));
+  } else {
+    const void *planar = src;
+    if (!on_device) {
+      HIP_TRY(c, hipMemcpyAsync(c->pop[1], src, c->pop_bytes, hipMemcpyHostToDevice, c->stream));
+      planar = c->pop[1];
+    }
+    HIP_TRY(c, launch_relayout(c->fp32, nsets(c), make_consts(c), planar, c->pop[0], 1,
+                               c->stream));
+  }
   rc = clear_flag(c);
   if (rc) return rc;
   if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -1,10 +1,12 @@
 // HIP kernels (gfx950) around the SLLBM step: initialisation, moments, the
 // mass reduction, and the dispatch to the stream + collide kernels.
 //
-// Memory layout: populations are structure-of-arrays [S][25][ny][nx] (S = 2:
-// f then g), so a wavefront of 64 consecutive x-nodes touches 64
-// consecutive words of one population.  Moments, temperature, equilibrium
-// and relaxation are evaluated in float64 for both population types.
+// Memory layout: populations are structure-of-arrays, S sets (S = 2: f then
+// g) of 25 values per node, in one of the two storage orders of PopLayout
+// (launch.hpp): planar [S][25][ny][nx], the order of the C ABI, or grouped,
+// the order of the row-segment step.  The per-node kernels here take the
+// order from StepConsts::layout.  Moments, temperature, equilibrium and
+// relaxation are evaluated in float64 for both population types.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -55,10 +57,50 @@ __global__ __launch_bounds__(256) void k_init_eq(const double *__restrict__ rho,
   const double r = rho[v], u = ux[v] * c.inv_cs, w = uy[v] * c.inv_cs;
   const double th = (MODEL == kIsothermal) ? 1.0 : temp[v] * (c.inv_cs * c.inv_cs);
   const long long N = c.n;
+  if (c.layout == kPlanar) {
+    for_each_equilibrium<Q1>(r, u, w, th, c, [&](int i, double feq) {
+      f[i * N + v] = T(feq);
+      if (Sets<MODEL>::S == 2) f[(Q1 * Q1 + i) * N + v] = T(c.gfac * th * feq);
+    });
+    return;
+  }
+  // grouped order: each velocity row's moving components in one wide store
+  constexpr int K = Q1 - 1, S = Sets<MODEL>::S;
+  constexpr unsigned E = sizeof(T);
+  const unsigned voff = unsigned(v) * E;
+  T row[S][Q1];
   for_each_equilibrium<Q1>(r, u, w, th, c, [&](int i, double feq) {
-    f[i * N + v] = T(feq);
-    if (Sets<MODEL>::S == 2) f[(Q1 * Q1 + i) * N + v] = T(c.gfac * th * feq);
+    const int a = i % Q1, b = i / Q1;
+    row[0][a] = T(feq);
+    if (S == 2) row[S - 1][a] = T(c.gfac * th * feq);
+    if (a == Q1 - 1) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        buffer_store_run<T, K>(
+            &row[s][1], make_rsrc(f + pop_base(kGrouped, Q1, s, 1, b, N), unsigned(N) * K * E),
+            voff * K, 0);
+        buffer_store<T>(row[s][0],
+                        make_rsrc(f + pop_base(kGrouped, Q1, s, 0, b, N), unsigned(N) * E), voff,
+                        0);
+      }
+    }
   });
+}
+
+// ---------------------------------------------------------------------------
+// storage order change (PopLayout), one thread per node and set
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_relayout(const T *__restrict__ src, T *__restrict__ dst,
+                                                  int sets, int q1, int from, int to,
+                                                  long long N) {
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (v >= N) return;
+  const int s = blockIdx.y;
+  if (s >= sets) return;
+  for (int b = 0; b < q1; ++b)
+    for (int a = 0; a < q1; ++a)
+      dst[pop_elem(to, q1, s, a, b, v, N)] = src[pop_elem(from, q1, s, a, b, v, N)];
 }
 
 // ---------------------------------------------------------------------------
@@ -82,7 +124,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
-      for (int i = 0; i < Q; ++i) fs[s][i] = f[(s * Q + i) * N + v];
+      for (int i = 0; i < Q; ++i) fs[s][i] = f[pop_elem(c.layout, Q1, s, i % Q1, i / Q1, v, N)];
     node_moments<T, MODEL, Q1>(fs, c, m);
     // physical units: u = c_s u_hat, T = c_s^2 theta
     if (rho_o) rho_o[v] = m[0];
@@ -112,7 +154,7 @@ __global__ __launch_bounds__(256) void k_mass(const T *__restrict__ f,
     const long long N = c.n;
     T fs[Q1 * Q1];
 #pragma unroll
-    for (int i = 0; i < Q1 * Q1; ++i) fs[i] = f[i * N + v];
+    for (int i = 0; i < Q1 * Q1; ++i) fs[i] = f[pop_elem(c.layout, Q1, 0, i % Q1, i / Q1, v, N)];
     double rho = 0.0;
 #pragma unroll
     for (int b = 0; b < Q1; ++b) {
@@ -146,7 +188,7 @@ __global__ __launch_bounds__(256) void k_sum(const double *__restrict__ partial,
 // viscosity term of the adjoint: per block, sum over nodes, sets and
 // velocities of lambda (F - F_eq(M)), F a post-collision state and M its
 // moments [K][n] (rho, u_x, u_y, theta); scaled and added on the host's
-// behalf by k_add_scaled
+// behalf by k_add_scaled.  lambda and F are caller arrays in the planar order.
 // ---------------------------------------------------------------------------
 template <typename T, int MODEL>
 __global__ __launch_bounds__(256) void k_nu_term(const T *__restrict__ lam,
@@ -234,6 +276,20 @@ hipError_t launch_init_eq(int fp32, int model, const StepConsts &c, const double
   if (model == kIsothermal) return init_t<double, kIsothermal>(c, rho, ux, uy, T, f, s);
   if (model == kMonatomic) return init_t<double, kMonatomic>(c, rho, ux, uy, T, f, s);
   return init_t<double, kPolyatomic>(c, rho, ux, uy, T, f, s);
+}
+
+hipError_t launch_relayout(int fp32, int sets, const StepConsts &c, const void *src, void *dst,
+                          int to_grouped, hipStream_t s) {
+  if (src == dst || sets < 1 || sets > 2) return hipErrorInvalidValue;
+  const dim3 grid(unsigned((c.n + 255) / 256), unsigned(sets));
+  const int from = to_grouped ? kPlanar : kGrouped, to = to_grouped ? kGrouped : kPlanar;
+  if (fp32)
+    k_relayout<float><<<grid, 256, 0, s>>>(static_cast<const float *>(src),
+                                           static_cast<float *>(dst), sets, c.q1, from, to, c.n);
+  else
+    k_relayout<double><<<grid, 256, 0, s>>>(static_cast<const double *>(src),
+                                            static_cast<double *>(dst), sets, c.q1, from, to, c.n);
+  return hipGetLastError();
 }
 
 hipError_t launch_step(int fp32, int model, int path, const StepConsts &c, const DevTables &t,

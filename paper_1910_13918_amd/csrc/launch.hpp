@@ -7,6 +7,39 @@
 
 namespace sllbm {
 
+// Storage orders of a population array of S sets of Q1^2 velocities over N
+// nodes; value (s, i = a + Q1 b, v), v = iy nx + ix.  Each set occupies
+// Q1^2 N consecutive values in both.
+//   kPlanar (the order of the C ABI): plane s Q1^2 + i, i.e. s Q1^2 N + i N + v.
+//   kGrouped (the order the row-segment kernel streams): the Q1 - 1 moving
+//     x-components a = 1 .. Q1-1 of velocity row b sit together for each
+//     node, followed by the Q1 planes of a = 0:
+//       a >= 1:  s Q1^2 N + (b N + v)(Q1 - 1) + a - 1
+//       a == 0:  s Q1^2 N + Q1 (Q1 - 1) N + b N + v
+//     The values a row segment streams for one velocity row b then lie in
+//     one contiguous stretch per source row instead of Q1 - 1 planes apart.
+enum PopLayout { kPlanar = 0, kGrouped = 1 };
+
+// Element index of (s, a, b, v) in `layout` (q1 velocities per axis).
+__host__ __device__ inline long long pop_elem(int layout, int q1, int s, int a, int b,
+                                              long long v, long long N) {
+  const long long set = (long long)s * q1 * q1 * N;
+  if (layout == kPlanar) return set + (long long)(a + q1 * b) * N + v;
+  const int k = q1 - 1;
+  return a == 0 ? set + (long long)q1 * k * N + (long long)b * N + v
+                : set + ((long long)b * N + v) * k + (a - 1);
+}
+
+// First element and node stride of the values of (s, a, b): value at node v
+// is base + v * stride.
+__host__ __device__ inline long long pop_base(int layout, int q1, int s, int a, int b,
+                                              long long N) {
+  return pop_elem(layout, q1, s, a, b, 0, N);
+}
+__host__ __device__ constexpr int pop_stride(int layout, int q1, int a) {
+  return layout == kGrouped && a != 0 ? q1 - 1 : 1;
+}
+
 // Per-step scalar constants, passed by value as kernel arguments.
 struct StepConsts {
   int nx, ny;
@@ -27,6 +60,8 @@ struct StepConsts {
   double cs, inv_cs;  // velocity-set scale: the kernels work in xi / cs, u / cs and T / cs^2
   int perx, pery;     // periodic axes
   int reverse;        // row-segment and records steps: visit the tiles / blocks in reverse order
+  int layout;         // PopLayout of the populations the per-node kernels (init, moments,
+                      // mass, adjoint seed, nu term) read or write
   double *mom_out;    // optional [K][n]: rho, u_x, u_y (and theta unless isothermal) of
                       // the streamed state
 };
@@ -69,6 +104,11 @@ struct DevTables {
 constexpr int kRowsMinCols = 32;
 
 enum Path { kPathDirect = 1, kPathTiled = 2, kPathRecords = 3, kPathMfma = 4, kPathRows = 5 };
+
+// dst = src in the other storage order (to_grouped: kPlanar -> kGrouped, else
+// back); S sets, c.q1 velocities per axis, c.n nodes; dst != src.
+hipError_t launch_relayout(int fp32, int sets, const StepConsts &c, const void *src, void *dst,
+                          int to_grouped, hipStream_t s);
 
 hipError_t launch_init_eq(int fp32, int model, const StepConsts &c, const double *rho,
                           const double *ux, const double *uy, const double *T, void *f,

@@ -94,6 +94,40 @@ __device__ __forceinline__ void buffer_load_run(__amdgpu_buffer_rsrc_t r, unsign
   }
 }
 
+// Stores K consecutive values at byte offset voff + soff with the widest
+// buffer stores (up to 16 bytes per lane per instruction).
+template <typename T, int K>
+__device__ __forceinline__ void buffer_store_run(const T *v, __amdgpu_buffer_rsrc_t r,
+                                                 unsigned voff, unsigned soff) {
+  using u4 = __attribute__((ext_vector_type(4))) unsigned;
+  using u2 = __attribute__((ext_vector_type(2))) unsigned;
+  constexpr int W32 = K * int(sizeof(T)) / 4;  // 32-bit words to write
+  unsigned w[W32];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    if constexpr (sizeof(T) == 4) {
+      w[m] = __builtin_bit_cast(unsigned, v[m]);
+    } else {
+      const unsigned long long b = __builtin_bit_cast(unsigned long long, v[m]);
+      w[2 * m] = unsigned(b);
+      w[2 * m + 1] = unsigned(b >> 32);
+    }
+  }
+  int k = 0;
+#pragma unroll
+  for (; k + 4 <= W32; k += 4)
+    __builtin_amdgcn_raw_buffer_store_b128(u4{w[k], w[k + 1], w[k + 2], w[k + 3]}, r,
+                                           voff + 4 * k, soff, 0);
+  if constexpr (W32 % 4 == 2) {
+    __builtin_amdgcn_raw_buffer_store_b64(u2{w[k], w[k + 1]}, r, voff + 4 * k, soff, 0);
+  } else if constexpr (W32 % 4 == 1) {
+    __builtin_amdgcn_raw_buffer_store_b32(w[k], r, voff + 4 * k, soff, 0);
+  } else if constexpr (W32 % 4 == 3) {
+    __builtin_amdgcn_raw_buffer_store_b64(u2{w[k], w[k + 1]}, r, voff + 4 * k, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(w[k + 2], r, voff + 4 * k + 8, soff, 0);
+  }
+}
+
 // Lagrange weights l_m(r) = den_m * prod_{n != m} (r - r_n).
 template <typename T, int P1>
 __device__ __forceinline__ void lagrange_eval(T r, const T (&rn)[P1], const T (&den)[P1],
@@ -292,20 +326,38 @@ __device__ __forceinline__ void relax_each(const T (&fs)[Sets<MODEL>::S][Q1 * Q1
   });
 }
 
-// Relaxation and store of one node at node index v.
-template <typename T, int MODEL, bool PR, int Q1 = 5>
+// Relaxation and store of one node at node index v, in storage order LAYOUT.
+template <typename T, int MODEL, bool PR, int Q1 = 5, int LAYOUT = kPlanar>
 __device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
                                             const double (&m)[4], const StepConsts &c,
                                             T *__restrict__ fout, long long v) {
-  constexpr int Q = Q1 * Q1;
   const long long N = c.n;
-  // one 32-bit lane offset for every plane; the plane base lives in the
+  constexpr unsigned E = sizeof(T);
+  // 32-bit lane offsets; the base of each velocity's values lives in the
   // (scalar) buffer resource
-  const unsigned voff = unsigned(v) * unsigned(sizeof(T));
-  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
-  relax_each<T, MODEL, PR, Q1>(fs, m, c, [&](int s, int i, T val) {
-    buffer_store<T>(val, make_rsrc(fout + (s * Q + i) * N, plane_bytes), voff, 0);
-  });
+  const unsigned voff = unsigned(v) * E;
+  if constexpr (LAYOUT == kPlanar) {
+    relax_each<T, MODEL, PR, Q1>(fs, m, c, [&](int s, int i, T val) {
+      const auto rs = make_rsrc(fout + pop_base(kPlanar, Q1, s, i % Q1, i / Q1, N), unsigned(N) * E);
+      buffer_store<T>(val, rs, voff, 0);
+    });
+  } else {
+    // a velocity row of each set is held until its last value is known, then
+    // its Q1 - 1 moving components go out in one wide store per lane, so each
+    // cache line is written whole by one instruction
+    constexpr int K = Q1 - 1;
+    T row[Sets<MODEL>::S][Q1];
+    relax_each<T, MODEL, PR, Q1>(fs, m, c, [&](int s, int i, T val) {
+      const int a = i % Q1, b = i / Q1;
+      row[s][a] = val;
+      if (a == Q1 - 1) {
+        const auto rg = make_rsrc(fout + pop_base(kGrouped, Q1, s, 1, b, N), unsigned(N) * K * E);
+        buffer_store_run<T, K>(&row[s][1], rg, voff * K, 0);
+        const auto r0 = make_rsrc(fout + pop_base(kGrouped, Q1, s, 0, b, N), unsigned(N) * E);
+        buffer_store<T>(row[s][0], r0, voff, 0);
+      }
+    });
+  }
 }
 
 // Moments of one node's streamed populations; when `valid`, records them for
@@ -335,13 +387,13 @@ __device__ __forceinline__ void collide_moments(const T (&fs)[Sets<MODEL>::S][Q1
 // (Pr != 1).  PR is a kernel template parameter rather than a runtime
 // branch: holding both variants in one kernel costs the Pr = 1 kernels
 // registers and occupancy.
-template <typename T, int MODEL, bool PR = false, int Q1 = 5>
+template <typename T, int MODEL, bool PR = false, int Q1 = 5, int LAYOUT = kPlanar>
 __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
                                               const StepConsts &c, T *__restrict__ fout,
                                               long long v, int *__restrict__ flag) {
   double m[4];
   collide_moments<T, MODEL, Q1>(fs, c, v, true, flag, m);
-  relax_store<T, MODEL, PR, Q1>(fs, m, c, fout, v);
+  relax_store<T, MODEL, PR, Q1, LAYOUT>(fs, m, c, fout, v);
 }
 
 // Workgroup barrier that orders LDS only: unlike __syncthreads() it does not

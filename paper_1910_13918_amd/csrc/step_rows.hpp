@@ -16,7 +16,13 @@
 // the wavefronts of neighbouring rows, which read overlapping source rows,
 // close enough together for those reads to hit in the L1 cache.
 // The streamed values stay in registers and the collision is the one of the
-// other paths (collide_store).
+// other paths (collide_store).  The forward step reads and writes the grouped
+// storage order (PopLayout), in which the four moving x-components of one
+// velocity row lie next to each other for every node: measured on the
+// Riemann 1025^2-node benchmark pattern (float32 f + g), the planes of one
+// row then come from one stretch of memory instead of four planes 4 MB
+// apart, and the step takes 94 instead of 105 us; the adjoint's transposed
+// gather keeps the planar order of its own arrays.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -167,6 +173,123 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
   }
 }
 
+// The forward step's gather over the grouped storage order (PopLayout): the
+// same interpolation as rows_stream, velocity row by velocity row.  For each
+// group (b, s) the wavefront issues the loads of all Q1 x-components of each
+// source row together (the Q1 - 1 moving ones lie in one stretch of memory,
+// so the loads share cache lines while in flight), y-combines them, writes
+// the Q1 - 1 moving rows to its own LDS rows and x-combines them after one
+// LDS sync; the component a = 0 (identity x-factor) is read at the node's own
+// column and needs no LDS.  The moving components of a segment share one
+// source window (xwin of component 1), so each lane reads the Q1 - 1 values
+// of its window column in one wide load: separate 4-byte loads at the
+// 16-byte node stride each touched four times the cache lines (L1 accesses
+// 81 M against 18 M per step on the planar order).  DG groups of loads run ahead of the arithmetic;
+// SYNC: a workgroup barrier before every group (every wavefront of the
+// workgroup must call this).  Measured on the Riemann 1025^2-node pattern
+// (float32 f + g, p = 2): 95 us per step against 157 us with the plane-by-
+// plane loop of rows_stream on the same order and 105 us on the planar order.
+template <typename T, int P1, int S, int DG, bool SYNC, int Q1>
+__device__ __forceinline__ void rows_stream_grouped(
+    const T *__restrict__ fin, const int32_t *__restrict__ xrel, const T *__restrict__ xw,
+    const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc, const T *__restrict__ yw,
+    int TX, int ntx, int tx, int iy, int lane, const StepConsts &c, T *lrow,
+    T (&fs)[S][Q1 * Q1]) {
+  constexpr int NG = Q1 * S;  // groups, in the order (b, s)
+  constexpr int K = Q1 - 1;   // moving x-components per group
+  const int ixc = min(tx * TX + min(lane, TX - 1), c.nx - 1);
+  const long long N = c.n;
+  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
+  const unsigned row_bytes = unsigned(c.nx) * unsigned(sizeof(T));
+  int xr0[Q1];
+  T wx[Q1][P1];
+#pragma unroll
+  for (int a = 1; a < Q1; ++a) {
+    xr0[a] = xrel[(a * P1) * c.nx + ixc];
+#pragma unroll
+    for (int m = 0; m < P1; ++m) wx[a][m] = xw[(a * P1 + m) * c.nx + ixc];
+  }
+  // the moving components share one window per segment (the host builds it
+  // so), and this lane reads the K values of its window column with one
+  // wide load; a = 0 is read at the node's own column
+  const unsigned colq =
+      unsigned(wrap_or_clamp(xwin[1 * ntx + tx] + lane, c.nx, c.perx)) * unsigned(sizeof(T) * K);
+  const unsigned own_off = unsigned(ixc) * unsigned(sizeof(T));
+  unsigned yoff[Q1][P1];
+  T wy[Q1][P1];
+  auto fetch_phase = [&](int b) {
+    int z = 0;
+    asm volatile("" : "+s"(z));  // keeps the scalar loads here
+#pragma unroll
+    for (int m = 0; m < P1; ++m) {
+      yoff[b][m] = unsigned(ysrc[(b * P1 + m) * c.ny + iy + z]) * row_bytes;
+      wy[b][m] = yw[(b * P1 + m) * c.ny + iy + z];
+    }
+  };
+  T pre[DG + 1][P1][Q1];
+  auto load = [&](int g, T (&d)[P1][Q1]) {
+    const int b = g / S, s = g % S;
+    if (b > 0 && s == 0) fetch_phase(b);
+    const int rows = b == 0 ? 1 : P1;  // b = 0: identity y-factor, the target row alone
+#pragma unroll
+    for (int m = 0; m < P1; ++m) {
+      if (m >= rows) {
+#pragma unroll
+        for (int a = 0; a < Q1; ++a) d[m][a] = T(0);
+        continue;
+      }
+      const unsigned ro = b == 0 ? unsigned(iy) * row_bytes : yoff[b][m];
+      T q[K];
+      buffer_load_run<T, K>(make_rsrc(fin + pop_base(kGrouped, Q1, s, 1, b, N), plane_bytes * K),
+                            colq, ro * K, q);
+#pragma unroll
+      for (int a = 1; a < Q1; ++a) d[m][a] = q[a - 1];
+      d[m][0] = buffer_load<T>(make_rsrc(fin + pop_base(kGrouped, Q1, s, 0, b, N), plane_bytes),
+                               own_off, ro);
+    }
+  };
+#pragma unroll
+  for (int g = 0; g < DG && g < NG; ++g) load(g, pre[g % (DG + 1)]);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (SYNC && g > 0) __builtin_amdgcn_s_barrier();
+    if (g + DG < NG) load(g + DG, pre[(g + DG) % (DG + 1)]);
+    const int b = g / S, s = g % S;
+    const T(&v)[P1][Q1] = pre[g % (DG + 1)];
+    T *rows = lrow + (g & 1) * K * 64;
+#pragma unroll
+    for (int a = 0; a < Q1; ++a) {
+      T y = v[0][a];
+      if (b != 0) {
+        y = wy[b][0] * v[0][a];
+#pragma unroll
+        for (int m = 1; m < P1; ++m) y = fma(wy[b][m], v[m][a], y);
+      }
+      if (a == 0) {
+        asm volatile("" : "+v"(y));
+        fs[s][Q1 * b] = y;  // identity x-factor
+      } else {
+        rows[(a - 1) * 64 + lane] = y;
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int a = 1; a < Q1; ++a) {
+      const T *row = rows + (a - 1) * 64;
+      T acc = wx[a][0] * row[xr0[a]];
+#pragma unroll
+      for (int m = 1; m < P1; ++m) acc = fma(wx[a][m], row[xr0[a] + m], acc);
+      asm volatile("" : "+v"(acc));  // keep the plane's arithmetic in its place
+      fs[s][a + Q1 * b] = acc;
+    }
+  }
+}
+
+// Groups of loads in flight ahead of the one being interpolated (grouped
+// order): one measured best for float32 f + g (two: +1 %).
+template <typename T, int P1, int S>
+constexpr int rows_group_lookahead() { return 1; }
+
 // Planes between workgroup barriers (0: none), measured on 1025^2-node
 // grids: for f + g, every 5 planes (with the deeper lookahead it allows)
 // gives float32 +5-6 % at p = 1-3 and +16 % at p = 4, float64 +-1 %; every
@@ -177,20 +300,22 @@ constexpr int rows_sync_planes() { return S == 2 ? 5 : 0; }
 
 // Minimum waves per SIMD the compiler is asked to fit: a single float32
 // population set gets 6 (70-73 VGPRs instead of ~97; Taylor-Green p = 2:
-// +14 %), f + g keeps the default (the same request spills and costs 3-18 %).
-template <typename T, int S>
-constexpr int rows_min_waves() { return sizeof(T) == 4 && S == 1 ? 6 : 1; }
+// +14 %), 5 from p = 3 on (the row-by-row gather of the grouped order spills
+// at 6 there), f + g keeps the default (the same request spills and costs
+// 3-18 %).
+template <typename T, int S, int P1>
+constexpr int rows_min_waves() { return sizeof(T) == 4 && S == 1 ? (P1 >= 4 ? 5 : 6) : 1; }
 
 template <typename T, int P, int MODEL, bool PR, int Q1 = 5>
 __global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
-                             (rows_min_waves<T, Sets<MODEL>::S>())) void k_step_rows(
+                             (rows_min_waves<T, Sets<MODEL>::S, P + 1>())) void k_step_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
     const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc,
     const T *__restrict__ yw, int TX, int ntx, int nty, int strip, StepConsts c,
     int *__restrict__ flag) {
   constexpr int S = Sets<MODEL>::S;
   constexpr int R = rows_tile_rows<T, Sets<MODEL>::S>();
-  __shared__ T rows_lds[R][2][64];
+  __shared__ T rows_lds[R][2 * (Q1 - 1)][64];
   int tile = xcd_tile(blockIdx.x, ntx * nty);
   if (tile >= ntx * nty) return;
   if (c.reverse) tile = ntx * nty - 1 - tile;
@@ -203,11 +328,11 @@ __global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
   const int iy_t = ty * R + wv;
   const int iy = min(iy_t, c.ny - 1);
   T fs[S][Q1 * Q1];
-  rows_stream<T, P + 1, S, rows_lookahead<T, P + 1, S, PR>(), rows_sync_planes<P + 1, S>(), Q1>(
+  rows_stream_grouped<T, P + 1, S, rows_group_lookahead<T, P + 1, S>(), S == 2, Q1>(
       fin, xrel, xw, xwin, ysrc, yw, TX, ntx, tx, iy, lane, c, &rows_lds[wv][0][0], fs);
   const int ix = tx * TX + lane;
   if (ix < c.nx && lane < TX && iy_t < c.ny)
-    collide_store<T, MODEL, PR, Q1>(fs, c, fout, (long long)iy * c.nx + ix, flag);
+    collide_store<T, MODEL, PR, Q1, kGrouped>(fs, c, fout, (long long)iy * c.nx + ix, flag);
 }
 
 // Segments per strip of the strip-major tile order (strip_tile): rows of up
