@@ -40,6 +40,8 @@ def workload(name):
         return W.tgv(), "tgv_8x8cells_p2"
     if name == "adjoint_tgv":
         return W.adjoint_tgv(), "tgv_128x128cells_p4"
+    if name == "curvilinear":
+        return W.tgv_wavy(256, 4, amp=0.3), "tgv_wavy_256x256cells_p4_amp0.3"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -69,7 +71,8 @@ def profiled_traffic(wname, precision, path):
     since it was taken."""
     import hashlib
     tag = {"riemann2d_512x512cells_p2": "riemann512_p2",
-           "shock_vortex_1024x512cells_p3_stretched": "svi1024x512_p3"}.get(wname)
+           "shock_vortex_1024x512cells_p3_stretched": "svi1024x512_p3",
+           "tgv_wavy_256x256cells_p4_amp0.3": "curvilinear_tgv_wavy256_p4"}.get(wname)
     if tag is None:
         return None
     f = os.path.join(ROOT, "profiles", f"stream_collide_{tag}_{precision}_{path}.json")
@@ -150,11 +153,13 @@ def curvilinear_entry(precision, steps=20, warmup=3):
     s, ms, unstable = timed(wl, precision, "auto", steps, warmup)
     nu_s = s.n * steps / (ms * 1e-3)
     bpn = bytes_per_node_update(wl, precision, s.resolved_path())
+    tr = profiled_traffic("tgv_wavy_256x256cells_p4_amp0.3", precision, s.resolved_path())
     out = {"workload": "tgv_wavy_256x256cells_p4_amp0.3", "path": s.resolved_path(),
            "steps": steps, "warmup": warmup, "value": nu_s, "unit": "node-updates/s",
            "ms_per_step": ms / steps, "bytes_per_node_update": bpn,
            "achieved_gbs": nu_s * bpn / 1e9, "frac": nu_s * bpn / 1e9 / HBM_PEAK_GBS,
-           "unstable_flag": unstable}
+           "unstable_flag": unstable, "traffic": tr,
+           "traffic_over_algorithmic": tr / (s.n * bpn) if tr else None}
     s.close()
     return out
 
@@ -508,9 +513,11 @@ def main():
         other = "tiled" if s_path == "rows" else "rows"
         so, mso, _ = timed(wl, args.precision, other, args.steps, args.warmup)
         v = so.n * args.steps / (mso * 1e-3)
+        tro = profiled_traffic(wname, args.precision, other)
         out[f"{other}_path"] = {"path": other, "value": v, "unit": "node-updates/s",
                                 "ms_per_step": mso / args.steps, "achieved_gbs": v * bpn / 1e9,
-                                "frac": v * bpn / 1e9 / HBM_PEAK_GBS}
+                                "frac": v * bpn / 1e9 / HBM_PEAK_GBS, "traffic": tro,
+                                "traffic_over_algorithmic": tro / (so.n * bpn) if tro else None}
         so.close()
     if not args.no_svi and args.workload == "riemann":
         out["shock_vortex"] = shock_vortex_entry(args.precision)
