@@ -302,11 +302,18 @@ int sllbm_set_check_interval(sllbm_ctx *ctx, int64_t k);
 
 /* sllbm_step that also records, for each of the n steps, the moments of the
  * streamed (pre-collision) state: moments[s][0..K-1][ny][nx] = rho, u_x, u_y
- * and, unless isothermal, theta (float64, device pointer, K * nx * ny values
- * per step, K = 3 or 4).  These are the moments the collision Jacobian of
+ * and, unless isothermal, theta, and with Pr != 1 the centred second moments
+ * sum f (xi_x - u_x)^2, sum f (xi_x - u_x)(xi_y - u_y), sum f (xi_y - u_y)^2
+ * of f and then of g (float64, device pointer, K * nx * ny values per step,
+ * K from sllbm_recorded_moments).  These are what the collision Jacobian of
  * step s depends on; the adjoint sweep replays a checkpointed segment with
  * this call. */
 int sllbm_step_record(sllbm_ctx *ctx, int64_t n, double *moments);
+
+/* K, the moments sllbm_step_record keeps per node and step: 3 isothermal,
+ * 4 for the thermal models at Pr = 1, 4 + 3 S at Pr != 1 (S population
+ * sets).  Needs the physics (SLLBM_E_STATE otherwise). */
+int sllbm_recorded_moments(const sllbm_ctx *ctx, int *k);
 
 /* Synchronise and report the stability flag (1 = raised) and step count. */
 int sllbm_status_flags(sllbm_ctx *ctx, int *unstable, int64_t *steps_done);
@@ -348,18 +355,20 @@ int sllbm_mass_noalloc(sllbm_ctx *ctx, double *mass_dev);
 int sllbm_get_populations(sllbm_ctx *ctx, void *dst, int on_device);
 int sllbm_set_populations(sllbm_ctx *ctx, const void *src, int on_device);
 
-/* ---- adjoint of the step (every model, Pr = 1) ----
- * The paper has no adjoint; these calls differentiate exactly the step above
- * with Pr = 1 (SLLBM_E_UNSUPPORTED otherwise).
+/* ---- adjoint of the step (every model and Prandtl number) ----
+ * The paper has no adjoint; these calls differentiate exactly the step above.
  * One step is F' = C(S F) with S the interpolation of every population plane
- * (Sec. II.E, eq. (17)) and C the BGK collision (Sec. II.D, eq. (16)).
+ * (Sec. II.E, eq. (17)) and C the collision of Sec. II.D, eq. (16): BGK, plus
+ * with Pr != 1 the quasi-equilibrium term (1/tau - 1/tau_Pr) f*(Q) built from
+ * the centred third moments Q of each set (Sec. II.C), whose transpose needs
+ * the centred second moments the record then holds.
  * Reverse sweep:  mu^n = J_C(M^n)^T lambda^{n+1},  lambda^n = S^T mu^n,
  * where M^n are the moments recorded by sllbm_step_record for step n.
  * All arrays are device pointers on the context's device; lambda / mu arrays
  * are [S][25][ny][nx] in the population type (S = 2 for the polyatomic
  * model); node fields are float64 [ny][nx]; a moments record is [K][ny][nx]
- * with K = 3 (rho, u_x, u_y) for the isothermal model and K = 4 (theta
- * added) otherwise.  Calls are asynchronous on the bound stream. */
+ * as sllbm_step_record writes it (K from sllbm_recorded_moments).  Calls
+ * are asynchronous on the bound stream. */
 
 /* lambda = dL/dF of the current populations F for a loss with gradients
  * g_rho, g_ux, g_uy, g_T with respect to the node moments rho, u_x, u_y and
@@ -386,7 +395,9 @@ int sllbm_adjoint_nu_term(sllbm_ctx *ctx, const void *lambda, const void *popula
 
 /* out = S^T mu (the transposed interpolation, a gather through transposed
  * departure tables), followed by J_C(M_prev)^T when moments_prev (the record
- * of the previous step) is not NULL.  mu and out must differ. */
+ * of the previous step) is not NULL (fused into one kernel at Pr = 1; at
+ * Pr != 1 two kernels through a library-owned scratch array of one state).
+ * mu and out must differ. */
 int sllbm_adjoint_step(sllbm_ctx *ctx, const void *mu, const double *moments_prev, void *out);
 
 /* Gradient through the initialisation f = f_eq(rho0, u0, T0), g = g_eq:

@@ -9,12 +9,13 @@ backward pass runs the adjoint of every step in the library:
 * backward: for each segment, newest first, the checkpoint is restored and the
   segment replayed with ``sllbm_step_record`` (which keeps only the moments
   per node and step that the collision Jacobian needs: rho, u and, unless
-  isothermal, theta), then ``mu = J_C^T lambda`` and ``lambda = S^T mu`` are
-  applied step by step, and finally the gradient is carried through the
-  initialisation F = F_eq.
+  isothermal, theta; with Pr != 1 also each set's centred second moments),
+  then ``mu = J_C^T lambda`` and ``lambda = S^T mu`` are applied step by
+  step, and finally the gradient is carried through the initialisation
+  F = F_eq.
 
-Memory: one population copy per checkpoint plus 3 (4) float64 per node and
-step of one segment.  With ``every=0`` the forward records the moments of
+Memory: one population copy per checkpoint plus K float64 per node and step
+of one segment (K = 3 isothermal, 4 thermal, 4 + 3 S at Pr != 1).  With ``every=0`` the forward records the moments of
 every step instead (24 or 32 bytes per node and step: 3.1 GB for 500
 isothermal steps of 512^2 nodes) and the backward replays nothing.  Every
 arithmetic step runs in the HIP kernels; this module only sequences the calls
@@ -128,7 +129,8 @@ def rollout(rho0, ux0, uy0, solver, nsteps, every=50, T0=None, nu=None):
 
     nu: optional 0-dim tensor holding the solver's viscosity; when it requires
     grad, the backward also gives dL/d(nu) (Pr = 1, tau != 1, every > 0; each
-    replayed segment then keeps its steps' populations)."""
+    replayed segment then keeps its steps' populations).  The gradients in the
+    initial fields cover every Prandtl number."""
     if every < 0:
         raise ValueError("every must be >= 0")
     if solver.model != "isothermal" and T0 is None:
@@ -138,6 +140,8 @@ def rollout(rho0, ux0, uy0, solver, nsteps, every=50, T0=None, nu=None):
             raise ValueError("the viscosity gradient needs checkpoints (every > 0)")
         if abs(float(nu) - solver.nu) > 1e-12 * abs(solver.nu):
             raise ValueError("nu must hold the solver's viscosity")
+        if nu.requires_grad and solver.Pr != 1.0:
+            raise ValueError("the viscosity gradient covers Pr = 1")
     rho, ux, uy, T = SLLBMRollout.apply(rho0, ux0, uy0, T0, nu, solver, nsteps, every)
     return (rho, ux, uy) if solver.model == "isothermal" else (rho, ux, uy, T)
 

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_adjoint_seed(const T *__restrict__ f,
     }
 }
 
-template <typename T, int MODEL>
+template <typename T, int MODEL, bool PR = false>
 __global__ __launch_bounds__(256) void k_adjoint_collide(const T *__restrict__ lam,
                                                          const double *__restrict__ mom,
                                                          T *__restrict__ mu, StepConsts c) {
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_adjoint_collide(const T *__restrict__ l
   for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int i = 0; i < 25; ++i) l[s][i] = lam[(s * 25 + i) * c.n + v];
-  collision_adjoint_store<T, MODEL>(l, mom, c, mu, v);
+  collision_adjoint_store<T, MODEL, PR>(l, mom, c, mu, v);
 }
 
 // S^T by direct gathers through the transposed tables (no LDS).
@@ -181,7 +181,17 @@ hipError_t launch_adjoint_seed(int fp32, int model, const StepConsts &c, const v
 hipError_t launch_adjoint_collide(int fp32, int model, const StepConsts &c, const void *lam,
                                   const double *mom, void *mu, hipStream_t s) {
   const unsigned blocks = unsigned((c.n + 255) / 256);
+  const bool pr = c.omega_pr != c.omega;  // the quasi-equilibrium term (thermal models)
   return dispatch_model(fp32, model, [&]<typename T, int MODEL>() -> hipError_t {
+    if constexpr (MODEL != kIsothermal) {
+      if (pr) {
+        k_adjoint_collide<T, MODEL, true><<<blocks, 256, 0, s>>>(static_cast<const T *>(lam), mom,
+                                                                 static_cast<T *>(mu), c);
+        return hipGetLastError();
+      }
+    } else if (pr) {
+      return hipErrorInvalidValue;
+    }
     k_adjoint_collide<T, MODEL><<<blocks, 256, 0, s>>>(static_cast<const T *>(lam), mom,
                                                        static_cast<T *>(mu), c);
     return hipGetLastError();
@@ -192,6 +202,8 @@ hipError_t launch_adjoint_step(int fp32, int model, int kind, const StepConsts &
                                const DevTables &t, const void *mu, const double *mom_prev,
                                void *out, hipStream_t s) {
   if (t.taps < 2 || t.taps > kMaxTaps) return hipErrorInvalidValue;
+  // the fused J_C^T is the Pr = 1 one; the host splits the Pr != 1 step
+  if (mom_prev && c.omega_pr != c.omega) return hipErrorInvalidValue;
   if (kind == kAdjointRows) return launch_adjoint_step_rows(fp32, model, c, t, mu, mom_prev, out, s);
   if (kind == kAdjointTiled)
     return fp32 ? launch_adjoint_step_tiled_t<float>(model, c, t, mu, mom_prev, out, s)

@@ -105,8 +105,61 @@ __device__ __forceinline__ void equilibrium_adjoint(const T (&lam)[Sets<MODEL>::
   }
 }
 
-// mu = J_C(rho, u, theta)^T lam, stored at node v of an [S][25][n] array.
-template <typename T, int MODEL>
+// Transpose of the quasi-equilibrium term of the Pr != 1 collision.  The
+// term added to set s is kappa f*_i(Q^s) with kappa = 1/tau - 1/tau_Pr,
+// f*_i = sum_k C_ik Q^s_k, C_ik = w_a w_b He_k(xi_a)/k! He_(3-k)(xi_b)/(3-k)!
+// (the form relax_each evaluates) and Q^s_k = sum_j s_j c_x^k c_y^(3-k) the
+// centred third moments of set s about u = u(f) (c = xi - u).  With
+// L^s_k = sum_i lam^s_i C_ik:
+//   d/ds_j (direct):  kappa sum_k L^s_k c_x,j^k c_y,j^(3-k)          (every set);
+//   through u (f only, du/df_j = c_j / rho):
+//     kappa / rho (c_x,j sum_s,k L^s_k dQ^s_k/du_x + c_y,j sum_s,k L^s_k dQ^s_k/du_y),
+//   dQ_k/du_x = -k M_(k-1,3-k), dQ_k/du_y = -(3-k) M_(k,2-k), M the centred
+//   second moments the forward step recorded (mom slots 4 + 3 s ...).
+// Returns L (per set) and the two u-coefficients ax, ay.
+template <typename T, int S>
+__device__ __forceinline__ void quasi_equilibrium_adjoint(const T (&lam)[S][25],
+                                                          const double *__restrict__ mom,
+                                                          const StepConsts &c, long long v,
+                                                          double (&L)[S][4], double &ax,
+                                                          double &ay) {
+  const double kq = c.omega - c.omega_pr;
+  const double rho = mom[v];
+  ax = 0.0;
+  ay = 0.0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // sum_b w_b He_(3-k)(xi_b)/(3-k)! sum_a w_a He_k(xi_a)/k! lam_(a+5b)
+      double t = 0.0;
+#pragma unroll
+      for (int b = 0; b < 5; ++b) {
+        double r = 0.0;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) r = fma(c.whk[a][k], double(lam[s][a + 5 * b]), r);
+        t = fma(c.w[b] * c.hk[b][3 - k], r, t);
+      }
+      L[s][k] = t;
+    }
+    const double mxx = mom[(4 + 3 * s) * c.n + v], mxy = mom[(5 + 3 * s) * c.n + v],
+                 myy = mom[(6 + 3 * s) * c.n + v];
+    // sum_k L_k dQ_k/du_x and sum_k L_k dQ_k/du_y
+    ax -= L[s][1] * myy + 2.0 * L[s][2] * mxy + 3.0 * L[s][3] * mxx;
+    ay -= 3.0 * L[s][0] * myy + 2.0 * L[s][1] * mxy + L[s][2] * mxx;
+  }
+  ax *= kq / rho;
+  ay *= kq / rho;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L[s][k] *= kq;
+}
+
+// mu = J_C(rho, u, theta)^T lam, stored at node v of an [S][25][n] array;
+// PR: the Pr != 1 collision, whose quasi-equilibrium term also needs the
+// recorded centred second moments.
+template <typename T, int MODEL, bool PR = false>
 __device__ __forceinline__ void collision_adjoint_store(const T (&lam)[Sets<MODEL>::S][25],
                                                         const double *__restrict__ mom,
                                                         const StepConsts &c, T *__restrict__ out,
@@ -116,6 +169,8 @@ __device__ __forceinline__ void collision_adjoint_store(const T (&lam)[Sets<MODE
   const double theta = MODEL == kIsothermal ? 1.0 : mom[3 * c.n + v];
   double P, Px, Py, Pt;
   equilibrium_adjoint<T, MODEL>(lam, ux, uy, theta, c, P, Px, Py, Pt);
+  double L[S][4], ax = 0.0, ay = 0.0;
+  if constexpr (PR) quasi_equilibrium_adjoint<T, S>(lam, mom, c, v, L, ax, ay);
   const double om = c.omega;
   const double two_cv_theta = theta / c.inv_2cv;
   const unsigned voff = unsigned(v) * unsigned(sizeof(T));
@@ -129,10 +184,28 @@ __device__ __forceinline__ void collision_adjoint_store(const T (&lam)[Sets<MODE
       double r = fma(Px, dx, fma(Py, dy, P));
       if constexpr (MODEL != kIsothermal)
         r = fma(Pt * c.inv_2cv, dx * dx + dy * dy - two_cv_theta, r);
-      const double mu = fma(1.0 - om, double(lam[0][i]), om * r);
+      double mu = fma(1.0 - om, double(lam[0][i]), om * r);
+      // c_x^k c_y^(3-k), k = 0..3
+      double cq[4];
+      if constexpr (PR) {
+        cq[0] = dy * dy * dy;
+        cq[1] = dx * dy * dy;
+        cq[2] = dx * dx * dy;
+        cq[3] = dx * dx * dx;
+        double q = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q = fma(L[0][k], cq[k], q);
+        mu += q + fma(ax, dx, ay * dy);
+      }
       buffer_store<T>(T(mu), make_rsrc(out + i * c.n, plane_bytes), voff, 0);
       if constexpr (S == 2) {
-        const double mg = fma(1.0 - om, double(lam[S - 1][i]), om * Pt * c.inv_2cv);
+        double mg = fma(1.0 - om, double(lam[S - 1][i]), om * Pt * c.inv_2cv);
+        if constexpr (PR) {
+          double q = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) q = fma(L[S - 1][k], cq[k], q);
+          mg += q;
+        }
         buffer_store<T>(T(mg), make_rsrc(out + (25 + i) * c.n, plane_bytes), voff, 0);
       }
     }

@@ -88,6 +88,7 @@ struct sllbm_ctx {
   DeviceBuf xsrc, xw, ysrc, yw, yrel_d, ywin_d, xrel_d, xwin_d, mxd, myd, flag, partial, scalar,
       macro;
   DeviceBuf rec_cell, rec_r, rec_s;
+  DeviceBuf adj_tmp;  // Pr != 1 adjoint step: S^T mu before the collision transpose
   void *pop[2] = {nullptr, nullptr};
   bool own_pop = false;
   size_t pop_bytes = 0;
@@ -542,8 +543,6 @@ void pad_taps(AxisTable &t, const Axis &ax, int taps) {
 int prepare_adjoint(sllbm_ctx *c) {
   int rc = prepare_device(c);
   if (rc) return rc;
-  if (c->omega_pr != c->omega)
-    return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers Pr = 1 only");
   if (c->curvi)
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers axis-product grids only");
   if (q1(c) != kQ1)
@@ -641,7 +640,7 @@ void sllbm_destroy(sllbm_ctx *c) {
                          &c->myd, &c->mnode_d, &c->flag, &c->partial, &c->scalar, &c->macro,
                          &c->rec_cell,
                          &c->rec_r, &c->rec_s, &c->rows_xrel_d, &c->rows_xwin_d,
-                         &c->rows_xrelT_d, &c->rows_xwinT_d};
+                         &c->rows_xrelT_d, &c->rows_xwinT_d, &c->adj_tmp};
     for (DeviceBuf *b : bufs) free_buf(*b);
     if (c->own_pop) {
       (void)hipFree(c->pop[0]);
@@ -1015,8 +1014,12 @@ static int read_flag(sllbm_ctx *c, int *flag) {
 }
 
 // Moments per node recorded by sllbm_step_record: rho, u_x, u_y and, unless
-// isothermal, theta.
-static int recorded_moments(const sllbm_ctx *c) { return c->model == SLLBM_ISOTHERMAL ? 3 : 4; }
+// isothermal, theta; with Pr != 1 also the centred second moments of each set
+// (what the transposed quasi-equilibrium term needs).
+static int recorded_moments(const sllbm_ctx *c) {
+  if (c->model == SLLBM_ISOTHERMAL) return 3;
+  return c->omega_pr != c->omega ? 4 + 3 * nsets(c) : 4;
+}
 
 static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
   if (!c) return SLLBM_E_ARG;
@@ -1079,6 +1082,13 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
 
 int sllbm_step(sllbm_ctx *c, int64_t n) { return run_steps(c, n, nullptr); }
 
+int sllbm_recorded_moments(const sllbm_ctx *c, int *k) {
+  if (!c || !k) return SLLBM_E_ARG;
+  if (!c->have_phys) return fail(const_cast<sllbm_ctx *>(c), SLLBM_E_STATE, "physics not set");
+  *k = recorded_moments(c);
+  return SLLBM_OK;
+}
+
 int sllbm_step_record(sllbm_ctx *c, int64_t n, double *moments) {
   if (!c) return SLLBM_E_ARG;
   if (!moments) return fail(c, SLLBM_E_ARG, "null moments buffer");
@@ -1117,6 +1127,8 @@ int sllbm_adjoint_nu_term(sllbm_ctx *c, const void *lam, const void *pop, const 
     return fail(c, SLLBM_E_UNSUPPORTED,
                 "tau = 1: post-collision populations are at equilibrium and do not give the "
                 "pre-collision non-equilibrium part");
+  if (c->omega_pr != c->omega)
+    return fail(c, SLLBM_E_UNSUPPORTED, "the viscosity term covers Pr = 1 (BGK) only");
   // f - f_eq before the collision is (f+ - f_eq) / (1 - omega) (the moments
   // are collision invariants), d(omega)/d(nu) = -1 / (tau^2 dt), and
   // dC/d(omega) = -(f - f_eq)
@@ -1148,6 +1160,19 @@ int sllbm_adjoint_step(sllbm_ctx *c, const void *mu, const double *moments_prev,
            : tiled_ok        ? kAdjointTiled
            : rows_ok         ? kAdjointRows
                              : kAdjointDirect;
+  }
+  if (moments_prev && c->omega_pr != c->omega) {
+    // Pr != 1: S^T into scratch, then the quasi-equilibrium-aware J_C^T
+    rc = alloc_buf(c, c->adj_tmp, c->pop_bytes ? c->pop_bytes
+                                                : size_t(nsets(c)) * nvel(c) * nnodes(c) *
+                                                      pop_size(c));
+    if (rc) return rc;
+    const StepConsts k = make_consts(c);
+    HIP_TRY(c, launch_adjoint_step(c->fp32, c->model, kind, k, make_adjoint_tables(c), mu,
+                                   nullptr, c->adj_tmp.ptr, c->stream));
+    HIP_TRY(c, launch_adjoint_collide(c->fp32, c->model, k, c->adj_tmp.ptr, moments_prev, out,
+                                      c->stream));
+    return SLLBM_OK;
   }
   HIP_TRY(c, launch_adjoint_step(c->fp32, c->model, kind, make_consts(c),
                                  make_adjoint_tables(c), mu, moments_prev, out, c->stream));

@@ -168,10 +168,12 @@ hipError_t launch_adjoint_seed(int fp32, int model, const StepConsts &c, const v
                                const double *g_rho, const double *g_ux, const double *g_uy,
                                const double *g_th, void *lam, hipStream_t s);
 // mu = J_C(M)^T lam, node by node (M: [K][n] moments of the streamed state,
-// K = 3 isothermal, 4 with theta)
+// K = 3 isothermal, 4 with theta, and with Pr != 1 another 3 per set: the
+// centred second moments of f (and g))
 hipError_t launch_adjoint_collide(int fp32, int model, const StepConsts &c, const void *lam,
                                   const double *mom, void *mu, hipStream_t s);
-// out = S^T mu (transposed tables t), then J_C(M_prev)^T when mom_prev is given;
+// out = S^T mu (transposed tables t), then J_C(M_prev)^T when mom_prev is given
+// (Pr = 1 only: with Pr != 1 the host applies J_C^T through launch_adjoint_collide);
 // kind: the gather (direct, tiled windows or row segments)
 enum AdjointKind { kAdjointDirect = 0, kAdjointTiled = 1, kAdjointRows = 2 };
 hipError_t launch_adjoint_step(int fp32, int model, int kind, const StepConsts &c,

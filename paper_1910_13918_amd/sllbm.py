@@ -99,6 +99,7 @@ _SIGS = {
     "sllbm_get_populations": ([_vp, _vp, _c], _c),
     "sllbm_set_populations": ([_vp, _vp, _c], _c),
     "sllbm_step_record": ([_vp, _i64, _vp], _c),
+    "sllbm_recorded_moments": ([_vp, _ip], _c),
     "sllbm_adjoint_seed": ([_vp, _vp, _vp, _vp, _vp, _vp], _c),
     "sllbm_adjoint_collide": ([_vp, _vp, _vp, _vp], _c),
     "sllbm_adjoint_step": ([_vp, _vp, _vp, _vp], _c),
@@ -273,6 +274,12 @@ def sllbm_set_populations(ctx, src_ptr, on_device):
 
 def sllbm_step_record(ctx, n, moments_ptr):
     return check(ctx, lib.sllbm_step_record(ctx, n, moments_ptr))
+
+
+def sllbm_recorded_moments(ctx):
+    k = ctypes.c_int()
+    check(ctx, lib.sllbm_recorded_moments(ctx, ctypes.byref(k)))
+    return k.value
 
 
 def sllbm_adjoint_seed(ctx, g_rho_ptr, g_ux_ptr, g_uy_ptr, g_T_ptr, lam_ptr):

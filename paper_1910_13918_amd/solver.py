@@ -35,6 +35,7 @@ class Solver:
         self.precision = precision
         self.model = model
         self.nu = float(nu)
+        self.Pr = float(Pr)
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.ctx = C.sllbm_create(device, _PREC[precision])
         try:
@@ -157,12 +158,14 @@ class Solver:
 
     @property
     def recorded_moments(self):
-        """Moments per node and step of step_record: rho, u_x, u_y (+ theta)."""
-        return 3 if self.model == "isothermal" else 4
+        """Moments per node and step of step_record: rho, u_x, u_y (+ theta;
+        + the centred second moments of each set when Pr != 1)."""
+        return C.sllbm_recorded_moments(self.ctx)
 
     def step_record(self, n):
         """Advance n steps and return the moments (rho, u_x, u_y and, unless
-        isothermal, theta) of each step's streamed state as a device tensor
+        isothermal, theta; with Pr != 1 also each set's centred second
+        moments) of each step's streamed state as a device tensor
         [n, K, nodes] (float64)."""
         m = torch.empty((n, self.recorded_moments, self.n), dtype=torch.float64,
                         device=self.device)

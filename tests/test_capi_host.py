@@ -396,3 +396,21 @@ def test_scaled_velocity_set_tables_and_tau():
             np.testing.assert_allclose(M_l, M_o, rtol=0, atol=2e-13)
     finally:
         C.sllbm_destroy(ctx)
+
+
+def test_recorded_moments_per_model_and_prandtl_number():
+    """K of sllbm_step_record: rho, u (3); + theta for the thermal models (4);
+    + three centred second moments per set when Pr != 1 (what the transposed
+    quasi-equilibrium term needs)."""
+    cases = [(C.ISOTHERMAL, 1.0, 3), (C.MONATOMIC, 1.0, 4), (C.POLYATOMIC, 1.0, 4),
+             (C.MONATOMIC, 0.75, 7), (C.POLYATOMIC, 0.75, 10), (C.POLYATOMIC, 2.0, 10)]
+    for model, Pr, k in cases:
+        ctx = _ctx()
+        try:
+            assert _code(C.sllbm_recorded_moments, ctx) == C.E_STATE  # physics not set
+            C.sllbm_set_order(ctx, 2, C.NODES_GLC)
+            C.sllbm_init_grid_uniform(ctx, 4, 4, 0.0, 1.0, 0.0, 1.0, C.PERIODIC, C.PERIODIC)
+            C.sllbm_set_physics(ctx, 0.01, 0.01, 1.4, Pr, model)
+            assert C.sllbm_recorded_moments(ctx) == k, (model, Pr)
+        finally:
+            C.sllbm_destroy(ctx)

@@ -476,3 +476,118 @@ def test_checkpointed_rollout_nu_gradient(model):
     else:
         loss = lambda sm, F: thermal_misfit_loss(sm, F, ut, vt, Tt)
     assert dnu == pytest.approx(complex_step_nu(sim, f0, 10, loss), rel=1e-9)
+
+
+# ------------------------------------------------------------ Pr != 1
+PRANDTL = [(m, Pr) for m in ("monatomic", "polyatomic") for Pr in (0.75, 2.0)]
+
+
+def _prandtl(model, Pr):
+    wl = dict(THERMAL)[model]()
+    wl.Pr = Pr
+    return wl
+
+
+@pytest.mark.parametrize("model,Pr", PRANDTL)
+def test_prandtl_one_step_adjoint_against_central_differences(model, Pr):
+    """J^T of one step with the quasi-equilibrium collision (Sec. II.C-D):
+    <J^T lam, v> against central differences of <lam, step(F + e v)>; the
+    record carries the centred second moments of each set; the library's
+    combined S^T + J_C^T call equals the two separate calls."""
+    from paper_1910_13918_amd import sllbm as C
+    wl = _prandtl(model, Pr)
+    s = _solver(wl, "fp64")
+    try:
+        print(f"[gpu] Pr adjoint one step {model} Pr={Pr} nodes={s.n}", flush=True)
+        s.init_from_workload()
+        s.step(3)
+        F = s.populations_device().clone()
+        shape = tuple(F.shape)
+        lam = _rand(shape, 7)
+        v = _rand(shape, 8) * F.abs().mean()
+        s.set_populations(F)
+        mom = s.step_record(1)
+        assert mom.shape[1] == 4 + 3 * s.nsets
+        mu, out = torch.empty_like(lam), torch.empty_like(lam)
+        C.sllbm_adjoint_collide(s.ctx, lam.data_ptr(), mom[0].data_ptr(), mu.data_ptr())
+        C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, out.data_ptr())
+        torch.cuda.synchronize()
+        adj = float((out * v).sum())
+
+        def g(e):
+            s.set_populations(F + e * v)
+            s.step(1)
+            return float((lam * s.populations_device()).sum())
+
+        fd = (g(1e-6) - g(-1e-6)) / 2e-6
+        assert adj == pytest.approx(fd, rel=1e-6)
+        x = _rand(shape, 9)
+        a1, a2, b = torch.empty_like(lam), torch.empty_like(lam), torch.empty_like(lam)
+        C.sllbm_adjoint_step(s.ctx, x.data_ptr(), mom[0].data_ptr(), a1.data_ptr())
+        C.sllbm_adjoint_step(s.ctx, x.data_ptr(), None, b.data_ptr())
+        C.sllbm_adjoint_collide(s.ctx, b.data_ptr(), mom[0].data_ptr(), a2.data_ptr())
+        torch.cuda.synchronize()
+        assert torch.equal(a1, a2)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("model", ["monatomic", "polyatomic"])
+def test_prandtl_rollout_gradient_matches_complex_step(model):
+    """12 steps at Pr = 0.75 (8 x 8 cells p = 2, periodic, checkpoints every
+    5): the gradient in (rho0, u0, v0, T0) of the kinetic energy + velocity
+    and temperature misfit, along seeded directions, against the oracle's
+    complex-step derivative of the same Pr = 0.75 rollout."""
+    from oracle.adjoint import complex_step_fields, thermal_misfit_loss
+    from paper_1910_13918_amd.adjoint import rollout
+    wl = _thermal(W.tgv(8, 2, U0=0.3, steps=12), model, periodic=True)
+    wl.Pr = 0.75
+    s = _solver(wl, "fp64")
+    try:
+        print(f"[gpu] Pr adjoint rollout {model}", flush=True)
+        X, Y = s.coords()
+        f0 = wl.fields(X, Y)
+        ut, vt = W.fourier_target(X, Y, 0.3, seed=1234)
+        Tt = 1.0 + 0.05 * np.sin(X)
+        t = lambda a: torch.tensor(a, device="cuda")
+        leaves = [t(a).requires_grad_(True) for a in f0]
+        rho, ux, uy, T = rollout(leaves[0], leaves[1], leaves[2], s, 12, 5, T0=leaves[3])
+        M = _mass_weights(s)
+        L = _loss_torch(rho, ux, uy, M, t(ut), t(vt)) + (M * (T - t(Tt)) ** 2).sum()
+        L.backward()
+        grads = [a.grad.detach().cpu().numpy() for a in leaves]
+    finally:
+        s.close()
+    g = Grid(wl.edges_x, wl.edges_y, wl.p, True, True)
+    sim = Sim(g, wl.dt, wl.nu, model, gamma=wl.gamma, Pr=0.75)
+    loss = lambda sm, F: thermal_misfit_loss(sm, F, ut, vt, Tt)
+    rng = np.random.default_rng(78)
+    for _ in range(3):
+        d = [rng.standard_normal(g.nnodes) for _ in range(4)]
+        ref = complex_step_fields(sim, f0, d, 12, loss)
+        got = sum(float(np.dot(gr, di)) for gr, di in zip(grads, d))
+        assert got == pytest.approx(ref, rel=1e-9, abs=1e-13)
+
+
+def test_viscosity_term_refused_at_prandtl():
+    from paper_1910_13918_amd import sllbm as C
+    from paper_1910_13918_amd.adjoint import rollout
+    wl = _prandtl("monatomic", 0.75)
+    s = _solver(wl, "fp64")
+    try:
+        s.init_from_workload()
+        mom = s.step_record(1)
+        F = s.populations_device()
+        lam = torch.zeros_like(F)
+        acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+        with pytest.raises(C.SllbmError) as e:
+            C.sllbm_adjoint_nu_term(s.ctx, lam.data_ptr(), F.data_ptr(), mom[0].data_ptr(),
+                                    acc.data_ptr())
+        assert e.value.code == C.E_UNSUPPORTED
+        X, Y = s.coords()
+        f0 = [torch.tensor(a, device="cuda") for a in wl.fields(X, Y)]
+        nu = torch.tensor(wl.nu, dtype=torch.float64, requires_grad=True)
+        with pytest.raises(ValueError):
+            rollout(f0[0], f0[1], f0[2], s, 3, 2, T0=f0[3], nu=nu)
+    finally:
+        s.close()

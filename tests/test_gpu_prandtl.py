@@ -144,17 +144,32 @@ def test_riemann_trajectory_fp64():
         s.close()
 
 
-def test_adjoint_refuses_prandtl():
-    from paper_1910_13918_amd import sllbm as C
-    wl = _wl("monatomic", 2, True, 0.75)
-    s = _solver(wl, "fp64", "auto")
+@pytest.mark.parametrize("model", ["monatomic", "polyatomic"])
+@pytest.mark.parametrize("path", ["rows", "tiled", "direct", "records"])
+def test_recorded_second_moments_match_the_oracle(model, path):
+    """With Pr != 1 the step record carries, after rho, u and theta, the
+    centred second moments sum s (xi - u)_a (xi - u)_b of each set of the
+    streamed state (what the transposed quasi-equilibrium term needs):
+    against the oracle's streamed state, every gather."""
+    wl = _wl(model, 2, True, 0.75)
+    g, sim = _sim(wl, 0.75)
+    F0 = _state(wl, sim, g, 17, False)
+    s = _solver(wl, "fp64", path)
     try:
-        s.init_from_workload()
-        lam = torch.zeros(s.nsets * s.q * s.n, dtype=torch.float64, device="cuda")
-        mu = torch.zeros_like(lam)
-        mom = torch.ones(4 * s.n, dtype=torch.float64, device="cuda")
-        with pytest.raises(C.SllbmError) as e:
-            C.sllbm_adjoint_collide(s.ctx, lam.data_ptr(), mom.data_ptr(), mu.data_ptr())
-        assert e.value.code == C.E_UNSUPPORTED
+        print(f"[gpu] recorded second moments {model} {path}", flush=True)
+        s.set_populations(F0)
+        mom = s.step_record(1)[0].cpu().numpy()
     finally:
         s.close()
+    Fs = sim.stream(F0)
+    rho, ux, uy, theta = sim.moments(Fs)
+    assert mom.shape[0] == 4 + 3 * sim.S
+    for k, want in enumerate((rho, ux, uy, theta)):
+        assert np.abs(mom[k] - want).max() <= 1e-12 * max(np.abs(want).max(), 1.0)
+    cx = sim.xi[:, 0, None] - ux[None]
+    cy = sim.xi[:, 1, None] - uy[None]
+    for s_ in range(sim.S):
+        for j, w in enumerate((cx * cx, cx * cy, cy * cy)):
+            want = (Fs[s_] * w).sum(axis=0)
+            got = mom[4 + 3 * s_ + j]
+            assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), (s_, j)
