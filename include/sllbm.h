@@ -307,7 +307,9 @@ int sllbm_set_check_interval(sllbm_ctx *ctx, int64_t k);
  * of f and then of g (float64, device pointer, K * nx * ny values per step,
  * K from sllbm_recorded_moments).  These are what the collision Jacobian of
  * step s depends on; the adjoint sweep replays a checkpointed segment with
- * this call. */
+ * this call.  The second moments are recovered after each step from its
+ * post-collision state (the collision moves them by the factor 1 - 1/tau),
+ * so a Pr != 1 record needs tau != 1 (SLLBM_E_UNSUPPORTED otherwise). */
 int sllbm_step_record(sllbm_ctx *ctx, int64_t n, double *moments);
 
 /* K, the moments sllbm_step_record keeps per node and step: 3 isothermal,

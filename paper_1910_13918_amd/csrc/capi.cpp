@@ -1058,6 +1058,12 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
       (path == kPathRecords ? double(nvel(c)) * double(nnodes(c)) * double(4 + 2 * pop_size(c))
                             : 0.0);
   const bool big_state = state_bytes > 256.0 * (1 << 20);
+  // Pr != 1 records also carry each set's centred second moments, recovered
+  // after the step from the post-collision state (needs omega != 1)
+  const bool rec_m2 = moments && c->model != SLLBM_ISOTHERMAL && c->omega_pr != c->omega;
+  if (rec_m2 && (c->omega == 1.0 || q1(c) != kQ1))
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "a Pr != 1 moment record needs tau != 1 and the 5-velocity set");
   for (int64_t s = 0; s < n; ++s) {
     k.mom_out = moments ? moments + s * recorded_moments(c) * k.n : nullptr;
     // when what a step streams exceeds the 256 MB last-level cache (MALL)
@@ -1069,6 +1075,8 @@ static int run_steps(sllbm_ctx *c, int64_t n, double *moments) {
     HIP_TRY(c, launch_step(c->fp32, c->model, path, k, t, c->pop[c->cur], c->pop[1 - c->cur],
                            flag, c->stream));
     c->cur ^= 1;
+    if (rec_m2)
+      HIP_TRY(c, launch_record_m2(c->fp32, c->model, k, c->pop[c->cur], k.mom_out, c->stream));
     ++c->steps_done;
     if (c->check_interval > 0 && c->steps_done % c->check_interval == 0) {
       int f = 0;

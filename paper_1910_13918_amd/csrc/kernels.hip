@@ -172,6 +172,52 @@ __global__ __launch_bounds__(256) void k_mass(const T *__restrict__ f,
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
+// ---------------------------------------------------------------------------
+// centred second moments of a step's streamed state, for the record of a
+// Pr != 1 step, from its post-collision state F+ (storage order c.layout)
+// and the step's recorded rho, u, theta.  Per set, the collision moves the
+// centred second moment M (about u) as M+ = (1 - omega) M + omega M_eq:
+// f* is built from third-order Hermite terms, whose moments of degree <= 2
+// vanish under the D1Q5 rule (exact to degree 9), and the equilibrium's
+// centred second moment is rho theta I for f and (2 C_v - D) rho theta^2 I
+// for g.  Hence M = (M+ - omega M_eq) / (1 - omega) (omega != 1, checked by
+// the host); written to record slots 4 + 3 s .. 6 + 3 s: xx, xy, yy.
+// ---------------------------------------------------------------------------
+template <typename T, int MODEL>
+__global__ __launch_bounds__(256) void k_record_m2(const T *__restrict__ f,
+                                                   double *__restrict__ mom, StepConsts c) {
+  constexpr int S = Sets<MODEL>::S;
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (v >= c.n) return;
+  const long long N = c.n;
+  const double rho = mom[v], ux = mom[N + v], uy = mom[2 * N + v], th = mom[3 * N + v];
+  const double om = c.omega, inv = 1.0 / (1.0 - om);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    double sxx = 0.0, sxy = 0.0, syy = 0.0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const double cy = c.xi[b] - uy;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        const double val = double(f[pop_elem(c.layout, 5, s, a, b, v, N)]);
+        const double cx = c.xi[a] - ux;
+        s0 += val;
+        s1 = fma(cx, val, s1);
+        s2 = fma(cx * cx, val, s2);
+      }
+      sxx += s2;
+      sxy = fma(s1, cy, sxy);
+      syy = fma(s0, cy * cy, syy);
+    }
+    const double iso = om * rho * th * (s == 0 ? 1.0 : c.gfac * th);
+    mom[(4 + 3 * s) * N + v] = (sxx - iso) * inv;
+    mom[(5 + 3 * s) * N + v] = sxy * inv;
+    mom[(6 + 3 * s) * N + v] = (syy - iso) * inv;
+  }
+}
+
 __global__ void k_clear_int(int *__restrict__ p) {
   if (threadIdx.x == 0) p[0] = 0;
 }
@@ -346,6 +392,23 @@ hipError_t launch_nu_term(int fp32, int model, const StepConsts &c, const void *
   k_sum<<<1, 256, 0, s>>>(partial, mass_blocks(c), scalar);
   k_add_scaled<<<1, 64, 0, s>>>(scalar, scale, acc);
   return hipGetLastError();
+}
+
+hipError_t launch_record_m2(int fp32, int model, const StepConsts &c, const void *f, double *mom,
+                            hipStream_t s) {
+  const unsigned blocks = unsigned((c.n + 255) / 256);
+  if (c.q1 != 5 || c.omega == 1.0) return hipErrorInvalidValue;
+  auto go = [&]<typename T, int MODEL>() {
+    k_record_m2<T, MODEL><<<blocks, 256, 0, s>>>(static_cast<const T *>(f), mom, c);
+    return hipGetLastError();
+  };
+  if (model == kMonatomic)
+    return fp32 ? go.template operator()<float, kMonatomic>()
+                : go.template operator()<double, kMonatomic>();
+  if (model == kPolyatomic)
+    return fp32 ? go.template operator()<float, kPolyatomic>()
+                : go.template operator()<double, kPolyatomic>();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_clear_flag(int *flag, hipStream_t s) {

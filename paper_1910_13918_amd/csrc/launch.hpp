@@ -158,6 +158,13 @@ constexpr int kScratchDoubles = 1 << 17;  // mass partials of up to 2^25 nodes
 constexpr int kMaxDevices = 64;
 hipError_t scratch_buffer(int device, double **ptr);
 
+// Record slots 4 + 3 s .. 6 + 3 s of a Pr != 1 step (thermal models, D2Q25,
+// omega != 1): each set's centred second moments of the streamed state,
+// recovered from the post-collision state f (order c.layout) and the step's
+// recorded rho, u, theta in mom ([K][n]).
+hipError_t launch_record_m2(int fp32, int model, const StepConsts &c, const void *f, double *mom,
+                            hipStream_t s);
+
 // flag = 0 (a kernel, not a memset, so the call can live inside a captured graph)
 hipError_t launch_clear_flag(int *flag, hipStream_t s);
 

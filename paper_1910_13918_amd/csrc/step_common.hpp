@@ -249,33 +249,6 @@ __device__ __forceinline__ void centred_third_moments(const T (&f)[25], double u
   }
 }
 
-// Centred second moments of one population set about u:
-// m2 = (sum f (xi_a - u_x)^2, sum f (xi_a - u_x)(xi_b - u_y), sum f (xi_b - u_y)^2).
-// Recorded with Pr != 1 for the adjoint: the u-derivative of the centred
-// third moment Q_k = sum f c_x^k c_y^(3-k) is -k M_(k-1,3-k) in u_x and
-// -(3-k) M_(k,2-k) in u_y.
-template <typename T>
-__device__ __forceinline__ void centred_second_moments(const T (&f)[25], double ux, double uy,
-                                                       const StepConsts &c, double (&m2)[3]) {
-  m2[0] = m2[1] = m2[2] = 0.0;
-#pragma unroll
-  for (int b = 0; b < 5; ++b) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      const double v = double(f[a + 5 * b]);
-      const double cx = c.xi[a] - ux;
-      s0 += v;
-      s1 = fma(cx, v, s1);
-      s2 = fma(cx * cx, v, s2);
-    }
-    const double cy = c.xi[b] - uy;
-    m2[0] += s2;
-    m2[1] = fma(s1, cy, m2[1]);
-    m2[2] = fma(s0, cy * cy, m2[2]);
-  }
-}
-
 // Quasi-equilibrium population of velocity i = a + 5b from the row factors
 // y[k] = kappa Q_{k,3-k} He_{3-k}(xi_b)/(3-k)!:  kappa f*_i with
 // f*_i = (w_i / 3!) Q : H^(3)(xi_i).  Grouping the 8 index triples by their
@@ -389,10 +362,8 @@ __device__ __forceinline__ void relax_store(const T (&fs)[Sets<MODEL>::S][Q1 * Q
 
 // Moments of one node's streamed populations; when `valid`, records them for
 // the adjoint (if asked) and raises the stability flag on rho <= 0,
-// theta <= 0 or a non-finite moment.  Recorded per node: rho, u_x, u_y,
-// theta (thermal models) and, with PR (Pr != 1), the centred second moments
-// of each set (slots 4 + 3 s .. 6 + 3 s).
-template <typename T, int MODEL, int Q1 = 5, bool PR = false>
+// theta <= 0 or a non-finite moment.
+template <typename T, int MODEL, int Q1 = 5>
 __device__ __forceinline__ void collide_moments(const T (&fs)[Sets<MODEL>::S][Q1 * Q1],
                                                 const StepConsts &c, long long v, bool valid,
                                                 int *__restrict__ flag, double (&m)[4]) {
@@ -403,15 +374,6 @@ __device__ __forceinline__ void collide_moments(const T (&fs)[Sets<MODEL>::S][Q1
     c.mom_out[c.n + v] = m[1];
     c.mom_out[2 * c.n + v] = m[2];
     if (MODEL != kIsothermal) c.mom_out[3 * c.n + v] = m[3];
-    if constexpr (PR && Q1 == 5) {
-#pragma unroll
-      for (int s = 0; s < Sets<MODEL>::S; ++s) {
-        double m2[3];
-        centred_second_moments<T>(fs[s], m[1], m[2], c, m2);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) c.mom_out[(4 + 3 * s + j) * c.n + v] = m2[j];
-      }
-    }
   }
   const bool ok = (m[0] > 0.0) && (m[3] > 0.0) && isfinite(m[0]) && isfinite(m[1]) &&
                   isfinite(m[2]) && isfinite(m[3]);
@@ -430,7 +392,7 @@ __device__ __forceinline__ void collide_store(const T (&fs)[Sets<MODEL>::S][Q1 *
                                               const StepConsts &c, T *__restrict__ fout,
                                               long long v, int *__restrict__ flag) {
   double m[4];
-  collide_moments<T, MODEL, Q1, PR>(fs, c, v, true, flag, m);
+  collide_moments<T, MODEL, Q1>(fs, c, v, true, flag, m);
   relax_store<T, MODEL, PR, Q1, LAYOUT>(fs, m, c, fout, v);
 }
 
