@@ -204,3 +204,40 @@ def test_shock_vortex_reduced_trajectory_against_oracle(precision, path, bound):
     # oracle's by ~1e-7 per step (measured: mass change 6.0e-6 against the
     # oracle's 2.2e-6 after 200 steps; the per-axis tables < 1e-6)
     assert abs(dm - ref["mass_rel_change"]) <= (1e-12 if precision == "fp64" else 2e-5)
+
+
+def test_shock_vortex_paper_stretching_needs_half_time_step():
+    """Reading R29: with the paper's stretching Lambda = 0.95 on this grid
+    (2-3 times finer per vortex radius than the paper's), the CFL time step of
+    the finest cells is too long once the vortex reaches the shock: the
+    stability flag rises before step 2000 (FP32, checked every 50 steps); at
+    half that time step the 2000 steps run through."""
+    import copy
+
+    from paper_1910_13918_amd import sllbm as C
+    from paper_1910_13918_amd.solver import Solver
+    wl = W.svi(1024, 512, 3, lam=0.95)
+    half = copy.copy(wl)
+    half.dt = wl.dt / 2
+    print("[gpu] shock-vortex lambda = 0.95 at half the time step, 2000 steps", flush=True)
+    s = Solver.from_workload(half, precision="fp32")
+    try:
+        s.init_from_workload()
+        s.step(2000)
+        assert s.flags() == (0, 2000)
+        assert all(np.isfinite(a).all() for a in s.moments())
+    finally:
+        s.close()
+    print("[gpu] shock-vortex lambda = 0.95 at the CFL time step", flush=True)
+    s = Solver.from_workload(wl, precision="fp32")
+    try:
+        s.init_from_workload()
+        C.sllbm_set_check_interval(s.ctx, 50)
+        with pytest.raises(C.SllbmError) as e:
+            s.step(2000)
+        assert e.value.code == C.E_UNSTABLE
+        unstable, done = s.flags()
+        print(f"[gpu] flag raised by step {done}", flush=True)
+        assert unstable == 1 and 400 <= done < 2000
+    finally:
+        s.close()
