@@ -73,9 +73,11 @@ struct DevTables {
   const void *xw;       // [5][p+1][nx], population type
   const int32_t *ysrc;  // [5][p+1][ny]
   const void *yw;       // [5][p+1][ny]
-  const int32_t *rec_cell;  // [25][n]: cx | cy << 16
-  const void *rec_r;        // [25][n] reference x coordinate, population type
-  const void *rec_s;        // [25][n] reference y coordinate
+  // departure records per (velocity, node), velocity-major: float32: {cell,
+  // r, s} triples of 32-bit words in `rec`; float64: {r, s} pairs in `rec`
+  // and the cells in `rec_cell`; cell = cx | cy << 16
+  const int32_t *rec_cell;  // [25][n] (float64 populations)
+  const void *rec;          // [25][n] triples (float32) or pairs (float64)
   const double *rnodes;     // p + 1 reference support points (records path)
   const double *mx;     // [nx] mass weights
   const double *my;     // [ny]

@@ -39,6 +39,40 @@ __device__ __forceinline__ T records_interp(__amdgpu_buffer_rsrc_t rs, const uns
   return acc;
 }
 
+// Three 32-bit words (one float32 departure record).
+typedef unsigned rec_words3 __attribute__((ext_vector_type(3)));
+
+// Departure record of velocity i at node v (the layout of DevTables::rec):
+// float32 one 12-byte {cell, r, s} load, float64 the cell plane and one
+// 16-byte {r, s} load.  Each velocity's records get their own buffer
+// resource, so offsets stay 32-bit on the largest grids.
+template <typename T>
+__device__ __forceinline__ void load_record(const int32_t *__restrict__ cell,
+                                            const void *__restrict__ rec, int i, long long v,
+                                            long long N, int &cellv, T &r, T &s) {
+  if constexpr (sizeof(T) == 4) {
+    const auto rs = make_rsrc(static_cast<const uint32_t *>(rec) + (long long)i * N * 3,
+                              unsigned(N) * 12u);
+    const rec_words3 q = __builtin_amdgcn_raw_buffer_load_b96(rs, unsigned(v) * 12u, 0, 0);
+    // the words go through scalars: a bit cast of a vector element itself
+    // was compiled as a read of the vector's first element
+    const unsigned w0 = q[0], w1 = q[1], w2 = q[2];
+    cellv = int(w0);
+    r = __builtin_bit_cast(T, w1);
+    s = __builtin_bit_cast(T, w2);
+  } else {
+    using u4 = __attribute__((ext_vector_type(4))) unsigned;
+    using u2 = __attribute__((ext_vector_type(2))) unsigned;
+    const auto rc = make_rsrc(cell + (long long)i * N, unsigned(N) * 4u);
+    cellv = int(__builtin_amdgcn_raw_buffer_load_b32(rc, unsigned(v) * 4u, 0, 0));
+    const auto rs = make_rsrc(static_cast<const double *>(rec) + (long long)i * N * 2,
+                              unsigned(N) * 16u);
+    const u4 q = __builtin_amdgcn_raw_buffer_load_b128(rs, unsigned(v) * 16u, 0, 0);
+    r = __builtin_bit_cast(T, u2{q.x, q.y});
+    s = __builtin_bit_cast(T, u2{q.z, q.w});
+  }
+}
+
 // Whether the gather of the next velocity is issued before this velocity's
 // interpolation: float32 f + g, where it measured +13 % on the shock-vortex
 // grid (p = 3) and +3 % at p = 2; a single set and float64 lose 1-3 % to the
@@ -53,8 +87,8 @@ constexpr int kRecTileRows = 4;
 template <typename T, int P, int MODEL, bool PR, int Q1 = 5>
 __global__ __launch_bounds__(64 * kRecTileRows) void k_step_records(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ cell,
-    const T *__restrict__ rr, const T *__restrict__ ss, int ntx, int nty, int strip,
-    StepConsts c, int *__restrict__ flag) {
+    const void *__restrict__ rec, int ntx, int nty, int strip, StepConsts c,
+    int *__restrict__ flag) {
   constexpr int S = Sets<MODEL>::S;
   constexpr int P1 = P + 1;
   constexpr int Q = Q1 * Q1;
@@ -71,9 +105,6 @@ __global__ __launch_bounds__(64 * kRecTileRows) void k_step_records(
   const long long v = (long long)iy * c.nx + ix;
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
-  const unsigned voff = unsigned(v) * unsigned(sizeof(T));
-  const auto rcell = make_rsrc(cell, unsigned(N * Q * (long long)sizeof(int32_t)));
-  const unsigned cell_off = unsigned(v) * unsigned(sizeof(int32_t));
   T rn[P1], den[P1];
 #pragma unroll
   for (int m = 0; m < P1; ++m) {
@@ -89,10 +120,7 @@ __global__ __launch_bounds__(64 * kRecTileRows) void k_step_records(
     int recq[RD + 1];
     T rq[RD + 1], sq[RD + 1];
     auto load_rec = [&](int i) {
-      recq[i % (RD + 1)] = int(__builtin_amdgcn_raw_buffer_load_b32(rcell, cell_off,
-                                                               unsigned(i) * unsigned(N) * 4u, 0));
-      rq[i % (RD + 1)] = buffer_load<T>(make_rsrc(rr + i * N, plane_bytes), voff, 0);
-      sq[i % (RD + 1)] = buffer_load<T>(make_rsrc(ss + i * N, plane_bytes), voff, 0);
+      load_record<T>(cell, rec, i, v, N, recq[i % (RD + 1)], rq[i % (RD + 1)], sq[i % (RD + 1)]);
     };
     T vals[2][S][P1][P1];
     T wxq[2][P1], wyq[2][P1];
@@ -162,10 +190,7 @@ __global__ __launch_bounds__(64 * kRecTileRows) void k_step_records(
     int recq[RD + 1];
     T rq[RD + 1], sq[RD + 1];
     auto load_rec = [&](int i) {
-      recq[i % (RD + 1)] = int(__builtin_amdgcn_raw_buffer_load_b32(rcell, cell_off,
-                                                               unsigned(i) * unsigned(N) * 4u, 0));
-      rq[i % (RD + 1)] = buffer_load<T>(make_rsrc(rr + i * N, plane_bytes), voff, 0);
-      sq[i % (RD + 1)] = buffer_load<T>(make_rsrc(ss + i * N, plane_bytes), voff, 0);
+      load_record<T>(cell, rec, i, v, N, recq[i % (RD + 1)], rq[i % (RD + 1)], sq[i % (RD + 1)]);
     };
   #pragma unroll
     for (int i = 0; i < RD; ++i) load_rec(i);
@@ -223,9 +248,8 @@ hipError_t launch_records_family(int fp32, int model, const StepConsts &c, const
     } else {
       return dispatch_q3(fp32, c.p, model, [&]<typename T, int P>() {
         k_step_records<T, P, kIsothermal, false, 3><<<grid, 64 * kRecTileRows, 0, s>>>(
-            static_cast<const T *>(fin), static_cast<T *>(fout), t.rec_cell,
-            static_cast<const T *>(t.rec_r), static_cast<const T *>(t.rec_s), ntx, nty, strip, c,
-            flag);
+            static_cast<const T *>(fin), static_cast<T *>(fout), t.rec_cell, t.rec, ntx, nty,
+            strip, c, flag);
         return hipGetLastError();
       });
     }
@@ -233,9 +257,8 @@ hipError_t launch_records_family(int fp32, int model, const StepConsts &c, const
   if (c.q1 != 5) return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
     k_step_records<T, P, MODEL, PR><<<grid, 64 * kRecTileRows, 0, s>>>(
-        static_cast<const T *>(fin), static_cast<T *>(fout), t.rec_cell,
-        static_cast<const T *>(t.rec_r), static_cast<const T *>(t.rec_s), ntx, nty, strip, c,
-        flag);
+        static_cast<const T *>(fin), static_cast<T *>(fout), t.rec_cell, t.rec, ntx, nty, strip,
+        c, flag);
     return hipGetLastError();
   });
 }
