@@ -378,8 +378,8 @@ int prepare_device(sllbm_ctx *c) {
       if (!e.empty()) return fail(c, SLLBM_E_ARG, e);
     // one record per (velocity, node) in one stretch of memory, read with one
     // load (float32: {cell, r, s}, 12 bytes; float64: {r, s} with the cells
-    // in a plane of their own): the records gather of the shock-vortex
-    // pattern ran 13 % faster than with three separate planes
+    // in a plane of their own): the shock-vortex records step took 1.04
+    // against 1.05 ms with three separate planes
     const size_t nrec = size_t(nq) * N;
     if (c->fp32) {
       std::vector<uint32_t> rec(3 * nrec);

@@ -18,11 +18,11 @@
 // The streamed values stay in registers and the collision is the one of the
 // other paths (collide_store).  The forward step reads and writes the grouped
 // storage order (PopLayout), in which the four moving x-components of one
-// velocity row lie next to each other for every node: measured on the
-// Riemann 1025^2-node benchmark pattern (float32 f + g), the planes of one
-// row then come from one stretch of memory instead of four planes 4 MB
-// apart, and the step takes 94 instead of 105 us; the adjoint's transposed
-// gather keeps the planar order of its own arrays.
+// velocity row lie next to each other for every node: the planes of one row
+// then come from one stretch of memory instead of four planes 4 MB apart
+// (Riemann 1025^2 nodes, float32 f + g: 99.7 against 108.8 us per step on
+// one box); the adjoint's transposed gather keeps the planar order of its
+// own arrays.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -186,9 +186,11 @@ __device__ __forceinline__ void rows_stream(const T *__restrict__ fin,
 // 16-byte node stride each touched four times the cache lines (L1 accesses
 // 81 M against 18 M per step on the planar order).  DG groups of loads run ahead of the arithmetic;
 // SYNC: a workgroup barrier before every group (every wavefront of the
-// workgroup must call this).  Measured on the Riemann 1025^2-node pattern
-// (float32 f + g, p = 2): 95 us per step against 157 us with the plane-by-
-// plane loop of rows_stream on the same order and 105 us on the planar order.
+// workgroup must call this).  Measured on the Riemann 1025^2-node step
+// (float32 f + g, p = 2): the plane-by-plane loop of rows_stream on this
+// order took 155 us (four strided 4-byte loads per row, each touching four
+// times the cache lines), this one 99.7 against 108.8 us for the planar
+// order on the same box.
 template <typename T, int P1, int S, int DG, bool SYNC, int Q1>
 __device__ __forceinline__ void rows_stream_grouped(
     const T *__restrict__ fin, const int32_t *__restrict__ xrel, const T *__restrict__ xw,
@@ -286,7 +288,8 @@ __device__ __forceinline__ void rows_stream_grouped(
 }
 
 // Groups of loads in flight ahead of the one being interpolated (grouped
-// order): one measured best for float32 f + g (two: +1 %).
+// order): two measured within 1 % of one for float32 f + g and 2 % slower
+// for float64 f + g, so one.
 template <typename T, int P1, int S>
 constexpr int rows_group_lookahead() { return 1; }
 
