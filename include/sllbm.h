@@ -195,9 +195,11 @@ int sllbm_init_grid_mapped(sllbm_ctx *ctx, int ncx, int ncy, const double *edges
  * a departure point that is not found fails that step with SLLBM_E_ARG) and
  * streamed with the records gather: AUTO resolves to SLLBM_PATH_RECORDS and
  * every other path is refused (SLLBM_E_UNSUPPORTED), as are the per-axis
- * queries (sllbm_node_coords, sllbm_departure_table, sllbm_mass_weights)
- * and the adjoint.  sllbm_mass integrates the interpolated density with the
- * node masses of the bilinear cells (sllbm_node_masses). */
+ * queries (sllbm_node_coords, sllbm_departure_table, sllbm_mass_weights).
+ * sllbm_mass integrates the interpolated density with the node masses of the
+ * bilinear cells (sllbm_node_masses).  The adjoint's S^T is the transposed
+ * records gather (built on the host at the first adjoint call: per velocity,
+ * N (p+1)^2 entries of a target index and a weight). */
 int sllbm_init_grid_curvilinear(sllbm_ctx *ctx, int ncx, int ncy, const double *vx,
                                 const double *vy);
 
@@ -208,8 +210,8 @@ int sllbm_init_grid_curvilinear(sllbm_ctx *ctx, int ncx, int ncy, const double *
  * velocity set that integrates the Gaussian's moments exactly up to degree 7
  * (the default set does), so that the equilibrium has no centred third
  * moment; SLLBM_E_UNSUPPORTED otherwise (also from a later
- * sllbm_set_velocity_set that breaks it).  The adjoint calls below refuse
- * Pr != 1 (SLLBM_E_UNSUPPORTED). */
+ * sllbm_set_velocity_set that breaks it).  The adjoint calls below cover
+ * Pr != 1 except the viscosity term (SLLBM_E_UNSUPPORTED there). */
 int sllbm_set_physics(sllbm_ctx *ctx, double dt, double nu, double gamma, double Pr, int model);
 
 /* Streaming kernel family (sllbm_path).  SLLBM_PATH_TILED needs departures
@@ -391,12 +393,13 @@ int sllbm_adjoint_collide(sllbm_ctx *ctx, const void *lambda, const double *mome
  * the term is sum lambda (F+ - F_eq) / ((1 - 1/tau) tau^2 dt).  Summed over
  * the steps it is dL/d(nu).  acc: one float64 on the device, accumulated in
  * stream order.  SLLBM_E_UNSUPPORTED when tau = 1 (F+ = F_eq carries no
- * non-equilibrium part), with Pr != 1 or on a curvilinear mesh. */
+ * non-equilibrium part) or with Pr != 1. */
 int sllbm_adjoint_nu_term(sllbm_ctx *ctx, const void *lambda, const void *populations,
                           const double *moments, double *acc);
 
 /* out = S^T mu (the transposed interpolation, a gather through transposed
- * departure tables), followed by J_C(M_prev)^T when moments_prev (the record
+ * departure tables, or on a curvilinear mesh through the transposed
+ * records), followed by J_C(M_prev)^T when moments_prev (the record
  * of the previous step) is not NULL (fused into one kernel at Pr = 1; at
  * Pr != 1 two kernels through a library-owned scratch array of one state).
  * mu and out must differ. */

@@ -95,6 +95,43 @@ __global__ __launch_bounds__(256) void k_adjoint_collide(const T *__restrict__ l
   collision_adjoint_store<T, MODEL, PR>(l, mom, c, mu, v);
 }
 
+// S^T on a curvilinear mesh: for source node j and velocity i, the sum over
+// the targets whose departure stencil holds j (their records' Lagrange
+// weights, built on the host) of weight x mu_i(target); then J_C^T of the
+// previous step when mom_prev is given (Pr = 1).  One thread per source node.
+template <typename T, int MODEL>
+__global__ __launch_bounds__(256) void k_adjoint_step_csr(const T *__restrict__ mu,
+                                                          const uint32_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const T *__restrict__ w,
+                                                          const double *__restrict__ mom_prev,
+                                                          T *__restrict__ out, StepConsts c) {
+  constexpr int S = Sets<MODEL>::S;
+  const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= c.n) return;
+  const long long N = c.n;
+  T lam[S][25];
+#pragma unroll
+  for (int i = 0; i < 25; ++i) {
+    const uint32_t e0 = ptr[i * (N + 1) + j], e1 = ptr[i * (N + 1) + j + 1];
+    T acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = T(0);
+    for (uint32_t e = e0; e < e1; ++e) {
+      const long long v = col[e];
+      const T we = w[e];
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[s] = fma(we, mu[(s * 25 + i) * N + v], acc[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) lam[s][i] = acc[s];
+  }
+  if (mom_prev)
+    collision_adjoint_store<T, MODEL>(lam, mom_prev, c, out, j);
+  else
+    store_sets<T, S>(lam, c, out, j);
+}
+
 // S^T by direct gathers through the transposed tables (no LDS).
 template <typename T, int MODEL, int TAPS>
 __global__ __launch_bounds__(256) void k_adjoint_step_direct(
@@ -201,9 +238,19 @@ hipError_t launch_adjoint_collide(int fp32, int model, const StepConsts &c, cons
 hipError_t launch_adjoint_step(int fp32, int model, int kind, const StepConsts &c,
                                const DevTables &t, const void *mu, const double *mom_prev,
                                void *out, hipStream_t s) {
-  if (t.taps < 2 || t.taps > kMaxTaps) return hipErrorInvalidValue;
   // the fused J_C^T is the Pr = 1 one; the host splits the Pr != 1 step
   if (mom_prev && c.omega_pr != c.omega) return hipErrorInvalidValue;
+  if (kind == kAdjointCsr) {
+    if (!t.csr_ptr || !t.csr_col || !t.csr_w || c.q1 != 5) return hipErrorInvalidValue;
+    const unsigned blocks = unsigned((c.n + 255) / 256);
+    return dispatch_model(fp32, model, [&]<typename T, int MODEL>() -> hipError_t {
+      k_adjoint_step_csr<T, MODEL><<<blocks, 256, 0, s>>>(
+          static_cast<const T *>(mu), t.csr_ptr, t.csr_col, static_cast<const T *>(t.csr_w),
+          mom_prev, static_cast<T *>(out), c);
+      return hipGetLastError();
+    });
+  }
+  if (t.taps < 2 || t.taps > kMaxTaps) return hipErrorInvalidValue;
   if (kind == kAdjointRows) return launch_adjoint_step_rows(fp32, model, c, t, mu, mom_prev, out, s);
   if (kind == kAdjointTiled)
     return fp32 ? launch_adjoint_step_tiled_t<float>(model, c, t, mu, mom_prev, out, s)

@@ -89,6 +89,7 @@ struct sllbm_ctx {
       macro;
   DeviceBuf rec_cell, rec;  // departure records (see DevTables)
   DeviceBuf adj_tmp;  // Pr != 1 adjoint step: S^T mu before the collision transpose
+  DeviceBuf csr_ptr, csr_col, csr_w;  // curvilinear mesh: transposed records (DevTables)
   void *pop[2] = {nullptr, nullptr};
   bool own_pop = false;
   size_t pop_bytes = 0;
@@ -559,11 +560,74 @@ void pad_taps(AxisTable &t, const Axis &ax, int taps) {
   t.taps = taps;
 }
 
+// Transposed records gather of a curvilinear mesh: for every velocity i and
+// source node j, the targets v whose departure stencil (the records' cell,
+// p+1 x p+1 nodes) holds j, with the Lagrange weight l_m(r_v) l_n(s_v) of
+// j in it.  Every target contributes (p+1)^2 entries, so velocity i's entries
+// start at i N (p+1)^2; within a source node they are in target order.
+int build_records_transpose(sllbm_ctx *c) {
+  const long long N = nnodes(c);
+  const int nq = nvel(c), P1 = c->p + 1, p = c->p;
+  const int nx = c->ax.n, ny = c->ay.n;
+  const uint64_t per_vel = uint64_t(N) * uint64_t(P1 * P1);
+  if (per_vel * uint64_t(nq) > uint64_t(0xffffffffu))
+    return fail(c, SLLBM_E_UNSUPPORTED,
+                "curvilinear mesh too large for the adjoint's 32-bit transposed records");
+  const std::vector<double> pts = support_points(p, c->glc);
+  std::vector<uint32_t> ptr(size_t(nq) * size_t(N + 1));
+  std::vector<int32_t> col(size_t(per_vel) * nq);
+  std::vector<double> w(size_t(per_vel) * nq);
+  std::vector<std::string> errs(nq);
+  const int nthreads = std::max(1, std::min({nq, 16, int(std::thread::hardware_concurrency())}));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthreads; ++t)
+    pool.emplace_back([&, t] {
+      std::vector<int32_t> cell(N);
+      std::vector<double> r(N), s(N);
+      std::vector<uint32_t> next(N);
+      for (int i = t; i < nq; i += nthreads) {
+        errs[i] = departure_records(c, i, cell.data(), r.data(), s.data());
+        if (!errs[i].empty()) continue;
+        auto node = [&](long long v, int m, int n) {  // as the records gather reads it
+          const int32_t rec = cell[v];
+          int jx = (rec & 0xffff) * p + m, jy = int(uint32_t(rec) >> 16) * p + n;
+          if (jx >= nx) jx -= nx;
+          if (jy >= ny) jy -= ny;
+          return (long long)jy * nx + jx;
+        };
+        uint32_t *rp = ptr.data() + size_t(i) * size_t(N + 1);
+        std::fill(rp, rp + N + 1, 0u);
+        for (long long v = 0; v < N; ++v)
+          for (int n = 0; n < P1; ++n)
+            for (int m = 0; m < P1; ++m) ++rp[node(v, m, n) + 1];
+        rp[0] = uint32_t(uint64_t(i) * per_vel);
+        for (long long j = 0; j < N; ++j) rp[j + 1] += rp[j];
+        for (long long j = 0; j < N; ++j) next[j] = rp[j];
+        double lx[kMaxOrder + 1], ly[kMaxOrder + 1];
+        for (long long v = 0; v < N; ++v) {
+          lagrange_weights(pts, r[v], lx);
+          lagrange_weights(pts, s[v], ly);
+          for (int n = 0; n < P1; ++n)
+            for (int m = 0; m < P1; ++m) {
+              const uint32_t e = next[node(v, m, n)]++;
+              col[e] = int32_t(v);
+              w[e] = lx[m] * ly[n];
+            }
+        }
+      }
+    });
+  for (auto &th : pool) th.join();
+  for (const auto &e : errs)
+    if (!e.empty()) return fail(c, SLLBM_E_ARG, e);
+  int rc = upload(c, c->csr_ptr, ptr);
+  if (!rc) rc = upload(c, c->csr_col, col);
+  if (!rc) rc = upload_weights(c, c->csr_w, w);
+  return rc;
+}
+
 int prepare_adjoint(sllbm_ctx *c) {
   int rc = prepare_device(c);
   if (rc) return rc;
-  if (c->curvi)
-    return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers axis-product grids only");
   if (q1(c) != kQ1)
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers the 5-velocity set (D2Q25) only");
   if (c->bf16x)
@@ -571,6 +635,12 @@ int prepare_adjoint(sllbm_ctx *c) {
   if (c->cs != 1.0)
     return fail(c, SLLBM_E_UNSUPPORTED, "the adjoint covers the unscaled velocity set (c_s = 1)");
   if (!c->adj_dirty) return SLLBM_OK;
+  if (c->curvi) {  // the transposed records gather
+    rc = build_records_transpose(c);
+    if (rc) return rc;
+    c->adj_dirty = false;
+    return SLLBM_OK;
+  }
   int taps = 0;
   for (int a = 0; a < kQ1; ++a) {
     c->xtT[a] = transpose_axis_table(c->ax, c->xt[a]);
@@ -626,6 +696,9 @@ DevTables make_adjoint_tables(const sllbm_ctx *c) {
   t.rows_xwin = c->rows_txT ? static_cast<const int32_t *>(c->rows_xwinT_d.ptr) : nullptr;
   t.ident_x = c->ident_xT;
   t.ident_y = c->ident_yT;
+  t.csr_ptr = static_cast<const uint32_t *>(c->csr_ptr.ptr);
+  t.csr_col = static_cast<const int32_t *>(c->csr_col.ptr);
+  t.csr_w = c->csr_w.ptr;
   return t;
 }
 
@@ -659,7 +732,8 @@ void sllbm_destroy(sllbm_ctx *c) {
                          &c->myd, &c->mnode_d, &c->flag, &c->partial, &c->scalar, &c->macro,
                          &c->rec_cell,
                          &c->rec, &c->rows_xrel_d, &c->rows_xwin_d,
-                         &c->rows_xrelT_d, &c->rows_xwinT_d, &c->adj_tmp};
+                         &c->rows_xrelT_d, &c->rows_xwinT_d, &c->adj_tmp, &c->csr_ptr,
+                         &c->csr_col, &c->csr_w};
     for (DeviceBuf *b : bufs) free_buf(*b);
     if (c->own_pop) {
       (void)hipFree(c->pop[0]);
@@ -1178,7 +1252,9 @@ int sllbm_adjoint_step(sllbm_ctx *c, const void *mu, const double *moments_prev,
   const bool tiled_ok = c->win_rowsT <= 3 * kTileRows && c->win_colsT <= kMaxWindowCols;
   const bool rows_ok = c->rows_txT >= kRowsMinCols;
   int kind = kAdjointDirect;
-  if (c->path == SLLBM_PATH_TILED) {
+  if (c->curvi) {
+    kind = kAdjointCsr;
+  } else if (c->path == SLLBM_PATH_TILED) {
     kind = tiled_ok ? kAdjointTiled : kAdjointDirect;
   } else if (c->path == SLLBM_PATH_ROWS && rows_ok) {
     kind = kAdjointRows;

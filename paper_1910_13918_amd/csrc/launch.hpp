@@ -99,6 +99,12 @@ struct DevTables {
   const int32_t *rows_xwin;    // [5][nsegments]
   int ident_x, ident_y;        // bit a (b): the x- (y-) table of component a (b) is the
                                // identity (the row-segment kernels need bit 0: xi_0 = 0)
+  // adjoint on a curvilinear mesh: the transposed records gather, per
+  // velocity i and source node j the entries csr_ptr[i (n+1) + j] ..
+  // csr_ptr[i (n+1) + j + 1] - 1 of (target node csr_col, weight csr_w)
+  const uint32_t *csr_ptr;     // [25][n + 1], offsets into csr_col / csr_w
+  const int32_t *csr_col;
+  const void *csr_w;           // population type
 };
 
 // Narrowest row segment of the row-segment path (narrower ones leave most
@@ -183,8 +189,9 @@ hipError_t launch_adjoint_collide(int fp32, int model, const StepConsts &c, cons
                                   const double *mom, void *mu, hipStream_t s);
 // out = S^T mu (transposed tables t), then J_C(M_prev)^T when mom_prev is given
 // (Pr = 1 only: with Pr != 1 the host applies J_C^T through launch_adjoint_collide);
-// kind: the gather (direct, tiled windows or row segments)
-enum AdjointKind { kAdjointDirect = 0, kAdjointTiled = 1, kAdjointRows = 2 };
+// kind: the gather (direct, tiled windows, row segments, or the transposed
+// records of a curvilinear mesh)
+enum AdjointKind { kAdjointDirect = 0, kAdjointTiled = 1, kAdjointRows = 2, kAdjointCsr = 3 };
 hipError_t launch_adjoint_step(int fp32, int model, int kind, const StepConsts &c,
                                const DevTables &t, const void *mu, const double *mom_prev,
                                void *out, hipStream_t s);

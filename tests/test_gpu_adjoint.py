@@ -128,7 +128,7 @@ def _rollout_grad(wl, precision, nsteps, every, seed_target=1234):
     rho, ux, uy = rollout(r0, u0, v0, s, nsteps, every)
     L = _loss_torch(rho, ux, uy, _mass_weights(s), t(ut), t(vt))
     L.backward()
-    out = (float(L), u0.grad.detach().cpu().numpy(), v0.grad.detach().cpu().numpy(),
+    out = (float(L.detach()), u0.grad.detach().cpu().numpy(), v0.grad.detach().cpu().numpy(),
            r0.grad.detach().cpu().numpy(), s)
     return out
 

@@ -147,7 +147,7 @@ def test_trajectory_fp64():
         s.close()
 
 
-def test_other_paths_and_adjoint_refused():
+def test_other_paths_refused():
     wl = _wl("isothermal", 2)
     s = _solver(wl, "fp64", path="tiled")
     try:
@@ -157,13 +157,156 @@ def test_other_paths_and_adjoint_refused():
         assert e.value.code == C.E_UNSUPPORTED
         C.sllbm_set_path(s.ctx, C.PATH_RECORDS)
         s.step(1)
-        lam = torch.zeros(s.nsets * s.q * s.n, dtype=torch.float64, device="cuda")
-        mom = torch.ones(3 * s.n, dtype=torch.float64, device="cuda")
-        with pytest.raises(C.SllbmError) as e:
-            C.sllbm_adjoint_collide(s.ctx, lam.data_ptr(), mom.data_ptr(), lam.data_ptr())
-        assert e.value.code == C.E_UNSUPPORTED
     finally:
         s.close()
+
+
+# ------------------------------------------------------------------ adjoint
+def _rand(shape, seed):
+    g = torch.Generator().manual_seed(seed)
+    return torch.randn(shape, generator=g, dtype=torch.float64).to("cuda")
+
+
+@pytest.mark.parametrize("model,p", [("isothermal", 2), ("isothermal", 4), ("polyatomic", 3)])
+def test_transposed_records_dot_product(model, p):
+    """<mu, S v> = <S^T mu, v> with 1/tau = 0 (the step is the records
+    interpolation alone) on 7 x 7 wavy cells: the transposed records gather
+    is the exact transpose of the forward gather (FP64)."""
+    wl = _wl(model, p)
+    wl.nu = np.inf
+    s = _solver(wl, "fp64")
+    try:
+        print(f"[gpu] curvilinear adjoint dot product {model} p={p} nodes={s.n}", flush=True)
+        shape = (s.nsets, s.q, s.n)
+        v = _rand(shape, 1)
+        mu = _rand(shape, 2)
+        s.set_populations(v)
+        s.step(1)
+        Sv = s.populations_device()
+        StMu = torch.empty_like(mu)
+        C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, StMu.data_ptr())
+        torch.cuda.synchronize()
+        lhs = float((mu * Sv).sum())
+        rhs = float((StMu * v).sum())
+        assert lhs == pytest.approx(rhs, rel=1e-12)
+        # the weights of every departure stencil sum to one, so S^T 1 sums
+        # to N over the nodes of each velocity
+        ones = torch.ones(shape, dtype=torch.float64, device="cuda")
+        C.sllbm_adjoint_step(s.ctx, ones.data_ptr(), None, StMu.data_ptr())
+        torch.cuda.synchronize()
+        tot = StMu.sum(dim=2).cpu().numpy()
+        assert np.allclose(tot, s.n, rtol=1e-12)
+    finally:
+        s.close()
+
+
+def test_fp32_transposed_records_close_to_fp64():
+    """The float32 transposed gather (weights rounded to float32) against the
+    float64 one on the same mesh and input, polyatomic p = 4."""
+    wl = _wl("polyatomic", 4)
+    outs = []
+    for precision in ("fp64", "fp32"):
+        s = _solver(wl, precision)
+        try:
+            print(f"[gpu] curvilinear adjoint {precision}", flush=True)
+            mu = _rand((s.nsets, s.q, s.n), 5).to(s.dtype)
+            out = torch.empty_like(mu)
+            C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, out.data_ptr())
+            torch.cuda.synchronize()
+            outs.append(out.double().cpu().numpy())
+        finally:
+            s.close()
+    assert _rel(outs[1], outs[0]) <= 2e-6
+
+
+@pytest.mark.parametrize("model,Pr", [("isothermal", 1.0), ("polyatomic", 1.0),
+                                      ("monatomic", 0.75)])
+def test_curvilinear_one_step_adjoint_against_central_differences(model, Pr):
+    """J^T of one records step on wavy cells, <J^T lam, v> against central
+    differences of <lam, step(F + e v)> (FP64), with the combined S^T + J_C^T
+    call equal to the two separate calls."""
+    wl = _wl(model, 3, Pr=Pr)
+    s = _solver(wl, "fp64")
+    try:
+        print(f"[gpu] curvilinear adjoint one step {model} Pr={Pr} nodes={s.n}", flush=True)
+        s.init_from_workload()
+        s.step(2)
+        F = s.populations_device().clone()
+        lam = _rand(tuple(F.shape), 7)
+        v = _rand(tuple(F.shape), 8) * F.abs().mean()
+        s.set_populations(F)
+        mom = s.step_record(1)
+        mu, out = torch.empty_like(lam), torch.empty_like(lam)
+        C.sllbm_adjoint_collide(s.ctx, lam.data_ptr(), mom[0].data_ptr(), mu.data_ptr())
+        C.sllbm_adjoint_step(s.ctx, mu.data_ptr(), None, out.data_ptr())
+        torch.cuda.synchronize()
+        adj = float((out * v).sum())
+
+        def g(e):
+            s.set_populations(F + e * v)
+            s.step(1)
+            return float((lam * s.populations_device()).sum())
+
+        fd = (g(1e-6) - g(-1e-6)) / 2e-6
+        assert adj == pytest.approx(fd, rel=1e-6)
+        x = _rand(tuple(F.shape), 9)
+        a1, a2, b = torch.empty_like(lam), torch.empty_like(lam), torch.empty_like(lam)
+        C.sllbm_adjoint_step(s.ctx, x.data_ptr(), mom[0].data_ptr(), a1.data_ptr())
+        C.sllbm_adjoint_step(s.ctx, x.data_ptr(), None, b.data_ptr())
+        C.sllbm_adjoint_collide(s.ctx, b.data_ptr(), mom[0].data_ptr(), a2.data_ptr())
+        torch.cuda.synchronize()
+        assert torch.equal(a1, a2)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("model,Pr", [("isothermal", 1.0), ("polyatomic", 0.75)])
+def test_curvilinear_rollout_gradient_matches_complex_step(model, Pr):
+    """12 steps on 6 x 6 wavy cells (p = 2, checkpoints every 5): the gradient
+    of the kinetic energy + misfit loss (node masses of the bilinear cells),
+    and for the polyatomic model the temperature misfit, in the initial
+    fields along seeded directions, against the complex-step derivative of
+    the curvilinear oracle."""
+    from oracle.adjoint import complex_step_fields, kinetic_misfit_loss, thermal_misfit_loss
+    from paper_1910_13918_amd.adjoint import rollout
+    wl = _wl(model, 2, ncells=6, Pr=Pr)
+    s = _solver(wl, "fp64")
+    try:
+        print(f"[gpu] curvilinear adjoint rollout {model} Pr={Pr} nodes={s.n}", flush=True)
+        X, Y = s.coords()
+        f0 = wl.fields(X, Y)
+        ut, vt = W.fourier_target(X, Y, 0.2, seed=1234)
+        Tt = 0.9 + 0.05 * np.sin(X)
+        t = lambda a: torch.tensor(a, device="cuda")
+        leaves = [t(np.asarray(a, dtype=np.float64) * np.ones(s.n)).requires_grad_(True)
+                  for a in f0]
+        out = rollout(leaves[0], leaves[1], leaves[2], s, 12, 5,
+                      T0=None if model == "isothermal" else leaves[3])
+        m = np.zeros(s.n)
+        C.sllbm_node_masses(s.ctx, m.ctypes.data)
+        M = t(m)
+        rho, ux, uy = out[:3]
+        L = 0.5 * (M * rho * (ux * ux + uy * uy)).sum() + (M * ((ux - t(ut)) ** 2
+                                                                + (uy - t(vt)) ** 2)).sum()
+        if model != "isothermal":
+            L = L + (M * (out[3] - t(Tt)) ** 2).sum()
+        L.backward()
+        nf = 3 if model == "isothermal" else 4
+        grads = [a.grad.detach().cpu().numpy() for a in leaves[:nf]]
+    finally:
+        s.close()
+    g, sim = _sim(wl)
+    if model == "isothermal":
+        loss = lambda sm, F: kinetic_misfit_loss(sm, F, ut, vt)
+    else:
+        loss = lambda sm, F: thermal_misfit_loss(sm, F, ut, vt, Tt)
+    rng = np.random.default_rng(91)
+    f0 = [np.asarray(a, dtype=np.float64) * np.ones(g.nnodes) for a in f0]
+    for _ in range(3):
+        d = [rng.standard_normal(g.nnodes) for _ in range(nf)] + [np.zeros(g.nnodes)] * (4 - nf)
+        ref = complex_step_fields(sim, f0, d, 12, loss)
+        got = sum(float(np.dot(gr, di)) for gr, di in zip(grads, d))
+        assert got == pytest.approx(ref, rel=1e-9, abs=1e-13)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
