@@ -25,6 +25,9 @@ The oracle is a literal, slow transcription of Wilde, Kraemer, Reith, Foysi,
                       treatment, interpolation (eq. (17)), moments (eqs.
                       (3)-(5)), BGK relaxation (eq. (16)); initialisation,
                       moments, mass.
+* ``sllbm3d``      -- the same step in three dimensions (D3Q125, the paper's
+                      outlook): 3^n-tuple equilibrium contraction, tensor
+                      product of three axes, isothermal BGK.
 * ``riemann``      -- exact solution of the 1-D Riemann problem for the ideal
                       gas (reference for the Sod shock tube of Sec. III.C).
 * ``adjoint``      -- complex-step derivatives of the oracle, used as the

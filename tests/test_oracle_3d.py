@@ -1,0 +1,187 @@
+"""Pins of the three-dimensional oracle (D3Q125, oracle/sllbm3d.py).
+
+Compared against: the Gaussian's moments in closed form (quadrature through
+degree 9 per axis; the equilibrium's moments through total order 4 at any
+theta), the two-dimensional oracle (a field that does not vary along one axis
+has marginals that follow the D2Q25 step exactly, for each of the three
+axes), polynomial reproduction of the tensor Lagrange interpolant, the
+collision's invariants, and the viscous decay of a shear wave.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.grid import Grid, uniform_edges
+from oracle.sllbm import Sim
+from oracle.sllbm3d import Grid3, Sim3, d3q125, f_eq3
+
+
+def _gauss_moment(k, mu=0.0, theta=1.0):
+    """E[X^k] for X ~ N(mu, theta): sum_j C(k, 2j) mu^(k-2j) theta^j (2j-1)!!."""
+    tot = 0.0
+    for j in range(k // 2 + 1):
+        dfac = math.prod(range(2 * j - 1, 0, -2)) if j > 0 else 1
+        tot += math.comb(k, 2 * j) * mu ** (k - 2 * j) * theta ** j * dfac
+    return tot
+
+
+def test_d3q125_quadrature_through_degree_nine():
+    xi, w = d3q125()
+    assert xi.shape == (125, 3)
+    assert w.sum() == pytest.approx(1.0, abs=1e-15)
+    for k in range(10):
+        for l in range(10):
+            for m in range(10):
+                term = w * xi[:, 0] ** k * xi[:, 1] ** l * xi[:, 2] ** m
+                ref = _gauss_moment(k) * _gauss_moment(l) * _gauss_moment(m)
+                scale = np.abs(term).sum()
+                assert term.sum() == pytest.approx(ref, rel=1e-12, abs=1e-14 * scale), (k, l, m)
+    # D1Q5 is exact through degree 9 only
+    assert np.sum(w * xi[:, 2] ** 10) != pytest.approx(_gauss_moment(10), rel=1e-3)
+    # index order i = a + 5 b + 25 c
+    assert tuple(xi[1 + 5 * 2 + 25 * 3]) == (xi[1, 0], xi[2, 0], xi[3, 0])
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.8, 1.3])
+def test_equilibrium_moments_are_gaussian_through_order_four(theta):
+    xi, w = d3q125()
+    rho, u = 1.3, (0.31, -0.22, 0.17)
+    feq = f_eq3(xi, w, rho, *u, theta=theta)[:, 0]
+    for k in range(5):
+        for l in range(5 - k):
+            for m in range(5 - k - l):
+                got = np.sum(feq * xi[:, 0] ** k * xi[:, 1] ** l * xi[:, 2] ** m)
+                ref = rho * (_gauss_moment(k, u[0], theta) * _gauss_moment(l, u[1], theta)
+                             * _gauss_moment(m, u[2], theta))
+                assert got == pytest.approx(ref, rel=1e-12, abs=1e-13), (k, l, m)
+    # truncated at 4th order: a 5th moment is not the Gaussian's
+    got = np.sum(feq * xi[:, 0] ** 5)
+    ref = rho * _gauss_moment(5, u[0], theta)
+    assert abs(got - ref) > 1e-4 * abs(ref)
+    if theta == 1.0:  # the dropped term a^(5)_xxxxx He_5 / 5! carries rho u_x^5
+        assert got - ref == pytest.approx(-rho * u[0] ** 5, rel=1e-9)
+
+
+def test_equilibrium_at_rest_is_weights():
+    xi, w = d3q125()
+    np.testing.assert_allclose(f_eq3(xi, w, 0.7, 0.0, 0.0, 0.0)[:, 0], 0.7 * w, rtol=1e-14)
+
+
+def _grid3(p, periodic, ncs=(3, 2, 2), seed=0):
+    """Non-uniform cells along every axis (a smooth stretching of [0, L])."""
+    rng = np.random.default_rng(seed)
+    edges = []
+    for n, L in zip(ncs, (1.0, 0.8, 0.9)):
+        e = np.cumsum(np.concatenate([[0.0], 1.0 + 0.3 * rng.random(n)]))
+        edges.append(L * e / e[-1])
+    return Grid3(*edges, p, periodic), edges
+
+
+@pytest.mark.parametrize("drop", ["z", "y", "x"])
+def test_marginal_of_an_axis_independent_field_follows_the_2d_step(drop):
+    """If F does not vary along one axis, interpolation along it is exact and
+    sum_c w_c He_m(xi_c) = delta_m0 makes the marginal of f_eq (over that
+    axis's velocity component) the D2Q25 equilibrium of the other two, for any
+    velocity along the dropped axis; so the marginal of one 3-D step equals
+    one step of the 2-D oracle applied to the marginal."""
+    p = 2
+    periodic = {"z": (True, False, True), "y": (False, False, True), "x": (True, True, False)}[drop]
+    g3, edges = _grid3(p, periodic)
+    dt, nu = 0.004, 0.003
+    sim3 = Sim3(g3, dt, nu)
+    keep = {"z": (0, 1), "y": (0, 2), "x": (1, 2)}[drop]
+    g2 = Grid(edges[keep[0]], edges[keep[1]], p, periodic[keep[0]], periodic[keep[1]])
+    sim2 = Sim(g2, dt, nu, "isothermal")
+    rng = np.random.default_rng(11)
+    # random positive populations on the 2-D grid for all 125 velocities
+    F2full = 0.02 + rng.random((125, g2.nnodes))
+    # lift: 3-D node (ix, iy, iz) takes the 2-D node of its kept coordinates
+    iz, iy, ix = np.meshgrid(np.arange(g3.nz), np.arange(g3.ny), np.arange(g3.nx), indexing="ij")
+    idx3 = {"x": ix, "y": iy, "z": iz}
+    kname = {0: "x", 1: "y", 2: "z"}
+    n2x = g2.nx
+    v2 = (idx3[kname[keep[1]]] * n2x + idx3[kname[keep[0]]]).reshape(-1)
+    F3 = F2full[:, v2]
+    out3 = sim3.step(F3)
+    # marginal over the dropped axis's component: index (a, b, c) -> 2-D index
+    a3 = np.arange(125) % 5
+    b3 = (np.arange(125) // 5) % 5
+    c3 = np.arange(125) // 25
+    comp = (a3, b3, c3)
+    i2 = comp[keep[0]] + 5 * comp[keep[1]]
+    M0 = np.zeros((25, g2.nnodes))
+    M3 = np.zeros((25, g3.nnodes))
+    np.add.at(M0, i2, F2full)
+    np.add.at(M3, i2, out3)
+    ref = sim2.step(M0[None])[0]
+    np.testing.assert_allclose(M3, ref[:, v2], rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_streaming_reproduces_tensor_polynomials(p):
+    """Nodal values of a random polynomial of degree <= p per axis, streamed
+    with 1/tau = 0, equal the polynomial at the (clamped) departure points."""
+    g, _ = _grid3(p, (False, False, False), ncs=(2, 2, 2), seed=p)
+    sim = Sim3(g, 0.03, np.inf)
+    X, Y, Z = g.coords()
+    C = np.random.default_rng(p).normal(size=(p + 1,) * 3)
+
+    def P(x, y, z):
+        return sum(C[a, b, c] * x ** a * y ** b * z ** c
+                   for a in range(p + 1) for b in range(p + 1) for c in range(p + 1))
+
+    F = np.tile(P(X, Y, Z), (125, 1))
+    out = sim.stream(F)
+    for i in range(125):
+        xd = np.clip(X - sim.dt * sim.xi[i, 0], 0.0, 1.0)
+        yd = np.clip(Y - sim.dt * sim.xi[i, 1], 0.0, 0.8)
+        zd = np.clip(Z - sim.dt * sim.xi[i, 2], 0.0, 0.9)
+        np.testing.assert_allclose(out[i], P(xd, yd, zd), rtol=1e-11, atol=1e-11)
+
+
+def test_collision_conserves_mass_and_momentum_and_fixes_equilibrium():
+    g, _ = _grid3(2, (True, True, True), ncs=(1, 1, 2))
+    sim = Sim3(g, 0.01, 0.004)
+    rng = np.random.default_rng(3)
+    F = 0.01 + rng.random((125, g.nnodes))
+    out = sim.collide(F)
+    np.testing.assert_allclose(out.sum(0), F.sum(0), rtol=1e-13)
+    for k in range(3):
+        np.testing.assert_allclose((sim.xi[:, k, None] * out).sum(0),
+                                   (sim.xi[:, k, None] * F).sum(0), rtol=1e-12, atol=1e-13)
+    rho = 1.0 + 0.1 * rng.random(g.nnodes)
+    u = [0.1 * rng.standard_normal(g.nnodes) for _ in range(3)]
+    feq = sim.init(rho, *u)
+    np.testing.assert_allclose(sim.collide(feq), feq, rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(sim.moments(feq)[0], rho, rtol=1e-14)
+    for k in range(3):
+        np.testing.assert_allclose(sim.moments(feq)[k + 1], u[k], rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.slow
+def test_shear_wave_decays_at_the_viscous_rate():
+    """u_x = U0 sin z on a periodic box (low Mach): between two times after the
+    start-up (the initial f = f_eq carries no shear stress; it builds up over
+    about tau steps), the amplitude decays as exp(-nu k^2 dt) per step (k = 1),
+    nu = (tau - 1/2) dt; the flow stays along x."""
+    p, L = 4, 2 * np.pi
+    g = Grid3(uniform_edges(1, 0, L), uniform_edges(1, 0, L), uniform_edges(8, 0, L), p,
+              (True, True, True))
+    dt, nu, U0 = 0.02, 0.05, 0.01
+    sim = Sim3(g, dt, nu)
+    X, Y, Z = g.coords()
+
+    def amp(F):
+        _, ux, uy, uz = sim.moments(F)
+        assert np.abs(uy).max() < 1e-12 * U0 and np.abs(uz).max() < 1e-6 * U0
+        return np.sum(ux * np.sin(Z)) / np.sum(np.sin(Z) ** 2)
+
+    F = sim.run(sim.init(np.ones(g.nnodes), U0 * np.sin(Z), 0 * Z, 0 * Z), 20)
+    a1 = amp(F)
+    a2 = amp(sim.run(F, 40))
+    rate = -np.log(a2 / a1) / (40 * dt)
+    # measured 0.9976 nu: the discrete-time BGK shear mode carries a relative
+    # correction of order (k dt)^2 (tau^2 - tau + 1/6) = 2.5e-3 here; nu
+    # taken as tau dt (or (tau - 1) dt) would be 20 % off
+    assert rate == pytest.approx(nu, rel=1e-2)
