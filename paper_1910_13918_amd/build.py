@@ -26,7 +26,7 @@ FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
 SOURCES = ["kernels.hip", "step_direct.hip", "step_tiled.hip", "step_records.hip", "step_mfma.hip",
            "step_rows.hip", "step_tiled_pr.hip", "step_prandtl.hip", "adjoint.hip",
            "adjoint_rows.hip", "adjoint_tiled_f32.hip", "adjoint_tiled_f64.hip", "capi.cpp",
-           "tables.cpp", "curvilinear.cpp"]
+           "tables.cpp", "curvilinear.cpp", "step3d.hip", "capi3d.cpp"]
 
 _INCLUDE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
 

@@ -1,0 +1,47 @@
+// Interface between the three-dimensional C ABI (capi3d.cpp) and its HIP
+// kernels (step3d.hip): isothermal D3Q125 on a tensor product of three axes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sllbm {
+
+// Populations: 125 planes of N values, plane i = a + 5 b + 25 c (the 1-D
+// components along x, y, z), node v = (iz ny + iy) nx + ix.
+constexpr int kQ3 = 125;
+
+struct Consts3 {
+  int nx, ny, nz, p;
+  long long n;       // nx ny nz
+  double omega;      // 1 / tau
+  double xi[5];      // 1-D abscissae
+  double w[5];       // 1-D weights
+  double hk[5][5];   // He_k(xi_a) / k!
+};
+
+// Per-axis departure tables, component-major: entry (comp, tap, j) at
+// (comp * (p + 1) + tap) * n_axis + j; src holds node indices on that axis,
+// w the Lagrange weights (float or double as the populations).
+struct Tables3 {
+  const int32_t *xsrc, *ysrc, *zsrc;
+  const void *xw, *yw, *zw;
+  const double *mx, *my, *mz;  // per-axis node masses (float64)
+};
+
+// One step fin -> fout (both planar, 125 N values); flag |= 1 when a node's
+// rho is not positive or a moment is not finite.
+hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const void *fin,
+                         void *fout, int *flag, hipStream_t s);
+// f = f_eq(rho, u) from float64 device fields.
+hipError_t launch_init3d(int fp32, const Consts3 &c, const double *rho, const double *ux,
+                         const double *uy, const double *uz, void *f, hipStream_t s);
+// rho, u per node (float64).
+hipError_t launch_moments3d(int fp32, const Consts3 &c, const void *f, double *rho, double *ux,
+                            double *uy, double *uz, hipStream_t s);
+// sum_v M_v rho_v into out[0]; partial holds (n + 255) / 256 doubles.
+hipError_t launch_mass3d(int fp32, const Consts3 &c, const Tables3 &t, const void *f,
+                         double *partial, double *out, hipStream_t s);
+
+}  // namespace sllbm

@@ -1,0 +1,359 @@
+// Isothermal D3Q125 stream + collide on a tensor product of three axes
+// (HIP, gfx950): the two-dimensional step with a third axis (the paper's
+// outlook, Sec. IV-V).  Velocity i = a + 5 b + 25 c has the 1-D components
+// xi_a, xi_b, xi_c of the D1Q5 rule (Table I); its departure point
+// x - dt xi_i is separable, so each axis has its own gather table and the
+// interpolant of eq. (17) is the triple product of 1-D Lagrange weights.
+#include "launch3d.hpp"
+#include "step_common.hpp"
+
+namespace sllbm {
+namespace {
+
+// Calls fn(i, f_eq_i) for the 125 velocities: the 4th-order Hermite
+// equilibrium at theta = 1 (Sec. II.A, eqs. (9)-(10) in three components),
+// whose coefficients are the powers of u, factorised per axis:
+//   f_eq_{a+5b+25c} = rho w_a w_b w_c sum_{k+l+m<=4} X_k[a] Y_l[b] Z_m[c],
+//   X_k[a] = u_x^k He_k(xi_a)/k!  (Y, Z with u_y, u_z).
+// Evaluated per (b, c) as sum_j YZ_j Xc_{4-j}[a] with YZ_j = sum_{l+m=j}
+// Y_l Z_m and the running sums Xc_n[a] = sum_{k<=n} X_k[a].  The (b, c)
+// loops stay rolled: unrolled, the relaxation's 125 independent loads were
+// all hoisted (255 registers, one wavefront per SIMD).
+template <class Fn>
+__device__ __forceinline__ void for_each_eq3(double rho, double ux, double uy, double uz,
+                                             const Consts3 &c, Fn &&fn) {
+  const double px[5] = {1.0, ux, ux * ux, ux * ux * ux, (ux * ux) * (ux * ux)};
+  const double py[5] = {1.0, uy, uy * uy, uy * uy * uy, (uy * uy) * (uy * uy)};
+  const double pz[5] = {1.0, uz, uz * uz, uz * uz * uz, (uz * uz) * (uz * uz)};
+  double xc[5][5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      s = fma(c.hk[a][k], px[k], s);
+      xc[a][k] = s;
+    }
+  }
+#pragma unroll 1
+  for (int cc = 0; cc < 5; ++cc) {
+    double z[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) z[m] = c.hk[cc][m] * pz[m];
+#pragma unroll 1
+    for (int b = 0; b < 5; ++b) {
+      double yz[5];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l <= j; ++l) s = fma(c.hk[b][l] * py[l], z[j - l], s);
+        yz[j] = s;
+      }
+      const double rbc = rho * c.w[b] * c.w[cc];
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) s = fma(yz[j], xc[a][4 - j], s);
+        fn(a + 5 * b + 25 * cc, rbc * c.w[a] * s);
+      }
+    }
+  }
+}
+
+// Interpolated value of one plane at a lane's departure point: the (p+1)^2
+// source rows (z tap l, y tap n; byte offsets so[l][n], wave-uniform) are
+// each read as p+1 consecutive values from x0 (one wide load per row), or
+// value by value at xs[m] where the x-stencil wraps around a periodic seam.
+template <typename T, int P1, bool SEAM>
+__device__ __forceinline__ T gather3(__amdgpu_buffer_rsrc_t rs, unsigned x0,
+                                     const unsigned (&xs)[P1], const T (&wx)[P1],
+                                     const unsigned (&so)[P1][P1], const T (&wy)[P1],
+                                     const T (&wz)[P1]) {
+  T acc = T(0);
+#pragma unroll
+  for (int l = 0; l < P1; ++l) {
+    T accl = T(0);
+#pragma unroll
+    for (int n = 0; n < P1; ++n) {
+      T v[P1];
+      if constexpr (SEAM) {
+#pragma unroll
+        for (int m = 0; m < P1; ++m) v[m] = buffer_load<T>(rs, xs[m], so[l][n]);
+      } else {
+        buffer_load_run<T, P1>(rs, x0, so[l][n], v);
+      }
+      T row = T(0);
+#pragma unroll
+      for (int m = 0; m < P1; ++m) row = fma(wx[m], v[m], row);
+      accl = fma(wy[n], row, accl);
+    }
+    acc = fma(wz[l], accl, acc);
+  }
+  return acc;
+}
+
+// Pass 1 of the step: stream every velocity into the node's own slots of
+// fout and accumulate rho and j (float64) on the way.
+template <typename T, int P, bool SEAM>
+__device__ __forceinline__ void stream3(const T *__restrict__ fin, T *__restrict__ fout,
+                                        const Tables3 &t, const Consts3 &c, int ix, int iy,
+                                        int iz, long long v, const unsigned (&x0)[5],
+                                        const T (&wx)[5][P + 1], double (&mom)[4]) {
+  constexpr int P1 = P + 1;
+  const long long N = c.n;
+  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
+  const unsigned row_bytes = unsigned(c.nx) * unsigned(sizeof(T));
+  const unsigned vo = unsigned(v) * unsigned(sizeof(T));
+  const T *yw = static_cast<const T *>(t.yw);
+  const T *zw = static_cast<const T *>(t.zw);
+  double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll 1
+  for (int cc = 0; cc < 5; ++cc) {
+    int zs[P1];
+    T wz[P1];
+#pragma unroll
+    for (int l = 0; l < P1; ++l) {
+      zs[l] = t.zsrc[(cc * P1 + l) * c.nz + iz];
+      wz[l] = zw[(cc * P1 + l) * c.nz + iz];
+    }
+#pragma unroll 1
+    for (int b = 0; b < 5; ++b) {
+      unsigned so[P1][P1];
+      T wy[P1];
+#pragma unroll
+      for (int n = 0; n < P1; ++n) {
+        const int ys = t.ysrc[(b * P1 + n) * c.ny + iy];
+        wy[n] = yw[(b * P1 + n) * c.ny + iy];
+#pragma unroll
+        for (int l = 0; l < P1; ++l)
+          so[l][n] = (unsigned(zs[l]) * unsigned(c.ny) + unsigned(ys)) * row_bytes;
+      }
+      double r_b = 0.0, jx_b = 0.0;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        const int i = a + 5 * b + 25 * cc;
+        unsigned xs[P1] = {};
+        if constexpr (SEAM) {
+#pragma unroll
+          for (int m = 0; m < P1; ++m)
+            xs[m] = unsigned(t.xsrc[(a * P1 + m) * c.nx + ix]) * unsigned(sizeof(T));
+        }
+        const auto rs = make_rsrc(fin + (long long)i * N, plane_bytes);
+        T val = gather3<T, P1, SEAM>(rs, x0[a], xs, wx[a], so, wy, wz);
+        // keep the interpolation next to its loads
+        asm volatile("" : "+v"(val));
+        buffer_store<T>(val, make_rsrc(fout + (long long)i * N, plane_bytes), vo, 0);
+        const double d = double(val);
+        r_b += d;
+        jx_b = fma(c.xi[a], d, jx_b);
+      }
+      rho += r_b;
+      jx += jx_b;
+      jy = fma(c.xi[b], r_b, jy);
+      jz = fma(c.xi[cc], r_b, jz);
+    }
+  }
+  mom[0] = rho;
+  mom[1] = jx;
+  mom[2] = jy;
+  mom[3] = jz;
+}
+
+// One thread per node; a workgroup is 64 consecutive x-nodes of 4 rows (one
+// wavefront per row), so each wavefront's y and z taps are uniform.  Pass 1
+// streams all 125 velocities into the node's own slots of fout (the values
+// are not held in registers: 125 of them would leave one or two wavefronts
+// per SIMD), pass 2 reads them back, relaxes toward f_eq of the streamed
+// moments and overwrites them (the same thread, the same addresses).
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_step3d(const T *__restrict__ fin, T *__restrict__ fout,
+                                                Tables3 t, Consts3 c, int *__restrict__ flag) {
+  constexpr int P1 = P + 1;
+  const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int iy = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * 4 + int(threadIdx.x >> 6));
+  const int iz = blockIdx.z;
+  if (iy >= c.ny || ix >= c.nx) return;
+  const long long N = c.n;
+  const long long v = ((long long)iz * c.ny + iy) * c.nx + ix;
+  const T *xw = static_cast<const T *>(t.xw);
+  unsigned x0[5];
+  T wx[5][P1];
+  bool seam = false;
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    const int first = t.xsrc[(a * P1) * c.nx + ix];
+    const int last = t.xsrc[(a * P1 + P) * c.nx + ix];
+    x0[a] = unsigned(first) * unsigned(sizeof(T));
+    seam |= last != first + P;  // the x-stencil wraps around a periodic seam
+#pragma unroll
+    for (int m = 0; m < P1; ++m) wx[a][m] = xw[(a * P1 + m) * c.nx + ix];
+  }
+  double mom[4];
+  if (__builtin_amdgcn_ballot_w64(seam))
+    stream3<T, P, true>(fin, fout, t, c, ix, iy, iz, v, x0, wx, mom);
+  else
+    stream3<T, P, false>(fin, fout, t, c, ix, iy, iz, v, x0, wx, mom);
+  const double rho = mom[0], ux = mom[1] / rho, uy = mom[2] / rho, uz = mom[3] / rho;
+  const bool ok = (rho > 0.0) && isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+  if (!ok) atomicOr(flag, 1);
+  const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
+  const unsigned vo = unsigned(v) * unsigned(sizeof(T));
+  const double om = c.omega;
+  for_each_eq3(rho, ux, uy, uz, c, [&](int i, double feq) {
+    const auto rs = make_rsrc(fout + (long long)i * N, plane_bytes);
+    const double f = double(buffer_load<T>(rs, vo, 0));
+    buffer_store<T>(T(f - om * (f - feq)), rs, vo, 0);
+  });
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init3d(const double *__restrict__ rho,
+                                                const double *__restrict__ ux,
+                                                const double *__restrict__ uy,
+                                                const double *__restrict__ uz, T *__restrict__ f,
+                                                Consts3 c) {
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (v >= c.n) return;
+  const long long N = c.n;
+  for_each_eq3(rho[v], ux[v], uy[v], uz[v], c,
+               [&](int i, double feq) { f[(long long)i * N + v] = T(feq); });
+}
+
+template <typename T>
+__device__ __forceinline__ void node_moments3(const T *__restrict__ f, long long v,
+                                              const Consts3 &c, double (&m)[4]) {
+  const long long N = c.n;
+  double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll 1
+  for (int cc = 0; cc < 5; ++cc) {
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      double r_b = 0.0, jx_b = 0.0;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        const double d = double(f[(long long)(a + 5 * b + 25 * cc) * N + v]);
+        r_b += d;
+        jx_b = fma(c.xi[a], d, jx_b);
+      }
+      rho += r_b;
+      jx += jx_b;
+      jy = fma(c.xi[b], r_b, jy);
+      jz = fma(c.xi[cc], r_b, jz);
+    }
+  }
+  m[0] = rho;
+  m[1] = jx / rho;
+  m[2] = jy / rho;
+  m[3] = jz / rho;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments3d(const T *__restrict__ f,
+                                                   double *__restrict__ rho,
+                                                   double *__restrict__ ux,
+                                                   double *__restrict__ uy,
+                                                   double *__restrict__ uz, Consts3 c) {
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (v >= c.n) return;
+  double m[4];
+  node_moments3<T>(f, v, c, m);
+  rho[v] = m[0];
+  ux[v] = m[1];
+  uy[v] = m[2];
+  uz[v] = m[3];
+}
+
+// Per-block partial sums of M_v rho_v, M_v = mx[ix] my[iy] mz[iz].
+template <typename T>
+__global__ __launch_bounds__(256) void k_mass3d(const T *__restrict__ f, Tables3 t,
+                                                double *__restrict__ partial, Consts3 c) {
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  double mass = 0.0;
+  if (v < c.n) {
+    const long long N = c.n;
+    double rho = 0.0;
+#pragma unroll 5
+    for (int i = 0; i < kQ3; ++i) rho += double(f[(long long)i * N + v]);
+    const long long row = v / c.nx;
+    const int ix = int(v - row * c.nx);
+    const int iy = int(row % c.ny), iz = int(row / c.ny);
+    mass = t.mx[ix] * t.my[iy] * t.mz[iz] * rho;
+  }
+  const double tot = block_sum_256(mass);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// Sum of the partials in a fixed order (one block).
+__global__ __launch_bounds__(256) void k_sum3d(const double *__restrict__ partial, long long n,
+                                               double *__restrict__ out) {
+  double s = 0.0;
+  for (long long k = threadIdx.x; k < n; k += 256) s += partial[k];
+  const double tot = block_sum_256(s);
+  if (threadIdx.x == 0) out[0] = tot;
+}
+
+template <class F>
+hipError_t dispatch3(int fp32, int p, F &&f) {
+  auto by_p = [&]<typename T>() -> hipError_t {
+    switch (p) {
+      case 1: return f.template operator()<T, 1>();
+      case 2: return f.template operator()<T, 2>();
+      case 3: return f.template operator()<T, 3>();
+      case 4: return f.template operator()<T, 4>();
+    }
+    return hipErrorInvalidValue;
+  };
+  return fp32 ? by_p.template operator()<float>() : by_p.template operator()<double>();
+}
+
+}  // namespace
+
+hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const void *fin,
+                         void *fout, int *flag, hipStream_t s) {
+  if (c.nz > 65535 || c.ny > 4 * 65535) return hipErrorInvalidValue;
+  return dispatch3(fp32, c.p, [&]<typename T, int P>() -> hipError_t {
+    const dim3 grid(unsigned((c.nx + 63) / 64), unsigned((c.ny + 3) / 4), unsigned(c.nz));
+    k_step3d<T, P><<<grid, 256, 0, s>>>(static_cast<const T *>(fin), static_cast<T *>(fout), t, c,
+                                        flag);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_init3d(int fp32, const Consts3 &c, const double *rho, const double *ux,
+                         const double *uy, const double *uz, void *f, hipStream_t s) {
+  const unsigned blocks = unsigned((c.n + 255) / 256);
+  if (fp32)
+    k_init3d<float><<<blocks, 256, 0, s>>>(rho, ux, uy, uz, static_cast<float *>(f), c);
+  else
+    k_init3d<double><<<blocks, 256, 0, s>>>(rho, ux, uy, uz, static_cast<double *>(f), c);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments3d(int fp32, const Consts3 &c, const void *f, double *rho, double *ux,
+                            double *uy, double *uz, hipStream_t s) {
+  const unsigned blocks = unsigned((c.n + 255) / 256);
+  if (fp32)
+    k_moments3d<float><<<blocks, 256, 0, s>>>(static_cast<const float *>(f), rho, ux, uy, uz, c);
+  else
+    k_moments3d<double><<<blocks, 256, 0, s>>>(static_cast<const double *>(f), rho, ux, uy, uz,
+                                               c);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass3d(int fp32, const Consts3 &c, const Tables3 &t, const void *f,
+                         double *partial, double *out, hipStream_t s) {
+  const long long blocks = (c.n + 255) / 256;
+  if (fp32)
+    k_mass3d<float><<<unsigned(blocks), 256, 0, s>>>(static_cast<const float *>(f), t, partial, c);
+  else
+    k_mass3d<double><<<unsigned(blocks), 256, 0, s>>>(static_cast<const double *>(f), t, partial,
+                                                      c);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_sum3d<<<1, 256, 0, s>>>(partial, blocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace sllbm

@@ -104,6 +104,24 @@ _SIGS = {
     "sllbm_adjoint_collide": ([_vp, _vp, _vp, _vp], _c),
     "sllbm_adjoint_step": ([_vp, _vp, _vp, _vp], _c),
     "sllbm_eq_init_vjp": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _c),
+    # three dimensions (include/sllbm3d.h)
+    "sllbm3d_create": ([ctypes.POINTER(_vp), _c, _c], _c),
+    "sllbm3d_destroy": ([_vp], None),
+    "sllbm3d_last_error": ([_vp], ctypes.c_char_p),
+    "sllbm3d_set_stream": ([_vp, _vp], _c),
+    "sllbm3d_set_order": ([_vp, _c, _c], _c),
+    "sllbm3d_init_grid": ([_vp, _c, _c, _c, _vp, _vp, _vp, _c, _c, _c], _c),
+    "sllbm3d_set_physics": ([_vp, _d, _d], _c),
+    "sllbm3d_num_nodes": ([_vp, _i64p, _i64p, _i64p], _c),
+    "sllbm3d_node_coords": ([_vp, _vp, _vp, _vp], _c),
+    "sllbm3d_bind_populations": ([_vp, _vp, _vp], _c),
+    "sllbm3d_init_macro": ([_vp, _vp, _vp, _vp, _vp, _c], _c),
+    "sllbm3d_step": ([_vp, _i64], _c),
+    "sllbm3d_status_flags": ([_vp, _ip, _i64p], _c),
+    "sllbm3d_moments": ([_vp, _vp, _vp, _vp, _vp, _c], _c),
+    "sllbm3d_mass": ([_vp, _dp], _c),
+    "sllbm3d_get_populations": ([_vp, _vp, _c], _c),
+    "sllbm3d_set_populations": ([_vp, _vp, _c], _c),
 }
 
 for _name, (_args, _res) in _SIGS.items():
@@ -124,6 +142,14 @@ def check(ctx, code):
     """Raise SllbmError for a non-zero status, with the context's message."""
     if code != OK:
         msg = lib.sllbm_last_error(ctx).decode() if ctx else ""
+        raise SllbmError(code, msg)
+    return code
+
+
+def check3(ctx, code):
+    """check() for a three-dimensional context."""
+    if code != OK:
+        msg = lib.sllbm3d_last_error(ctx).decode() if ctx else ""
         raise SllbmError(code, msg)
     return code
 
@@ -298,3 +324,81 @@ def sllbm_eq_init_vjp(ctx, lam0_ptr, rho0_ptr, ux0_ptr, uy0_ptr, T0_ptr, g_rho_p
                       g_uy_ptr, g_T_ptr):
     return check(ctx, lib.sllbm_eq_init_vjp(ctx, lam0_ptr, rho0_ptr, ux0_ptr, uy0_ptr, T0_ptr,
                                             g_rho_ptr, g_ux_ptr, g_uy_ptr, g_T_ptr))
+
+
+# --- three dimensions ------------------------------------------------------------
+def sllbm3d_create(hip_device, precision):
+    h = _vp()
+    check3(None, lib.sllbm3d_create(ctypes.byref(h), hip_device, precision))
+    return h.value
+
+
+def sllbm3d_destroy(ctx):
+    lib.sllbm3d_destroy(ctx)
+
+
+def sllbm3d_last_error(ctx):
+    return lib.sllbm3d_last_error(ctx).decode()
+
+
+def sllbm3d_set_stream(ctx, stream):
+    return check3(ctx, lib.sllbm3d_set_stream(ctx, stream))
+
+
+def sllbm3d_set_order(ctx, p, nodes):
+    return check3(ctx, lib.sllbm3d_set_order(ctx, p, nodes))
+
+
+def sllbm3d_init_grid(ctx, ncx, ncy, ncz, ex_ptr, ey_ptr, ez_ptr, bcx, bcy, bcz):
+    return check3(ctx, lib.sllbm3d_init_grid(ctx, ncx, ncy, ncz, ex_ptr, ey_ptr, ez_ptr, bcx, bcy,
+                                             bcz))
+
+
+def sllbm3d_set_physics(ctx, dt, nu):
+    return check3(ctx, lib.sllbm3d_set_physics(ctx, dt, nu))
+
+
+def sllbm3d_num_nodes(ctx):
+    n = [ctypes.c_int64() for _ in range(3)]
+    check3(ctx, lib.sllbm3d_num_nodes(ctx, *[ctypes.byref(v) for v in n]))
+    return tuple(v.value for v in n)
+
+
+def sllbm3d_node_coords(ctx, x_ptr, y_ptr, z_ptr):
+    return check3(ctx, lib.sllbm3d_node_coords(ctx, x_ptr, y_ptr, z_ptr))
+
+
+def sllbm3d_bind_populations(ctx, a_ptr, b_ptr):
+    return check3(ctx, lib.sllbm3d_bind_populations(ctx, a_ptr, b_ptr))
+
+
+def sllbm3d_init_macro(ctx, rho_ptr, ux_ptr, uy_ptr, uz_ptr, on_device):
+    return check3(ctx, lib.sllbm3d_init_macro(ctx, rho_ptr, ux_ptr, uy_ptr, uz_ptr, on_device))
+
+
+def sllbm3d_step(ctx, n):
+    return check3(ctx, lib.sllbm3d_step(ctx, n))
+
+
+def sllbm3d_status_flags(ctx):
+    u, s = ctypes.c_int(), ctypes.c_int64()
+    check3(ctx, lib.sllbm3d_status_flags(ctx, ctypes.byref(u), ctypes.byref(s)))
+    return u.value, s.value
+
+
+def sllbm3d_moments(ctx, rho_ptr, ux_ptr, uy_ptr, uz_ptr, on_device):
+    return check3(ctx, lib.sllbm3d_moments(ctx, rho_ptr, ux_ptr, uy_ptr, uz_ptr, on_device))
+
+
+def sllbm3d_mass(ctx):
+    m = ctypes.c_double()
+    check3(ctx, lib.sllbm3d_mass(ctx, ctypes.byref(m)))
+    return m.value
+
+
+def sllbm3d_get_populations(ctx, dst_ptr, on_device):
+    return check3(ctx, lib.sllbm3d_get_populations(ctx, dst_ptr, on_device))
+
+
+def sllbm3d_set_populations(ctx, src_ptr, on_device):
+    return check3(ctx, lib.sllbm3d_set_populations(ctx, src_ptr, on_device))

@@ -198,3 +198,107 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class Solver3D:
+    """The three-dimensional context (isothermal D3Q125): torch owns the two
+    population buffers [125, nz, ny, nx] and the stream."""
+
+    def __init__(self, *, p, edges, periodic, dt, nu, precision="fp32", device=0, nodes="glc"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver3D needs a HIP device (torch.cuda is not available)")
+        self.device = torch.device("cuda", device)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.ctx = C.sllbm3d_create(device, C.FP64 if precision == "fp64" else C.FP32)
+        try:
+            C.sllbm3d_set_order(self.ctx, p, C.NODES_GLC if nodes == "glc" else C.NODES_EQUIDISTANT)
+            self._edges = [np.ascontiguousarray(e, dtype=np.float64) for e in edges]
+            bc = [C.PERIODIC if per else C.ZERO_GRADIENT for per in periodic]
+            C.sllbm3d_init_grid(self.ctx, *[len(e) - 1 for e in self._edges],
+                                *[_ptr(e) for e in self._edges], *bc)
+            C.sllbm3d_set_physics(self.ctx, dt, nu)
+            self.nx, self.ny, self.nz = C.sllbm3d_num_nodes(self.ctx)
+            self.n = self.nx * self.ny * self.nz
+            self.q = 125
+            with torch.cuda.device(self.device):
+                self.stream = torch.cuda.current_stream(self.device)
+                C.sllbm3d_set_stream(self.ctx, self.stream.cuda_stream)
+                self.buf_a = torch.empty(self.q * self.n, dtype=self.dtype, device=self.device)
+                self.buf_b = torch.empty(self.q * self.n, dtype=self.dtype, device=self.device)
+            C.sllbm3d_bind_populations(self.ctx, self.buf_a.data_ptr(), self.buf_b.data_ptr())
+        except Exception:
+            C.sllbm3d_destroy(self.ctx)
+            self.ctx = None
+            raise
+        self.workload = None
+
+    @classmethod
+    def from_workload(cls, wl, precision="fp32", device=0):
+        s = cls(p=wl.p, edges=wl.edges, periodic=wl.periodic, dt=wl.dt, nu=wl.nu,
+                precision=precision, device=device)
+        s.workload = wl
+        return s
+
+    def coords(self):
+        """Coordinates of every node, flattened [nz * ny * nx]."""
+        x, y, z = np.zeros(self.nx), np.zeros(self.ny), np.zeros(self.nz)
+        C.sllbm3d_node_coords(self.ctx, _ptr(x), _ptr(y), _ptr(z))
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        return X.reshape(-1), Y.reshape(-1), Z.reshape(-1)
+
+    def init_macro(self, rho, ux, uy, uz):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, ux, uy, uz)]
+        for a in arrs:
+            if a.size != self.n:
+                raise ValueError("field size does not match the grid")
+        C.sllbm3d_init_macro(self.ctx, *[_ptr(a) for a in arrs], 0)
+
+    def init_from_workload(self):
+        self.init_macro(*self.workload.fields(*self.coords()))
+
+    def set_populations(self, F):
+        if isinstance(F, torch.Tensor):
+            t = F.to(device=self.device, dtype=self.dtype).contiguous().reshape(-1)
+            C.sllbm3d_set_populations(self.ctx, t.data_ptr(), 1)
+            torch.cuda.synchronize(self.device)
+            return
+        a = np.ascontiguousarray(F, dtype=np.float64 if self.precision == "fp64" else np.float32)
+        if a.size != self.q * self.n:
+            raise ValueError("population array size does not match the grid")
+        C.sllbm3d_set_populations(self.ctx, _ptr(a), 0)
+
+    def populations_device(self):
+        t = torch.empty(self.q * self.n, dtype=self.dtype, device=self.device)
+        C.sllbm3d_get_populations(self.ctx, t.data_ptr(), 1)
+        return t.view(self.q, self.n)
+
+    def populations(self):
+        a = np.empty(self.q * self.n, dtype=np.float64 if self.precision == "fp64" else np.float32)
+        C.sllbm3d_get_populations(self.ctx, _ptr(a), 0)
+        return a.reshape(self.q, self.n)
+
+    def step(self, n=1):
+        C.sllbm3d_step(self.ctx, n)
+
+    def flags(self):
+        return C.sllbm3d_status_flags(self.ctx)
+
+    def moments(self):
+        out = [np.empty(self.n) for _ in range(4)]
+        C.sllbm3d_moments(self.ctx, *[_ptr(a) for a in out], 0)
+        return tuple(out)
+
+    def mass(self):
+        return C.sllbm3d_mass(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            C.sllbm3d_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

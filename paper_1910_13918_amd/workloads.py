@@ -385,3 +385,69 @@ def population_noise(shape, seed, rel=0.05):
     """Seeded multiplicative perturbation factors 1 + rel * U(-1, 1)."""
     rng = np.random.default_rng(seed)
     return 1.0 + rel * rng.uniform(-1.0, 1.0, size=shape)
+
+
+# ------------------------------------------------------ three dimensions (D3Q125)
+@dataclass
+class Workload3:
+    name: str
+    edges: tuple          # (edges_x, edges_y, edges_z)
+    p: int
+    periodic: tuple       # (x, y, z)
+    nu: float
+    dt: float
+    steps: int
+    fields: Callable      # (x, y, z) -> rho, ux, uy, uz
+    meta: dict = field(default_factory=dict)
+
+
+def tgv3d(ncells=64, p=2, U0=0.1, Re=100.0, steps=100, cfl=0.5, name=None):
+    """Three-dimensional Taylor-Green vortex on the periodic box [0, 2 pi]^3
+    (isothermal, P = rho): u = U0 sin x cos y cos z, v = -U0 cos x sin y cos z,
+    w = 0, rho = 1 + (U0^2 / 16)(cos 2x + cos 2y)(cos 2z + 2), nu = U0 2 pi / Re."""
+    L = 2.0 * np.pi
+    h = L / ncells
+    dt, n = cfl_time_step(h * GLC_MIN_GAP[p], cfl, steps=steps)
+    nu = U0 * L / Re
+
+    def fields(x, y, z):
+        ux = U0 * np.sin(x) * np.cos(y) * np.cos(z)
+        uy = -U0 * np.cos(x) * np.sin(y) * np.cos(z)
+        rho = 1.0 + U0 * U0 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)
+        return rho, ux, uy, np.zeros_like(x)
+
+    e = uniform_edges(ncells, 0.0, L)
+    return Workload3(name or f"tgv3d_{ncells}^3_p{p}", (e, e.copy(), e.copy()), p,
+                     (True, True, True), nu, dt, n, fields, {"U0": U0, "Re": Re})
+
+
+def sine_stretched_edges(ncells, lo, hi, amp=0.3):
+    """Cell edges of [lo, hi] moved by amp h sin(2 pi k / ncells) / (2 pi) (a
+    smooth, monotone stretching for amp < 1)."""
+    k = np.arange(ncells + 1, dtype=float)
+    h = (hi - lo) / ncells
+    return lo + h * (k + amp * np.sin(2 * np.pi * k / ncells) / (2 * np.pi))
+
+
+def box3d(ncells=(5, 4, 3), p=2, periodic=(True, False, True), U0=0.15, cfl=0.6, seed=3,
+          name=None):
+    """Small mapped (stretched) box of unit-ish extents with seeded smooth
+    fields (a few low Fourier modes per velocity component, density 1 +/- 5 %),
+    for parity tests: mixed periodic and zero-gradient axes."""
+    lengths = (1.0, 0.8, 0.9)
+    edges = tuple(sine_stretched_edges(n, 0.0, L) for n, L in zip(ncells, lengths))
+    hmin = min(float(np.min(np.diff(e))) for e in edges)
+    dt, n = cfl_time_step(hmin * GLC_MIN_GAP[p], cfl, steps=10)
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, size=(4, 3))
+    amp = rng.uniform(0.5, 1.0, size=4)
+
+    def fields(x, y, z):
+        k = [2 * np.pi / L for L in lengths]
+        s = [amp[j] * np.sin(k[0] * x + ph[j, 0]) * np.cos(k[1] * y + ph[j, 1])
+             * np.sin(k[2] * z + ph[j, 2]) for j in range(4)]
+        return 1.0 + 0.05 * s[0], U0 * s[1], U0 * s[2], U0 * s[3]
+
+    # tau = nu / dt + 1/2 = 0.8
+    return Workload3(name or f"box3d_{ncells}_p{p}", edges, p, tuple(periodic), 0.3 * dt, dt, n,
+                     fields, {"U0": U0})

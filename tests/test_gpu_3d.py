@@ -1,0 +1,167 @@
+"""GPU parity of the three-dimensional step (isothermal D3Q125) against the
+FP64 oracle of oracle/sllbm3d.py.
+
+Tolerances as for the two-dimensional paths: one step FP64 <= 1e-12 and FP32
+<= 2e-6 relative to max |F| (float32 populations and weights, float64
+moments and equilibrium); a 20-step FP64 trajectory and its moments <= 1e-11.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.sllbm3d import Grid3, Sim3, d3q125
+from paper_1910_13918_amd import sllbm as C
+from paper_1910_13918_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a HIP device")]
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _solver(wl, precision):
+    from paper_1910_13918_amd.solver import Solver3D
+    return Solver3D.from_workload(wl, precision=precision)
+
+
+def _oracle(wl):
+    g = Grid3(*wl.edges, wl.p, wl.periodic)
+    return g, Sim3(g, wl.dt, wl.nu)
+
+
+def _state(wl, g, sim, seed, fp32):
+    F = sim.init(*wl.fields(*g.coords()))
+    F = F * W.population_noise(F.shape, seed, 0.05)
+    return F.astype(np.float32).astype(np.float64) if fp32 else F
+
+
+CASES = [(p, per) for p in (1, 2, 3, 4) for per in ((True, False, True), (False, True, False))]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("p,periodic", CASES)
+def test_one_step_matches_the_oracle(p, periodic, precision):
+    """A stretched 5 x 4 x 3-cell box, periodic and zero-gradient axes mixed
+    both ways, a perturbed equilibrium (non-equilibrium parts in every
+    velocity)."""
+    wl = W.box3d(p=p, periodic=periodic)
+    g, sim = _oracle(wl)
+    F0 = _state(wl, g, sim, 20 + p, precision == "fp32")
+    want = sim.step(F0)
+    s = _solver(wl, precision)
+    try:
+        print(f"[gpu] 3d one step p={p} periodic={periodic} {precision} nodes={s.n}", flush=True)
+        s.set_populations(F0)
+        s.step(1)
+        got = s.populations()
+        assert s.flags() == (0, 1)
+    finally:
+        s.close()
+    assert _rel(got, want) <= (1e-12 if precision == "fp64" else 2e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_several_tiles_and_ragged_tails(precision):
+    """x spans two 64-node tiles with a ragged tail (72 nodes, periodic: the
+    seam path), y ends inside a 4-row workgroup (10 rows), z 6 planes; two
+    steps."""
+    wl = W.box3d(ncells=(24, 3, 2), p=3, periodic=(True, False, True), seed=9)
+    g, sim = _oracle(wl)
+    assert (g.nx, g.ny, g.nz) == (72, 10, 6)
+    F0 = _state(wl, g, sim, 31, precision == "fp32")
+    want = sim.run(F0, 2)
+    s = _solver(wl, precision)
+    try:
+        print(f"[gpu] 3d tiles {precision} nodes={s.n}", flush=True)
+        s.set_populations(F0)
+        s.step(2)
+        got = s.populations()
+    finally:
+        s.close()
+    assert _rel(got, want) <= (1e-12 if precision == "fp64" else 4e-6)
+
+
+def test_taylor_green_trajectory_moments_and_mass():
+    """20 FP64 steps of the 3-D Taylor-Green vortex (4^3 cells of order 3)
+    from the device initialisation f = f_eq: populations, moments and mass
+    against the oracle."""
+    wl = W.tgv3d(4, 3, U0=0.1, steps=20)
+    g, sim = _oracle(wl)
+    rho0, ux0, uy0, uz0 = wl.fields(*g.coords())
+    want = sim.run(sim.init(rho0, ux0, uy0, uz0), 20)
+    s = _solver(wl, "fp64")
+    try:
+        print(f"[gpu] 3d tgv trajectory nodes={s.n}", flush=True)
+        s.init_from_workload()
+        m0 = s.mass()
+        # factorised against the literal 3^n-tuple contraction: rounding only
+        assert _rel(s.populations(), sim.init(rho0, ux0, uy0, uz0)) <= 1e-14
+        s.step(20)
+        got = s.populations()
+        mom = s.moments()
+        m1 = s.mass()
+    finally:
+        s.close()
+    assert _rel(got, want) <= 1e-11
+    ref = sim.moments(want)
+    for a, b in zip(mom, ref):
+        assert np.abs(a - b).max() <= 1e-11 * max(np.abs(b).max(), 1e-3)
+    assert m0 == pytest.approx(sim.mass(sim.init(rho0, ux0, uy0, uz0)), rel=1e-13)
+    assert m1 == pytest.approx(sim.mass(want), rel=1e-12)
+
+
+def test_stability_flag_and_refusals():
+    wl = W.box3d(p=2)
+    g, sim = _oracle(wl)
+    F = _state(wl, g, sim, 5, False)
+    F[7, 11] = np.nan
+    s = _solver(wl, "fp64")
+    try:
+        s.set_populations(F)
+        assert s.flags()[0] == 0
+        s.step(1)
+        assert s.flags()[0] == 1
+        # set-up is fixed once the populations exist
+        with pytest.raises(C.SllbmError) as e:
+            C.sllbm3d_set_physics(s.ctx, wl.dt, wl.nu)
+        assert e.value.code == C.E_STATE
+        for buf in (s.buf_a, s.buf_b):
+            with pytest.raises(C.SllbmError) as e:
+                C.sllbm3d_get_populations(s.ctx, buf.data_ptr(), 1)
+            assert e.value.code == C.E_ARG
+        s.set_populations(_state(wl, g, sim, 6, False))
+        assert s.flags()[0] == 0
+    finally:
+        s.close()
+
+
+def test_full_size_one_step_at_sampled_nodes():
+    """The bench workload (Taylor-Green, 64^3 cells of order 2: 128^3 nodes,
+    float32) in the bench's launch configuration: one step against the oracle
+    at 300 seeded nodes.  The input is the rest state w_i everywhere except on
+    the sources of the sampled nodes' stencils, which carry the perturbed
+    Taylor-Green equilibrium, so the oracle only evaluates those."""
+    wl = W.tgv3d(64, 2)
+    g, sim = _oracle(wl)
+    N = g.nnodes
+    rng = np.random.default_rng(2024)
+    nodes = np.sort(rng.choice(N, 300, replace=False))
+    src = np.unique(np.concatenate([sim.departure_stencil(i, nodes)[0].reshape(-1)
+                                    for i in range(125)]))
+    _, w = d3q125()
+    F = np.repeat(w[:, None].astype(np.float32), N, axis=1)
+    X, Y, Z = g.coords()
+    feq = sim.init(*wl.fields(X[src], Y[src], Z[src]))
+    F[:, src] = (feq * W.population_noise(feq.shape, 77, 0.05)).astype(np.float32)
+    want = sim.step(F.astype(np.float64), nodes)
+    s = _solver(wl, "fp32")
+    try:
+        print(f"[gpu] 3d full size sampled nodes={s.n}", flush=True)
+        s.set_populations(F)
+        s.step(1)
+        got = s.populations_device()[:, torch.tensor(nodes, device="cuda")].cpu().numpy()
+    finally:
+        s.close()
+    assert _rel(got.astype(np.float64), want) <= 2e-6
