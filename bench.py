@@ -72,7 +72,8 @@ def profiled_traffic(wname, precision, path):
     import hashlib
     tag = {"riemann2d_512x512cells_p2": "riemann512_p2",
            "shock_vortex_1024x512cells_p3_stretched": "svi1024x512_p3",
-           "tgv_wavy_256x256cells_p4_amp0.3": "curvilinear_tgv_wavy256_p4"}.get(wname)
+           "tgv_wavy_256x256cells_p4_amp0.3": "curvilinear_tgv_wavy256_p4",
+           "tgv3d_64^3cells_p2": "d3q125_tgv3d64_p2"}.get(wname)
     if tag is None:
         return None
     f = os.path.join(ROOT, "profiles", f"stream_collide_{tag}_{precision}_{path}.json")
@@ -161,6 +162,51 @@ def curvilinear_entry(precision, steps=20, warmup=3):
            "unstable_flag": unstable, "traffic": tr,
            "traffic_over_algorithmic": tr / (s.n * bpn) if tr else None}
     s.close()
+    return out
+
+
+def d3q125_entry(steps=20, warmup=3):
+    """Throughput of the three-dimensional step (isothermal D3Q125): the 3-D
+    Taylor-Green vortex on 64^3 cells of order 2 (128^3 nodes, 125 planes;
+    float32: 1000 B per node update, every population read and written once),
+    float32 and float64, with their moment differences after the run."""
+    import numpy as np
+    import torch
+
+    from paper_1910_13918_amd import workloads as W
+    from paper_1910_13918_amd.solver import Solver3D
+    wl = W.tgv3d(64, 2)
+    wname = "tgv3d_64^3cells_p2"
+    out = {"workload": wname, "steps": steps, "warmup": warmup}
+    mom = {}
+    for precision in ("fp32", "fp64"):
+        s = Solver3D.from_workload(wl, precision=precision)
+        s.init_from_workload()
+        s.step(warmup)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(s.stream)
+        s.step(steps)
+        ev1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        nu_s = s.n * steps / (ms * 1e-3)
+        bpn = 2 * 125 * (8 if precision == "fp64" else 4)
+        tr = profiled_traffic(wname, precision, "direct3d")
+        out[precision] = {"value": nu_s, "unit": "node-updates/s", "ms_per_step": ms / steps,
+                          "bytes_per_node_update": bpn, "achieved_gbs": nu_s * bpn / 1e9,
+                          "frac": nu_s * bpn / 1e9 / HBM_PEAK_GBS, "traffic": tr,
+                          "traffic_over_algorithmic": tr / (s.n * bpn) if tr else None,
+                          "unstable_flag": s.flags()[0]}
+        mom[precision] = s.moments()
+        out["nodes"] = s.n
+        s.close()
+    a, b = mom["fp32"], mom["fp64"]
+    umax = max(np.abs(b[k]).max() for k in (1, 2, 3))
+    out["fp32_vs_fp64_after_steps"] = {
+        "rho_max_rel": float(np.abs(a[0] - b[0]).max() / np.abs(b[0]).max()),
+        "u_max_rel": float(max(np.abs(a[k] - b[k]).max() for k in (1, 2, 3)) / umax)}
     return out
 
 
@@ -419,6 +465,8 @@ def main():
     ap.add_argument("--no-svi", action="store_true",
                     help="skip the shock-vortex (stretched 1024 x 512 cells, p = 3) and "
                          "curvilinear-mesh lines")
+    ap.add_argument("--d3q125-only", action="store_true",
+                    help="only time the three-dimensional step (prints its JSON object)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only time the checkpointed adjoint rollout (prints its JSON object)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -433,6 +481,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}))
+        return
+    if args.d3q125_only:
+        print(json.dumps(d3q125_entry(args.steps, args.warmup)))
         return
     if args.adjoint_only:
         print(json.dumps(adjoint_cost(args.precision)))
@@ -522,6 +573,7 @@ def main():
     if not args.no_svi and args.workload == "riemann":
         out["shock_vortex"] = shock_vortex_entry(args.precision)
         out["curvilinear"] = curvilinear_entry(args.precision)
+        out["d3q125"] = d3q125_entry()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_cost()
         rec = adjoint_cost(every=0)

@@ -4,6 +4,7 @@
 // kernel launches (step3d.hip).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <limits>
 #include <string>
@@ -40,6 +41,9 @@ struct sllbm3d_ctx {
   bool dev_checked = false;
   bool dev_dirty = true;
   Buf3 xsrc, xw, ysrc, yw, zsrc, zw, mx, my, mz, flag, partial, scalar, macro;
+  // float32 row segments (Rows3): segment width (0: unavailable) and windows
+  int rows_tx = 0, rows_ntx = 0;
+  Buf3 xwin, xrel;
   void *pop[2] = {nullptr, nullptr};
   bool own_pop = false;
   int cur = 0;
@@ -113,15 +117,49 @@ int upload(sllbm3d_ctx *c, Buf3 &b, const std::vector<V> &v) {
   return SLLBM_OK;
 }
 
+// Row segments of the float32 step along x: the widest segment (at most 64
+// nodes, at least 32) whose x-stencils fit 64 consecutive source columns for
+// every segment and 1-D velocity; fills the windows (first unwrapped column
+// per component and segment) and each node's first tap within its window.
+int rows3_windows(const AxisTable *t, int n, int P1, std::vector<int32_t> &win,
+                  std::vector<int32_t> &rel) {
+  int tx = 64;
+  while (tx >= 32) {
+    const int ntx = (n + tx - 1) / tx;
+    win.assign(size_t(5) * ntx, 0);
+    rel.assign(size_t(5) * n, 0);
+    long width = 0;
+    for (int a = 0; a < 5; ++a)
+      for (int k = 0; k < ntx; ++k) {
+        const int j0 = k * tx, j1 = std::min(j0 + tx, n);
+        long lo = std::numeric_limits<long>::max(), hi = std::numeric_limits<long>::min();
+        for (int j = j0; j < j1; ++j) {
+          lo = std::min(lo, t[a].start[j]);
+          hi = std::max(hi, t[a].start[j] + P1 - 1);
+        }
+        win[size_t(a) * ntx + k] = int32_t(lo);
+        width = std::max(width, hi - lo + 1);
+        for (int j = j0; j < j1; ++j) rel[size_t(a) * n + j] = int32_t(t[a].start[j] - lo);
+      }
+    if (width <= 64) return tx;
+    tx -= int(width) - 64;
+  }
+  win.clear();
+  rel.clear();
+  return 0;
+}
+
 // [comp][tap][node] order of five 1-D tables: node indices, or the weights
-// in the population type.
-int upload_axis(sllbm3d_ctx *c, const Axis &ax, Buf3 &src, Buf3 &w) {
+// in the population type.  `tables` (optional) receives the host tables.
+int upload_axis(sllbm3d_ctx *c, const Axis &ax, Buf3 &src, Buf3 &w,
+                std::vector<AxisTable> *tables = nullptr) {
   const int P1 = c->p + 1, n = ax.n;
   std::vector<int32_t> s(size_t(5) * P1 * n);
   std::vector<double> wd(s.size());
   for (int a = 0; a < 5; ++a) {
     // departure x - dt xi_a along this axis
     const AxisTable t = build_axis_table(ax, -c->dt * c->vs.xi[a]);
+    if (tables) tables->push_back(t);
     for (int m = 0; m < P1; ++m)
       for (int j = 0; j < n; ++j) {
         s[(size_t(a) * P1 + m) * n + j] = t.src[size_t(j) * P1 + m];
@@ -146,9 +184,25 @@ int prepare_device(sllbm3d_ctx *c) {
   }
   HIP_TRY3(c, hipSetDevice(c->device));
   if (c->dev_dirty) {
-    rc = upload_axis(c, c->ax, c->xsrc, c->xw);
-    if (!rc) rc = upload_axis(c, c->ay, c->ysrc, c->yw);
-    if (!rc) rc = upload_axis(c, c->az, c->zsrc, c->zw);
+    std::vector<AxisTable> xt, yt, zt;
+    rc = upload_axis(c, c->ax, c->xsrc, c->xw, &xt);
+    if (!rc) rc = upload_axis(c, c->ay, c->ysrc, c->yw, &yt);
+    if (!rc) rc = upload_axis(c, c->az, c->zsrc, c->zw, &zt);
+    // float32 row segments: the zero component must depart from the node
+    // itself on every axis (identity tables), and the 125 planes must stay
+    // within one 32-bit buffer range
+    c->rows_tx = 0;
+    if (!rc && c->fp32 && double(kQ3) * double(nnodes(c)) * 4.0 < 4294967296.0 &&
+        identity_table(xt[0], c->ax.n) && identity_table(yt[0], c->ay.n) &&
+        identity_table(zt[0], c->az.n)) {
+      std::vector<int32_t> win, rel;
+      c->rows_tx = rows3_windows(xt.data(), c->ax.n, c->p + 1, win, rel);
+      if (c->rows_tx) {
+        c->rows_ntx = (c->ax.n + c->rows_tx - 1) / c->rows_tx;
+        rc = upload(c, c->xwin, win);
+        if (!rc) rc = upload(c, c->xrel, rel);
+      }
+    }
     if (!rc) rc = upload(c, c->mx, c->ax.node_mass());
     if (!rc) rc = upload(c, c->my, c->ay.node_mass());
     if (!rc) rc = upload(c, c->mz, c->az.node_mass());
@@ -180,6 +234,16 @@ Consts3 make_consts(const sllbm3d_ctx *c) {
     for (int m = 0; m < 5; ++m) k.hk[a][m] = c->vs.hk[a][m];
   }
   return k;
+}
+
+Rows3 make_rows(const sllbm3d_ctx *c) {
+  Rows3 r{};
+  r.tx = c->rows_tx;
+  r.ntx = c->rows_ntx;
+  r.perx = c->ax.periodic ? 1 : 0;
+  r.xwin = static_cast<const int32_t *>(c->xwin.ptr);
+  r.xrel = static_cast<const int32_t *>(c->xrel.ptr);
+  return r;
 }
 
 Tables3 make_tables(const sllbm3d_ctx *c) {
@@ -219,7 +283,8 @@ void sllbm3d_destroy(sllbm3d_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     Buf3 *bufs[] = {&c->xsrc, &c->xw,   &c->ysrc,    &c->yw,     &c->zsrc, &c->zw,   &c->mx,
-                    &c->my,   &c->mz,   &c->flag,    &c->partial, &c->scalar, &c->macro};
+                    &c->my,   &c->mz,   &c->flag,    &c->partial, &c->scalar, &c->macro,
+                    &c->xwin, &c->xrel};
     for (Buf3 *b : bufs) free_buf(*b);
     if (c->own_pop) {
       (void)hipFree(c->pop[0]);
@@ -380,8 +445,9 @@ int sllbm3d_step(sllbm3d_ctx *c, int64_t n) {
   if (rc) return rc;
   const Consts3 k = make_consts(c);
   const Tables3 t = make_tables(c);
+  const Rows3 r = make_rows(c);
   for (int64_t s = 0; s < n; ++s) {
-    HIP_TRY3(c, launch_step3d(c->fp32, k, t, c->pop[c->cur], c->pop[1 - c->cur],
+    HIP_TRY3(c, launch_step3d(c->fp32, k, t, r, c->pop[c->cur], c->pop[1 - c->cur],
                               static_cast<int *>(c->flag.ptr), c->stream));
     c->cur ^= 1;
     ++c->steps_done;

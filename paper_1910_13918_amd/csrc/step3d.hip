@@ -6,9 +6,23 @@
 // interpolant of eq. (17) is the triple product of 1-D Lagrange weights.
 #include "launch3d.hpp"
 #include "step_common.hpp"
+#include "tiled_common.hpp"
+
+#include <utility>
 
 namespace sllbm {
 namespace {
+
+// f.template operator()<k>() for k = 0 .. N-1 as straight-line code: every
+// index is a compile-time constant, so arrays indexed by it stay in
+// registers (a 125-iteration #pragma unroll loop with a large body exceeds
+// the compiler's full-unroll threshold and leaves the index dynamic).
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  [&]<int... K>(std::integer_sequence<int, K...>) {
+    (f.template operator()<K>(), ...);
+  }(std::make_integer_sequence<int, N>{});
+}
 
 // Calls fn(i, f_eq_i) for the 125 velocities: the 4th-order Hermite
 // equilibrium at theta = 1 (Sec. II.A, eqs. (9)-(10) in three components),
@@ -18,8 +32,32 @@ namespace {
 // Evaluated per (b, c) as sum_j YZ_j Xc_{4-j}[a] with YZ_j = sum_{l+m=j}
 // Y_l Z_m and the running sums Xc_n[a] = sum_{k<=n} X_k[a].  The (b, c)
 // loops stay rolled: unrolled, the relaxation's 125 independent loads were
-// all hoisted (255 registers, one wavefront per SIMD).
+// all hoisted (255 registers, one wavefront per SIMD); ROLLED = false for
+// values held in registers, which need compile-time velocity indices.
+// The contribution of one (b, c) row: fn(a + 5 b + 25 c, f_eq) for a = 0..4.
 template <class Fn>
+__device__ __forceinline__ void eq3_row(int b, int cc, double rho, const double (&py)[5],
+                                        const double (&pz)[5], const double (&xc)[5][5],
+                                        const Consts3 &c, Fn &&fn) {
+  double yz[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l <= j; ++l) s = fma(c.hk[b][l] * py[l], c.hk[cc][j - l] * pz[j - l], s);
+    yz[j] = s;
+  }
+  const double rbc = rho * c.w[b] * c.w[cc];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s = fma(yz[j], xc[a][4 - j], s);
+    fn(a + 5 * b + 25 * cc, rbc * c.w[a] * s);
+  }
+}
+
+template <bool ROLLED = true, class Fn>
 __device__ __forceinline__ void for_each_eq3(double rho, double ux, double uy, double uz,
                                              const Consts3 &c, Fn &&fn) {
   const double px[5] = {1.0, ux, ux * ux, ux * ux * ux, (ux * ux) * (ux * ux)};
@@ -35,30 +73,23 @@ __device__ __forceinline__ void for_each_eq3(double rho, double ux, double uy, d
       xc[a][k] = s;
     }
   }
+  if constexpr (ROLLED) {
 #pragma unroll 1
-  for (int cc = 0; cc < 5; ++cc) {
-    double z[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) z[m] = c.hk[cc][m] * pz[m];
+    for (int cc = 0; cc < 5; ++cc)
 #pragma unroll 1
-    for (int b = 0; b < 5; ++b) {
-      double yz[5];
-#pragma unroll
-      for (int j = 0; j < 5; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int l = 0; l <= j; ++l) s = fma(c.hk[b][l] * py[l], z[j - l], s);
-        yz[j] = s;
-      }
-      const double rbc = rho * c.w[b] * c.w[cc];
-#pragma unroll
-      for (int a = 0; a < 5; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) s = fma(yz[j], xc[a][4 - j], s);
-        fn(a + 5 * b + 25 * cc, rbc * c.w[a] * s);
-      }
-    }
+      for (int b = 0; b < 5; ++b) eq3_row(b, cc, rho, py, pz, xc, c, fn);
+  } else {
+    // one (b, c) row at a time: its inputs pass through an empty asm, so its
+    // arithmetic is not hoisted above the previous row (all 25 rows' float64
+    // terms evaluated up front took more registers than the 125 values)
+    static_for<25>([&]<int g>() {
+      double r = rho, vy = uy, vz = uz;
+      asm volatile("" : "+v"(r), "+v"(vy), "+v"(vz));
+      const double qy[5] = {1.0, vy, vy * vy, vy * vy * vy, (vy * vy) * (vy * vy)};
+      const double qz[5] = {1.0, vz, vz * vz, vz * vz * vz, (vz * vz) * (vz * vz)};
+      eq3_row(g % 5, g / 5, r, qy, qz, xc, c, fn);
+      __builtin_amdgcn_sched_barrier(0);
+    });
   }
 }
 
@@ -208,6 +239,178 @@ __global__ __launch_bounds__(256) void k_step3d(const T *__restrict__ fin, T *__
   });
 }
 
+// ---------------------------------------------------------------------------
+// float32 step on row segments.  A wavefront owns TX consecutive x-nodes of
+// one (y, z) row, so the y- and z-taps of every velocity are uniform over its
+// lanes.  Per velocity i = a + 5 b + 25 c it loads the (p+1)^2 source rows
+// (one value per lane: column xwin + lane of the window of component a),
+// combines them with the z- and y-weights in registers, writes the one
+// interpolated row to its LDS row and evaluates the x-factor from LDS with
+// the lane's p+1 x-weights (eq. (17), z and y factors first).  The zero
+// component of each axis departs from the node itself (the host checks that
+// its tables are the identity): b = 0 or c = 0 loads one row along that
+// axis, a = 0 loads the node's own column and needs no LDS.  The 125 values
+// stay in registers (float32) for the collision; loads run D velocities
+// ahead, and a workgroup barrier every SYNC velocities keeps its RY x RZ
+// wavefronts, whose source rows overlap, close enough for those re-reads to
+// hit in the L1 cache.  Tiles (64 x RY x RZ nodes) go to the XCDs in
+// contiguous ranges of the (x, y, z) order, so neighbouring rows share an L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync3() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// The y- and z-tables come as restrict-qualified parameters: read-only and
+// unaliased, their wave-uniform entries are fetched with scalar loads (read
+// through the Tables3 pointers, they were vector loads, and every buffer
+// load whose row offset depended on them became a waterfall loop).
+template <int P, int RY, int RZ, int D, int SYNC>
+__global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
+    const float *__restrict__ fin, float *__restrict__ fout, const int32_t *__restrict__ ysrc,
+    const float *__restrict__ yw, const int32_t *__restrict__ zsrc, const float *__restrict__ zw,
+    Tables3 t, Rows3 r, Consts3 c, int *__restrict__ flag) {
+  constexpr int P1 = P + 1;
+  constexpr int NV = P1 * P1;  // most loads of one velocity
+  __shared__ float lds[RY * RZ][2][64];
+  const int ntiles = r.ntx * r.nty * r.ntz;
+  const int tile = xcd_tile(int(blockIdx.x), ntiles);
+  if (tile >= ntiles) return;  // the whole workgroup
+  const int tx = tile % r.ntx, rest = tile / r.ntx;
+  const int ty = rest % r.nty, tz = rest / r.nty;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int iy0 = ty * RY + wv % RY, iz0 = tz * RZ + wv / RY;
+  // rows past the grid stream its last row and store nothing (every
+  // wavefront reaches every barrier)
+  const bool row_ok = iy0 < c.ny && iz0 < c.nz;
+  const int iy = min(iy0, c.ny - 1), iz = min(iz0, c.nz - 1);
+  const int TX = r.tx;
+  const int ix = tx * TX + lane;
+  const bool store = row_ok && lane < TX && ix < c.nx;
+  const int ixc = min(tx * TX + min(lane, TX - 1), c.nx - 1);
+  const long long N = c.n;
+  const unsigned plane_bytes = unsigned(N * 4);
+  const unsigned row_bytes = unsigned(c.nx) * 4u;
+  const float *xw = static_cast<const float *>(t.xw);
+  int xr0[5];
+  float wx[5][P1];
+  unsigned col_off[5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    xr0[a] = r.xrel[a * c.nx + ixc];
+#pragma unroll
+    for (int m = 0; m < P1; ++m) wx[a][m] = xw[(a * P1 + m) * c.nx + ixc];
+    col_off[a] = unsigned(wrap_or_clamp(r.xwin[a * r.ntx + tx] + lane, c.nx, r.perx)) * 4u;
+  }
+  col_off[0] = unsigned(ixc) * 4u;  // a = 0: the node's own column
+  float *lrow = &lds[wv][0][0];
+  auto row_of = [&](int zs, int ys) { return (unsigned(zs) * unsigned(c.ny) + unsigned(ys)) * row_bytes; };
+  float pre[D + 1][NV];
+  // one resource per array (the host keeps 125 N floats below 4 GiB); the
+  // plane is a uniform offset
+  const auto rin = make_rsrc(fin, unsigned(kQ3) * plane_bytes);
+  auto load = [&]<int q>(float(&dst)[NV]) {
+    constexpr int a = q % 5, b = (q / 5) % 5, cc = q / 25;
+    const unsigned po = unsigned(q) * plane_bytes;
+    // the table reads depend on k, which the empty asm pins here: they are
+    // not hoisted (the offsets of every velocity would not fit the scalar
+    // registers)
+    int k = 0;
+    asm volatile("" : "+s"(k));
+    const int ky = iy + k, kz = iz + k;
+    if constexpr (b == 0 && cc == 0) {
+      dst[0] = buffer_load<float>(rin, col_off[a], po + row_of(iz, iy));
+    } else if constexpr (cc == 0) {
+#pragma unroll
+      for (int n = 0; n < P1; ++n)
+        dst[n] = buffer_load<float>(rin, col_off[a], po + row_of(iz, ysrc[(b * P1 + n) * c.ny + ky]));
+    } else if constexpr (b == 0) {
+#pragma unroll
+      for (int l = 0; l < P1; ++l)
+        dst[l] = buffer_load<float>(rin, col_off[a], po + row_of(zsrc[(cc * P1 + l) * c.nz + kz], iy));
+    } else {
+#pragma unroll
+      for (int l = 0; l < P1; ++l)
+#pragma unroll
+        for (int n = 0; n < P1; ++n)
+          dst[l * P1 + n] = buffer_load<float>(
+              rin, col_off[a],
+              po + row_of(zsrc[(cc * P1 + l) * c.nz + kz], ysrc[(b * P1 + n) * c.ny + ky]));
+    }
+  };
+  float fs[kQ3];
+  double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  static_for<D>([&]<int q>() { load.template operator()<q>(pre[q]); });
+  static_for<kQ3>([&]<int q>() {
+    if constexpr (SYNC > 0 && q > 0 && q % SYNC == 0) __builtin_amdgcn_s_barrier();
+    if constexpr (q + D < kQ3) load.template operator()<q + D>(pre[(q + D) % (D + 1)]);
+    constexpr int a = q % 5, b = (q / 5) % 5, cc = q / 25;
+    const float(&v)[NV] = pre[q % (D + 1)];
+    int k = 0;
+    asm volatile("" : "+s"(k));
+    const int ky = iy + k, kz = iz + k;
+    float y;
+    if constexpr (b == 0 && cc == 0) {
+      y = v[0];
+    } else if constexpr (cc == 0) {
+      y = 0.0f;
+#pragma unroll
+      for (int n = 0; n < P1; ++n) y = fma(yw[(b * P1 + n) * c.ny + ky], v[n], y);
+    } else if constexpr (b == 0) {
+      y = 0.0f;
+#pragma unroll
+      for (int l = 0; l < P1; ++l) y = fma(zw[(cc * P1 + l) * c.nz + kz], v[l], y);
+    } else {
+      y = 0.0f;
+#pragma unroll
+      for (int l = 0; l < P1; ++l) {
+        float yl = 0.0f;
+#pragma unroll
+        for (int n = 0; n < P1; ++n) yl = fma(yw[(b * P1 + n) * c.ny + ky], v[l * P1 + n], yl);
+        y = fma(zw[(cc * P1 + l) * c.nz + kz], yl, y);
+      }
+    }
+    float acc = y;  // a = 0: loaded at the node's own column
+    if constexpr (a != 0) {
+      float *row = lrow + (q & 1) * 64;
+      row[lane] = y;
+      wave_lds_sync3();
+      acc = 0.0f;
+#pragma unroll
+      for (int m = 0; m < P1; ++m) acc = fma(wx[a][m], row[xr0[a] + m], acc);
+    }
+    asm volatile("" : "+v"(acc));  // keep the velocity's arithmetic in its place
+    fs[q] = acc;
+    // moments as the values arrive: each float64 conversion is used at once
+    // (summed after the loop, the scheduler kept all 125 of them live)
+    const double d = double(acc);
+    rho += d;
+    jx = fma(c.xi[a], d, jx);
+    jy = fma(c.xi[b], d, jy);
+    jz = fma(c.xi[cc], d, jz);
+    // one scheduling region per velocity: in a single region of all 125 the
+    // scheduler moved the moment sums behind the last load and kept every
+    // value's float64 conversion live
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  // stability flag, BGK toward the 4th-order equilibrium
+  if (!store) return;
+  const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+  const bool ok = (rho > 0.0) && isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+  if (!ok) atomicOr(flag, 1);
+  const unsigned vo = unsigned(((long long)iz * c.ny + iy) * c.nx + ix) * 4u;
+  const double om = c.omega;
+  const auto rout = make_rsrc(fout, unsigned(kQ3) * plane_bytes);
+  for_each_eq3<false>(rho, ux, uy, uz, c, [&](int i, double feq) {
+    float x = fs[i];
+    asm volatile("" : "+v"(x));  // not the conversion of the moment sums
+    const double f = double(x);
+    buffer_store<float>(float(f - om * (f - feq)), rout, vo, unsigned(i) * plane_bytes);
+  });
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_init3d(const double *__restrict__ rho,
                                                 const double *__restrict__ ux,
@@ -310,8 +513,35 @@ hipError_t dispatch3(int fp32, int p, F &&f) {
 
 }  // namespace
 
-hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const void *fin,
-                         void *fout, int *flag, hipStream_t s) {
+// Row-segment shape of the float32 step: workgroups of RY x RZ rows, loads
+// D velocities ahead, a barrier every SYNC velocities.
+constexpr int kRows3Y = 4, kRows3Z = 1, kRows3D = 2, kRows3Sync = 5;
+
+hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
+                         const void *fin, void *fout, int *flag, hipStream_t s) {
+  if (fp32 && r.tx > 0) {
+    Rows3 rr = r;
+    rr.nty = (c.ny + kRows3Y - 1) / kRows3Y;
+    rr.ntz = (c.nz + kRows3Z - 1) / kRows3Z;
+    const long long ntiles = (long long)rr.ntx * rr.nty * rr.ntz;
+    if (ntiles >= (1LL << 31) - 8) return hipErrorInvalidValue;
+    const unsigned grid = unsigned((ntiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
+    auto go = [&]<int P>() -> hipError_t {
+      k_step3d_rows<P, kRows3Y, kRows3Z, kRows3D, kRows3Sync>
+          <<<grid, 64 * kRows3Y * kRows3Z, 0, s>>>(
+              static_cast<const float *>(fin), static_cast<float *>(fout), t.ysrc,
+              static_cast<const float *>(t.yw), t.zsrc, static_cast<const float *>(t.zw), t, rr, c,
+              flag);
+      return hipGetLastError();
+    };
+    switch (c.p) {
+      case 1: return go.template operator()<1>();
+      case 2: return go.template operator()<2>();
+      case 3: return go.template operator()<3>();
+      case 4: return go.template operator()<4>();
+    }
+    return hipErrorInvalidValue;
+  }
   if (c.nz > 65535 || c.ny > 4 * 65535) return hipErrorInvalidValue;
   return dispatch3(fp32, c.p, [&]<typename T, int P>() -> hipError_t {
     const dim3 grid(unsigned((c.nx + 63) / 64), unsigned((c.ny + 3) / 4), unsigned(c.nz));
