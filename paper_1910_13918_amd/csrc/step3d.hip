@@ -266,7 +266,7 @@ __device__ __forceinline__ void wave_lds_sync3() {
 // unaliased, their wave-uniform entries are fetched with scalar loads (read
 // through the Tables3 pointers, they were vector loads, and every buffer
 // load whose row offset depended on them became a waterfall loop).
-template <int P, int RY, int RZ, int D, int SYNC>
+template <int P, int RY, int RZ, int D, int SYNC, bool ZFIRST>
 __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
     const float *__restrict__ fin, float *__restrict__ fout, const int32_t *__restrict__ ysrc,
     const float *__restrict__ yw, const int32_t *__restrict__ zsrc, const float *__restrict__ zw,
@@ -278,7 +278,8 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
   const int tile = xcd_tile(int(blockIdx.x), ntiles);
   if (tile >= ntiles) return;  // the whole workgroup
   const int tx = tile % r.ntx, rest = tile / r.ntx;
-  const int ty = rest % r.nty, tz = rest / r.nty;
+  const int ty = ZFIRST ? rest / r.ntz : rest % r.nty;
+  const int tz = ZFIRST ? rest % r.ntz : rest / r.nty;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int iy0 = ty * RY + wv % RY, iz0 = tz * RZ + wv / RY;
@@ -305,6 +306,23 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
     col_off[a] = unsigned(wrap_or_clamp(r.xwin[a * r.ntx + tx] + lane, c.nx, r.perx)) * 4u;
   }
   col_off[0] = unsigned(ixc) * 4u;  // a = 0: the node's own column
+  // this row's y- and z-taps, one table entry per lane (lane k = comp (p+1)
+  // + tap): each velocity takes its uniform entries with v_readlane, so no
+  // scalar memory load is in flight when a wavefront waits for its LDS row
+  // (one wait counter covers both)
+  const int kk = lane < 5 * P1 ? lane : 0;
+  const int ys_v = ysrc[kk * c.ny + iy];
+  const float wy_v = yw[kk * c.ny + iy];
+  const int zs_v = zsrc[kk * c.nz + iz];
+  const float wz_v = zw[kk * c.nz + iz];
+  auto ys_of = [&](int k) { return __builtin_amdgcn_readlane(ys_v, k); };
+  auto zs_of = [&](int k) { return __builtin_amdgcn_readlane(zs_v, k); };
+  auto wy_of = [&](int k) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wy_v), k));
+  };
+  auto wz_of = [&](int k) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wz_v), k));
+  };
   float *lrow = &lds[wv][0][0];
   auto row_of = [&](int zs, int ys) { return (unsigned(zs) * unsigned(c.ny) + unsigned(ys)) * row_bytes; };
   float pre[D + 1][NV];
@@ -314,22 +332,16 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
   auto load = [&]<int q>(float(&dst)[NV]) {
     constexpr int a = q % 5, b = (q / 5) % 5, cc = q / 25;
     const unsigned po = unsigned(q) * plane_bytes;
-    // the table reads depend on k, which the empty asm pins here: they are
-    // not hoisted (the offsets of every velocity would not fit the scalar
-    // registers)
-    int k = 0;
-    asm volatile("" : "+s"(k));
-    const int ky = iy + k, kz = iz + k;
     if constexpr (b == 0 && cc == 0) {
       dst[0] = buffer_load<float>(rin, col_off[a], po + row_of(iz, iy));
     } else if constexpr (cc == 0) {
 #pragma unroll
       for (int n = 0; n < P1; ++n)
-        dst[n] = buffer_load<float>(rin, col_off[a], po + row_of(iz, ysrc[(b * P1 + n) * c.ny + ky]));
+        dst[n] = buffer_load<float>(rin, col_off[a], po + row_of(iz, ys_of(b * P1 + n)));
     } else if constexpr (b == 0) {
 #pragma unroll
       for (int l = 0; l < P1; ++l)
-        dst[l] = buffer_load<float>(rin, col_off[a], po + row_of(zsrc[(cc * P1 + l) * c.nz + kz], iy));
+        dst[l] = buffer_load<float>(rin, col_off[a], po + row_of(zs_of(cc * P1 + l), iy));
     } else {
 #pragma unroll
       for (int l = 0; l < P1; ++l)
@@ -337,7 +349,7 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
         for (int n = 0; n < P1; ++n)
           dst[l * P1 + n] = buffer_load<float>(
               rin, col_off[a],
-              po + row_of(zsrc[(cc * P1 + l) * c.nz + kz], ysrc[(b * P1 + n) * c.ny + ky]));
+              po + row_of(zs_of(cc * P1 + l), ys_of(b * P1 + n)));
     }
   };
   float fs[kQ3];
@@ -348,28 +360,25 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
     if constexpr (q + D < kQ3) load.template operator()<q + D>(pre[(q + D) % (D + 1)]);
     constexpr int a = q % 5, b = (q / 5) % 5, cc = q / 25;
     const float(&v)[NV] = pre[q % (D + 1)];
-    int k = 0;
-    asm volatile("" : "+s"(k));
-    const int ky = iy + k, kz = iz + k;
     float y;
     if constexpr (b == 0 && cc == 0) {
       y = v[0];
     } else if constexpr (cc == 0) {
       y = 0.0f;
 #pragma unroll
-      for (int n = 0; n < P1; ++n) y = fma(yw[(b * P1 + n) * c.ny + ky], v[n], y);
+      for (int n = 0; n < P1; ++n) y = fma(wy_of(b * P1 + n), v[n], y);
     } else if constexpr (b == 0) {
       y = 0.0f;
 #pragma unroll
-      for (int l = 0; l < P1; ++l) y = fma(zw[(cc * P1 + l) * c.nz + kz], v[l], y);
+      for (int l = 0; l < P1; ++l) y = fma(wz_of(cc * P1 + l), v[l], y);
     } else {
       y = 0.0f;
 #pragma unroll
       for (int l = 0; l < P1; ++l) {
         float yl = 0.0f;
 #pragma unroll
-        for (int n = 0; n < P1; ++n) yl = fma(yw[(b * P1 + n) * c.ny + ky], v[l * P1 + n], yl);
-        y = fma(zw[(cc * P1 + l) * c.nz + kz], yl, y);
+        for (int n = 0; n < P1; ++n) yl = fma(wy_of(b * P1 + n), v[l * P1 + n], yl);
+        y = fma(wz_of(cc * P1 + l), yl, y);
       }
     }
     float acc = y;  // a = 0: loaded at the node's own column
@@ -515,7 +524,10 @@ hipError_t dispatch3(int fp32, int p, F &&f) {
 
 // Row-segment shape of the float32 step: workgroups of RY x RZ rows, loads
 // D velocities ahead, a barrier every SYNC velocities.
-constexpr int kRows3Y = 4, kRows3Z = 1, kRows3D = 2, kRows3Sync = 5;
+constexpr int kRows3Y = 4, kRows3Z = 1, kRows3Sync = 0;
+// velocities of loads in flight ahead: about 45 registers of prefetch
+constexpr int rows3_lookahead(int p) { return p == 1 ? 6 : p == 2 ? 4 : p == 3 ? 2 : 1; }
+constexpr bool kRows3ZFirst = false;
 
 hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
                          const void *fin, void *fout, int *flag, hipStream_t s) {
@@ -527,7 +539,7 @@ hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Row
     if (ntiles >= (1LL << 31) - 8) return hipErrorInvalidValue;
     const unsigned grid = unsigned((ntiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
     auto go = [&]<int P>() -> hipError_t {
-      k_step3d_rows<P, kRows3Y, kRows3Z, kRows3D, kRows3Sync>
+      k_step3d_rows<P, kRows3Y, kRows3Z, rows3_lookahead(P), kRows3Sync, kRows3ZFirst>
           <<<grid, 64 * kRows3Y * kRows3Z, 0, s>>>(
               static_cast<const float *>(fin), static_cast<float *>(fout), t.ysrc,
               static_cast<const float *>(t.yw), t.zsrc, static_cast<const float *>(t.zw), t, rr, c,
