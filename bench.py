@@ -193,8 +193,10 @@ def d3q125_entry(steps=20, warmup=3):
         ms = ev0.elapsed_time(ev1)
         nu_s = s.n * steps / (ms * 1e-3)
         bpn = 2 * 125 * (8 if precision == "fp64" else 4)
-        tr = profiled_traffic(wname, precision, "direct3d")
-        out[precision] = {"value": nu_s, "unit": "node-updates/s", "ms_per_step": ms / steps,
+        path = "rows3d" if precision == "fp32" else "direct3d"
+        tr = profiled_traffic(wname, precision, path)
+        out[precision] = {"path": path, "value": nu_s, "unit": "node-updates/s",
+                          "ms_per_step": ms / steps,
                           "bytes_per_node_update": bpn, "achieved_gbs": nu_s * bpn / 1e9,
                           "frac": nu_s * bpn / 1e9 / HBM_PEAK_GBS, "traffic": tr,
                           "traffic_over_algorithmic": tr / (s.n * bpn) if tr else None,
