@@ -354,6 +354,9 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
   };
   float fs[kQ3];
   double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  // wave priority 2 while streaming, 0 for the float64 collision (as the 2-D
+  // row step; 1.284 -> 1.260 ms)
+  __builtin_amdgcn_s_setprio(2);
   static_for<D>([&]<int q>() { load.template operator()<q>(pre[q]); });
   static_for<kQ3>([&]<int q>() {
     if constexpr (SYNC > 0 && q > 0 && q % SYNC == 0) __builtin_amdgcn_s_barrier();
@@ -404,6 +407,7 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
     // value's float64 conversion live
     __builtin_amdgcn_sched_barrier(0);
   });
+  __builtin_amdgcn_s_setprio(0);
   // stability flag, BGK toward the 4th-order equilibrium
   if (!store) return;
   const double ux = jx / rho, uy = jy / rho, uz = jz / rho;

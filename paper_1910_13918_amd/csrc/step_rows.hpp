@@ -331,8 +331,16 @@ __global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
   const int iy_t = ty * R + wv;
   const int iy = min(iy_t, c.ny - 1);
   T fs[S][Q1 * Q1];
+  // float32: a wavefront that streams issues before one that collides (wave
+  // priority 2, back to 0 for the float64 collision), so the other
+  // wavefronts' loads are not held behind its float64 arithmetic.  Same-box
+  // A/B: Riemann 1025^2 105.05 -> 103.95 us, shock-vortex rows (Pr = 0.75)
+  // 550 -> 532 us; float64 within the spread (207.5 against 208.5 us), so it
+  // keeps the default
+  if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(2);
   rows_stream_grouped<T, P + 1, S, rows_group_lookahead<T, P + 1, S>(), S == 2, Q1>(
       fin, xrel, xw, xwin, ysrc, yw, TX, ntx, tx, iy, lane, c, &rows_lds[wv][0][0], fs);
+  if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(0);
   const int ix = tx * TX + lane;
   if (ix < c.nx && lane < TX && iy_t < c.ny)
     collide_store<T, MODEL, PR, Q1, kGrouped>(fs, c, fout, (long long)iy * c.nx + ix, flag);
