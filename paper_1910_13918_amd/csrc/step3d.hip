@@ -251,10 +251,11 @@ __global__ __launch_bounds__(256) void k_step3d(const T *__restrict__ fin, T *__
 // its tables are the identity): b = 0 or c = 0 loads one row along that
 // axis, a = 0 loads the node's own column and needs no LDS.  The 125 values
 // stay in registers (float32) for the collision; loads run D velocities
-// ahead, and a workgroup barrier every SYNC velocities keeps its RY x RZ
-// wavefronts, whose source rows overlap, close enough for those re-reads to
-// hit in the L1 cache.  Tiles (64 x RY x RZ nodes) go to the XCDs in
-// contiguous ranges of the (x, y, z) order, so neighbouring rows share an L2.
+// ahead.  Tiles (64 x RY x RZ nodes) go to the XCDs in contiguous ranges of
+// the (x, y, z) order, so neighbouring rows share an L2.  Measured and not
+// kept on the 128^3-node Taylor-Green grid: a workgroup barrier every five
+// velocities (+7 %), 4 x 2 or 2 x 2 rows per workgroup and a z-first tile
+// order (+1 to +7 %).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_lds_sync3() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
@@ -266,7 +267,7 @@ __device__ __forceinline__ void wave_lds_sync3() {
 // unaliased, their wave-uniform entries are fetched with scalar loads (read
 // through the Tables3 pointers, they were vector loads, and every buffer
 // load whose row offset depended on them became a waterfall loop).
-template <int P, int RY, int RZ, int D, int SYNC, bool ZFIRST>
+template <int P, int RY, int RZ, int D>
 __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
     const float *__restrict__ fin, float *__restrict__ fout, const int32_t *__restrict__ ysrc,
     const float *__restrict__ yw, const int32_t *__restrict__ zsrc, const float *__restrict__ zw,
@@ -278,13 +279,11 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
   const int tile = xcd_tile(int(blockIdx.x), ntiles);
   if (tile >= ntiles) return;  // the whole workgroup
   const int tx = tile % r.ntx, rest = tile / r.ntx;
-  const int ty = ZFIRST ? rest / r.ntz : rest % r.nty;
-  const int tz = ZFIRST ? rest % r.ntz : rest / r.nty;
+  const int ty = rest % r.nty, tz = rest / r.nty;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int iy0 = ty * RY + wv % RY, iz0 = tz * RZ + wv / RY;
-  // rows past the grid stream its last row and store nothing (every
-  // wavefront reaches every barrier)
+  // rows past the grid stream its last row and store nothing
   const bool row_ok = iy0 < c.ny && iz0 < c.nz;
   const int iy = min(iy0, c.ny - 1), iz = min(iz0, c.nz - 1);
   const int TX = r.tx;
@@ -359,7 +358,6 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
   __builtin_amdgcn_s_setprio(2);
   static_for<D>([&]<int q>() { load.template operator()<q>(pre[q]); });
   static_for<kQ3>([&]<int q>() {
-    if constexpr (SYNC > 0 && q > 0 && q % SYNC == 0) __builtin_amdgcn_s_barrier();
     if constexpr (q + D < kQ3) load.template operator()<q + D>(pre[(q + D) % (D + 1)]);
     constexpr int a = q % 5, b = (q / 5) % 5, cc = q / 25;
     const float(&v)[NV] = pre[q % (D + 1)];
@@ -527,11 +525,10 @@ hipError_t dispatch3(int fp32, int p, F &&f) {
 }  // namespace
 
 // Row-segment shape of the float32 step: workgroups of RY x RZ rows, loads
-// D velocities ahead, a barrier every SYNC velocities.
-constexpr int kRows3Y = 4, kRows3Z = 1, kRows3Sync = 0;
+// D velocities ahead.
+constexpr int kRows3Y = 4, kRows3Z = 1;
 // velocities of loads in flight ahead: about 45 registers of prefetch
 constexpr int rows3_lookahead(int p) { return p == 1 ? 6 : p == 2 ? 4 : p == 3 ? 2 : 1; }
-constexpr bool kRows3ZFirst = false;
 
 hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
                          const void *fin, void *fout, int *flag, hipStream_t s) {
@@ -543,7 +540,7 @@ hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Row
     if (ntiles >= (1LL << 31) - 8) return hipErrorInvalidValue;
     const unsigned grid = unsigned((ntiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
     auto go = [&]<int P>() -> hipError_t {
-      k_step3d_rows<P, kRows3Y, kRows3Z, rows3_lookahead(P), kRows3Sync, kRows3ZFirst>
+      k_step3d_rows<P, kRows3Y, kRows3Z, rows3_lookahead(P)>
           <<<grid, 64 * kRows3Y * kRows3Z, 0, s>>>(
               static_cast<const float *>(fin), static_cast<float *>(fout), t.ysrc,
               static_cast<const float *>(t.yw), t.zsrc, static_cast<const float *>(t.zw), t, rr, c,
