@@ -255,7 +255,12 @@ __device__ __forceinline__ void rows_stream_grouped(
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (SYNC && g > 0) __builtin_amdgcn_s_barrier();
+    // float32: the group's loads issue at priority 3, the arithmetic at the
+    // kernel's 2 (Riemann 1025^2 104.4 -> 102.6 us; shock-vortex within the
+    // spread)
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(3);
     if (g + DG < NG) load(g + DG, pre[(g + DG) % (DG + 1)]);
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(2);
     const int b = g / S, s = g % S;
     const T(&v)[P1][Q1] = pre[g % (DG + 1)];
     T *rows = lrow + (g & 1) * K * 64;
