@@ -255,12 +255,13 @@ __device__ __forceinline__ void rows_stream_grouped(
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (SYNC && g > 0) __builtin_amdgcn_s_barrier();
-    // float32: the group's loads issue at priority 3, the arithmetic at the
-    // kernel's 2 (Riemann 1025^2 104.4 -> 102.6 us; shock-vortex within the
-    // spread)
-    if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(3);
+    // the group's loads issue at priority 3, the arithmetic at the kernel's 2
+    // (float32 Riemann 1025^2 104.4 -> 102.6 us, shock-vortex within the
+    // spread; float64 with the kernel's priority below: Riemann 208.5 ->
+    // 206.6 us, shock-vortex 1101 -> 1077 us)
+    __builtin_amdgcn_s_setprio(3);
     if (g + DG < NG) load(g + DG, pre[(g + DG) % (DG + 1)]);
-    if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(2);
+    __builtin_amdgcn_s_setprio(2);
     const int b = g / S, s = g % S;
     const T(&v)[P1][Q1] = pre[g % (DG + 1)];
     T *rows = lrow + (g & 1) * K * 64;
@@ -293,10 +294,11 @@ __device__ __forceinline__ void rows_stream_grouped(
 }
 
 // Groups of loads in flight ahead of the one being interpolated (grouped
-// order): two measured within 1 % of one for float32 f + g and 2 % slower
-// for float64 f + g, so one.
+// order), measured with the float32 wave priorities: float32 f + g at p = 3
+// takes two (shock-vortex rows 538-543 -> 529 us), at p = 2 two were 0.8 %
+// slower (Riemann 1025^2); float64 f + g lost 2 % with two.  Elsewhere one.
 template <typename T, int P1, int S>
-constexpr int rows_group_lookahead() { return 1; }
+constexpr int rows_group_lookahead() { return sizeof(T) == 4 && S == 2 && P1 == 4 ? 2 : 1; }
 
 // Planes between workgroup barriers (0: none), measured on 1025^2-node
 // grids: for f + g, every 5 planes (with the deeper lookahead it allows)
@@ -336,16 +338,16 @@ __global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
   const int iy_t = ty * R + wv;
   const int iy = min(iy_t, c.ny - 1);
   T fs[S][Q1 * Q1];
-  // float32: a wavefront that streams issues before one that collides (wave
-  // priority 2, back to 0 for the float64 collision), so the other
-  // wavefronts' loads are not held behind its float64 arithmetic.  Same-box
-  // A/B: Riemann 1025^2 105.05 -> 103.95 us, shock-vortex rows (Pr = 0.75)
-  // 550 -> 532 us; float64 within the spread (207.5 against 208.5 us), so it
-  // keeps the default
-  if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(2);
+  // a wavefront that streams issues before one that collides (wave priority
+  // 2, back to 0 for the float64 collision), so the other wavefronts' loads
+  // are not held behind its float64 arithmetic.  Same-box A/B: float32
+  // Riemann 1025^2 105.05 -> 103.95 us, shock-vortex rows (Pr = 0.75) 550 ->
+  // 532 us (float64 alone was within the spread; with the load-issue
+  // priority of the gather it gains, see there)
+  __builtin_amdgcn_s_setprio(2);
   rows_stream_grouped<T, P + 1, S, rows_group_lookahead<T, P + 1, S>(), S == 2, Q1>(
       fin, xrel, xw, xwin, ysrc, yw, TX, ntx, tx, iy, lane, c, &rows_lds[wv][0][0], fs);
-  if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(0);
+  __builtin_amdgcn_s_setprio(0);
   const int ix = tx * TX + lane;
   if (ix < c.nx && lane < TX && iy_t < c.ny)
     collide_store<T, MODEL, PR, Q1, kGrouped>(fs, c, fout, (long long)iy * c.nx + ix, flag);
