@@ -36,10 +36,14 @@ namespace sllbm {
 constexpr int kRowsTileRows = 4;  // wavefronts (rows) per workgroup: adjoint, float32 step
 
 // Rows per workgroup of the forward step: float64 f + g takes 8 (+1-3 % over
-// 4 on 1025^2-node grids, Pr = 0.75 alike); a single float64 set (-3 %) and
-// float32 (-5 %) keep 4.
-template <typename T, int S>
-constexpr int rows_tile_rows() { return sizeof(T) == 8 && S == 2 ? 8 : kRowsTileRows; }
+// 4 on 1025^2-node grids, Pr = 0.75 alike), and so does float32 f + g at p = 2
+// since the wave priorities (Riemann 1025^2 102.4 -> 101.7 us over three
+// same-box pairs; at p = 3 the shock-vortex rows lost 25 % with 8); a single
+// float64 set (-3 %) and the other float32 cases keep 4.
+template <typename T, int S, int P1 = 0>
+constexpr int rows_tile_rows() {
+  return S == 2 && (sizeof(T) == 8 || P1 == 3) ? 8 : kRowsTileRows;
+}
 
 // Orders this wavefront's LDS accesses: what its lanes wrote before is
 // visible to its lanes after (LDS instructions of one wavefront complete in
@@ -317,14 +321,14 @@ template <typename T, int S, int P1>
 constexpr int rows_min_waves() { return sizeof(T) == 4 && S == 1 ? (P1 >= 4 ? 5 : 6) : 1; }
 
 template <typename T, int P, int MODEL, bool PR, int Q1 = 5>
-__global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S>()),
+__global__ __launch_bounds__((64 * rows_tile_rows<T, Sets<MODEL>::S, P + 1>()),
                              (rows_min_waves<T, Sets<MODEL>::S, P + 1>())) void k_step_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ xrel,
     const T *__restrict__ xw, const int32_t *__restrict__ xwin, const int32_t *__restrict__ ysrc,
     const T *__restrict__ yw, int TX, int ntx, int nty, int strip, StepConsts c,
     int *__restrict__ flag) {
   constexpr int S = Sets<MODEL>::S;
-  constexpr int R = rows_tile_rows<T, Sets<MODEL>::S>();
+  constexpr int R = rows_tile_rows<T, Sets<MODEL>::S, P + 1>();
   __shared__ T rows_lds[R][2 * (Q1 - 1)][64];
   int tile = xcd_tile(blockIdx.x, ntx * nty);
   if (tile >= ntx * nty) return;
@@ -388,7 +392,7 @@ hipError_t launch_rows_family(int fp32, int model, const StepConsts &c, const De
   }
   if (c.q1 != 5) return hipErrorInvalidValue;
   return dispatch_step<PR>(fp32, c.p, model, [&]<typename T, int P, int MODEL>() {
-    constexpr int R = rows_tile_rows<T, Sets<MODEL>::S>();
+    constexpr int R = rows_tile_rows<T, Sets<MODEL>::S, P + 1>();
     const int ntx = (c.nx + t.rows_tx - 1) / t.rows_tx;
     const int nty = (c.ny + R - 1) / R;
     const int grid = ((ntx * nty + 7) / 8) * 8;
