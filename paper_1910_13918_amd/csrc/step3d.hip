@@ -129,16 +129,18 @@ __device__ __forceinline__ T gather3(__amdgpu_buffer_rsrc_t rs, unsigned x0,
 // fout and accumulate rho and j (float64) on the way.
 template <typename T, int P, bool SEAM>
 __device__ __forceinline__ void stream3(const T *__restrict__ fin, T *__restrict__ fout,
-                                        const Tables3 &t, const Consts3 &c, int ix, int iy,
-                                        int iz, long long v, const unsigned (&x0)[5],
-                                        const T (&wx)[5][P + 1], double (&mom)[4]) {
+                                        const int32_t *__restrict__ ysrc,
+                                        const T *__restrict__ yw,
+                                        const int32_t *__restrict__ zsrc,
+                                        const T *__restrict__ zw, const Tables3 &t,
+                                        const Consts3 &c, int ix, int iy, int iz, long long v,
+                                        const unsigned (&x0)[5], const T (&wx)[5][P + 1],
+                                        double (&mom)[4]) {
   constexpr int P1 = P + 1;
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * (long long)sizeof(T));
   const unsigned row_bytes = unsigned(c.nx) * unsigned(sizeof(T));
   const unsigned vo = unsigned(v) * unsigned(sizeof(T));
-  const T *yw = static_cast<const T *>(t.yw);
-  const T *zw = static_cast<const T *>(t.zw);
   double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll 1
   for (int cc = 0; cc < 5; ++cc) {
@@ -146,7 +148,7 @@ __device__ __forceinline__ void stream3(const T *__restrict__ fin, T *__restrict
     T wz[P1];
 #pragma unroll
     for (int l = 0; l < P1; ++l) {
-      zs[l] = t.zsrc[(cc * P1 + l) * c.nz + iz];
+      zs[l] = zsrc[(cc * P1 + l) * c.nz + iz];
       wz[l] = zw[(cc * P1 + l) * c.nz + iz];
     }
 #pragma unroll 1
@@ -155,7 +157,7 @@ __device__ __forceinline__ void stream3(const T *__restrict__ fin, T *__restrict
       T wy[P1];
 #pragma unroll
       for (int n = 0; n < P1; ++n) {
-        const int ys = t.ysrc[(b * P1 + n) * c.ny + iy];
+        const int ys = ysrc[(b * P1 + n) * c.ny + iy];
         wy[n] = yw[(b * P1 + n) * c.ny + iy];
 #pragma unroll
         for (int l = 0; l < P1; ++l)
@@ -198,9 +200,16 @@ __device__ __forceinline__ void stream3(const T *__restrict__ fin, T *__restrict
 // are not held in registers: 125 of them would leave one or two wavefronts
 // per SIMD), pass 2 reads them back, relaxes toward f_eq of the streamed
 // moments and overwrites them (the same thread, the same addresses).
+// The y- and z-tables are restrict-qualified parameters, so their
+// wave-uniform entries are scalar loads (through the Tables3 pointers they
+// were vector loads, and every gather became a waterfall loop).
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_step3d(const T *__restrict__ fin, T *__restrict__ fout,
-                                                Tables3 t, Consts3 c, int *__restrict__ flag) {
+                                                const int32_t *__restrict__ ysrc,
+                                                const T *__restrict__ yw,
+                                                const int32_t *__restrict__ zsrc,
+                                                const T *__restrict__ zw, Tables3 t, Consts3 c,
+                                                int *__restrict__ flag) {
   constexpr int P1 = P + 1;
   const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
   const int iy = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * 4 + int(threadIdx.x >> 6));
@@ -223,9 +232,9 @@ __global__ __launch_bounds__(256) void k_step3d(const T *__restrict__ fin, T *__
   }
   double mom[4];
   if (__builtin_amdgcn_ballot_w64(seam))
-    stream3<T, P, true>(fin, fout, t, c, ix, iy, iz, v, x0, wx, mom);
+    stream3<T, P, true>(fin, fout, ysrc, yw, zsrc, zw, t, c, ix, iy, iz, v, x0, wx, mom);
   else
-    stream3<T, P, false>(fin, fout, t, c, ix, iy, iz, v, x0, wx, mom);
+    stream3<T, P, false>(fin, fout, ysrc, yw, zsrc, zw, t, c, ix, iy, iz, v, x0, wx, mom);
   const double rho = mom[0], ux = mom[1] / rho, uy = mom[2] / rho, uz = mom[3] / rho;
   const bool ok = (rho > 0.0) && isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(uz);
   if (!ok) atomicOr(flag, 1);
@@ -558,8 +567,9 @@ hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Row
   if (c.nz > 65535 || c.ny > 4 * 65535) return hipErrorInvalidValue;
   return dispatch3(fp32, c.p, [&]<typename T, int P>() -> hipError_t {
     const dim3 grid(unsigned((c.nx + 63) / 64), unsigned((c.ny + 3) / 4), unsigned(c.nz));
-    k_step3d<T, P><<<grid, 256, 0, s>>>(static_cast<const T *>(fin), static_cast<T *>(fout), t, c,
-                                        flag);
+    k_step3d<T, P><<<grid, 256, 0, s>>>(static_cast<const T *>(fin), static_cast<T *>(fout), t.ysrc,
+                                        static_cast<const T *>(t.yw), t.zsrc,
+                                        static_cast<const T *>(t.zw), t, c, flag);
     return hipGetLastError();
   });
 }
