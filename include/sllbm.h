@@ -52,6 +52,9 @@
  *     stream); calls that return host data synchronise that stream.
  *   - One context per thread; contexts are independent.
  *   - The library never takes ownership of caller memory.
+ *
+ * The same step in three dimensions (D3Q125, isothermal) has a context of its
+ * own, declared in sllbm3d.h; it shares these status codes and enums.
  */
 #ifndef SLLBM_H
 #define SLLBM_H
