@@ -193,7 +193,7 @@ def d3q125_entry(steps=20, warmup=3):
         ms = ev0.elapsed_time(ev1)
         nu_s = s.n * steps / (ms * 1e-3)
         bpn = 2 * 125 * (8 if precision == "fp64" else 4)
-        path = "rows3d" if precision == "fp32" else "direct3d"
+        path = "rows3d"
         tr = profiled_traffic(wname, precision, path)
         out[precision] = {"path": path, "value": nu_s, "unit": "node-updates/s",
                           "ms_per_step": ms / steps,

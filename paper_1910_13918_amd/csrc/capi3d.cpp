@@ -41,7 +41,7 @@ struct sllbm3d_ctx {
   bool dev_checked = false;
   bool dev_dirty = true;
   Buf3 xsrc, xw, ysrc, yw, zsrc, zw, mx, my, mz, flag, partial, scalar, macro;
-  // float32 row segments (Rows3): segment width (0: unavailable) and windows
+  // row segments (Rows3): segment width (0: unavailable) and windows
   int rows_tx = 0, rows_ntx = 0;
   Buf3 xwin, xrel;
   void *pop[2] = {nullptr, nullptr};
@@ -117,7 +117,7 @@ int upload(sllbm3d_ctx *c, Buf3 &b, const std::vector<V> &v) {
   return SLLBM_OK;
 }
 
-// Row segments of the float32 step along x: the widest segment (at most 64
+// Row segments of the step along x: the widest segment (at most 64
 // nodes, at least 32) whose x-stencils fit 64 consecutive source columns for
 // every segment and 1-D velocity; fills the windows (first unwrapped column
 // per component and segment) and each node's first tap within its window.
@@ -188,11 +188,11 @@ int prepare_device(sllbm3d_ctx *c) {
     rc = upload_axis(c, c->ax, c->xsrc, c->xw, &xt);
     if (!rc) rc = upload_axis(c, c->ay, c->ysrc, c->yw, &yt);
     if (!rc) rc = upload_axis(c, c->az, c->zsrc, c->zw, &zt);
-    // float32 row segments: the zero component must depart from the node
-    // itself on every axis (identity tables), and the 125 planes must stay
-    // within one 32-bit buffer range
+    // row segments: the zero component must depart from the node itself on
+    // every axis (identity tables), and the 125 planes must stay within one
+    // 32-bit buffer range
     c->rows_tx = 0;
-    if (!rc && c->fp32 && double(kQ3) * double(nnodes(c)) * 4.0 < 4294967296.0 &&
+    if (!rc && double(kQ3) * double(nnodes(c)) * double(value_bytes(c)) < 4294967296.0 &&
         identity_table(xt[0], c->ax.n) && identity_table(yt[0], c->ay.n) &&
         identity_table(zt[0], c->az.n)) {
       std::vector<int32_t> win, rel;

@@ -30,11 +30,12 @@ struct Tables3 {
   const double *mx, *my, *mz;  // per-axis node masses (float64)
 };
 
-// Row segments of the float32 step: each wavefront owns TX consecutive
-// x-nodes of one (y, z) row and loads, per 1-D x-component a, the 64 source
-// columns starting at xwin[a * ntx + tx] (unwrapped; the kernel wraps or
-// clamps); xrel[a * nx + ix] is node ix's first x-tap within that window.
-// tx == 0: unavailable (the direct kernel runs instead).
+// Row segments of the step: the wavefronts of one (y, z) row own TX
+// consecutive x-nodes (float64 splits the velocities over two to five
+// wavefronts) and load, per 1-D x-component a, the 64 source columns
+// starting at xwin[a * ntx + tx] (unwrapped; the kernel wraps or clamps);
+// xrel[a * nx + ix] is node ix's first x-tap within that window.  tx == 0:
+// unavailable (the direct kernel runs instead).
 struct Rows3 {
   int tx, ntx, nty, ntz;
   int perx;
@@ -42,8 +43,8 @@ struct Rows3 {
 };
 
 // One step fin -> fout (both planar, 125 N values); flag |= 1 when a node's
-// rho is not positive or a moment is not finite.  The float32 step runs on
-// row segments when r.tx > 0.
+// rho is not positive or a moment is not finite.  The step runs on row
+// segments when r.tx > 0.
 hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
                          const void *fin, void *fout, int *flag, hipStream_t s);
 // f = f_eq(rho, u) from float64 device fields.

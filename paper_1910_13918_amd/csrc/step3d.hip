@@ -93,6 +93,33 @@ __device__ __forceinline__ void for_each_eq3(double rho, double ux, double uy, d
   }
 }
 
+// The unrolled (register) form of for_each_eq3 over rows G0 .. G0 + NG - 1
+// (row g = b + 5 c), each row's inputs pinned by an empty asm (see there).
+template <int G0, int NG, class Fn>
+__device__ __forceinline__ void for_each_eq3_rows(double rho, double ux, double uy, double uz,
+                                                  const Consts3 &c, Fn &&fn) {
+  static_for<NG>([&]<int k>() {
+    constexpr int g = G0 + k;
+    double r = rho, vx = ux, vy = uy, vz = uz;
+    asm volatile("" : "+v"(r), "+v"(vx), "+v"(vy), "+v"(vz));
+    const double qx[5] = {1.0, vx, vx * vx, vx * vx * vx, (vx * vx) * (vx * vx)};
+    const double qy[5] = {1.0, vy, vy * vy, vy * vy * vy, (vy * vy) * (vy * vy)};
+    const double qz[5] = {1.0, vz, vz * vz, vz * vz * vz, (vz * vz) * (vz * vz)};
+    double xr[5][5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      double t = 0.0;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        t = fma(c.hk[a][m], qx[m], t);
+        xr[a][m] = t;
+      }
+    }
+    eq3_row(g % 5, g / 5, r, qy, qz, xr, c, fn);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
 // Interpolated value of one plane at a lane's departure point: the (p+1)^2
 // source rows (z tap l, y tap n; byte offsets so[l][n], wave-uniform) are
 // each read as p+1 consecutive values from x0 (one wide load per row), or
@@ -194,12 +221,14 @@ __device__ __forceinline__ void stream3(const T *__restrict__ fin, T *__restrict
   mom[3] = jz;
 }
 
-// One thread per node; a workgroup is 64 consecutive x-nodes of 4 rows (one
-// wavefront per row), so each wavefront's y and z taps are uniform.  Pass 1
-// streams all 125 velocities into the node's own slots of fout (the values
-// are not held in registers: 125 of them would leave one or two wavefronts
-// per SIMD), pass 2 reads them back, relaxes toward f_eq of the streamed
-// moments and overwrites them (the same thread, the same addresses).
+// The direct step, for grids the row segments do not serve (no segment of
+// 32 or more x-nodes whose stencils fit 64 source columns, or 125 planes
+// beyond 4 GiB).  One thread per node; a workgroup is 64 consecutive
+// x-nodes of 4 rows (one wavefront per row), so each wavefront's y and z
+// taps are uniform.  Pass 1 streams all 125 velocities into the node's own
+// slots of fout (the values are not held in registers), pass 2 reads them
+// back, relaxes toward f_eq of the streamed moments and overwrites them
+// (the same thread, the same addresses).
 // The y- and z-tables are restrict-qualified parameters, so their
 // wave-uniform entries are scalar loads (through the Tables3 pointers they
 // were vector loads, and every gather became a waterfall loop).
@@ -249,7 +278,7 @@ __global__ __launch_bounds__(256) void k_step3d(const T *__restrict__ fin, T *__
 }
 
 // ---------------------------------------------------------------------------
-// float32 step on row segments.  A wavefront owns TX consecutive x-nodes of
+// The step on row segments.  A wavefront owns TX consecutive x-nodes of
 // one (y, z) row, so the y- and z-taps of every velocity are uniform over its
 // lanes.  Per velocity i = a + 5 b + 25 c it loads the (p+1)^2 source rows
 // (one value per lane: column xwin + lane of the window of component a),
@@ -258,11 +287,14 @@ __global__ __launch_bounds__(256) void k_step3d(const T *__restrict__ fin, T *__
 // the lane's p+1 x-weights (eq. (17), z and y factors first).  The zero
 // component of each axis departs from the node itself (the host checks that
 // its tables are the identity): b = 0 or c = 0 loads one row along that
-// axis, a = 0 loads the node's own column and needs no LDS.  The 125 values
-// stay in registers (float32) for the collision; loads run D velocities
-// ahead.  Tiles (64 x RY x RZ nodes) go to the XCDs in contiguous ranges of
-// the (x, y, z) order, so neighbouring rows share an L2.  Measured and not
-// kept on the 128^3-node Taylor-Green grid: a workgroup barrier every five
+// axis, a = 0 loads the node's own column and needs no LDS.  The values
+// stay in registers for the collision (float32: all 125 in one wavefront;
+// float64: split over H wavefronts, below); loads run D velocities ahead.
+// Float64 on the 128^3-node grid: 2.54 ms against 5.83 ms of the direct
+// two-pass kernel, which rereads its own output for the collision.  Tiles
+// (64 x RY x RZ nodes) go to the XCDs in contiguous ranges of the (x, y, z)
+// order, so neighbouring rows share an L2.  Measured and not kept on the
+// 128^3-node Taylor-Green grid (float32): a workgroup barrier every five
 // velocities (+7 %), 4 x 2 or 2 x 2 rows per workgroup and a z-first tile
 // order (+1 to +7 %).
 // ---------------------------------------------------------------------------
@@ -272,18 +304,41 @@ __device__ __forceinline__ void wave_lds_sync3() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// A wave-uniform value of lane k (32-bit lanes; a double takes two reads).
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int k) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(u)), k));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(u >> 32)), k));
+    return __builtin_bit_cast(T, (static_cast<unsigned long long>(hi) << 32) | lo);
+  }
+}
+
+// First (b, c) row of part k of H: the 25 rows of five velocities split
+// into H consecutive parts (H = 2: 13 + 12, H = 3: 9 + 8 + 8, H = 5: 5 each).
+constexpr int rows3_part(int H, int k) { return (25 * k + H - 1) / H; }
+
 // The y- and z-tables come as restrict-qualified parameters: read-only and
 // unaliased, their wave-uniform entries are fetched with scalar loads (read
 // through the Tables3 pointers, they were vector loads, and every buffer
 // load whose row offset depended on them became a waterfall loop).
-template <int P, int RY, int RZ, int D>
-__global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
-    const float *__restrict__ fin, float *__restrict__ fout, const int32_t *__restrict__ ysrc,
-    const float *__restrict__ yw, const int32_t *__restrict__ zsrc, const float *__restrict__ zw,
+// H > 1 (float64, whose 125 values do not fit the registers of one
+// wavefront): the velocities of a row segment are split over H wavefronts,
+// each holding its part's values; the parts add their moment sums through
+// LDS in a fixed order (every part gets the same totals) and relax their
+// own velocities.
+template <typename T, int P, int RY, int RZ, int D, int H>
+__global__ __launch_bounds__(64 * RY * RZ * H) void k_step3d_rows(
+    const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ ysrc,
+    const T *__restrict__ yw, const int32_t *__restrict__ zsrc, const T *__restrict__ zw,
     Tables3 t, Rows3 r, Consts3 c, int *__restrict__ flag) {
   constexpr int P1 = P + 1;
   constexpr int NV = P1 * P1;  // most loads of one velocity
-  __shared__ float lds[RY * RZ][2][64];
+  constexpr unsigned E = sizeof(T);
+  __shared__ T lds[RY * RZ * H][2][64];
   const int ntiles = r.ntx * r.nty * r.ntz;
   const int tile = xcd_tile(int(blockIdx.x), ntiles);
   if (tile >= ntiles) return;  // the whole workgroup
@@ -291,7 +346,8 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
   const int ty = rest % r.nty, tz = rest / r.nty;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-  const int iy0 = ty * RY + wv % RY, iz0 = tz * RZ + wv / RY;
+  const int h = wv % H, rw = wv / H;  // part of the velocities, row of the workgroup
+  const int iy0 = ty * RY + rw % RY, iz0 = tz * RZ + rw / RY;
   // rows past the grid stream its last row and store nothing
   const bool row_ok = iy0 < c.ny && iz0 < c.nz;
   const int iy = min(iy0, c.ny - 1), iz = min(iz0, c.nz - 1);
@@ -300,134 +356,171 @@ __global__ __launch_bounds__(64 * RY * RZ) void k_step3d_rows(
   const bool store = row_ok && lane < TX && ix < c.nx;
   const int ixc = min(tx * TX + min(lane, TX - 1), c.nx - 1);
   const long long N = c.n;
-  const unsigned plane_bytes = unsigned(N * 4);
-  const unsigned row_bytes = unsigned(c.nx) * 4u;
-  const float *xw = static_cast<const float *>(t.xw);
+  const unsigned plane_bytes = unsigned(N * E);
+  const unsigned row_bytes = unsigned(c.nx) * E;
+  const T *xw = static_cast<const T *>(t.xw);
   int xr0[5];
-  float wx[5][P1];
+  T wx[5][P1];
   unsigned col_off[5];
 #pragma unroll
   for (int a = 0; a < 5; ++a) {
     xr0[a] = r.xrel[a * c.nx + ixc];
 #pragma unroll
     for (int m = 0; m < P1; ++m) wx[a][m] = xw[(a * P1 + m) * c.nx + ixc];
-    col_off[a] = unsigned(wrap_or_clamp(r.xwin[a * r.ntx + tx] + lane, c.nx, r.perx)) * 4u;
+    col_off[a] = unsigned(wrap_or_clamp(r.xwin[a * r.ntx + tx] + lane, c.nx, r.perx)) * E;
   }
-  col_off[0] = unsigned(ixc) * 4u;  // a = 0: the node's own column
+  col_off[0] = unsigned(ixc) * E;  // a = 0: the node's own column
   // this row's y- and z-taps, one table entry per lane (lane k = comp (p+1)
   // + tap): each velocity takes its uniform entries with v_readlane, so no
   // scalar memory load is in flight when a wavefront waits for its LDS row
   // (one wait counter covers both)
   const int kk = lane < 5 * P1 ? lane : 0;
   const int ys_v = ysrc[kk * c.ny + iy];
-  const float wy_v = yw[kk * c.ny + iy];
+  const T wy_v = yw[kk * c.ny + iy];
   const int zs_v = zsrc[kk * c.nz + iz];
-  const float wz_v = zw[kk * c.nz + iz];
+  const T wz_v = zw[kk * c.nz + iz];
   auto ys_of = [&](int k) { return __builtin_amdgcn_readlane(ys_v, k); };
   auto zs_of = [&](int k) { return __builtin_amdgcn_readlane(zs_v, k); };
-  auto wy_of = [&](int k) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wy_v), k));
-  };
-  auto wz_of = [&](int k) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wz_v), k));
-  };
-  float *lrow = &lds[wv][0][0];
+  auto wy_of = [&](int k) { return lane_value<T>(wy_v, k); };
+  auto wz_of = [&](int k) { return lane_value<T>(wz_v, k); };
+  T *lrow = &lds[wv][0][0];
   auto row_of = [&](int zs, int ys) { return (unsigned(zs) * unsigned(c.ny) + unsigned(ys)) * row_bytes; };
-  float pre[D + 1][NV];
-  // one resource per array (the host keeps 125 N floats below 4 GiB); the
+  T pre[D + 1][NV];
+  // one resource per array (the host keeps the 125 planes below 4 GiB); the
   // plane is a uniform offset
   const auto rin = make_rsrc(fin, unsigned(kQ3) * plane_bytes);
-  auto load = [&]<int q>(float(&dst)[NV]) {
+  auto load = [&]<int q>(T(&dst)[NV]) {
     constexpr int a = q % 5, b = (q / 5) % 5, cc = q / 25;
     const unsigned po = unsigned(q) * plane_bytes;
     if constexpr (b == 0 && cc == 0) {
-      dst[0] = buffer_load<float>(rin, col_off[a], po + row_of(iz, iy));
+      dst[0] = buffer_load<T>(rin, col_off[a], po + row_of(iz, iy));
     } else if constexpr (cc == 0) {
 #pragma unroll
       for (int n = 0; n < P1; ++n)
-        dst[n] = buffer_load<float>(rin, col_off[a], po + row_of(iz, ys_of(b * P1 + n)));
+        dst[n] = buffer_load<T>(rin, col_off[a], po + row_of(iz, ys_of(b * P1 + n)));
     } else if constexpr (b == 0) {
 #pragma unroll
       for (int l = 0; l < P1; ++l)
-        dst[l] = buffer_load<float>(rin, col_off[a], po + row_of(zs_of(cc * P1 + l), iy));
+        dst[l] = buffer_load<T>(rin, col_off[a], po + row_of(zs_of(cc * P1 + l), iy));
     } else {
 #pragma unroll
       for (int l = 0; l < P1; ++l)
 #pragma unroll
         for (int n = 0; n < P1; ++n)
-          dst[l * P1 + n] = buffer_load<float>(
-              rin, col_off[a],
-              po + row_of(zs_of(cc * P1 + l), ys_of(b * P1 + n)));
+          dst[l * P1 + n] = buffer_load<T>(rin, col_off[a],
+                                           po + row_of(zs_of(cc * P1 + l), ys_of(b * P1 + n)));
     }
   };
-  float fs[kQ3];
+  constexpr int QH = 5 * (H == 1 ? 25 : rows3_part(H, 1));  // values one wavefront holds
+  T fs[QH];
   double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-  // wave priority 2 while streaming, 0 for the float64 collision (as the 2-D
-  // row step; 1.284 -> 1.260 ms)
-  __builtin_amdgcn_s_setprio(2);
-  static_for<D>([&]<int q>() { load.template operator()<q>(pre[q]); });
-  static_for<kQ3>([&]<int q>() {
-    if constexpr (q + D < kQ3) load.template operator()<q + D>(pre[(q + D) % (D + 1)]);
-    constexpr int a = q % 5, b = (q / 5) % 5, cc = q / 25;
-    const float(&v)[NV] = pre[q % (D + 1)];
-    float y;
-    if constexpr (b == 0 && cc == 0) {
-      y = v[0];
-    } else if constexpr (cc == 0) {
-      y = 0.0f;
+  // velocities [Q0, Q0 + NQ) of this wavefront
+  auto stream = [&]<int Q0, int NQ>() {
+    static_for<(D < NQ ? D : NQ)>([&]<int k>() { load.template operator()<Q0 + k>(pre[k]); });
+    static_for<NQ>([&]<int k>() {
+      constexpr int q = Q0 + k;
+      if constexpr (k + D < NQ) load.template operator()<q + D>(pre[(k + D) % (D + 1)]);
+      constexpr int a = q % 5, b = (q / 5) % 5, cc = q / 25;
+      const T(&v)[NV] = pre[k % (D + 1)];
+      T y;
+      if constexpr (b == 0 && cc == 0) {
+        y = v[0];
+      } else if constexpr (cc == 0) {
+        y = T(0);
 #pragma unroll
-      for (int n = 0; n < P1; ++n) y = fma(wy_of(b * P1 + n), v[n], y);
-    } else if constexpr (b == 0) {
-      y = 0.0f;
+        for (int n = 0; n < P1; ++n) y = fma(wy_of(b * P1 + n), v[n], y);
+      } else if constexpr (b == 0) {
+        y = T(0);
 #pragma unroll
-      for (int l = 0; l < P1; ++l) y = fma(wz_of(cc * P1 + l), v[l], y);
-    } else {
-      y = 0.0f;
+        for (int l = 0; l < P1; ++l) y = fma(wz_of(cc * P1 + l), v[l], y);
+      } else {
+        y = T(0);
 #pragma unroll
-      for (int l = 0; l < P1; ++l) {
-        float yl = 0.0f;
+        for (int l = 0; l < P1; ++l) {
+          T yl = T(0);
 #pragma unroll
-        for (int n = 0; n < P1; ++n) yl = fma(wy_of(b * P1 + n), v[l * P1 + n], yl);
-        y = fma(wz_of(cc * P1 + l), yl, y);
+          for (int n = 0; n < P1; ++n) yl = fma(wy_of(b * P1 + n), v[l * P1 + n], yl);
+          y = fma(wz_of(cc * P1 + l), yl, y);
+        }
       }
-    }
-    float acc = y;  // a = 0: loaded at the node's own column
-    if constexpr (a != 0) {
-      float *row = lrow + (q & 1) * 64;
-      row[lane] = y;
-      wave_lds_sync3();
-      acc = 0.0f;
+      T acc = y;  // a = 0: loaded at the node's own column
+      if constexpr (a != 0) {
+        T *row = lrow + (k & 1) * 64;
+        row[lane] = y;
+        wave_lds_sync3();
+        acc = T(0);
 #pragma unroll
-      for (int m = 0; m < P1; ++m) acc = fma(wx[a][m], row[xr0[a] + m], acc);
-    }
-    asm volatile("" : "+v"(acc));  // keep the velocity's arithmetic in its place
-    fs[q] = acc;
-    // moments as the values arrive: each float64 conversion is used at once
-    // (summed after the loop, the scheduler kept all 125 of them live)
-    const double d = double(acc);
-    rho += d;
-    jx = fma(c.xi[a], d, jx);
-    jy = fma(c.xi[b], d, jy);
-    jz = fma(c.xi[cc], d, jz);
-    // one scheduling region per velocity: in a single region of all 125 the
-    // scheduler moved the moment sums behind the last load and kept every
-    // value's float64 conversion live
-    __builtin_amdgcn_sched_barrier(0);
+        for (int m = 0; m < P1; ++m) acc = fma(wx[a][m], row[xr0[a] + m], acc);
+      }
+      asm volatile("" : "+v"(acc));  // keep the velocity's arithmetic in its place
+      fs[k] = acc;
+      // moments as the values arrive: each float64 conversion is used at
+      // once (summed after the loop, the scheduler kept all of them live)
+      const double d = double(acc);
+      rho += d;
+      jx = fma(c.xi[a], d, jx);
+      jy = fma(c.xi[b], d, jy);
+      jz = fma(c.xi[cc], d, jz);
+      // one scheduling region per velocity: in a single region of all 125
+      // the scheduler moved the moment sums behind the last load and kept
+      // every value's float64 conversion live
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  };
+  // wave priority 2 while streaming, 0 for the float64 collision (as the 2-D
+  // row step; float32 1.284 -> 1.260 ms)
+  __builtin_amdgcn_s_setprio(2);
+  static_for<H>([&]<int k>() {
+    if (h == k)
+      stream.template operator()<5 * rows3_part(H, k),
+                                 5 * (rows3_part(H, k + 1) - rows3_part(H, k))>();
   });
   __builtin_amdgcn_s_setprio(0);
+  if constexpr (H > 1) {
+    // the parts' moment sums, added in a fixed order
+    __shared__ double mom_part[RY * RZ][H][4][64];
+    mom_part[rw][h][0][lane] = rho;
+    mom_part[rw][h][1][lane] = jx;
+    mom_part[rw][h][2][lane] = jy;
+    mom_part[rw][h][3][lane] = jz;
+    __syncthreads();
+    rho = jx = jy = jz = 0.0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      rho += mom_part[rw][k][0][lane];
+      jx += mom_part[rw][k][1][lane];
+      jy += mom_part[rw][k][2][lane];
+      jz += mom_part[rw][k][3][lane];
+    }
+  }
   // stability flag, BGK toward the 4th-order equilibrium
   if (!store) return;
   const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
   const bool ok = (rho > 0.0) && isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(uz);
-  if (!ok) atomicOr(flag, 1);
-  const unsigned vo = unsigned(((long long)iz * c.ny + iy) * c.nx + ix) * 4u;
+  if (!ok && h == 0) atomicOr(flag, 1);
+  const unsigned vo = unsigned(((long long)iz * c.ny + iy) * c.nx + ix) * E;
   const double om = c.omega;
   const auto rout = make_rsrc(fout, unsigned(kQ3) * plane_bytes);
-  for_each_eq3<false>(rho, ux, uy, uz, c, [&](int i, double feq) {
-    float x = fs[i];
-    asm volatile("" : "+v"(x));  // not the conversion of the moment sums
-    const double f = double(x);
-    buffer_store<float>(float(f - om * (f - feq)), rout, vo, unsigned(i) * plane_bytes);
+  if constexpr (H == 1) {
+    for_each_eq3<false>(rho, ux, uy, uz, c, [&](int i, double feq) {
+      T x = fs[i];
+      asm volatile("" : "+v"(x));  // not the conversion of the moment sums
+      const double f = double(x);
+      buffer_store<T>(T(f - om * (f - feq)), rout, vo, unsigned(i) * plane_bytes);
+    });
+    return;
+  }
+  static_for<H>([&]<int k>() {
+    if (h == k) {
+      constexpr int G0 = rows3_part(H, k);
+      for_each_eq3_rows<G0, rows3_part(H, k + 1) - G0>(
+          rho, ux, uy, uz, c, [&](int i, double feq) {
+            T x = fs[i - 5 * G0];
+            asm volatile("" : "+v"(x));  // not the conversion of the moment sums
+            const double f = double(x);
+            buffer_store<T>(T(f - om * (f - feq)), rout, vo, unsigned(i) * plane_bytes);
+          });
+    }
   });
 }
 
@@ -533,34 +626,41 @@ hipError_t dispatch3(int fp32, int p, F &&f) {
 
 }  // namespace
 
-// Row-segment shape of the float32 step: workgroups of RY x RZ rows, loads
-// D velocities ahead.
-constexpr int kRows3Y = 4, kRows3Z = 1;
+// Row-segment shape of the step: workgroups of RY rows (of H wavefronts
+// each), loads D velocities ahead.
+constexpr int kRows3Y = 4;  // rows of a float32 workgroup
 // velocities of loads in flight ahead: about 45 registers of prefetch
 constexpr int rows3_lookahead(int p) { return p == 1 ? 6 : p == 2 ? 4 : p == 3 ? 2 : 1; }
+// float64: two parts of the velocities for p <= 2 (two rows a workgroup),
+// three for p = 3 and five for p = 4 (one row)
+constexpr int rows3_parts64(int p) { return p <= 2 ? 2 : p == 3 ? 3 : 5; }
+constexpr int rows3_lookahead64(int p) { return p == 1 ? 4 : p == 2 ? 2 : 1; }
 
 hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
                          const void *fin, void *fout, int *flag, hipStream_t s) {
-  if (fp32 && r.tx > 0) {
-    Rows3 rr = r;
-    rr.nty = (c.ny + kRows3Y - 1) / kRows3Y;
-    rr.ntz = (c.nz + kRows3Z - 1) / kRows3Z;
-    const long long ntiles = (long long)rr.ntx * rr.nty * rr.ntz;
-    if (ntiles >= (1LL << 31) - 8) return hipErrorInvalidValue;
-    const unsigned grid = unsigned((ntiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
-    auto go = [&]<int P>() -> hipError_t {
-      k_step3d_rows<P, kRows3Y, kRows3Z, rows3_lookahead(P)>
-          <<<grid, 64 * kRows3Y * kRows3Z, 0, s>>>(
-              static_cast<const float *>(fin), static_cast<float *>(fout), t.ysrc,
-              static_cast<const float *>(t.yw), t.zsrc, static_cast<const float *>(t.zw), t, rr, c,
-              flag);
+  if (r.tx > 0) {
+    auto go = [&]<typename T, int P, int RY, int D, int H>() -> hipError_t {
+      Rows3 rr = r;
+      rr.nty = (c.ny + RY - 1) / RY;
+      rr.ntz = c.nz;
+      const long long ntiles = (long long)rr.ntx * rr.nty * rr.ntz;
+      if (ntiles >= (1LL << 31) - 8) return hipErrorInvalidValue;
+      const unsigned grid = unsigned((ntiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
+      k_step3d_rows<T, P, RY, 1, D, H><<<grid, 64 * RY * H, 0, s>>>(
+          static_cast<const T *>(fin), static_cast<T *>(fout), t.ysrc,
+          static_cast<const T *>(t.yw), t.zsrc, static_cast<const T *>(t.zw), t, rr, c, flag);
       return hipGetLastError();
     };
+    auto pick = [&]<int P>() -> hipError_t {
+      if (fp32) return go.template operator()<float, P, kRows3Y, rows3_lookahead(P), 1>();
+      constexpr int H = rows3_parts64(P);
+      return go.template operator()<double, P, H == 2 ? 2 : 1, rows3_lookahead64(P), H>();
+    };
     switch (c.p) {
-      case 1: return go.template operator()<1>();
-      case 2: return go.template operator()<2>();
-      case 3: return go.template operator()<3>();
-      case 4: return go.template operator()<4>();
+      case 1: return pick.template operator()<1>();
+      case 2: return pick.template operator()<2>();
+      case 3: return pick.template operator()<3>();
+      case 4: return pick.template operator()<4>();
     }
     return hipErrorInvalidValue;
   }

@@ -83,6 +83,60 @@ def test_several_tiles_and_ragged_tails(precision):
     assert _rel(got, want) <= (1e-12 if precision == "fp64" else 4e-6)
 
 
+def _row_segment_width(ax, dt, xi):
+    """Host-side replica of the library's choice of x-segments for the row
+    kernel: the widest segment (64 down to 32 nodes) whose departure stencils,
+    for every 1-D velocity, fit 64 consecutive source columns; 0 when none
+    does and the direct kernel runs."""
+    P1 = ax.p + 1
+    starts = []
+    for x in xi:
+        d = ax.node_coords() - dt * x
+        shift = np.floor((d - ax.lo) / ax.length).astype(np.int64)
+        cell, _ = ax.locate(d - shift * ax.length)
+        starts.append((np.minimum(cell, ax.ncells - 1) + shift * ax.ncells) * ax.p)
+    tx = 64
+    while tx >= 32:
+        width = max(s[j:j + tx].max() - s[j:j + tx].min() + P1
+                    for s in starts for j in range(0, ax.n, tx))
+        if width <= 64:
+            return tx
+        tx -= width - 64
+    return 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_direct_kernel_on_a_graded_axis(p, precision):
+    """A periodic x-axis of 40 cells of width 0.002 followed by 20 of width
+    0.05: the departures of the fine nodes cross up to 20 cells while the
+    coarse ones cross less than one, so no x-segment of 32 or more nodes
+    reads within 64 source columns and the step runs on the direct kernel
+    (the replica of the segment choice says so); one step against the
+    oracle."""
+    import dataclasses
+    ex = np.concatenate([np.arange(40) * 0.002, 0.08 + np.arange(21) * 0.05])
+    base = W.box3d(ncells=(1, 2, 2), p=p, periodic=(True, False, True), seed=13)
+    dt = 0.014
+    wl = dataclasses.replace(base, edges=(ex,) + tuple(base.edges[1:]), dt=dt, nu=0.3 * dt)
+    g, sim = _oracle(wl)
+    xi = np.unique(d3q125()[0][:, 0])
+    assert _row_segment_width(g.ax, dt, xi) == 0
+    assert _row_segment_width(_oracle(W.box3d(p=p))[0].ax, W.box3d(p=p).dt, xi) > 0
+    F0 = _state(wl, g, sim, 40 + p, precision == "fp32")
+    want = sim.step(F0)
+    s = _solver(wl, precision)
+    try:
+        print(f"[gpu] 3d direct kernel p={p} {precision} nodes={s.n}", flush=True)
+        s.set_populations(F0)
+        s.step(1)
+        got = s.populations()
+        assert s.flags() == (0, 1)
+    finally:
+        s.close()
+    assert _rel(got, want) <= (1e-12 if precision == "fp64" else 2e-6)
+
+
 def test_taylor_green_trajectory_moments_and_mass():
     """20 FP64 steps of the 3-D Taylor-Green vortex (4^3 cells of order 3)
     from the device initialisation f = f_eq: populations, moments and mass
