@@ -632,9 +632,12 @@ constexpr int kRows3Y = 4;  // rows of a float32 workgroup
 // velocities of loads in flight ahead: about 45 registers of prefetch
 constexpr int rows3_lookahead(int p) { return p == 1 ? 6 : p == 2 ? 4 : p == 3 ? 2 : 1; }
 // float64: two parts of the velocities for p <= 2 (two rows a workgroup),
-// three for p = 3 and five for p = 4 (one row)
+// three for p = 3 and five for p = 4 (one row).  Measured at p = 2 on the
+// 128^3-node grid: loads one velocity ahead 2.514 ms, two 2.540, three
+// 2.555; one row a workgroup 2.550; five parts (three wavefronts per SIMD)
+// 2.808.
 constexpr int rows3_parts64(int p) { return p <= 2 ? 2 : p == 3 ? 3 : 5; }
-constexpr int rows3_lookahead64(int p) { return p == 1 ? 4 : p == 2 ? 2 : 1; }
+constexpr int rows3_lookahead64(int p) { return p == 1 ? 4 : 1; }
 
 hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
                          const void *fin, void *fout, int *flag, hipStream_t s) {
