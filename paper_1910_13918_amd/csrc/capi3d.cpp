@@ -43,6 +43,7 @@ struct sllbm3d_ctx {
   Buf3 xsrc, xw, ysrc, yw, zsrc, zw, mx, my, mz, flag, partial, scalar, macro;
   // row segments (Rows3): segment width (0: unavailable) and windows
   int rows_tx = 0, rows_ntx = 0;
+  bool rows_ok = false;  // the row kernels apply (identity zero components, < 4 GiB)
   Buf3 xwin, xrel;
   void *pop[2] = {nullptr, nullptr};
   bool own_pop = false;
@@ -192,9 +193,10 @@ int prepare_device(sllbm3d_ctx *c) {
     // every axis (identity tables), and the 125 planes must stay within one
     // 32-bit buffer range
     c->rows_tx = 0;
-    if (!rc && double(kQ3) * double(nnodes(c)) * double(value_bytes(c)) < 4294967296.0 &&
-        identity_table(xt[0], c->ax.n) && identity_table(yt[0], c->ay.n) &&
-        identity_table(zt[0], c->az.n)) {
+    c->rows_ok = !rc && double(kQ3) * double(nnodes(c)) * double(value_bytes(c)) < 4294967296.0 &&
+                 identity_table(xt[0], c->ax.n) && identity_table(yt[0], c->ay.n) &&
+                 identity_table(zt[0], c->az.n);
+    if (c->rows_ok) {
       std::vector<int32_t> win, rel;
       c->rows_tx = rows3_windows(xt.data(), c->ax.n, c->p + 1, win, rel);
       if (c->rows_tx) {
@@ -241,6 +243,7 @@ Rows3 make_rows(const sllbm3d_ctx *c) {
   r.tx = c->rows_tx;
   r.ntx = c->rows_ntx;
   r.perx = c->ax.periodic ? 1 : 0;
+  if (c->rows_ok && c->ax.n <= 64 * kRows3MaxX) r.full = (c->ax.n + 63) / 64;
   r.xwin = static_cast<const int32_t *>(c->xwin.ptr);
   r.xrel = static_cast<const int32_t *>(c->xrel.ptr);
   return r;

@@ -35,10 +35,16 @@ struct Tables3 {
 // wavefronts) and load, per 1-D x-component a, the 64 source columns
 // starting at xwin[a * ntx + tx] (unwrapped; the kernel wraps or clamps);
 // xrel[a * nx + ix] is node ix's first x-tap within that window.  tx == 0:
-// unavailable (the direct kernel runs instead).
+// unavailable.  Whole rows (full > 0) need no windows; with neither, the
+// direct kernel runs.
+// Whole-row mode: at most this many wavefronts along x (rows of up to 256
+// nodes).
+constexpr int kRows3MaxX = 4;
+
 struct Rows3 {
   int tx, ntx, nty, ntz;
   int perx;
+  int full;  // > 0: wavefronts along x of the whole-row mode (rows of at most 64 kRows3MaxX nodes)
   const int32_t *xwin, *xrel;
 };
 

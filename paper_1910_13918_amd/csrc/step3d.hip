@@ -221,9 +221,10 @@ __device__ __forceinline__ void stream3(const T *__restrict__ fin, T *__restrict
   mom[3] = jz;
 }
 
-// The direct step, for grids the row segments do not serve (no segment of
-// 32 or more x-nodes whose stencils fit 64 source columns, or 125 planes
-// beyond 4 GiB).  One thread per node; a workgroup is 64 consecutive
+// The direct step, for grids the row kernels do not serve (rows longer than
+// the whole-row mode takes, or float64 at p >= 3, with no segment of 32 or
+// more x-nodes whose stencils fit 64 source columns; or 125 planes beyond
+// 4 GiB).  One thread per node; a workgroup is 64 consecutive
 // x-nodes of 4 rows (one wavefront per row), so each wavefront's y and z
 // taps are uniform.  Pass 1 streams all 125 velocities into the node's own
 // slots of fout (the values are not held in registers), pass 2 reads them
@@ -325,36 +326,54 @@ constexpr int rows3_part(int H, int k) { return (25 * k + H - 1) / H; }
 // unaliased, their wave-uniform entries are fetched with scalar loads (read
 // through the Tables3 pointers, they were vector loads, and every buffer
 // load whose row offset depended on them became a waterfall loop).
+// Whole rows (FR; rows of at most 64 kRows3MaxX nodes): the RX wavefronts of
+// a workgroup cover one (y, z) row, 64 x-nodes each, and load only their
+// own nodes' columns; the interpolated rows go to one LDS row of the whole
+// x-extent (a periodic row followed by a copy of its first columns) and
+// each lane reads its x-taps there, from its first tap's column on, after
+// a workgroup barrier.  No source column is loaded twice, and a row needs
+// RX wavefronts instead of one per segment of at most 64 - p - 1 nodes
+// (three for the 128 nodes of the 64^3-cell grid at p = 2, the last with 6
+// nodes): float32 1.258 -> 0.888 ms, float64 2.515 -> 1.847 ms there.  Any
+// x-stencil fits, so graded axes whose stencils spread beyond the segment
+// windows run here too.
 // H > 1 (float64, whose 125 values do not fit the registers of one
 // wavefront): the velocities of a row segment are split over H wavefronts,
 // each holding its part's values; the parts add their moment sums through
 // LDS in a fixed order (every part gets the same totals) and relax their
 // own velocities.
-template <typename T, int P, int RY, int RZ, int D, int H>
-__global__ __launch_bounds__(64 * RY * RZ * H) void k_step3d_rows(
+template <typename T, int P, int RY, int RZ, int D, int H, bool FR = false>
+__global__ __launch_bounds__(64 * (FR ? kRows3MaxX : RZ) * RY * H) void k_step3d_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ ysrc,
     const T *__restrict__ yw, const int32_t *__restrict__ zsrc, const T *__restrict__ zw,
     Tables3 t, Rows3 r, Consts3 c, int *__restrict__ flag) {
+  static_assert(!FR || RZ == 1, "whole rows: rows along y");
   constexpr int P1 = P + 1;
   constexpr int NV = P1 * P1;  // most loads of one velocity
   constexpr unsigned E = sizeof(T);
-  __shared__ T lds[RY * RZ * H][2][64];
-  const int ntiles = r.ntx * r.nty * r.ntz;
+  constexpr int ROW = FR ? 64 * kRows3MaxX + 8 : 64;  // LDS row length
+  __shared__ T lds[RY * RZ * H][2][ROW];
+  const int ntx = FR ? 1 : r.ntx;
+  const int ntiles = ntx * r.nty * r.ntz;
   const int tile = xcd_tile(int(blockIdx.x), ntiles);
   if (tile >= ntiles) return;  // the whole workgroup
-  const int tx = tile % r.ntx, rest = tile / r.ntx;
+  const int tx = tile % ntx, rest = tile / ntx;
   const int ty = rest % r.nty, tz = rest / r.nty;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-  const int h = wv % H, rw = wv / H;  // part of the velocities, row of the workgroup
+  // whole rows: wavefront seg of RX covers x-nodes [64 seg, 64 seg + 64)
+  const int RX = FR ? r.full : 1;
+  const int h = wv % H;                      // part of the velocities
+  const int seg = FR ? (wv / H) % RX : tx;   // segment along x
+  const int rw = FR ? wv / (H * RX) : wv / H;  // row of the workgroup
   const int iy0 = ty * RY + rw % RY, iz0 = tz * RZ + rw / RY;
   // rows past the grid stream its last row and store nothing
   const bool row_ok = iy0 < c.ny && iz0 < c.nz;
   const int iy = min(iy0, c.ny - 1), iz = min(iz0, c.nz - 1);
-  const int TX = r.tx;
-  const int ix = tx * TX + lane;
+  const int TX = FR ? 64 : r.tx;
+  const int ix = seg * TX + lane;
   const bool store = row_ok && lane < TX && ix < c.nx;
-  const int ixc = min(tx * TX + min(lane, TX - 1), c.nx - 1);
+  const int ixc = min(seg * TX + min(lane, TX - 1), c.nx - 1);
   const long long N = c.n;
   const unsigned plane_bytes = unsigned(N * E);
   const unsigned row_bytes = unsigned(c.nx) * E;
@@ -364,10 +383,17 @@ __global__ __launch_bounds__(64 * RY * RZ * H) void k_step3d_rows(
   unsigned col_off[5];
 #pragma unroll
   for (int a = 0; a < 5; ++a) {
-    xr0[a] = r.xrel[a * c.nx + ixc];
 #pragma unroll
     for (int m = 0; m < P1; ++m) wx[a][m] = xw[(a * P1 + m) * c.nx + ixc];
-    col_off[a] = unsigned(wrap_or_clamp(r.xwin[a * r.ntx + tx] + lane, c.nx, r.perx)) * E;
+    if constexpr (FR) {
+      // the first x-tap's column; the others follow it (the last one of a
+      // periodic row wraps into the copy of its first columns)
+      xr0[a] = t.xsrc[a * P1 * c.nx + ixc];
+      col_off[a] = unsigned(ixc) * E;
+    } else {
+      xr0[a] = r.xrel[a * c.nx + ixc];
+      col_off[a] = unsigned(wrap_or_clamp(r.xwin[a * r.ntx + tx] + lane, c.nx, r.perx)) * E;
+    }
   }
   col_off[0] = unsigned(ixc) * E;  // a = 0: the node's own column
   // this row's y- and z-taps, one table entry per lane (lane k = comp (p+1)
@@ -383,7 +409,7 @@ __global__ __launch_bounds__(64 * RY * RZ * H) void k_step3d_rows(
   auto zs_of = [&](int k) { return __builtin_amdgcn_readlane(zs_v, k); };
   auto wy_of = [&](int k) { return lane_value<T>(wy_v, k); };
   auto wz_of = [&](int k) { return lane_value<T>(wz_v, k); };
-  T *lrow = &lds[wv][0][0];
+  T *lrow = &lds[rw * H + h][0][0];
   auto row_of = [&](int zs, int ys) { return (unsigned(zs) * unsigned(c.ny) + unsigned(ys)) * row_bytes; };
   T pre[D + 1][NV];
   // one resource per array (the host keeps the 125 planes below 4 GiB); the
@@ -445,9 +471,15 @@ __global__ __launch_bounds__(64 * RY * RZ * H) void k_step3d_rows(
       }
       T acc = y;  // a = 0: loaded at the node's own column
       if constexpr (a != 0) {
-        T *row = lrow + (k & 1) * 64;
-        row[lane] = y;
-        wave_lds_sync3();
+        T *row = lrow + (k & 1) * ROW;
+        if constexpr (FR) {
+          if (ix < c.nx) row[ix] = y;
+          if (r.perx && ix < P) row[c.nx + ix] = y;
+          __syncthreads();
+        } else {
+          row[lane] = y;
+          wave_lds_sync3();
+        }
         acc = T(0);
 #pragma unroll
         for (int m = 0; m < P1; ++m) acc = fma(wx[a][m], row[xr0[a] + m], acc);
@@ -466,6 +498,12 @@ __global__ __launch_bounds__(64 * RY * RZ * H) void k_step3d_rows(
       // every value's float64 conversion live
       __builtin_amdgcn_sched_barrier(0);
     });
+    if constexpr (FR) {
+      // every wavefront of the workgroup passes the same number of barriers:
+      // one per velocity with a != 0, as many as the largest part has
+      constexpr int most = 4 * (H == 1 ? 25 : rows3_part(H, 1));
+      static_for<most - 4 * (NQ / 5)>([&]<int>() { __syncthreads(); });
+    }
   };
   // wave priority 2 while streaming, 0 for the float64 collision (as the 2-D
   // row step; float32 1.284 -> 1.260 ms)
@@ -478,19 +516,20 @@ __global__ __launch_bounds__(64 * RY * RZ * H) void k_step3d_rows(
   __builtin_amdgcn_s_setprio(0);
   if constexpr (H > 1) {
     // the parts' moment sums, added in a fixed order
-    __shared__ double mom_part[RY * RZ][H][4][64];
-    mom_part[rw][h][0][lane] = rho;
-    mom_part[rw][h][1][lane] = jx;
-    mom_part[rw][h][2][lane] = jy;
-    mom_part[rw][h][3][lane] = jz;
+    __shared__ double mom_part[RY * (FR ? kRows3MaxX : RZ)][H][4][64];
+    const int mi = wv / H;  // the row segment
+    mom_part[mi][h][0][lane] = rho;
+    mom_part[mi][h][1][lane] = jx;
+    mom_part[mi][h][2][lane] = jy;
+    mom_part[mi][h][3][lane] = jz;
     __syncthreads();
     rho = jx = jy = jz = 0.0;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-      rho += mom_part[rw][k][0][lane];
-      jx += mom_part[rw][k][1][lane];
-      jy += mom_part[rw][k][2][lane];
-      jz += mom_part[rw][k][3][lane];
+      rho += mom_part[mi][k][0][lane];
+      jx += mom_part[mi][k][1][lane];
+      jy += mom_part[mi][k][2][lane];
+      jz += mom_part[mi][k][3][lane];
     }
   }
   // stability flag, BGK toward the 4th-order equilibrium
@@ -629,6 +668,8 @@ hipError_t dispatch3(int fp32, int p, F &&f) {
 // Row-segment shape of the step: workgroups of RY rows (of H wavefronts
 // each), loads D velocities ahead.
 constexpr int kRows3Y = 4;  // rows of a float32 workgroup
+// rows of a whole-row workgroup (two: float32 0.895 against 0.888 ms)
+constexpr int kRows3FullY = 1;
 // velocities of loads in flight ahead: about 45 registers of prefetch
 constexpr int rows3_lookahead(int p) { return p == 1 ? 6 : p == 2 ? 4 : p == 3 ? 2 : 1; }
 // float64: two parts of the velocities for p <= 2 (two rows a workgroup),
@@ -641,23 +682,30 @@ constexpr int rows3_lookahead64(int p) { return p == 1 ? 4 : 1; }
 
 hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
                          const void *fin, void *fout, int *flag, hipStream_t s) {
-  if (r.tx > 0) {
-    auto go = [&]<typename T, int P, int RY, int D, int H>() -> hipError_t {
-      Rows3 rr = r;
-      rr.nty = (c.ny + RY - 1) / RY;
-      rr.ntz = c.nz;
-      const long long ntiles = (long long)rr.ntx * rr.nty * rr.ntz;
-      if (ntiles >= (1LL << 31) - 8) return hipErrorInvalidValue;
-      const unsigned grid = unsigned((ntiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
-      k_step3d_rows<T, P, RY, 1, D, H><<<grid, 64 * RY * H, 0, s>>>(
-          static_cast<const T *>(fin), static_cast<T *>(fout), t.ysrc,
-          static_cast<const T *>(t.yw), t.zsrc, static_cast<const T *>(t.zw), t, rr, c, flag);
-      return hipGetLastError();
-    };
+  auto launch = [&]<typename T, int P, int RY, int D, int H, bool FR>(Rows3 rr) -> hipError_t {
+    rr.nty = (c.ny + RY - 1) / RY;
+    rr.ntz = c.nz;
+    const long long ntiles = (long long)(FR ? 1 : rr.ntx) * rr.nty * rr.ntz;
+    if (ntiles >= (1LL << 31) - 8) return hipErrorInvalidValue;
+    const unsigned grid = unsigned((ntiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
+    k_step3d_rows<T, P, RY, 1, D, H, FR><<<grid, 64 * RY * H * (FR ? rr.full : 1), 0, s>>>(
+        static_cast<const T *>(fin), static_cast<T *>(fout), t.ysrc,
+        static_cast<const T *>(t.yw), t.zsrc, static_cast<const T *>(t.zw), t, rr, c, flag);
+    return hipGetLastError();
+  };
+  // whole rows: float32, and float64 where its velocities split in two (a
+  // workgroup of up to 8 wavefronts keeps 256 registers per lane)
+  const bool whole = r.full > 0 && r.full <= kRows3MaxX && (fp32 || c.p <= 2);
+  if (whole || r.tx > 0) {
     auto pick = [&]<int P>() -> hipError_t {
-      if (fp32) return go.template operator()<float, P, kRows3Y, rows3_lookahead(P), 1>();
       constexpr int H = rows3_parts64(P);
-      return go.template operator()<double, P, H == 2 ? 2 : 1, rows3_lookahead64(P), H>();
+      if (whole) {
+        if (fp32) return launch.template operator()<float, P, kRows3FullY, rows3_lookahead(P), 1, true>(r);
+        if constexpr (H == 2)
+          return launch.template operator()<double, P, kRows3FullY, rows3_lookahead64(P), 2, true>(r);
+      }
+      if (fp32) return launch.template operator()<float, P, kRows3Y, rows3_lookahead(P), 1, false>(r);
+      return launch.template operator()<double, P, H == 2 ? 2 : 1, rows3_lookahead64(P), H, false>(r);
     };
     switch (c.p) {
       case 1: return pick.template operator()<1>();

@@ -107,27 +107,32 @@ def _row_segment_width(ax, dt, xi):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("p", [2, 3])
-def test_direct_kernel_on_a_graded_axis(p, precision):
-    """A periodic x-axis of 40 cells of width 0.002 followed by 20 of width
-    0.05: the departures of the fine nodes cross up to 20 cells while the
-    coarse ones cross less than one, so no x-segment of 32 or more nodes
-    reads within 64 source columns and the step runs on the direct kernel
-    (the replica of the segment choice says so); one step against the
+@pytest.mark.parametrize("ncoarse", [20, 100])
+def test_graded_axis_without_row_windows(p, precision, ncoarse):
+    """A periodic x-axis of 40 cells of width 0.002 followed by ncoarse of
+    width 0.05: the departures of the fine nodes cross up to 20 cells while
+    the coarse ones cross less than one, so no x-segment of 32 or more nodes
+    reads within 64 source columns (the replica of the segment choice says
+    so).  With 20 coarse cells (120 or 180 nodes along x) whole rows fit a
+    workgroup: the whole-row kernel runs in float32 and, at p = 2, in
+    float64; the float64 p = 3 case runs the direct kernel.  With 100 (280
+    or 420 nodes) every case runs the direct kernel.  One step against the
     oracle."""
     import dataclasses
-    ex = np.concatenate([np.arange(40) * 0.002, 0.08 + np.arange(21) * 0.05])
+    ex = np.concatenate([np.arange(40) * 0.002, 0.08 + np.arange(ncoarse + 1) * 0.05])
     base = W.box3d(ncells=(1, 2, 2), p=p, periodic=(True, False, True), seed=13)
     dt = 0.014
     wl = dataclasses.replace(base, edges=(ex,) + tuple(base.edges[1:]), dt=dt, nu=0.3 * dt)
     g, sim = _oracle(wl)
     xi = np.unique(d3q125()[0][:, 0])
     assert _row_segment_width(g.ax, dt, xi) == 0
+    assert (g.nx <= 256) == (ncoarse == 20)
     assert _row_segment_width(_oracle(W.box3d(p=p))[0].ax, W.box3d(p=p).dt, xi) > 0
     F0 = _state(wl, g, sim, 40 + p, precision == "fp32")
     want = sim.step(F0)
     s = _solver(wl, precision)
     try:
-        print(f"[gpu] 3d direct kernel p={p} {precision} nodes={s.n}", flush=True)
+        print(f"[gpu] 3d graded axis p={p} {precision} nodes={s.n} nx={g.nx}", flush=True)
         s.set_populations(F0)
         s.step(1)
         got = s.populations()
