@@ -442,6 +442,7 @@ __global__ __launch_bounds__(64 * (FR ? kRows3MaxX : RZ) * RY * H) void k_step3d
   double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
   // velocities [Q0, Q0 + NQ) of this wavefront
   auto stream = [&]<int Q0, int NQ>() {
+    static_assert(Q0 % 5 == 0 && NQ % 5 == 0, "whole (b, c) rows of five velocities");
     static_for<(D < NQ ? D : NQ)>([&]<int k>() { load.template operator()<Q0 + k>(pre[k]); });
     static_for<NQ>([&]<int k>() {
       constexpr int q = Q0 + k;
@@ -471,7 +472,12 @@ __global__ __launch_bounds__(64 * (FR ? kRows3MaxX : RZ) * RY * H) void k_step3d
       }
       T acc = y;  // a = 0: loaded at the node's own column
       if constexpr (a != 0) {
-        T *row = lrow + (k & 1) * ROW;
+        // the two LDS rows alternate over the velocities that use them (the
+        // a = 0 ones do not): with whole rows a wavefront may write the next
+        // row before the others have read the last, never the one before it
+        // (they read that before the barrier it waited for)
+        constexpr int slot = (4 * (k / 5) + a - 1) & 1;
+        T *row = lrow + slot * ROW;
         if constexpr (FR) {
           if (ix < c.nx) row[ix] = y;
           if (r.perx && ix < P) row[c.nx + ix] = y;
@@ -679,6 +685,11 @@ constexpr int rows3_lookahead(int p) { return p == 1 ? 6 : p == 2 ? 4 : p == 3 ?
 // 2.808.
 constexpr int rows3_parts64(int p) { return p <= 2 ? 2 : p == 3 ? 3 : 5; }
 constexpr int rows3_lookahead64(int p) { return p == 1 ? 4 : 1; }
+// whole rows at p = 2, 128-node rows (the same box): float32 six velocities
+// ahead 0.897 ms, five 0.901, four 0.907, three 0.908; float64 two 1.812,
+// three 1.808, one 1.854, none 2.327
+constexpr int rows3_lookahead_whole(int p) { return p == 2 ? 6 : rows3_lookahead(p); }
+constexpr int rows3_lookahead64_whole(int p) { return p == 2 ? 2 : rows3_lookahead64(p); }
 
 hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
                          const void *fin, void *fout, int *flag, hipStream_t s) {
@@ -700,9 +711,11 @@ hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Row
     auto pick = [&]<int P>() -> hipError_t {
       constexpr int H = rows3_parts64(P);
       if (whole) {
-        if (fp32) return launch.template operator()<float, P, kRows3FullY, rows3_lookahead(P), 1, true>(r);
+        if (fp32)
+          return launch.template operator()<float, P, kRows3FullY, rows3_lookahead_whole(P), 1, true>(r);
         if constexpr (H == 2)
-          return launch.template operator()<double, P, kRows3FullY, rows3_lookahead64(P), 2, true>(r);
+          return launch.template operator()<double, P, kRows3FullY, rows3_lookahead64_whole(P), 2, true>(
+              r);
       }
       if (fp32) return launch.template operator()<float, P, kRows3Y, rows3_lookahead(P), 1, false>(r);
       return launch.template operator()<double, P, H == 2 ? 2 : 1, rows3_lookahead64(P), H, false>(r);

@@ -171,6 +171,29 @@ def test_taylor_green_trajectory_moments_and_mass():
     assert m1 == pytest.approx(sim.mass(want), rel=1e-12)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bench_grid_is_bitwise_reproducible(precision):
+    """Two runs of 20 steps of the bench workload (128^3 nodes, whole rows,
+    every wavefront of a row sharing its LDS rows) from the same
+    initialisation give identical bits: every sum has a fixed order, so a
+    difference means a race between the wavefronts of a workgroup (as the
+    one where two velocities with an a = 0 velocity between them wrote the
+    same LDS row)."""
+    wl = W.tgv3d(64, 2)
+    runs = []
+    for _ in range(2):
+        s = _solver(wl, precision)
+        try:
+            print(f"[gpu] 3d reproducibility {precision} nodes={s.n}", flush=True)
+            s.init_from_workload()
+            s.step(20)
+            runs.append(s.populations_device())
+            assert s.flags() == (0, 20)
+        finally:
+            s.close()
+    assert torch.equal(runs[0], runs[1])
+
+
 def test_stability_flag_and_refusals():
     wl = W.box3d(p=2)
     g, sim = _oracle(wl)
