@@ -40,6 +40,12 @@ struct Tables3 {
 // Whole-row mode: at most this many wavefronts along x (rows of up to 256
 // nodes).
 constexpr int kRows3MaxX = 4;
+// ... and their tile order: blocks of this many rows along y and z.  On the
+// 128^3-node grid (same box) against the plain (y, z) order, float32 /
+// float64 ms per step: 16 x 8 0.862 / 1.686, 8 x 16 0.859 / 1.692, 32 x 4
+// 0.866 / 1.750, plain 0.875 / 1.801; on another box 16 x 8 0.866 / 1.693,
+// 8 x 8 0.871 / 1.689, 16 x 16 0.862 / 1.700, 4 x 16 0.881 / 1.696.
+constexpr int kRows3BlockY = 16, kRows3BlockZ = 8;
 
 struct Rows3 {
   int tx, ntx, nty, ntz;

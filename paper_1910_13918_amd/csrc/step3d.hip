@@ -358,7 +358,22 @@ __global__ __launch_bounds__(64 * (FR ? kRows3MaxX : RZ) * RY * H) void k_step3d
   const int tile = xcd_tile(int(blockIdx.x), ntiles);
   if (tile >= ntiles) return;  // the whole workgroup
   const int tx = tile % ntx, rest = tile / ntx;
-  const int ty = rest % r.nty, tz = rest / r.nty;
+  int ty = rest % r.nty, tz = rest / r.nty;
+  if constexpr (FR) {
+    // whole rows go to the XCDs in blocks of kRows3BlockY x kRows3BlockZ
+    // rows (bands of kRows3BlockZ planes, blocks along y inside a band; the
+    // last band and block of each band may be smaller), so the z-neighbours
+    // that read the same source rows run at the same time on one L2
+    constexpr int BY = kRows3BlockY, BZ = kRows3BlockZ;
+    const int band = tile / (r.nty * BZ);
+    const int t1 = tile - band * r.nty * BZ;
+    const int hz = min(BZ, r.ntz - band * BZ);
+    const int by = t1 / (BY * hz);
+    const int w = t1 - by * BY * hz;
+    const int wy = min(BY, r.nty - by * BY);
+    ty = by * BY + w % wy;
+    tz = band * BZ + w / wy;
+  }
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   // whole rows: wavefront seg of RX covers x-nodes [64 seg, 64 seg + 64)
