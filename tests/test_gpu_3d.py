@@ -142,6 +142,31 @@ def test_graded_axis_without_row_windows(p, precision, ncoarse):
     assert _rel(got, want) <= (1e-12 if precision == "fp64" else 2e-6)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("periodic_x", [True, False])
+def test_whole_rows_of_four_wavefronts(precision, periodic_x):
+    """Rows of 200 (periodic) and 201 (zero-gradient) nodes: four wavefronts
+    per row, the last one partly idle (float64: two parts each, eight
+    wavefronts a workgroup), the periodic row's copy of its first columns
+    read by the nodes at its end; two steps of a stretched 100 x 2 x 2-cell
+    box at p = 2."""
+    wl = W.box3d(ncells=(100, 2, 2), p=2, periodic=(periodic_x, False, True), seed=21)
+    g, sim = _oracle(wl)
+    assert g.nx == (200 if periodic_x else 201)
+    F0 = _state(wl, g, sim, 50, precision == "fp32")
+    want = sim.run(F0, 2)
+    s = _solver(wl, precision)
+    try:
+        print(f"[gpu] 3d whole rows nx={g.nx} {precision} nodes={s.n}", flush=True)
+        s.set_populations(F0)
+        s.step(2)
+        got = s.populations()
+        assert s.flags() == (0, 2)
+    finally:
+        s.close()
+    assert _rel(got, want) <= (1e-12 if precision == "fp64" else 4e-6)
+
+
 def test_taylor_green_trajectory_moments_and_mass():
     """20 FP64 steps of the 3-D Taylor-Green vortex (4^3 cells of order 3)
     from the device initialisation f = f_eq: populations, moments and mass
