@@ -342,8 +342,8 @@ constexpr int rows3_part(int H, int k) { return (25 * k + H - 1) / H; }
 // each holding its part's values; the parts add their moment sums through
 // LDS in a fixed order (every part gets the same totals) and relax their
 // own velocities.
-template <typename T, int P, int RY, int RZ, int D, int H, bool FR = false>
-__global__ __launch_bounds__(64 * (FR ? kRows3MaxX : RZ) * RY * H) void k_step3d_rows(
+template <typename T, int P, int RY, int RZ, int D, int H, bool FR = false, int XM = kRows3MaxX>
+__global__ __launch_bounds__(64 * (FR ? XM : RZ) * RY * H) void k_step3d_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ ysrc,
     const T *__restrict__ yw, const int32_t *__restrict__ zsrc, const T *__restrict__ zw,
     Tables3 t, Rows3 r, Consts3 c, int *__restrict__ flag) {
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(64 * (FR ? kRows3MaxX : RZ) * RY * H) void k_step3d
   constexpr int P1 = P + 1;
   constexpr int NV = P1 * P1;  // most loads of one velocity
   constexpr unsigned E = sizeof(T);
-  constexpr int ROW = FR ? 64 * kRows3MaxX + 8 : 64;  // LDS row length
+  constexpr int ROW = FR ? 64 * XM + 8 : 64;  // LDS row length (XM: most wavefronts along x)
   __shared__ T lds[RY * RZ * H][2][ROW];
   const int ntx = FR ? 1 : r.ntx;
   const int ntiles = ntx * r.nty * r.ntz;
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(64 * (FR ? kRows3MaxX : RZ) * RY * H) void k_step3d
   __builtin_amdgcn_s_setprio(0);
   if constexpr (H > 1) {
     // the parts' moment sums, added in a fixed order
-    __shared__ double mom_part[RY * (FR ? kRows3MaxX : RZ)][H][4][64];
+    __shared__ double mom_part[RY * (FR ? XM : RZ)][H][4][64];
     const int mi = wv / H;  // the row segment
     mom_part[mi][h][0][lane] = rho;
     mom_part[mi][h][1][lane] = jx;
@@ -708,20 +708,23 @@ constexpr int rows3_lookahead64_whole(int p) { return p == 2 ? 2 : rows3_lookahe
 
 hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
                          const void *fin, void *fout, int *flag, hipStream_t s) {
-  auto launch = [&]<typename T, int P, int RY, int D, int H, bool FR>(Rows3 rr) -> hipError_t {
+  auto launch = [&]<typename T, int P, int RY, int D, int H, bool FR, int XM = kRows3MaxX>(
+                    Rows3 rr) -> hipError_t {
     rr.nty = (c.ny + RY - 1) / RY;
     rr.ntz = c.nz;
     const long long ntiles = (long long)(FR ? 1 : rr.ntx) * rr.nty * rr.ntz;
     if (ntiles >= (1LL << 31) - 8) return hipErrorInvalidValue;
     const unsigned grid = unsigned((ntiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
-    k_step3d_rows<T, P, RY, 1, D, H, FR><<<grid, 64 * RY * H * (FR ? rr.full : 1), 0, s>>>(
+    k_step3d_rows<T, P, RY, 1, D, H, FR, XM><<<grid, 64 * RY * H * (FR ? rr.full : 1), 0, s>>>(
         static_cast<const T *>(fin), static_cast<T *>(fout), t.ysrc,
         static_cast<const T *>(t.yw), t.zsrc, static_cast<const T *>(t.zw), t, rr, c, flag);
     return hipGetLastError();
   };
-  // whole rows: float32, and float64 where its velocities split in two (a
-  // workgroup of up to 8 wavefronts keeps 256 registers per lane)
-  const bool whole = r.full > 0 && r.full <= kRows3MaxX && (fp32 || c.p <= 2);
+  // whole rows: float32, and float64 where a workgroup of its parts has at
+  // most 8 wavefronts (256 registers per lane): two parts up to 256 nodes
+  // (p <= 2), three up to 128 (p = 3)
+  const bool whole = r.full > 0 && r.full <= kRows3MaxX &&
+                     (fp32 || c.p <= 2 || (c.p == 3 && r.full <= 2));
   if (whole || r.tx > 0) {
     auto pick = [&]<int P>() -> hipError_t {
       constexpr int H = rows3_parts64(P);
@@ -731,6 +734,9 @@ hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Row
         if constexpr (H == 2)
           return launch.template operator()<double, P, kRows3FullY, rows3_lookahead64_whole(P), 2, true>(
               r);
+        if constexpr (H == 3)
+          return launch.template operator()<double, P, kRows3FullY, rows3_lookahead64_whole(P), 3, true,
+                                            2>(r);
       }
       if (fp32) return launch.template operator()<float, P, kRows3Y, rows3_lookahead(P), 1, false>(r);
       return launch.template operator()<double, P, H == 2 ? 2 : 1, rows3_lookahead64(P), H, false>(r);
