@@ -334,7 +334,8 @@ constexpr int rows3_part(int H, int k) { return (25 * k + H - 1) / H; }
 // a workgroup barrier.  No source column is loaded twice, and a row needs
 // RX wavefronts instead of one per segment of at most 64 - p - 1 nodes
 // (three for the 128 nodes of the 64^3-cell grid at p = 2, the last with 6
-// nodes): float32 1.258 -> 0.888 ms, float64 2.515 -> 1.847 ms there.  Any
+// nodes): float32 1.258 -> 0.888 ms, float64 2.515 -> 1.847 ms there (0.86
+// and 1.70 ms with the block order of the rows).  Any
 // x-stencil fits, so graded axes whose stencils spread beyond the segment
 // windows run here too.
 // H > 1 (float64, whose 125 values do not fit the registers of one
@@ -527,7 +528,8 @@ __global__ __launch_bounds__(64 * (FR ? XM : RZ) * RY * H) void k_step3d_rows(
     }
   };
   // wave priority 2 while streaming, 0 for the float64 collision (as the 2-D
-  // row step; float32 1.284 -> 1.260 ms)
+  // row step; float32 segments 1.284 -> 1.260 ms; whole rows without it 3 %
+  // slower, with the loads issued at priority 3 unchanged)
   __builtin_amdgcn_s_setprio(2);
   static_for<H>([&]<int k>() {
     if (h == k)
