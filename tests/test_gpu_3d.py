@@ -144,20 +144,20 @@ def test_graded_axis_without_row_windows(p, precision, ncoarse):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("periodic_x", [True, False])
-def test_whole_rows_of_four_wavefronts(precision, periodic_x):
-    """Rows of 200 (periodic) and 201 (zero-gradient) nodes: four wavefronts
-    per row, the last one partly idle (float64: two parts each, eight
-    wavefronts a workgroup), the periodic row's copy of its first columns
-    read by the nodes at its end; two steps of a stretched 100 x 2 x 2-cell
-    box at p = 2."""
-    wl = W.box3d(ncells=(100, 2, 2), p=2, periodic=(periodic_x, False, True), seed=21)
+@pytest.mark.parametrize("p,ncx,ncyz", [(2, 100, 2), (1, 200, 2), (4, 63, 1)])
+def test_whole_rows_of_four_wavefronts(p, ncx, ncyz, precision, periodic_x):
+    """Rows of 200 to 253 nodes: four wavefronts per row, the last one partly
+    idle (float64 at p <= 2: two parts each, eight wavefronts a workgroup;
+    float64 at p = 4 runs on segments), the periodic row's copy of its first
+    columns read by the nodes at its end; two steps of a stretched box."""
+    wl = W.box3d(ncells=(ncx, ncyz, ncyz), p=p, periodic=(periodic_x, False, True), seed=21)
     g, sim = _oracle(wl)
-    assert g.nx == (200 if periodic_x else 201)
-    F0 = _state(wl, g, sim, 50, precision == "fp32")
+    assert 192 < g.nx <= 256
+    F0 = _state(wl, g, sim, 50 + p, precision == "fp32")
     want = sim.run(F0, 2)
     s = _solver(wl, precision)
     try:
-        print(f"[gpu] 3d whole rows nx={g.nx} {precision} nodes={s.n}", flush=True)
+        print(f"[gpu] 3d whole rows p={p} nx={g.nx} {precision} nodes={s.n}", flush=True)
         s.set_populations(F0)
         s.step(2)
         got = s.populations()
