@@ -43,7 +43,7 @@ struct sllbm3d_ctx {
   Buf3 xsrc, xw, ysrc, yw, zsrc, zw, mx, my, mz, flag, partial, scalar, macro;
   // row segments (Rows3): segment width (0: unavailable) and windows
   int rows_tx = 0, rows_ntx = 0;
-  bool rows_ok = false;  // the row kernels apply (identity zero components, < 4 GiB)
+  bool rows_ok = false;  // the row kernels apply (identity zero components)
   Buf3 xwin, xrel;
   void *pop[2] = {nullptr, nullptr};
   bool own_pop = false;
@@ -189,14 +189,13 @@ int prepare_device(sllbm3d_ctx *c) {
     rc = upload_axis(c, c->ax, c->xsrc, c->xw, &xt);
     if (!rc) rc = upload_axis(c, c->ay, c->ysrc, c->yw, &yt);
     if (!rc) rc = upload_axis(c, c->az, c->zsrc, c->zw, &zt);
-    // row segments: the zero component must depart from the node itself on
-    // every axis (identity tables), and the 125 planes must stay within one
-    // 32-bit buffer range
+    // row kernels: the zero component must depart from the node itself on
+    // every axis (identity tables); the segments also need the 125 planes
+    // within one 32-bit buffer range (whole rows take a resource per plane)
     c->rows_tx = 0;
-    c->rows_ok = !rc && double(kQ3) * double(nnodes(c)) * double(value_bytes(c)) < 4294967296.0 &&
-                 identity_table(xt[0], c->ax.n) && identity_table(yt[0], c->ay.n) &&
+    c->rows_ok = !rc && identity_table(xt[0], c->ax.n) && identity_table(yt[0], c->ay.n) &&
                  identity_table(zt[0], c->az.n);
-    if (c->rows_ok) {
+    if (c->rows_ok && double(kQ3) * double(nnodes(c)) * double(value_bytes(c)) < 4294967296.0) {
       std::vector<int32_t> win, rel;
       c->rows_tx = rows3_windows(xt.data(), c->ax.n, c->p + 1, win, rel);
       if (c->rows_tx) {

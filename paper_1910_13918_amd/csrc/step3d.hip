@@ -343,7 +343,8 @@ constexpr int rows3_part(int H, int k) { return (25 * k + H - 1) / H; }
 // each holding its part's values; the parts add their moment sums through
 // LDS in a fixed order (every part gets the same totals) and relax their
 // own velocities.
-template <typename T, int P, int RY, int RZ, int D, int H, bool FR = false, int XM = kRows3MaxX>
+template <typename T, int P, int RY, int RZ, int D, int H, bool FR = false, int XM = kRows3MaxX,
+          bool BIG = false>
 __global__ __launch_bounds__(64 * (FR ? XM : RZ) * RY * H) void k_step3d_rows(
     const T *__restrict__ fin, T *__restrict__ fout, const int32_t *__restrict__ ysrc,
     const T *__restrict__ yw, const int32_t *__restrict__ zsrc, const T *__restrict__ zw,
@@ -428,12 +429,14 @@ __global__ __launch_bounds__(64 * (FR ? XM : RZ) * RY * H) void k_step3d_rows(
   T *lrow = &lds[rw * H + h][0][0];
   auto row_of = [&](int zs, int ys) { return (unsigned(zs) * unsigned(c.ny) + unsigned(ys)) * row_bytes; };
   T pre[D + 1][NV];
-  // one resource per array (the host keeps the 125 planes below 4 GiB); the
-  // plane is a uniform offset
-  const auto rin = make_rsrc(fin, unsigned(kQ3) * plane_bytes);
+  // one resource per array, the plane a uniform offset (125 planes below
+  // 4 GiB); BIG: one resource per plane (each plane stays below 4 GiB), for
+  // grids beyond that (a few more scalar registers, which at p = 1 spill)
+  const auto rin_all = make_rsrc(fin, BIG ? 0u : unsigned(kQ3) * plane_bytes);
   auto load = [&]<int q>(T(&dst)[NV]) {
     constexpr int a = q % 5, b = (q / 5) % 5, cc = q / 25;
-    const unsigned po = unsigned(q) * plane_bytes;
+    const auto rin = BIG ? make_rsrc(fin + (long long)q * N, plane_bytes) : rin_all;
+    const unsigned po = BIG ? 0u : unsigned(q) * plane_bytes;
     if constexpr (b == 0 && cc == 0) {
       dst[0] = buffer_load<T>(rin, col_off[a], po + row_of(iz, iy));
     } else if constexpr (cc == 0) {
@@ -562,13 +565,19 @@ __global__ __launch_bounds__(64 * (FR ? XM : RZ) * RY * H) void k_step3d_rows(
   if (!ok && h == 0) atomicOr(flag, 1);
   const unsigned vo = unsigned(((long long)iz * c.ny + iy) * c.nx + ix) * E;
   const double om = c.omega;
-  const auto rout = make_rsrc(fout, unsigned(kQ3) * plane_bytes);
+  const auto rout_all = make_rsrc(fout, BIG ? 0u : unsigned(kQ3) * plane_bytes);
+  auto put = [&](int i, T v) {
+    if constexpr (BIG)
+      buffer_store<T>(v, make_rsrc(fout + (long long)i * N, plane_bytes), vo, 0);
+    else
+      buffer_store<T>(v, rout_all, vo, unsigned(i) * plane_bytes);
+  };
   if constexpr (H == 1) {
     for_each_eq3<false>(rho, ux, uy, uz, c, [&](int i, double feq) {
       T x = fs[i];
       asm volatile("" : "+v"(x));  // not the conversion of the moment sums
       const double f = double(x);
-      buffer_store<T>(T(f - om * (f - feq)), rout, vo, unsigned(i) * plane_bytes);
+      put(i, T(f - om * (f - feq)));
     });
     return;
   }
@@ -580,7 +589,7 @@ __global__ __launch_bounds__(64 * (FR ? XM : RZ) * RY * H) void k_step3d_rows(
             T x = fs[i - 5 * G0];
             asm volatile("" : "+v"(x));  // not the conversion of the moment sums
             const double f = double(x);
-            buffer_store<T>(T(f - om * (f - feq)), rout, vo, unsigned(i) * plane_bytes);
+            put(i, T(f - om * (f - feq)));
           });
     }
   });
@@ -710,35 +719,45 @@ constexpr int rows3_lookahead64_whole(int p) { return p == 2 ? 2 : rows3_lookahe
 
 hipError_t launch_step3d(int fp32, const Consts3 &c, const Tables3 &t, const Rows3 &r,
                          const void *fin, void *fout, int *flag, hipStream_t s) {
-  auto launch = [&]<typename T, int P, int RY, int D, int H, bool FR, int XM = kRows3MaxX>(
-                    Rows3 rr) -> hipError_t {
+  auto launch = [&]<typename T, int P, int RY, int D, int H, bool FR, int XM = kRows3MaxX,
+                    bool BIG = false>(Rows3 rr) -> hipError_t {
     rr.nty = (c.ny + RY - 1) / RY;
     rr.ntz = c.nz;
     const long long ntiles = (long long)(FR ? 1 : rr.ntx) * rr.nty * rr.ntz;
     if (ntiles >= (1LL << 31) - 8) return hipErrorInvalidValue;
     const unsigned grid = unsigned((ntiles + 7) / 8 * 8);  // whole rounds of the 8 XCDs
-    k_step3d_rows<T, P, RY, 1, D, H, FR, XM><<<grid, 64 * RY * H * (FR ? rr.full : 1), 0, s>>>(
-        static_cast<const T *>(fin), static_cast<T *>(fout), t.ysrc,
-        static_cast<const T *>(t.yw), t.zsrc, static_cast<const T *>(t.zw), t, rr, c, flag);
+    k_step3d_rows<T, P, RY, 1, D, H, FR, XM, BIG>
+        <<<grid, 64 * RY * H * (FR ? rr.full : 1), 0, s>>>(
+            static_cast<const T *>(fin), static_cast<T *>(fout), t.ysrc,
+            static_cast<const T *>(t.yw), t.zsrc, static_cast<const T *>(t.zw), t, rr, c, flag);
     return hipGetLastError();
   };
+  // the 125 planes beyond one 32-bit buffer range: whole rows only, with a
+  // resource per plane
+  const bool big = double(kQ3) * double(c.n) * (fp32 ? 4.0 : 8.0) >= 4294967296.0;
   // whole rows: float32, and float64 where a workgroup of its parts has at
   // most 8 wavefronts (256 registers per lane): two parts up to 256 nodes
   // (p <= 2), three up to 128 (p = 3)
   const bool whole = r.full > 0 && r.full <= kRows3MaxX &&
                      (fp32 || c.p <= 2 || (c.p == 3 && r.full <= 2));
-  if (whole || r.tx > 0) {
+  const bool segments = r.tx > 0 && !big;
+  if (whole || segments) {
     auto pick = [&]<int P>() -> hipError_t {
       constexpr int H = rows3_parts64(P);
       if (whole) {
-        if (fp32)
-          return launch.template operator()<float, P, kRows3FullY, rows3_lookahead_whole(P), 1, true>(r);
-        if constexpr (H == 2)
-          return launch.template operator()<double, P, kRows3FullY, rows3_lookahead64_whole(P), 2, true>(
-              r);
-        if constexpr (H == 3)
-          return launch.template operator()<double, P, kRows3FullY, rows3_lookahead64_whole(P), 3, true,
-                                            2>(r);
+        auto rows = [&]<bool BIG>() -> hipError_t {
+          if (fp32)
+            return launch.template operator()<float, P, kRows3FullY, rows3_lookahead_whole(P), 1,
+                                              true, kRows3MaxX, BIG>(r);
+          if constexpr (H == 2)
+            return launch.template operator()<double, P, kRows3FullY, rows3_lookahead64_whole(P), 2,
+                                              true, kRows3MaxX, BIG>(r);
+          if constexpr (H == 3)
+            return launch.template operator()<double, P, kRows3FullY, rows3_lookahead64_whole(P), 3,
+                                              true, 2, BIG>(r);
+          return hipErrorInvalidValue;
+        };
+        return big ? rows.template operator()<true>() : rows.template operator()<false>();
       }
       if (fp32) return launch.template operator()<float, P, kRows3Y, rows3_lookahead(P), 1, false>(r);
       return launch.template operator()<double, P, H == 2 ? 2 : 1, rows3_lookahead64(P), H, false>(r);

@@ -219,6 +219,43 @@ def test_bench_grid_is_bitwise_reproducible(precision):
     assert torch.equal(runs[0], runs[1])
 
 
+@pytest.mark.parametrize("precision,ncells", [("fp32", 104), ("fp64", 82)])
+def test_grids_beyond_one_buffer_range_at_sampled_nodes(precision, ncells):
+    """Taylor-Green boxes whose 125 planes exceed 4 GiB (208^3 nodes in
+    float32, 164^3 in float64): whole rows with a buffer resource per plane.
+    One step from the device initialisation f = f_eq against the oracle at
+    200 seeded nodes (their stencils' sources set to the oracle's f_eq, in
+    the population precision)."""
+    wl = W.tgv3d(ncells, 2)
+    g, sim = _oracle(wl)
+    size = 4 if precision == "fp32" else 8
+    assert 125 * g.nnodes * size >= 2 ** 32
+    rng = np.random.default_rng(11)
+    nodes = np.sort(rng.choice(g.nnodes, 200, replace=False))
+    stencils = [sim.departure_stencil(i, nodes) for i in range(125)]
+    src = np.unique(np.concatenate([st[0].reshape(-1) for st in stencils]))
+    X, Y, Z = g.coords()
+    feq = sim.init(*wl.fields(X[src], Y[src], Z[src]))
+    if precision == "fp32":
+        feq = feq.astype(np.float32).astype(np.float64)
+    where = {v: k for k, v in enumerate(src)}
+    streamed = np.empty((125, len(nodes)))
+    for i, (sv, wv) in enumerate(stencils):
+        cols = np.vectorize(where.__getitem__)(sv)
+        streamed[i] = (wv * feq[i, cols]).sum(axis=(0, 1, 2))
+    want = sim.collide(streamed)
+    s = _solver(wl, precision)
+    try:
+        print(f"[gpu] 3d beyond one buffer range {precision} nodes={s.n}", flush=True)
+        s.init_from_workload()
+        s.step(1)
+        got = s.populations_device()[:, torch.tensor(nodes, device="cuda")].cpu().numpy()
+        assert s.flags() == (0, 1)
+    finally:
+        s.close()
+    assert _rel(got.astype(np.float64), want) <= (1e-12 if precision == "fp64" else 2e-6)
+
+
 def test_stability_flag_and_refusals():
     wl = W.box3d(p=2)
     g, sim = _oracle(wl)
