@@ -221,10 +221,10 @@ __device__ __forceinline__ void stream3(const T *__restrict__ fin, T *__restrict
   mom[3] = jz;
 }
 
-// The direct step, for grids the row kernels do not serve (rows longer than
-// the whole-row mode takes, or float64 at p >= 3, with no segment of 32 or
-// more x-nodes whose stencils fit 64 source columns; or 125 planes beyond
-// 4 GiB).  One thread per node; a workgroup is 64 consecutive
+// The direct step, for grids the row kernels do not serve: rows longer than
+// the whole-row mode takes (in float64 at p >= 3 fewer, at p = 4 none) with
+// no segment of 32 or more x-nodes whose stencils fit 64 source columns, or
+// whose 125 planes exceed 4 GiB.  One thread per node; a workgroup is 64 consecutive
 // x-nodes of 4 rows (one wavefront per row), so each wavefront's y and z
 // taps are uniform.  Pass 1 streams all 125 velocities into the node's own
 // slots of fout (the values are not held in registers), pass 2 reads them
